@@ -1,0 +1,237 @@
+"""Pins of the CPU oracle against facts fixed by the paper's definitions and by mathematics.
+
+Each test checks the oracle against something other than itself: hand-derived fixtures,
+closed-form counts, textbook special cases (Kruskal for H0), the dual union-find of the
+paper's Sec. 3.1 / Appendix A for the top dimension, persistent Betti numbers by brute-force
+ranks, the pairing lemma, the Euler-characteristic curve and symmetries.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+import _ref
+import fixtures
+
+RNG = np.random.default_rng(12345)
+
+
+def _tiny_cases(n2=24, n3=10, max2=5, max3=3):
+    rng = np.random.default_rng(7)
+    cases = []
+    for i in range(n2):
+        shape = tuple(int(x) for x in rng.integers(1, max2 + 1, size=2))
+        lev = int(rng.choice([2, 3, 5, 1000]))
+        cases.append(S.levels(shape, lev, 100 + i))
+    for i in range(n3):
+        shape = tuple(int(x) for x in rng.integers(1, max3 + 1, size=3))
+        lev = int(rng.choice([2, 3, 1000]))
+        cases.append(S.levels(shape, lev, 200 + i))
+    return cases
+
+
+def _as_tuples(pairs):
+    return [(int(p["dim"]), float(p["birth"]), float(p["death"]), int(p["birth_cell"]),
+             int(p["death_cell"]), int(p["birth_vertex"]), int(p["death_vertex"])) for p in pairs]
+
+
+# ------------------------------------------------------------------ P8 fixtures --
+
+@pytest.mark.parametrize("name,img,expected,case", fixtures.load(), ids=lambda x: x if isinstance(x, str) else "")
+def test_hand_fixtures(name, img, expected, case):
+    exp = [(d, float(np.float32(b)), float(np.float32(de)) if de != float("inf") else de, bc, dc, bv, dv)
+           for d, b, de, bc, dc, bv, dv in expected]
+    for method in (oracle.SPLIT, oracle.FULL):
+        got = _as_tuples(oracle.diagram(img, method=method))
+        assert got == exp, (name, method, got)
+    if img.ndim == 3:   # all dimensions: H1 of a shell / sphere has no non-zero pair
+        full = oracle.diagram(img, dims=(0, 1, 2), method=oracle.FULL)
+        assert not np.any(full["dim"] == 1)
+    if "grad_sq_persistence" in case:
+        pr = oracle.diagram(img)
+        fin = pr["death_cell"] >= 0
+        gb = np.where(fin, -2.0 * (pr["death"] - pr["birth"]), 0.0).astype(np.float32)
+        gd = np.where(fin, 2.0 * (pr["death"] - pr["birth"]), 0.0).astype(np.float32)
+        g = oracle.gradient(pr, gb, gd, img.shape)
+        np.testing.assert_allclose(g.ravel(), np.asarray(case["grad_sq_persistence"], np.float32), atol=1e-6)
+
+
+# -------------------------------------------------------- P1 / P2 closed forms --
+
+def _counts(shape):
+    e = (1,) * (3 - len(shape)) + tuple(shape)
+    out = [0, 0, 0, 0]
+    for dz, dy, dx in itertools.product((0, 1), repeat=3):
+        k = dz + dy + dx
+        out[k] += (e[0] - dz) * (e[1] - dy) * (e[2] - dx)
+    return out
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 7), (4, 5), (6, 3), (2, 2, 2), (3, 4, 2), (1, 3, 3)])
+def test_cell_and_pair_counts(shape):
+    img = S.levels(shape, 3, sum(shape))
+    nd = len(shape)
+    V, E, F, C = _counts(shape)
+    assert V - E + F - C == 1                       # Euler characteristic of a box
+    allp = oracle.diagram(img, dims=range(nd + 1), method=oracle.FULL, keep_zero=True)
+    # every cell appears exactly once, as a birth or as a death
+    seen = np.concatenate([allp["birth_cell"], allp["death_cell"][allp["death_cell"] >= 0]])
+    assert len(seen) == len(set(seen.tolist())) == sum(_counts(shape))
+    ess = allp[allp["death_cell"] < 0]
+    assert len(ess) == 1 and ess["dim"][0] == 0     # one essential class, in H0
+    h0 = allp[allp["dim"] == 0]
+    assert len(h0) == V                             # V-1 finite + 1 essential
+    top = C if nd == 3 else F
+    assert np.sum(allp["dim"] == nd - 1) == top     # every top cell kills a (top-1) class
+    if nd == 2:
+        assert np.sum(allp["dim"] == 1) == F
+    else:
+        assert np.sum(allp["dim"] == 1) == E - V + 1 == F - C
+
+
+# ------------------------------------------------------------- P3 Kruskal (H0) --
+
+def test_h0_equals_kruskal():
+    cases = _tiny_cases() + [S.grf((16, 16), 2.0, 5), S.uniform((9, 11), 3), S.levels((4, 4, 4), 3, 9)]
+    for img in cases:
+        for keep_zero in (False, True):
+            pr = oracle.diagram(img, dims=(0,), keep_zero=keep_zero)
+            got = sorted(zip(pr["birth_cell"].tolist(), pr["death_cell"].tolist()))
+            assert got == _ref.kruskal_h0(img, keep_zero=keep_zero)
+
+
+# --------------------------------------------------- P4 top dimension three ways --
+
+def test_top_dim_three_routes_agree():
+    cases = _tiny_cases() + [S.grf((12, 12), 1.5, 6), S.levels((4, 3, 4), 2, 8), S.uniform((3, 4, 4), 4)]
+    for img in cases:
+        nd = img.ndim
+        for keep_zero in (False, True):
+            a = oracle.diagram(img, dims=(nd - 1,), method=oracle.SPLIT, keep_zero=keep_zero)
+            b = oracle.diagram(img, dims=(nd - 1,), method=oracle.FULL, keep_zero=keep_zero)
+            assert _as_tuples(a) == _as_tuples(b)
+            got = sorted(zip(a["birth_cell"].tolist(), a["death_cell"].tolist()))
+            assert got == _ref.dual_union_find_top(img, keep_zero=keep_zero)
+
+
+# ------------------------------------------- P5 brute-force persistent Betti ranks --
+
+def test_value_multiset_brute_force():
+    for img in _tiny_cases(n2=14, n3=5, max2=4, max3=3):
+        nd = img.ndim
+        ref = _ref.persistent_betti_multiset(img)
+        full = oracle.diagram(img, dims=range(nd + 1), method=oracle.FULL)
+        assert _ref.multiset_of(full) == ref
+        split = oracle.diagram(img, method=oracle.SPLIT)
+        assert _ref.multiset_of(split) == {k: v for k, v in ref.items() if k[0] in (0, nd - 1)}
+
+
+# ---------------------------------------------------------- P6 pairing lemma --
+
+@pytest.mark.parametrize("shape,lev,seed", [((3, 3), 3, 1), ((2, 4), 2, 2), ((3, 3), 1000, 3),
+                                            ((2, 2, 2), 2, 4), ((2, 2, 2), 1000, 5), ((1, 5), 2, 6)])
+def test_exact_indices_pairing_lemma(shape, lev, seed):
+    img = S.levels(shape, lev, seed)
+    ref, cx = _ref.pairing_lemma_pairs(img)
+    allp = oracle.diagram(img, dims=range(len(shape) + 1), method=oracle.FULL, keep_zero=True)
+    got = {(int(p["birth_cell"]), int(p["death_cell"])) for p in allp if p["death_cell"] >= 0}
+    assert got == ref
+    # vertices: the last-entering vertex of each critical cell
+    for p in allp:
+        assert p["birth_vertex"] == cx.lsv[p["birth_cell"]]
+        if p["death_cell"] >= 0:
+            assert p["death_vertex"] == cx.lsv[p["death_cell"]]
+
+
+# ---------------------------------------------------- P7 Euler characteristic curve --
+
+@pytest.mark.parametrize("shape,lev,seed", [((10, 9), 4, 1), ((12, 12), 1000, 2), ((5, 4, 6), 3, 3),
+                                            ((4, 4, 4), 1000, 4)])
+def test_euler_characteristic_curve(shape, lev, seed):
+    img = S.levels(shape, lev, seed)
+    nd = len(shape)
+    pr = oracle.diagram(img, dims=range(nd + 1), method=oracle.FULL)
+    cx = _ref.Complex(img)
+    for t in np.unique(img):
+        chi = sum((-1) ** int(cx.dim[c]) for c in range(cx.n) if cx.f[c] <= t)
+        alive = sum((-1) ** int(p["dim"]) for p in pr if p["birth"] <= t < p["death"])
+        assert chi == alive
+
+
+# ---------------------------------------------------------------- P9 metamorphic --
+
+def test_rank_replacement_keeps_indices():
+    for img in _tiny_cases(n2=8, n3=4) + [S.grf((20, 17), 2.0, 3)]:
+        flat = img.ravel()
+        order = np.lexsort((np.arange(flat.size), flat.astype(np.float64)))
+        rk = np.empty(flat.size, np.float32)
+        rk[order] = np.arange(flat.size, dtype=np.float32)
+        a = oracle.diagram(img, keep_zero=True)
+        b = oracle.diagram(rk.reshape(img.shape), keep_zero=True)
+        for f in ("dim", "birth_cell", "death_cell", "birth_vertex", "death_vertex"):
+            assert np.array_equal(a[f], b[f])
+
+
+def test_symmetries_keep_value_multiset():
+    imgs = [S.levels((5, 4), 3, 11), S.uniform((6, 5), 12), S.levels((3, 3, 4), 3, 13),
+            S.uniform((3, 4, 3), 14)]
+    for img in imgs:
+        nd = img.ndim
+        base = _ref.multiset_of(oracle.diagram(img, dims=range(nd + 1), method=oracle.FULL))
+        for perm in itertools.permutations(range(nd)):
+            for flips in itertools.product((False, True), repeat=nd):
+                t = np.transpose(img, perm)
+                for ax, fl in enumerate(flips):
+                    if fl:
+                        t = np.flip(t, ax)
+                t = np.ascontiguousarray(t)
+                got = _ref.multiset_of(oracle.diagram(t, dims=range(nd + 1), method=oracle.FULL))
+                assert got == base
+
+
+# ---------------------------------------------------------------- P11 gradient --
+
+def test_gradient_finite_differences():
+    h = 1e-4
+    for k in range(3):
+        img = S.tie_free((16, 16), 4000 + k)
+
+        def loss(x):
+            pr = oracle.diagram(x)
+            fin = pr["death_cell"] >= 0
+            d = pr["death"][fin].astype(np.float64) - pr["birth"][fin].astype(np.float64)
+            return float(np.sum(d * d))
+
+        pr = oracle.diagram(img)
+        fin = pr["death_cell"] >= 0
+        gb = np.where(fin, -2.0 * (pr["death"].astype(np.float64) - pr["birth"]), 0.0).astype(np.float32)
+        gd = np.where(fin, 2.0 * (pr["death"].astype(np.float64) - pr["birth"]), 0.0).astype(np.float32)
+        g = oracle.gradient(pr, gb, gd, img.shape).ravel()
+        rng = np.random.default_rng(k)
+        for p in rng.choice(img.size, 40, replace=False):
+            xp = img.copy().ravel()
+            xm = img.copy().ravel()
+            xp[p] = np.float32(xp[p] + h)
+            xm[p] = np.float32(xm[p] - h)
+            step = float(xp[p]) - float(xm[p])      # the exact float step
+            fd = (loss(xp.reshape(img.shape)) - loss(xm.reshape(img.shape))) / step
+            assert abs(fd - g[p]) <= 1e-3 * max(1.0, abs(fd)), (k, p, fd, g[p])
+
+
+# ------------------------------------------------------------------- errors --
+
+def test_errors():
+    with pytest.raises(oracle.OracleError):
+        oracle.diagram(np.array([[0.0, np.nan]], np.float32))
+    with pytest.raises(oracle.OracleError):
+        oracle.diagram(np.zeros((2, 2, 2, 2), np.float32))
+
+
+def test_signed_zero_and_infinities():
+    img = np.array([[0.0, -0.0, 1.0], [np.inf, -np.inf, 0.5]], np.float32)
+    pr = oracle.diagram(img, dims=(0, 1, 2), method=oracle.FULL)
+    assert _ref.multiset_of(pr) == _ref.persistent_betti_multiset(img)
+    ess = pr[pr["death_cell"] < 0]
+    assert len(ess) == 1 and ess["birth_vertex"][0] == 4     # -inf pixel is the minimum
