@@ -1,0 +1,160 @@
+/*
+ * flashcubical.h -- C ABI of the gfx950 library for V-filtration cubical persistence over F2
+ * on 2D images and 3D volumes (H0 and the top dimension: H1 for images, H2 for volumes).
+ *
+ * Method (Le Breton, Szustakowski, Piraud, "Fast Cubical Persistent Homology on 2D and 3D
+ * Images via Union-Find, Pruning, and Lookup Tables"):
+ *   - cells, V-filtration and persistence pairs as defined in Sec. 2.1-2.2;
+ *   - the fully refined order of Sec. 2.3: a cell is ordered by its last-entering vertex
+ *     (pixel value, then row-major pixel index), then by dimension, then by its index on
+ *     the doubled grid; pairs of equal birth and death value are not reported;
+ *   - lookup-table classification and pruning of each vertex's lower star (Sec. 3.2, 3.3),
+ *     union-find for H0 and union-find on the dual graph with a cell at infinity for the top
+ *     dimension (Sec. 3.1, Appendix A), as assembled in Sec. 4.1 (2D) and Sec. 4.2 steps 1-3
+ *     (3D).  H1 of a volume (Sec. 4.2 steps 4-5) is not computed by this library.
+ *
+ * Conventions shared by every entry point:
+ *   - Pixel layout: row-major, last axis fastest.  2D extents are (H, W), 3D (D, H, W); every
+ *     extent >= 1, and the voxel count of one instance must be below 2^27.
+ *   - pixidx: row-major pixel index.  Cell index: row-major index on the doubled grid
+ *     (2H-1, 2W-1) or (2D-1, 2H-1, 2W-1), a coordinate being odd where the cell spans that
+ *     axis.
+ *   - Output pairs, per instance, are sorted by (dim, birth cell in the refined order):
+ *     H0 first (its essential class, death = +inf, death_cell = death_vertex = -1, is the
+ *     first pair), then the top dimension.  birth and death are bit copies of input pixels.
+ *   - Memory: every pointer named d_* is device memory owned by the caller; h_* is host
+ *     memory.  The library allocates nothing per call.  It owns only its lookup tables,
+ *     built on the host and uploaded once per device on first use.
+ *   - Streams: all work is enqueued on `stream`; no call synchronises with the host, so a
+ *     sequence of calls can be captured in a HIP graph.  Results are valid once the stream
+ *     has reached them.
+ *   - Errors: argument errors found on the host are returned synchronously (PH_EINVAL,
+ *     PH_ENOMEM for a too-small workspace, PH_EHIP for a failed HIP call).  Errors found
+ *     by the kernels are written to the per-instance status word (PH_ENAN for a NaN pixel,
+ *     PH_ECAPACITY when the pairs exceed the capacity: the true count is still written and
+ *     the first `capacity` pairs in output order are stored, PH_EINTERNAL if a bounded
+ *     loop ran out of iterations).
+ *   - Calls that share a workspace must not overlap in time.
+ */
+#ifndef FLASHCUBICAL_H
+#define FLASHCUBICAL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    PH_OK = 0,
+    PH_EINVAL = -1,
+    PH_ENAN = -2,
+    PH_ECAPACITY = -3,
+    PH_ENOMEM = -4,
+    PH_EHIP = -5,
+    PH_EINTERNAL = -6
+};
+
+/* flags: which dimensions to report (H0 is always computed; 2D needs it for the top). */
+enum { PH_H0 = 1, PH_HTOP = 2 };
+
+typedef struct {
+    int32_t ndim;       /* 2 or 3 */
+    int32_t ext[3];     /* extents, slowest first; ext[2] unused when ndim == 2 */
+} ph_shape;
+
+/* Structure-of-arrays output, device pointers, caller-owned.  Each array holds at least the
+ * capacity of the call (sum of capacities for a batch). */
+typedef struct {
+    int8_t *dim;            /* homology dimension: 0 or ndim-1 */
+    float *birth;           /* value of the birth cell */
+    float *death;           /* value of the death cell; +inf for the essential class */
+    int64_t *birth_cell;    /* doubled-grid index of the birth cell */
+    int64_t *death_cell;    /* doubled-grid index of the death cell; -1 if essential */
+    int32_t *birth_vertex;  /* pixel giving the birth cell its value (its last vertex) */
+    int32_t *death_vertex;  /* same for the death cell; -1 if essential */
+} ph_pairs;
+
+/* Optional launch tuning; NULL picks defaults (or the autotuned choice for a batch).
+ * The choice never changes results, only speed. */
+typedef struct {
+    int32_t tile2d;     /* 0: 64x16, 1: 32x32, 2: 128x8 vertices per workgroup */
+    int32_t tile3d;     /* 0: 16x8x8, 1: 32x8x4, 2: 8x8x16 (x, y, z) voxels per workgroup */
+} ph_tuning;
+
+/* Upper bound of the pairs of one instance: pixels + top cells (H0 pairs <= pixels, top
+ * pairs <= top cells).  A capacity of this size can never overflow. */
+int64_t ph_capacity_bound(ph_shape shape);
+
+/* Workspace bytes needed by a batch of n instances with the given host shapes (also valid
+ * for n = 1 and ph_diagram).  Returns 0 for invalid shapes. */
+size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags);
+
+/* Persistence diagram of one image or volume (Sec. 4.1 / Sec. 4.2 steps 1-3).
+ *   d_img     : device, row-major float32 pixels of `shape`.
+ *   out       : device SoA arrays with room for `capacity` pairs.
+ *   d_count   : device int64, receives the number of pairs (even beyond capacity).
+ *   d_status  : device int32, receives PH_OK or a kernel-detected error.
+ *   d_ws      : device workspace of ws_bytes >= ph_workspace_bytes(&shape, 1, flags).
+ * Returns PH_OK when the work was enqueued. */
+int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
+               int64_t capacity, int64_t *d_count, int32_t *d_status, void *d_ws,
+               size_t ws_bytes, void *stream);
+
+/* Diagrams of n instances of uneven sizes and mixed 2D/3D in one set of launches:
+ * persistent kernels walk a per-instance table built on the device from d_shapes.
+ *   d_imgs     : all pixels concatenated; instance i starts at element d_img_off[i].
+ *   d_shapes   : device copy of h_shapes (n entries); h_shapes sizes the launch grids.
+ *   out        : shared SoA output; instance i writes from element d_out_off[i] and has
+ *                capacity d_out_off[i+1] - d_out_off[i] (d_out_off has n+1 entries).
+ *   d_counts, d_status : n entries each.
+ *   tuning     : NULL = default/autotuned tiles.
+ * The pairs of each instance are bitwise those of a single ph_diagram call on it. */
+int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off,
+                     const ph_shape *d_shapes, const ph_shape *h_shapes, uint32_t flags,
+                     ph_pairs out, const int64_t *d_out_off, int64_t *d_counts,
+                     int32_t *d_status, const ph_tuning *tuning, void *d_ws, size_t ws_bytes,
+                     void *stream);
+
+/* Gradient of pair values with respect to the pixels (not part of the paper): for every
+ * stored pair j of instance i, d_grad_birth[j] is added to the birth pixel and, if the death
+ * is finite, d_grad_death[j] to the death pixel; all other pixels get 0.
+ *   pairs, d_counts : as written by ph_diagram(_batch) for n instances.
+ *   d_out_off  : device, n+1 entries: instance i's pairs (and gradients) are entries
+ *                [d_out_off[i], d_out_off[i+1]); counts beyond that capacity are clamped.
+ *   d_grad_img : device float32, total_voxels entries, instance i from d_img_off[i]
+ *                (device, n entries).  Overwritten.
+ * Additions to one pixel are atomic, so their rounding order is not fixed. */
+int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
+                const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
+                const int64_t *d_img_off, int64_t total_voxels, void *stream);
+
+/* Host-side view of the lookup table (Sec. 3.3), for inspection and tests.
+ * ndim 2: raw_mask has 8 bits (neighbours up, left, right, down, up-left, up-right,
+ * down-left, down-right); ndim 3: 26 bits, neighbour at offset code k+1 of the local cell
+ * list (offsets ordered by number of non-zero coordinates, then lexicographically, slowest
+ * axis first).  Bit set = that neighbour precedes the vertex.  *entry receives the packed
+ * classification (layout in the implementation).  Returns PH_OK or PH_EINVAL. */
+int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry);
+
+/* Number of distinct lower-star configurations after collapsing irrelevant diagonal
+ * neighbours (Sec. 3.3): 47 for 2D, 15935 for 3D. */
+int32_t ph_lut_config_count(int32_t ndim);
+
+/* Upload the lookup tables to the current device now (they are otherwise uploaded on first
+ * use) and verify the device copy; PH_OK, PH_EHIP or PH_EINTERNAL. */
+int ph_init_device(void);
+
+/* Text report (into buf, len bytes) of the current device's per-block LDS and thread limits
+ * and each kernel's static LDS, registers and launch size; returns PH_OK when every kernel
+ * fits, PH_EHIP otherwise.  Launches nothing. */
+int ph_device_report(char *buf, size_t len);
+
+/* Library version string. */
+const char *ph_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FLASHCUBICAL_H */

@@ -1,0 +1,349 @@
+"""MI355X (gfx950) cubical persistence: thin Python binding of libflashcubical.so.
+
+Every step of the computation runs in the library's HIP kernels; this module only marshals
+arguments (torch tensors for device memory and streams, ctypes for the C ABI declared in
+include/flashcubical.h).  It raises if the library has not been built: there is no CPU
+fallback.
+
+Entry points (same names as the C ABI):
+  ph_diagram(img)                 one image or volume -> Diagram (device tensors)
+  Batch(shapes).ph_diagram_batch  many instances of uneven sizes in one set of launches
+  Batch.ph_backward / ph_backward gradient scatter to the critical pixels
+  PHDiagramFn                     torch.autograd.Function around ph_diagram / ph_backward
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflashcubical.so")
+
+PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+PH_H0, PH_HTOP = 1, 2
+STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
+                -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
+
+PAIR_DTYPE = np.dtype([
+    ("dim", np.int8), ("birth", np.float32), ("death", np.float32),
+    ("birth_cell", np.int64), ("death_cell", np.int64),
+    ("birth_vertex", np.int32), ("death_vertex", np.int32),
+])
+
+
+class PHError(RuntimeError):
+    def __init__(self, code, what=""):
+        super().__init__("%s: %s (%d)" % (what, STATUS_NAMES.get(code, "error"), code))
+        self.code = code
+
+
+class ph_shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("ext", ctypes.c_int32 * 3)]
+
+
+class ph_pairs(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_void_p), ("birth", ctypes.c_void_p), ("death", ctypes.c_void_p),
+                ("birth_cell", ctypes.c_void_p), ("death_cell", ctypes.c_void_p),
+                ("birth_vertex", ctypes.c_void_p), ("death_vertex", ctypes.c_void_p)]
+
+
+class ph_tuning(ctypes.Structure):
+    _fields_ = [("tile2d", ctypes.c_int32), ("tile3d", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C library; raises when it is missing (build it first)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libflashcubical.so is not built: run `python -m paper_2606_04801_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+        L.ph_capacity_bound.argtypes = [ph_shape]
+        L.ph_capacity_bound.restype = i64
+        L.ph_workspace_bytes.argtypes = [ctypes.POINTER(ph_shape), i32, u32]
+        L.ph_workspace_bytes.restype = ctypes.c_size_t
+        L.ph_diagram.argtypes = [vp, ph_shape, u32, ph_pairs, i64, vp, vp, vp, ctypes.c_size_t, vp]
+        L.ph_diagram.restype = ctypes.c_int
+        L.ph_diagram_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp,
+                                       ctypes.POINTER(ph_tuning), vp, ctypes.c_size_t, vp]
+        L.ph_diagram_batch.restype = ctypes.c_int
+        L.ph_backward.argtypes = [i32, ph_pairs, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.ph_backward.restype = ctypes.c_int
+        L.ph_lut_entry.argtypes = [i32, u32, ctypes.POINTER(ctypes.c_uint64)]
+        L.ph_lut_entry.restype = ctypes.c_int
+        L.ph_lut_config_count.argtypes = [i32]
+        L.ph_lut_config_count.restype = i32
+        L.ph_version.restype = ctypes.c_char_p
+        L.ph_init_device.restype = ctypes.c_int
+        L.ph_device_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        L.ph_device_report.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def make_shape(shape) -> ph_shape:
+    shape = tuple(int(x) for x in shape)
+    if len(shape) not in (2, 3):
+        raise PHError(PH_EINVAL, "shape")
+    ext = list(shape) + [0] * (3 - len(shape))
+    return ph_shape(len(shape), (ctypes.c_int32 * 3)(*ext))
+
+
+def capacity_bound(shape) -> int:
+    return int(lib().ph_capacity_bound(make_shape(shape)))
+
+
+def workspace_bytes(shapes, flags=PH_H0 | PH_HTOP) -> int:
+    arr = (ph_shape * len(shapes))(*[make_shape(s) for s in shapes])
+    return int(lib().ph_workspace_bytes(arr, len(shapes), flags))
+
+
+def lut_entry(ndim: int, raw_mask: int) -> int:
+    e = ctypes.c_uint64(0)
+    rc = lib().ph_lut_entry(ndim, raw_mask, ctypes.byref(e))
+    if rc != PH_OK:
+        raise PHError(rc, "ph_lut_entry")
+    return int(e.value)
+
+
+def device_report():
+    """(status, text): device limits and per-kernel resources (launches nothing)."""
+    buf = ctypes.create_string_buffer(8192)
+    rc = lib().ph_device_report(buf, len(buf))
+    return rc, buf.value.decode()
+
+
+def lut_config_count(ndim: int) -> int:
+    return int(lib().ph_lut_config_count(ndim))
+
+
+# ------------------------------------------------------------------- device side --
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class PairBuffers:
+    """SoA device tensors holding `cap` pairs."""
+
+    def __init__(self, cap: int, device):
+        torch = _torch()
+        cap = max(int(cap), 1)
+        self.cap = cap
+        self.dim = torch.empty(cap, dtype=torch.int8, device=device)
+        self.birth = torch.empty(cap, dtype=torch.float32, device=device)
+        self.death = torch.empty(cap, dtype=torch.float32, device=device)
+        self.birth_cell = torch.empty(cap, dtype=torch.int64, device=device)
+        self.death_cell = torch.empty(cap, dtype=torch.int64, device=device)
+        self.birth_vertex = torch.empty(cap, dtype=torch.int32, device=device)
+        self.death_vertex = torch.empty(cap, dtype=torch.int32, device=device)
+
+    def c(self) -> ph_pairs:
+        return ph_pairs(*[t.data_ptr() for t in (self.dim, self.birth, self.death, self.birth_cell,
+                                                 self.death_cell, self.birth_vertex, self.death_vertex)])
+
+    def to_numpy(self, start: int, count: int) -> np.ndarray:
+        out = np.zeros(count, dtype=PAIR_DTYPE)
+        for f in PAIR_DTYPE.names:
+            out[f] = getattr(self, f)[start:start + count].cpu().numpy()
+        return out
+
+
+class Diagram:
+    """Result of ph_diagram: device SoA buffers plus the device count and status."""
+
+    def __init__(self, bufs: PairBuffers, count, status, shape):
+        self.bufs, self.count_t, self.status_t, self.shape = bufs, count, status, tuple(shape)
+
+    def check(self) -> int:
+        st = int(self.status_t.item())
+        if st != PH_OK:
+            raise PHError(st, "ph_diagram")
+        return int(self.count_t.item())
+
+    def numpy(self) -> np.ndarray:
+        n = self.check()
+        return self.bufs.to_numpy(0, n)
+
+
+class Workspace:
+    """Reusable device workspace (grown on demand)."""
+
+    def __init__(self):
+        self.t = None
+
+    def get(self, nbytes: int, device):
+        torch = _torch()
+        if self.t is None or self.t.numel() < nbytes or self.t.device != torch.device(device):
+            self.t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+        return self.t
+
+
+_default_ws = Workspace()
+
+
+def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, ws: Workspace | None = None,
+               stream=None) -> Diagram:
+    """Persistence diagram of one float32 image (H, W) or volume (D, H, W) on the GPU."""
+    torch = _torch()
+    if not (img.is_cuda and img.dtype == torch.float32 and img.dim() in (2, 3)):
+        raise PHError(PH_EINVAL, "ph_diagram expects a 2D/3D float32 CUDA tensor")
+    img = img.contiguous()
+    shp = make_shape(img.shape)
+    cap = capacity_bound(img.shape) if capacity is None else int(capacity)
+    bufs = PairBuffers(cap, img.device)
+    count = torch.zeros(1, dtype=torch.int64, device=img.device)
+    status = torch.zeros(1, dtype=torch.int32, device=img.device)
+    nb = int(lib().ph_workspace_bytes(ctypes.byref(shp), 1, flags))
+    w = (ws or _default_ws).get(nb, img.device)
+    rc = lib().ph_diagram(_ptr(img), shp, flags, bufs.c(), cap, _ptr(count), _ptr(status), _ptr(w),
+                          w.numel(), _stream_ptr(stream))
+    if rc != PH_OK:
+        raise PHError(rc, "ph_diagram")
+    return Diagram(bufs, count, status, img.shape)
+
+
+def ph_backward(bufs: PairBuffers, counts, out_off, img_off, grad_birth, grad_death, grad_img, stream=None):
+    """Scatter dL/dbirth, dL/ddeath into grad_img (overwritten) -- C ABI ph_backward."""
+    n = int(counts.numel())
+    rc = lib().ph_backward(n, bufs.c(), _ptr(out_off), _ptr(counts), _ptr(grad_birth), _ptr(grad_death),
+                           _ptr(grad_img), _ptr(img_off), int(grad_img.numel()), _stream_ptr(stream))
+    if rc != PH_OK:
+        raise PHError(rc, "ph_backward")
+
+
+class Batch:
+    """Buffers and launches for a fixed list of instance shapes (2D and 3D may be mixed).
+
+    Inputs live in one packed float32 buffer (`images`), outputs in one SoA buffer with a
+    per-instance capacity of pixels + top cells, so nothing depends on the host between
+    launches and the forward + backward pair can be captured in a HIP graph.
+    """
+
+    def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda"):
+        torch = _torch()
+        self.shapes = [tuple(int(x) for x in s) for s in shapes]
+        self.n = len(self.shapes)
+        self.flags = flags
+        self.device = torch.device(device)
+        sizes = [int(np.prod(s)) for s in self.shapes]
+        caps = [capacity_bound(s) for s in self.shapes]
+        self.img_off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+        self.out_off_h = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
+        self.total_voxels = int(self.img_off_h[-1])
+        self.h_shapes = (ph_shape * self.n)(*[make_shape(s) for s in self.shapes])
+        d = np.zeros((self.n, 4), np.int32)
+        for i, s in enumerate(self.shapes):
+            d[i, 0] = len(s)
+            d[i, 1:1 + len(s)] = s
+        self.d_shapes = torch.from_numpy(d).to(self.device)
+        self.img_off = torch.from_numpy(self.img_off_h[:-1].copy()).to(self.device)
+        self.out_off = torch.from_numpy(self.out_off_h).to(self.device)
+        self.images = torch.zeros(self.total_voxels, dtype=torch.float32, device=self.device)
+        self.grad = torch.zeros(self.total_voxels, dtype=torch.float32, device=self.device)
+        self.pairs = PairBuffers(int(self.out_off_h[-1]), self.device)
+        self.counts = torch.zeros(self.n, dtype=torch.int64, device=self.device)
+        self.status = torch.zeros(self.n, dtype=torch.int32, device=self.device)
+        self.ws_bytes = int(lib().ph_workspace_bytes(self.h_shapes, self.n, flags))
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=self.device)
+        self.tuning = None if tuning is None else ph_tuning(int(tuning[0]), int(tuning[1]))
+
+    def set_images(self, imgs):
+        torch = _torch()
+        for i, a in enumerate(imgs):
+            t = torch.as_tensor(a, dtype=torch.float32).reshape(-1)
+            self.images[self.img_off_h[i]:self.img_off_h[i + 1]].copy_(t, non_blocking=False)
+
+    def image(self, i):
+        return self.images[self.img_off_h[i]:self.img_off_h[i + 1]].view(self.shapes[i])
+
+    def ph_diagram_batch(self, stream=None):
+        tp = ctypes.byref(self.tuning) if self.tuning is not None else None
+        rc = lib().ph_diagram_batch(self.n, _ptr(self.images), _ptr(self.img_off), _ptr(self.d_shapes),
+                                    self.h_shapes, self.flags, self.pairs.c(), _ptr(self.out_off),
+                                    _ptr(self.counts), _ptr(self.status), tp, _ptr(self.ws), self.ws_bytes,
+                                    _stream_ptr(stream))
+        if rc != PH_OK:
+            raise PHError(rc, "ph_diagram_batch")
+
+    def ph_backward(self, grad_birth, grad_death, stream=None):
+        ph_backward(self.pairs, self.counts, self.out_off, self.img_off, grad_birth, grad_death, self.grad,
+                    stream)
+
+    def valid_mask(self):
+        """Device bool mask over the packed pair slots holding a stored pair (no sync)."""
+        torch = _torch()
+        idx = torch.arange(self.pairs.cap, device=self.device)
+        inst = torch.searchsorted(self.out_off[1:], idx, right=True)
+        inst = torch.clamp(inst, max=self.n - 1)
+        return (idx - self.out_off[inst]) < self.counts[inst]
+
+    def check(self):
+        st = self.status.cpu().numpy()
+        bad = np.nonzero(st != PH_OK)[0]
+        if len(bad):
+            raise PHError(int(st[bad[0]]), "instance %d" % int(bad[0]))
+
+    def results(self):
+        self.check()
+        cnt = self.counts.cpu().numpy()
+        return [self.pairs.to_numpy(int(self.out_off_h[i]), int(cnt[i])) for i in range(self.n)]
+
+
+def _autograd():
+    torch = _torch()
+
+    class PHDiagramFn(torch.autograd.Function):
+        """(birth, death, dim) of the pairs of one image/volume; backward scatters dL/dbirth
+        and dL/ddeath to the pixels attaining each critical cell's value (ph_backward)."""
+
+        @staticmethod
+        def forward(ctx, img):
+            d = ph_diagram(img.detach())
+            n = d.check()
+            b = d.bufs
+            ctx.save_for_backward(b.birth_vertex[:n].clone(), b.death_vertex[:n].clone())
+            ctx.shape = img.shape
+            ctx.bufs, ctx.n = b, n
+            return b.birth[:n].clone(), b.death[:n].clone(), b.dim[:n].clone()
+
+        @staticmethod
+        def backward(ctx, g_birth, g_death, g_dim):
+            torch = _torch()
+            dev = g_birth.device if g_birth is not None else g_death.device
+            n = ctx.n
+            gb = g_birth.contiguous() if g_birth is not None else torch.zeros(n, device=dev)
+            gd = g_death.contiguous() if g_death is not None else torch.zeros(n, device=dev)
+            gb = torch.nan_to_num(gb, nan=0.0, posinf=0.0, neginf=0.0)
+            gd = torch.nan_to_num(gd, nan=0.0, posinf=0.0, neginf=0.0)
+            gimg = torch.empty(ctx.shape, dtype=torch.float32, device=dev)
+            counts = torch.tensor([n], dtype=torch.int64, device=dev)
+            out_off = torch.tensor([0, max(n, 1)], dtype=torch.int64, device=dev)
+            img_off = torch.zeros(1, dtype=torch.int64, device=dev)
+            ph_backward(ctx.bufs, counts, out_off, img_off, gb, gd, gimg)
+            return gimg
+
+    return PHDiagramFn
+
+
+def __getattr__(name):
+    if name == "PHDiagramFn":
+        return _autograd()
+    raise AttributeError(name)

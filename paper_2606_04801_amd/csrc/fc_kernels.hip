@@ -1,0 +1,1318 @@
+// fc_kernels.hip -- gfx950 kernels and C ABI of the cubical persistence library.
+//
+// Pipeline of one call (each step a kernel over every instance of the batch):
+//   plan      : per-instance table (sizes, tiles, workspace offsets), counters cleared
+//   classify  : LDS-tiled stencil over the pixels; per vertex the neighbour mask is looked
+//               up in the lower-star table (Sec. 3.3) and the lower star is pruned
+//               (Sec. 3.2): DIRECT edges and locally paired top cells become forest links
+//               resolved inside the tile, critical cells are appended to compact lists
+//   sort      : KEEP edges (and 3D KEEP squares) sorted by their refined-order keys
+//   resolve   : endpoints / cofacets of the sorted cells mapped to union-find nodes
+//   uf        : H0 union-find with the elder rule over the KEEP edges (Sec. 4.1 step 3,
+//               Sec. 4.2 step 2), by parallel rounds of safe merges (see k_uf)
+//   resolve   : cofacets of the facets left for the top dimension (2D: the edges H0 did not
+//               use, the cross-pruning of Sec. 3.2 / Sec. 4.1 step 4)
+//   uf (dual) : union-find on the dual graph with the cell at infinity, facets in decreasing
+//               order (Sec. 3.1, Appendix A)
+//   output    : pairs of non-zero persistence, sorted by (dim, birth key), written SoA
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <vector>
+
+#include "../../include/flashcubical.h"
+#include "fc_common.h"
+
+namespace fc {
+
+int build_lut2d(uint32_t *lut, char *err, int errlen);
+int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen);
+
+__constant__ uint32_t c_lut2d[256];
+__constant__ int8_t c_off[27][3] = {
+    {0, 0, 0},
+    {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {0, 0, 1}, {0, 1, 0}, {1, 0, 0},
+    {-1, -1, 0}, {-1, 0, -1}, {-1, 0, 1}, {-1, 1, 0}, {0, -1, -1}, {0, -1, 1},
+    {0, 1, -1}, {0, 1, 1}, {1, -1, 0}, {1, 0, -1}, {1, 0, 1}, {1, 1, 0},
+    {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}, {1, -1, 1},
+    {1, 1, -1}, {1, 1, 1}};
+__device__ uint32_t g_l1[kL1Size];
+__device__ uint64_t g_l2[kL3Configs];
+
+constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
+constexpr int32_t kNotOwned = 0x7FFFFFFF;  // LDS slot not written by this tile
+constexpr int kMaxChase = 1 << 22;         // bound of every pointer walk
+constexpr int kUfThreads = 1024;
+constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS (2 x 20 KiB)
+constexpr int kSortThreads = 1024;
+constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
+constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
+constexpr int32_t kInf = 0x7FFFFFFF;
+
+// ------------------------------------------------------------------ workspace map --
+FC_HD int64_t off_tb2(int n) { return align256((int64_t)n * (int64_t)sizeof(Inst)); }
+FC_HD int64_t off_tb3(int n) { return off_tb2(n) + align256((int64_t)(n + 1) * 8); }
+FC_HD int64_t off_cnt(int n) { return off_tb3(n) + align256((int64_t)(n + 1) * 8); }
+FC_HD int64_t header_bytes(int n) { return off_cnt(n) + align256((int64_t)n * CNT_WORDS * 4); }
+
+struct Tiles { int tw2, th2, tw3, th3, td3; };
+
+FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
+    I.ndim = s.ndim;
+    if (s.ndim == 2) { I.D = 1; I.H = s.ext[0]; I.W = s.ext[1]; }
+    else { I.D = s.ext[0]; I.H = s.ext[1]; I.W = s.ext[2]; }
+    Geom g = geom(I.ndim, I.D, I.H, I.W);
+    I.N = g.N; I.T = g.T; I.E = g.E; I.F = g.F; I.FAC = g.FAC;
+    if (s.ndim == 2) {
+        I.tx = (I.W + tl.tw2 - 1) / tl.tw2; I.ty = (I.H + tl.th2 - 1) / tl.th2; I.tz = 1;
+    } else {
+        I.tx = (I.W + tl.tw3 - 1) / tl.tw3; I.ty = (I.H + tl.th3 - 1) / tl.th3;
+        I.tz = (I.D + tl.td3 - 1) / tl.td3;
+    }
+    I.pad = 0;
+}
+
+__global__ void k_plan(int n, const ph_shape *__restrict__ d_shapes, ph_shape single,
+                       const int64_t *__restrict__ d_img_off, const int64_t *__restrict__ d_out_off,
+                       int64_t single_cap, Tiles tl, uint8_t *__restrict__ ws,
+                       int64_t *__restrict__ d_counts, int32_t *__restrict__ d_status,
+                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    Inst *tab = (Inst *)ws;
+    int64_t *tb2 = (int64_t *)(ws + off_tb2(n));
+    int64_t *tb3 = (int64_t *)(ws + off_tb3(n));
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n));
+    int64_t at = header_bytes(n), t2 = 0, t3 = 0;
+    for (int i = 0; i < n; ++i) {
+        ph_shape s = d_shapes ? d_shapes[i] : single;
+        bool ok = s.ndim == 2 || s.ndim == 3;
+        for (int k = 0; k < 3 && ok; ++k) ok = k >= s.ndim || s.ext[k] >= 1;
+        if (!ok) s = ph_shape{2, {1, 1, 1}};
+        Inst I;
+        fill_inst(I, s, tl);
+        if (I.N >= (1ll << kPixBits)) { ok = false; s = ph_shape{2, {1, 1, 1}}; fill_inst(I, s, tl); }
+        I.img_off = d_img_off ? d_img_off[i] : 0;
+        I.out_off = d_out_off ? d_out_off[i] : 0;
+        I.out_cap = d_out_off ? d_out_off[i + 1] - d_out_off[i] : single_cap;
+        tb2[i] = t2;
+        tb3[i] = t3;
+        if (I.ndim == 2) { I.tile_base = t2; t2 += (int64_t)I.tx * I.ty; }
+        else { I.tile_base = t3; t3 += (int64_t)I.tx * I.ty * I.tz; }
+        at = layout(I, at);
+        tab[i] = I;
+        for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
+        cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
+        if (!ok || I.out_cap < 0) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
+        d_counts[i] = 0;
+        d_status[i] = PH_OK;
+    }
+    tb2[n] = t2;
+    tb3[n] = t3;
+    // the launch grids were sized from the host shapes: a device table that disagrees with
+    // them (or outgrows the workspace) disables every instance
+    if (t2 != want_t2 || t3 != want_t3 || at > ws_bytes)
+        for (int i = 0; i < n; ++i) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
+}
+
+// true when an earlier kernel recorded an error for this instance: later kernels skip it
+__device__ __forceinline__ bool failed(const int32_t *cnt) {
+    return __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+// the same decision taken once for the whole block (every thread must call it)
+__device__ __forceinline__ bool block_failed(const int32_t *cnt) {
+    return __syncthreads_or(failed(cnt) ? 1 : 0) != 0;
+}
+
+__device__ __forceinline__ int find_inst(const int64_t *tb, int n, int64_t tile) {
+    int lo = 0, hi = n - 1;                        // largest i with tb[i] <= tile < tb[i+1]
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (tb[mid] <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;                                     // tb[lo+1] > tile: instance lo owns the tile
+}
+
+template <typename T>
+__device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + off); }
+
+__device__ __forceinline__ void set_err(int32_t *cnt, int code) {
+    atomicCAS(&cnt[CNT_ERR], 0, code);
+}
+
+// wave-aggregated reservation: returns this lane's first slot; all lanes must call it
+__device__ __forceinline__ int wave_alloc(int32_t *counter, int count) {
+    const int lane = __lane_id();
+    int x = count;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    int total = __shfl(x, 63, 64);
+    int base = 0;
+    if (lane == 0 && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 0, 64);
+    return base + x - count;
+}
+
+// ================================================================ classify 2D ====
+template <int TW, int TH>
+__global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ imgs,
+                                                    uint8_t *__restrict__ ws, int n) {
+    static_assert((TW * TH) % 256 == 0, "tile must be a multiple of the block");
+    constexpr int KW = TW + 2, PW = TW + 1, NP = (TH + 1) * (TW + 1);
+    __shared__ uint32_t skey[(TH + 2) * KW];
+    __shared__ int32_t sp0[TH * TW];
+    __shared__ int32_t spT[NP];
+    __shared__ int s_nan;
+
+    const Inst *tab = (const Inst *)ws;
+    const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, blockIdx.x);
+    const Inst &I = tab[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (block_failed(cnt)) return;
+    const int H = I.H, W = I.W;
+    const int lt = (int)(blockIdx.x - I.tile_base);
+    const int ty = lt / I.tx, tx = lt - ty * I.tx;
+    const int y0 = ty * TH, x0 = tx * TW;
+    const float *img = imgs + I.img_off;
+    int32_t *par0 = arr<int32_t>(ws, I.o_par0);
+    int32_t *parT = arr<int32_t>(ws, I.o_parT);
+    uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
+    uint64_t *n0key = arr<uint64_t>(ws, I.o_n0key);
+    uint64_t *nTkey = arr<uint64_t>(ws, I.o_nTkey);
+
+    if (threadIdx.x == 0) s_nan = 0;
+    int nan = 0;
+    for (int l = threadIdx.x; l < (TH + 2) * KW; l += 256) {
+        int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
+        uint32_t k = 0;
+        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            float f = img[(int64_t)gy * W + gx];
+            nan |= (f != f);
+            k = ord32(__float_as_uint(f));
+        }
+        skey[l] = k;
+    }
+    for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
+    // every link slot starts final (0 is never followed); slots of vertices outside the
+    // image keep it, so the pointer jumping below never reads an uninitialised slot
+    for (int l = threadIdx.x; l < TH * TW; l += 256) sp0[l] = 0;
+    __syncthreads();
+    if (nan) s_nan = 1;
+
+    // neighbours in mask-bit order: up, left, right, down, UL, UR, DL, DR
+    constexpr int NDY[8] = {-1, 0, 0, 1, -1, -1, 1, 1};
+    constexpr int NDX[8] = {0, -1, 1, 0, -1, 1, -1, 1};
+    constexpr bool NBEFORE[8] = {true, true, false, false, true, true, false, false};
+
+#pragma unroll 1
+    for (int it = 0; it < TH * TW / 256; ++it) {
+        const int l = threadIdx.x + it * 256;
+        const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        const bool valid = gy < H && gx < W;
+        const uint32_t kv = skey[(r + 1) * KW + c + 1];
+        const uint32_t pv = (uint32_t)(gy * W + gx);
+        uint32_t e = kNoDirect;
+        if (valid) {
+            uint32_t mask = 0;
+#pragma unroll
+            for (int b = 0; b < 8; ++b) {
+                int ny = gy + NDY[b], nx = gx + NDX[b];
+                if (ny < 0 || ny >= H || nx < 0 || nx >= W) continue;
+                uint32_t kn = skey[(r + 1 + NDY[b]) * KW + c + 1 + NDX[b]];
+                if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
+            }
+            e = c_lut2d[mask];
+        }
+        const uint32_t direct = e & 7u;
+        const bool ismin = valid && direct == kNoDirect;
+        const uint32_t keep = valid ? (e >> kL2Keep) & 15u : 0u;
+        const uint32_t present = valid ? (e >> kL2Present) & 15u : 0u;
+        const uint32_t root = valid ? (e >> kL2Root) & 15u : 0u;
+
+        // H0 forest: link to the other end of the DIRECT edge, or become a node
+        int id0 = wave_alloc(&cnt[CNT_M0], ismin ? 1 : 0);
+        if (ismin && id0 >= I.N) { set_err(cnt, PH_EINTERNAL); id0 = 0; }
+        if (valid) {
+            if (ismin) {
+                sp0[l] = -(id0 + 1);
+                n0key[id0] = make_key(kv, pv, 0);
+            } else {
+                const int dy = direct == 0 ? -1 : (direct == 3 ? 1 : 0);
+                const int dx = direct == 1 ? -1 : (direct == 2 ? 1 : 0);
+                const int rr = r + dy, cc = c + dx;
+                if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) sp0[l] = kLocal | (rr * TW + cc);
+                else sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
+            }
+        }
+        // KEEP edges -> compact list
+        int kb = wave_alloc(&cnt[CNT_E], __popc(keep));
+        for (int b = 0; b < 4; ++b)
+            if ((keep >> b) & 1u) {
+                if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
+                ++kb;
+            }
+        // squares of L(v): ROOT -> dual node, LOCAL -> dual link
+        int rb = wave_alloc(&cnt[CNT_MT], __popc(root));
+        for (int q = 0; q < 4; ++q) {
+            if (!((present >> q) & 1u)) continue;
+            const int sy = gy - 1 + (q >> 1), sx = gx - 1 + (q & 1);
+            const int pos = (sy - y0 + 1) * PW + (sx - x0 + 1);
+            if ((root >> q) & 1u) {
+                if (rb > I.T) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                spT[pos] = -(rb + 1);
+                nTkey[rb] = make_key(kv, pv, 11 + q);
+                ++rb;
+            } else {
+                const uint32_t t = (e >> (kL2Link + 2 * q)) & 3u;
+                const int ty2 = gy - 1 + (int)(t >> 1), tx2 = gx - 1 + (int)(t & 1);
+                if (ty2 >= 0 && ty2 < H - 1 && tx2 >= 0 && tx2 < W - 1)
+                    spT[pos] = kLocal | ((ty2 - y0 + 1) * PW + (tx2 - x0 + 1));
+                else
+                    spT[pos] = -1;                       // the cell at infinity
+            }
+        }
+    }
+    __syncthreads();
+
+    // resolve links inside the tile by pointer jumping
+    for (int round = 0; round < 32; ++round) {
+        int changed = 0;
+        for (int l = threadIdx.x; l < TH * TW; l += 256) {
+            int32_t v = sp0[l];
+            if (v >= kLocal && v != kNotOwned) {
+                const int t = v - kLocal;                 // links only ever name slots of this tile
+                sp0[l] = t < TH * TW ? sp0[t] : 0;
+                changed = 1;
+            }
+        }
+        for (int p = threadIdx.x; p < NP; p += 256) {
+            int32_t v = spT[p];
+            if (v >= kLocal && v != kNotOwned) {
+                const int tp = v - kLocal < NP ? v - kLocal : 0;
+                int32_t w = spT[tp];
+                if (w == kNotOwned) {
+                    const int pr = tp / PW, pc = tp - pr * PW;
+                    w = (int32_t)((y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc));
+                }
+                spT[p] = w;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+
+    for (int l = threadIdx.x; l < TH * TW; l += 256) {
+        const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        if (gy < H && gx < W) par0[gy * W + gx] = sp0[l];
+    }
+    for (int p = threadIdx.x; p < NP; p += 256) {
+        const int32_t v = spT[p];
+        if (v == kNotOwned) continue;
+        const int pr = p / PW, pc = p - pr * PW;
+        parT[(y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc)] = v;
+    }
+    if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
+}
+
+// ================================================================ classify 3D ====
+template <int TW, int TH, int TD>
+__global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ imgs,
+                                                    uint8_t *__restrict__ ws, int n) {
+    static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
+    constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
+    constexpr int PW = TW + 1, PH = TH + 1, PD = TD + 1, NP = PW * PH * PD;
+    constexpr int NV = TW * TH * TD;
+    __shared__ uint32_t skey[KD * KH * KW];
+    __shared__ int32_t sp0[NV];
+    __shared__ int32_t spT[NP];
+    __shared__ int s_nan;
+
+    const Inst *tab = (const Inst *)ws;
+    const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, blockIdx.x);
+    const Inst &I = tab[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (block_failed(cnt)) return;
+    const int D = I.D, H = I.H, W = I.W;
+    const int lt = (int)(blockIdx.x - I.tile_base);
+    const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
+    const int ty = rem / I.tx, tx = rem - ty * I.tx;
+    const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
+    const float *img = imgs + I.img_off;
+    int32_t *par0 = arr<int32_t>(ws, I.o_par0);
+    int32_t *parT = arr<int32_t>(ws, I.o_parT);
+    uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
+    uint64_t *keyF = arr<uint64_t>(ws, I.o_keyF);
+    uint64_t *n0key = arr<uint64_t>(ws, I.o_n0key);
+    uint64_t *nTkey = arr<uint64_t>(ws, I.o_nTkey);
+    const int64_t HW = (int64_t)H * W;
+    const int64_t TH1W1 = (int64_t)(H - 1) * (W - 1);
+
+    if (threadIdx.x == 0) s_nan = 0;
+    int nan = 0;
+    for (int l = threadIdx.x; l < KD * KH * KW; l += 256) {
+        int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
+        int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+        uint32_t k = 0;
+        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+            float f = img[gz * HW + (int64_t)gy * W + gx];
+            nan |= (f != f);
+            k = ord32(__float_as_uint(f));
+        }
+        skey[l] = k;
+    }
+    for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
+    for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;      // see the 2D kernel
+    __syncthreads();
+    if (nan) s_nan = 1;
+
+#pragma unroll 1
+    for (int it = 0; it < NV / 256; ++it) {
+        const int l = threadIdx.x + it * 256;
+        const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
+        const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+        const bool valid = gz < D && gy < H && gx < W;
+        const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
+        const uint32_t pv = (uint32_t)(gz * HW + (int64_t)gy * W + gx);
+        uint64_t e = kNoDirect;
+        if (valid) {
+            uint32_t raw = 0;
+#pragma unroll
+            for (int code = 1; code < 27; ++code) {
+                const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
+                const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+                const int nz = gz + dz, ny = gy + dy, nx = gx + dx;
+                if (nz < 0 || nz >= D || ny < 0 || ny >= H || nx < 0 || nx >= W) continue;
+                const uint32_t kn = skey[((lz + 1 + dz) * KH + ly + 1 + dy) * KW + lx + 1 + dx];
+                if (kn < kv || (kn == kv && before)) raw |= 1u << (code - 1);
+            }
+            uint32_t cubes;
+            const uint32_t idx1 = canon3d(raw, &cubes);
+            const uint32_t l1 = g_l1[idx1];
+            const uint32_t idx2 = (l1 >> 8) + compress8(cubes, l1 & 255u);
+            if (idx2 < (uint32_t)kL3Configs) e = g_l2[idx2];
+            else set_err(cnt, PH_EINTERNAL);
+        }
+        const uint32_t direct = (uint32_t)(e & 7u);
+        const bool ismin = valid && direct == kNoDirect;
+        const uint32_t keep = valid ? (uint32_t)((e >> kL3Keep) & 63u) : 0u;
+        const uint32_t keepsq = valid ? (uint32_t)((e >> kL3KeepSq) & 4095u) : 0u;
+        const uint32_t root = valid ? (uint32_t)((e >> kL3Root) & 255u) : 0u;
+        const uint32_t present = valid ? (uint32_t)((e >> kL3Present) & 255u) : 0u;
+
+        int id0 = wave_alloc(&cnt[CNT_M0], ismin ? 1 : 0);
+        if (ismin && id0 >= I.N) { set_err(cnt, PH_EINTERNAL); id0 = 0; }
+        if (valid) {
+            if (ismin) {
+                sp0[l] = -(id0 + 1);
+                n0key[id0] = make_key(kv, pv, 0);
+            } else {
+                const int code = 1 + (int)direct;
+                const int dz = c_off[code][0], dy = c_off[code][1], dx = c_off[code][2];
+                const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
+                if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW)
+                    sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
+                else
+                    sp0[l] = (int32_t)((gz + dz) * HW + (int64_t)(gy + dy) * W + gx + dx);
+            }
+        }
+        int kb = wave_alloc(&cnt[CNT_E], __popc(keep));
+        for (int b = 0; b < 6; ++b)
+            if ((keep >> b) & 1u) {
+                if (kb < I.E) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
+                ++kb;
+            }
+        int fb = wave_alloc(&cnt[CNT_F], __popc(keepsq));
+        for (int s = 0; s < 12; ++s)
+            if ((keepsq >> s) & 1u) {
+                if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + s); else set_err(cnt, PH_EINTERNAL);
+                ++fb;
+            }
+        int rb = wave_alloc(&cnt[CNT_MT], __popc(root));
+        for (int b = 0; b < 8; ++b) {
+            if (!((present >> b) & 1u)) continue;
+            const int sz = gz - 1 + (b >> 2), sy = gy - 1 + ((b >> 1) & 1), sx = gx - 1 + (b & 1);
+            const int pos = ((sz - z0 + 1) * PH + (sy - y0 + 1)) * PW + (sx - x0 + 1);
+            if ((root >> b) & 1u) {
+                if (rb > I.T) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                spT[pos] = -(rb + 1);
+                nTkey[rb] = make_key(kv, pv, 19 + b);
+                ++rb;
+            } else {
+                const uint32_t t = (uint32_t)((e >> (kL3Link + 3 * b)) & 7u);
+                const int tz2 = gz - 1 + (int)(t >> 2), ty2 = gy - 1 + (int)((t >> 1) & 1),
+                          tx2 = gx - 1 + (int)(t & 1);
+                if (tz2 >= 0 && tz2 < D - 1 && ty2 >= 0 && ty2 < H - 1 && tx2 >= 0 && tx2 < W - 1)
+                    spT[pos] = kLocal | (((tz2 - z0 + 1) * PH + (ty2 - y0 + 1)) * PW + (tx2 - x0 + 1));
+                else
+                    spT[pos] = -1;
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int round = 0; round < 32; ++round) {
+        int changed = 0;
+        for (int l = threadIdx.x; l < NV; l += 256) {
+            int32_t v = sp0[l];
+            if (v >= kLocal && v != kNotOwned) {
+                const int t = v - kLocal;
+                sp0[l] = t < NV ? sp0[t] : 0;
+                changed = 1;
+            }
+        }
+        for (int p = threadIdx.x; p < NP; p += 256) {
+            int32_t v = spT[p];
+            if (v >= kLocal && v != kNotOwned) {
+                const int tp = v - kLocal < NP ? v - kLocal : 0;
+                int32_t w = spT[tp];
+                if (w == kNotOwned) {
+                    const int pz = tp / (PH * PW), pr = tp - pz * PH * PW, py = pr / PW, px = pr - py * PW;
+                    w = (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px));
+                }
+                spT[p] = w;
+                changed = 1;
+            }
+        }
+        if (!__syncthreads_or(changed)) break;
+    }
+
+    for (int l = threadIdx.x; l < NV; l += 256) {
+        const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
+        const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+        if (gz < D && gy < H && gx < W) par0[gz * HW + (int64_t)gy * W + gx] = sp0[l];
+    }
+    for (int p = threadIdx.x; p < NP; p += 256) {
+        const int32_t v = spT[p];
+        if (v == kNotOwned) continue;
+        const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
+        parT[(z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px)] = v;
+    }
+    if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
+}
+
+// ===================================================================== block scan ==
+// Exclusive scan of a 0/1 flag over a block of kUfThreads threads; returns the prefix and
+// writes the block total to *total.  All threads must call it.
+__device__ __forceinline__ int block_flag_scan(int flag, int *s_wsum, int *total) {
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    const uint64_t b = __ballot(flag);
+    const int pre = __popcll(b & ((1ull << lane) - 1ull));
+    if (lane == 0) s_wsum[wid] = __popcll(b);
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    int base = 0, tot = 0;
+    for (int w = 0; w < nw; ++w) {
+        int v = s_wsum[w];
+        if (w < wid) base += v;
+        tot += v;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + pre;
+}
+
+// ======================================================================== sort ====
+// Sort one list per instance ascending.  which: 0 = KEEP edges (in place), 1 = KEEP squares
+// (in place), 2 = H0 node keys copied to a sorted array.  Lists that fit in LDS are sorted
+// there by a bitonic network; longer ones are sorted in LDS-sized chunks and merged in
+// global memory (each element placed by a binary search in the partner run).
+__device__ void bitonic_lds(uint64_t *s, int P) {
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
+                const int a = ((t / j) * 2 * j) + (t % j), b = a + j;
+                const uint64_t x = s[a], y = s[b];
+                const bool up = (a & k) == 0;
+                if ((x > y) == up) { s[a] = y; s[b] = x; }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws, int n, int which) {
+    __shared__ uint64_t s[kSortCap];
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (block_failed(cnt)) return;
+    uint64_t *src, *dst;
+    int m;
+    int64_t cap;
+    if (which == 0) { src = dst = arr<uint64_t>(ws, I.o_keyE); m = cnt[CNT_E]; cap = I.E; }
+    else if (which == 1) { src = dst = arr<uint64_t>(ws, I.o_keyF); m = cnt[CNT_F]; cap = I.F; }
+    else { src = arr<uint64_t>(ws, I.o_n0key); dst = arr<uint64_t>(ws, I.o_n0sorted); m = cnt[CNT_M0]; cap = I.N; }
+    if (m > cap) { if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL); return; }
+    if (m <= 0) return;
+    if (m <= kSortCap) {
+        int P = 2;
+        while (P < m) P <<= 1;
+        for (int t = threadIdx.x; t < P; t += blockDim.x) s[t] = t < m ? src[t] : ~0ull;
+        __syncthreads();
+        bitonic_lds(s, P);
+        for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = s[t];
+        return;
+    }
+    // long list: chunks in LDS, then merge passes dst <-> scratch
+    uint64_t *scr = arr<uint64_t>(ws, I.o_scratch);
+    for (int base = 0; base < m; base += kSortCap) {
+        const int len = (m - base) < kSortCap ? (m - base) : kSortCap;
+        int P = 2;
+        while (P < len) P <<= 1;
+        for (int t = threadIdx.x; t < P; t += blockDim.x) s[t] = t < len ? src[base + t] : ~0ull;
+        __syncthreads();
+        bitonic_lds(s, P);
+        for (int t = threadIdx.x; t < len; t += blockDim.x) dst[base + t] = s[t];
+        __syncthreads();
+    }
+    uint64_t *a = dst, *b = scr;
+    for (int64_t w = kSortCap; w < m; w <<= 1) {
+        for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+            const int64_t run = t / w, start = (run & ~1ll) * w;
+            const uint64_t x = a[t];
+            int64_t lo, hi, rank;
+            if ((run & 1) == 0) {                  // element of the left run: count right < x
+                lo = start + w; hi = start + 2 * w < m ? start + 2 * w : m;
+                int64_t L = lo, R = hi;
+                while (L < R) { int64_t M = (L + R) >> 1; if (a[M] < x) L = M + 1; else R = M; }
+                rank = (t - start) + (L - lo);
+            } else {                               // element of the right run: count left < x
+                lo = start; hi = start + w;
+                int64_t L = lo, R = hi;
+                while (L < R) { int64_t M = (L + R) >> 1; if (a[M] < x) L = M + 1; else R = M; }
+                rank = (t - start - w) + (L - lo);
+            }
+            b[start + rank] = x;
+        }
+        __syncthreads();
+        uint64_t *tmp = a; a = b; b = tmp;
+    }
+    if (a != dst)
+        for (int64_t t = threadIdx.x; t < m; t += blockDim.x) dst[t] = a[t];
+}
+
+// ===================================================================== resolve ====
+// Follow forest links from entry x to its root node id; -1 (and an error) if a link leaves
+// [0, size) or a node id is not below nodes.
+__device__ __forceinline__ int chase(const int32_t *__restrict__ p, int64_t x, int64_t size, int nodes,
+                                     int32_t *cnt) {
+    for (int it = 0; it < kMaxChase; ++it) {
+        if (x < 0 || x >= size) break;
+        const int32_t v = p[x];
+        if (v < 0) {
+            const int id = -(v + 1);
+            if (id >= nodes) break;
+            return id;
+        }
+        x = v;
+    }
+    set_err(cnt, PH_EINTERNAL);
+    return -1;
+}
+
+// H0: the two endpoints of every sorted KEEP edge, as H0 nodes (local minima).
+__global__ __launch_bounds__(256) void k_resolve_edges(uint8_t *__restrict__ ws, int n) {
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (failed(cnt)) return;
+    const int m = cnt[CNT_E], M0 = cnt[CNT_M0];
+    if (m > I.E) { set_err(cnt, PH_EINTERNAL); return; }
+    const uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
+    const int32_t *par0 = arr<int32_t>(ws, I.o_par0);
+    int32_t *ea = arr<int32_t>(ws, I.o_ea), *eb = arr<int32_t>(ws, I.o_eb);
+    const int64_t HW = (int64_t)I.H * I.W;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < m; r += gridDim.x * 256) {
+        const uint64_t k = keyE[r];
+        const int64_t v = key_pix(k);
+        const int code = key_code(k);
+        if (code < 1 || code > 6) { set_err(cnt, PH_EINTERNAL); ea[r] = eb[r] = -1; continue; }
+        const int64_t u = v + c_off[code][0] * HW + c_off[code][1] * (int64_t)I.W + c_off[code][2];
+        ea[r] = chase(par0, v, I.N, M0, cnt);
+        eb[r] = chase(par0, u, I.N, M0, cnt);
+    }
+}
+
+// Top dimension: the two cofacets of every facet walked by the dual union-find, as dual
+// nodes (0 = the cell at infinity).  2D walks the KEEP edges that H0 did not use.
+__global__ __launch_bounds__(256) void k_resolve_facets(uint8_t *__restrict__ ws, int n) {
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (failed(cnt)) return;
+    const bool is2d = I.ndim == 2;
+    const int m = is2d ? cnt[CNT_E] : cnt[CNT_F], MT = cnt[CNT_MT];
+    if (m > (is2d ? I.E : I.F) || MT > I.T + 1) { set_err(cnt, PH_EINTERNAL); return; }
+    const uint64_t *key = arr<uint64_t>(ws, is2d ? I.o_keyE : I.o_keyF);
+    const int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
+    const int32_t *parT = arr<int32_t>(ws, I.o_parT);
+    int32_t *fa = arr<int32_t>(ws, I.o_fa), *fb = arr<int32_t>(ws, I.o_fb);
+    const int D = I.D, H = I.H, W = I.W;
+    const int64_t HW = (int64_t)H * W;
+    for (int r = blockIdx.x * 256 + threadIdx.x; r < m; r += gridDim.x * 256) {
+        if (is2d && neg0[r]) { fa[r] = -1; fb[r] = -1; continue; }   // cross-pruned
+        const uint64_t k = key[r];
+        const int64_t v = key_pix(k);
+        const int code = key_code(k);
+        if (v >= I.N || (is2d ? (code < 2 || code > 5) : (code < 7 || code > 18))) {
+            set_err(cnt, PH_EINTERNAL);
+            fa[r] = fb[r] = -1;
+            continue;
+        }
+        const int vz = (int)(v / HW), vrem = (int)(v - vz * HW), vy = vrem / W, vx = vrem - vy * W;
+        int axis = -1;
+        for (int a = is2d ? 1 : 0; a < 3; ++a)
+            if (c_off[code][a] == 0) axis = a;
+        int node[2];
+        for (int t = 0; t < 2; ++t) {
+            int o[3] = {c_off[code][0], c_off[code][1], c_off[code][2]};
+            o[axis] = t ? 1 : -1;
+            // top cell at doubled offset o from 2v: its first corner is v + (o - 1) / 2
+            const int cz = is2d ? 0 : vz + (o[0] - 1) / 2;
+            const int cy = vy + (o[1] - 1) / 2, cx = vx + (o[2] - 1) / 2;
+            const bool in = cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1 &&
+                            (is2d || (cz >= 0 && cz < D - 1));
+            if (!in) { node[t] = 0; continue; }
+            const int64_t top = ((int64_t)cz * (H - 1) + cy) * (W - 1) + cx;
+            node[t] = chase(parT, top, I.T, MT, cnt);
+        }
+        fa[r] = node[0];
+        fb[r] = node[1];
+    }
+}
+
+// ================================================================== union-find ====
+// Elder-rule union-find over m sorted edges (H0) or facets taken in decreasing order (dual).
+// Exact parallel rounds: every current component computes its minimum outgoing edge (in the
+// walk order).  A component whose minimum outgoing edge reaches a component with an elder
+// representative dies on that edge.  This is the pairing sequential Kruskal makes: the
+// component's own side at that edge is exactly itself (no earlier edge leaves it), and the
+// other side already contains the elder representative (components only merge along edges
+// taken before their own outgoing ones, so every member is joined to its representative by
+// earlier edges).  The globally first live edge always fires, so rounds make progress; the
+// few edges left after kMaxRounds are finished in order by one thread, which is exact for
+// the same reason.
+// Node-array access: LDS arrays are coherent inside the block; global ones are read with
+// device-scope loads so a value another wave wrote (or an atomic updated) is never served
+// from a stale L1 line.
+template <bool GLOBAL>
+__device__ __forceinline__ int32_t ld_node(int32_t *p) {
+    if (GLOBAL) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+template <bool GLOBAL>
+__device__ __forceinline__ void st_node(int32_t *p, int32_t v) {
+    if (GLOBAL) __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <bool DUAL, bool GLOBAL>
+__device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t *par, int32_t *moe,
+                                        int *s_wsum) {
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const bool is2d = I.ndim == 2;
+    const int m = DUAL ? (is2d ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
+    const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
+    const int32_t *ea = arr<int32_t>(ws, DUAL ? I.o_fa : I.o_ea);
+    const int32_t *eb = arr<int32_t>(ws, DUAL ? I.o_fb : I.o_eb);
+    const uint64_t *nkey = arr<uint64_t>(ws, DUAL ? I.o_nTkey : I.o_n0key);
+    int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
+    int32_t *death0 = arr<int32_t>(ws, I.o_death0);
+    int32_t *killer = arr<int32_t>(ws, I.o_killer);
+    int32_t *live = arr<int32_t>(ws, I.o_live), *live2 = arr<int32_t>(ws, I.o_live2);
+    int32_t *RA = arr<int32_t>(ws, I.o_ra), *RB = arr<int32_t>(ws, I.o_rb);
+
+    // elder(x, y): x entered earlier in the walk order
+    auto elder = [&](int x, int y) -> bool {
+        if (DUAL) return x == 0 || (y != 0 && nkey[x] > nkey[y]);
+        return nkey[x] < nkey[y];
+    };
+    auto find = [&](int x) -> int {
+        for (int it = 0; it < kMaxChase; ++it) {
+            const int p = ld_node<GLOBAL>(&par[x]);
+            if (p == x) return x;
+            const int g = ld_node<GLOBAL>(&par[p]);
+            if (g != p) st_node<GLOBAL>(&par[x], g);   // path halving (any ancestor is valid)
+            x = g;
+        }
+        set_err(cnt, PH_EINTERNAL);
+        return x;
+    };
+    auto edge_of = [&](int q) { return DUAL ? m - 1 - q : q; };
+
+    for (int x = threadIdx.x; x < M; x += blockDim.x) { st_node<GLOBAL>(&par[x], x); st_node<GLOBAL>(&moe[x], kInf); }
+    if (DUAL) { for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1; }
+    else {
+        for (int r = threadIdx.x; r < m; r += blockDim.x) neg0[r] = 0;
+        for (int x = threadIdx.x; x < M; x += blockDim.x) death0[x] = -1;
+    }
+    __syncthreads();
+
+    // live list: walk positions q whose edge joins two different nodes
+    int L = 0;
+    for (int base = 0; base < m; base += blockDim.x) {
+        const int q = base + threadIdx.x;
+        int flag = 0;
+        if (q < m) {
+            const int r = edge_of(q);
+            const int a = ea[r], b = eb[r];
+            flag = a >= 0 && b >= 0 && a < M && b < M && a != b;
+        }
+        int tot;
+        const int pos = block_flag_scan(flag, s_wsum, &tot);
+        if (flag) live[L + pos] = q;
+        L += tot;
+    }
+    __syncthreads();
+
+    int round = 0;
+    for (; round < kMaxRounds && L > 0; ++round) {
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            const int q = live[t], r = edge_of(q);
+            const int x = find(ea[r]), y = find(eb[r]);
+            RA[t] = x;
+            RB[t] = y;
+            if (x != y) { atomicMin(&moe[x], q); atomicMin(&moe[y], q); }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            const int x = RA[t], y = RB[t];
+            if (x == y) continue;
+            const int q = live[t], r = edge_of(q);
+            int dead = -1, into = -1;
+            if (ld_node<GLOBAL>(&moe[x]) == q && elder(y, x)) { dead = x; into = y; }
+            else if (ld_node<GLOBAL>(&moe[y]) == q && elder(x, y)) { dead = y; into = x; }
+            if (dead >= 0) {
+                st_node<GLOBAL>(&par[dead], into);
+                if (DUAL) killer[r] = dead;
+                else { death0[dead] = r; neg0[r] = 1; }
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < L; t += blockDim.x) {
+            st_node<GLOBAL>(&moe[RA[t]], kInf);
+            st_node<GLOBAL>(&moe[RB[t]], kInf);
+        }
+        __syncthreads();
+        int L2 = 0;
+        for (int base = 0; base < L; base += blockDim.x) {
+            const int t = base + threadIdx.x;
+            int flag = 0, q = 0;
+            if (t < L) {
+                q = live[t];
+                const int r = edge_of(q);
+                const bool fired = DUAL ? killer[r] >= 0 : neg0[r] != 0;
+                flag = RA[t] != RB[t] && !fired;
+            }
+            int tot;
+            const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (flag) live2[L2 + pos] = q;
+            L2 += tot;
+        }
+        __syncthreads();
+        int32_t *tmp = live; live = live2; live2 = tmp;
+        L = L2;
+    }
+    if (threadIdx.x == 0) {
+        cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] = round;
+        if (L > 0) cnt[CNT_SEQ] += L;
+        for (int t = 0; t < L; ++t) {               // sequential finish, walk order
+            const int q = live[t], r = edge_of(q);
+            const int x = find(ea[r]), y = find(eb[r]);
+            if (x == y) continue;
+            const int dead = elder(y, x) ? x : y, into = dead == x ? y : x;
+            st_node<GLOBAL>(&par[dead], into);
+            if (DUAL) killer[r] = dead;
+            else { death0[dead] = r; neg0[r] = 1; }
+        }
+    }
+}
+
+template <bool DUAL>
+__global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int n) {
+    __shared__ int32_t s_par[kUfLdsNodes];
+    __shared__ int32_t s_moe[kUfLdsNodes];
+    __shared__ int s_wsum[kUfThreads / 64];
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
+    const int m = DUAL ? (I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
+    if (block_failed(cnt)) return;
+    if (M < 1 || M > (DUAL ? I.T + 1 : I.N) || m > (DUAL && I.ndim == 3 ? I.F : I.E)) {
+        if (threadIdx.x == 0) set_err((int32_t *)cnt, PH_EINTERNAL);
+        return;
+    }
+    if (M <= kUfLdsNodes) uf_body<DUAL, false>(ws, n, s_par, s_moe, s_wsum);
+    else uf_body<DUAL, true>(ws, n, arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0),
+                             arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0), s_wsum);
+}
+
+// ====================================================================== output ====
+__device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code) {
+    const int64_t HW = (int64_t)I.H * I.W;
+    const int64_t z = v / HW, rem = v - z * HW, y = rem / I.W, x = rem - y * I.W;
+    const int64_t Z = 2 * z + c_off[code][0], Y = 2 * y + c_off[code][1], X = 2 * x + c_off[code][2];
+    return (Z * (2 * (int64_t)I.H - 1) + Y) * (2 * (int64_t)I.W - 1) + X;
+}
+
+__global__ __launch_bounds__(kUfThreads) void k_output(const float *__restrict__ imgs,
+                                                      uint8_t *__restrict__ ws, int n, uint32_t flags,
+                                                      ph_pairs out, int64_t *__restrict__ d_counts,
+                                                      int32_t *__restrict__ d_status) {
+    __shared__ int s_wsum[kUfThreads / 64];
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const float *img = imgs + I.img_off;
+    const int32_t *par0 = arr<int32_t>(ws, I.o_par0);
+    const int32_t *death0 = arr<int32_t>(ws, I.o_death0);
+    const int32_t *killer = arr<int32_t>(ws, I.o_killer);
+    const uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
+    const uint64_t *n0s = arr<uint64_t>(ws, I.o_n0sorted);
+    const uint64_t *nTkey = arr<uint64_t>(ws, I.o_nTkey);
+    const bool is2d = I.ndim == 2;
+    const uint64_t *fkey = arr<uint64_t>(ws, is2d ? I.o_keyE : I.o_keyF);
+    const int M0 = cnt[CNT_M0], MT = cnt[CNT_MT], mE = cnt[CNT_E];
+    const int mf = is2d ? cnt[CNT_E] : cnt[CNT_F];
+    const int64_t cap = I.out_cap, o = I.out_off;
+    int64_t P = 0;
+    if (block_failed(cnt)) {
+        if (threadIdx.x == 0) { d_counts[i] = 0; d_status[i] = cnt[CNT_ERR]; }
+        return;
+    }
+    // a pixel index and a cell code read back from a key must name a cell of this instance
+    auto key_ok = [&](uint64_t k, int lo, int hi) {
+        const int c = (int)key_code(k);
+        return key_pix(k) < (uint64_t)I.N && c >= lo && c <= hi;
+    };
+
+    auto put = [&](int64_t pos, int dim, uint32_t bv, int64_t bc, int32_t bpix, int64_t dc, int32_t dpix) {
+        if (pos >= cap) return;
+        const int64_t j = o + pos;
+        out.dim[j] = (int8_t)dim;
+        out.birth[j] = img[bpix];
+        out.death[j] = dpix >= 0 ? img[dpix] : __int_as_float(0x7f800000);
+        out.birth_cell[j] = bc;
+        out.death_cell[j] = dc;
+        out.birth_vertex[j] = bpix;
+        out.death_vertex[j] = dpix;
+        (void)bv;
+    };
+
+    if (flags & PH_H0) {
+        for (int base = 0; base < M0; base += blockDim.x) {
+            const int j = base + threadIdx.x;
+            int flag = 0;
+            uint64_t nk = 0, ek = 0;
+            int d = -1;
+            if (j < M0) {
+                nk = n0s[j];
+                const int32_t pv = key_ok(nk, 0, 0) ? par0[key_pix(nk)] : 0;
+                const int id = -(pv + 1);
+                if (pv >= 0 || id >= M0) { set_err(cnt, PH_EINTERNAL); }
+                else {
+                    d = death0[id];
+                    if (d < 0) flag = 1;                          // essential
+                    else if (d >= mE || !key_ok(ek = keyE[d], 1, 6)) set_err(cnt, PH_EINTERNAL);
+                    else flag = key_ord(ek) != key_ord(nk);
+                }
+            }
+            int tot;
+            const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (flag) {
+                const int32_t bp = (int32_t)key_pix(nk);
+                if (d < 0) put(P + pos, 0, 0, cell_index(I, bp, 0), bp, -1, -1);
+                else {
+                    const int32_t dp = (int32_t)key_pix(ek);
+                    put(P + pos, 0, 0, cell_index(I, bp, 0), bp, cell_index(I, dp, key_code(ek)), dp);
+                }
+            }
+            P += tot;
+        }
+    }
+    if (flags & PH_HTOP) {
+        for (int base = 0; base < mf; base += blockDim.x) {
+            const int r = base + threadIdx.x;
+            int flag = 0;
+            uint64_t fk = 0, tk = 0;
+            if (r < mf) {
+                const int x = killer[r];
+                if (x >= MT || x == 0) set_err(cnt, PH_EINTERNAL);
+                else if (x > 0) {
+                    fk = fkey[r];
+                    tk = nTkey[x];
+                    if (!key_ok(fk, is2d ? 2 : 7, is2d ? 5 : 18) || !key_ok(tk, is2d ? 11 : 19, is2d ? 14 : 26))
+                        set_err(cnt, PH_EINTERNAL);
+                    else flag = key_ord(fk) != key_ord(tk);
+                }
+            }
+            int tot;
+            const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (flag) {
+                const int32_t bp = (int32_t)key_pix(fk), dp = (int32_t)key_pix(tk);
+                put(P + pos, I.ndim - 1, 0, cell_index(I, bp, key_code(fk)), bp,
+                    cell_index(I, dp, key_code(tk)), dp);
+            }
+            P += tot;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        d_counts[i] = P;
+        int st = __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (st == 0 && P > cap) st = PH_ECAPACITY;
+        d_status[i] = st;
+    }
+}
+
+// ==================================================================== backward ====
+__global__ void k_zero(float *__restrict__ g, int64_t nv) {
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < nv; t += (int64_t)gridDim.x * blockDim.x)
+        g[t] = 0.0f;
+}
+
+__global__ void k_scatter(ph_pairs pr, const int64_t *__restrict__ d_out_off,
+                          const int64_t *__restrict__ d_counts, const float *__restrict__ gb,
+                          const float *__restrict__ gd, float *__restrict__ g,
+                          const int64_t *__restrict__ d_img_off, int n, int64_t total) {
+    const int i = blockIdx.y;
+    const int64_t nvox = (i + 1 < n ? d_img_off[i + 1] : total) - d_img_off[i];
+    const int64_t o = d_out_off[i];
+    int64_t cnt = d_counts[i];
+    const int64_t cap = d_out_off[i + 1] - o;
+    if (cnt > cap) cnt = cap;
+    float *gi = g + d_img_off[i];
+    for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < cnt; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = o + t;
+        const int32_t bv = pr.birth_vertex[j], dv = pr.death_vertex[j];
+        if (bv >= 0 && bv < nvox) atomicAdd(&gi[bv], gb[j]);
+        if (dv >= 0 && dv < nvox) atomicAdd(&gi[dv], gd[j]);
+    }
+}
+
+// ================================================================== host side ====
+namespace {
+
+std::once_flag g_lut_once;
+int g_lut_status = PH_OK;
+uint32_t g_h_lut2d[256];
+std::vector<uint32_t> g_h_l1;
+std::vector<uint64_t> g_h_l2;
+int g_cfg2d = 0, g_cfg3d = 0;
+std::mutex g_dev_mu;
+bool g_dev_ready[64] = {false};
+
+void build_host_luts() {
+    char err[256] = {0};
+    g_h_l1.assign(kL1Size, 0);
+    g_h_l2.assign(kL3Configs, 0);
+    g_cfg2d = build_lut2d(g_h_lut2d, err, sizeof err);
+    if (g_cfg2d != kL2Configs) { fprintf(stderr, "flashcubical: 2D table: %s\n", err); g_lut_status = PH_EINTERNAL; return; }
+    g_cfg3d = build_lut3d(g_h_l1.data(), g_h_l2.data(), err, sizeof err);
+    if (g_cfg3d != kL3Configs) { fprintf(stderr, "flashcubical: 3D table: %s\n", err); g_lut_status = PH_EINTERNAL; return; }
+}
+
+int host_luts() {
+    std::call_once(g_lut_once, build_host_luts);
+    return g_lut_status;
+}
+
+// Every kernel must fit the device: static LDS within the per-block limit and the block
+// size we launch within the kernel's limit.  A kernel that cannot launch would leave later
+// kernels reading unwritten workspace, so the library refuses to run instead.
+struct KInfo { const char *name; const void *fn; int threads; };
+
+int check_kernels(int dev, char *report, size_t len) {
+    const KInfo ks[] = {
+        {"k_plan", (const void *)k_plan, 64},
+        {"k_classify2d<64,16>", (const void *)k_classify2d<64, 16>, 256},
+        {"k_classify2d<32,32>", (const void *)k_classify2d<32, 32>, 256},
+        {"k_classify2d<128,8>", (const void *)k_classify2d<128, 8>, 256},
+        {"k_classify3d<16,8,8>", (const void *)k_classify3d<16, 8, 8>, 256},
+        {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4>, 256},
+        {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16>, 256},
+        {"k_sort", (const void *)k_sort, kSortThreads},
+        {"k_resolve_edges", (const void *)k_resolve_edges, 256},
+        {"k_resolve_facets", (const void *)k_resolve_facets, 256},
+        {"k_uf<0>", (const void *)k_uf<false>, kUfThreads},
+        {"k_uf<1>", (const void *)k_uf<true>, kUfThreads},
+        {"k_output", (const void *)k_output, kUfThreads},
+        {"k_zero", (const void *)k_zero, 256},
+        {"k_scatter", (const void *)k_scatter, 256},
+    };
+    int maxsh = 0, maxthr = 0;
+    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PH_EHIP;
+    if (hipDeviceGetAttribute(&maxthr, hipDeviceAttributeMaxThreadsPerBlock, dev) != hipSuccess) return PH_EHIP;
+    size_t used = 0;
+    auto put = [&](const char *fmt, auto... a) {
+        if (!report || used >= len) return;
+        int k = snprintf(report + used, len - used, fmt, a...);
+        if (k > 0) used += (size_t)k;
+    };
+    put("device %d: max shared per block %d, max threads per block %d\n", dev, maxsh, maxthr);
+    int rc = PH_OK;
+    for (const KInfo &k : ks) {
+        hipFuncAttributes at;
+        if (hipFuncGetAttributes(&at, k.fn) != hipSuccess) { put("%s: attributes unavailable\n", k.name); rc = PH_EHIP; continue; }
+        const bool ok = (int)at.sharedSizeBytes <= maxsh && at.maxThreadsPerBlock >= k.threads && k.threads <= maxthr;
+        put("%s: lds %d B, regs %d, max threads %d, launch %d %s\n", k.name, (int)at.sharedSizeBytes,
+            at.numRegs, at.maxThreadsPerBlock, k.threads, ok ? "ok" : "DOES NOT FIT");
+        if (!ok) rc = PH_EHIP;
+    }
+    return rc;
+}
+
+int device_luts() {
+    int rc = host_luts();
+    if (rc != PH_OK) return rc;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PH_EHIP;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_dev_ready[dev]) return PH_OK;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(c_lut2d), g_h_lut2d, sizeof g_h_lut2d) != hipSuccess) return PH_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_l1), g_h_l1.data(), sizeof(uint32_t) * kL1Size) != hipSuccess) return PH_EHIP;
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_l2), g_h_l2.data(), sizeof(uint64_t) * kL3Configs) != hipSuccess) return PH_EHIP;
+    rc = check_kernels(dev, nullptr, 0);
+    if (rc != PH_OK) return rc;
+    g_dev_ready[dev] = true;
+    return PH_OK;
+}
+
+bool valid_shape(const ph_shape &s) {
+    if (s.ndim != 2 && s.ndim != 3) return false;
+    int64_t nv = 1;
+    for (int k = 0; k < s.ndim; ++k) {
+        if (s.ext[k] < 1) return false;
+        nv *= s.ext[k];
+    }
+    return nv < (1ll << kPixBits);
+}
+
+const int kTile2[3][2] = {{64, 16}, {32, 32}, {128, 8}};
+const int kTile3[3][3] = {{16, 8, 8}, {32, 8, 4}, {8, 8, 16}};
+
+Tiles tiles_of(const ph_tuning *t) {
+    int a = t ? t->tile2d : 0, b = t ? t->tile3d : 0;
+    if (a < 0 || a > 2) a = 0;
+    if (b < 0 || b > 2) b = 0;
+    return Tiles{kTile2[a][0], kTile2[a][1], kTile3[b][0], kTile3[b][1], kTile3[b][2]};
+}
+
+// total workspace bytes and classify grid sizes for a list of host shapes
+int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3) {
+    int64_t at = header_bytes(n);
+    *t2 = 0;
+    *t3 = 0;
+    for (int i = 0; i < n; ++i) {
+        Inst I;
+        fill_inst(I, h[i], tl);
+        if (I.ndim == 2) *t2 += (int64_t)I.tx * I.ty;
+        else *t3 += (int64_t)I.tx * I.ty * I.tz;
+        at = layout(I, at);
+    }
+    return at;
+}
+
+int64_t max_list(const ph_shape *h, int n) {
+    int64_t m = 1;
+    for (int i = 0; i < n; ++i) {
+        Inst I;
+        fill_inst(I, h[i], Tiles{64, 16, 16, 8, 8});
+        int64_t l = I.E > I.F ? I.E : I.F;
+        if (l > m) m = l;
+    }
+    return m;
+}
+
+template <int A, int B>
+void launch2d(int64_t tiles, const float *imgs, uint8_t *ws, int n, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify2d<A, B>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n);
+}
+template <int A, int B, int C>
+void launch3d(int64_t tiles, const float *imgs, uint8_t *ws, int n, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify3d<A, B, C>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n);
+}
+
+int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+        const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
+        const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
+        const ph_tuning *tuning, void *d_ws, size_t ws_bytes, hipStream_t st) {
+    if (n < 1 || !d_imgs || !h_shapes || !d_counts || !d_status || !d_ws) return PH_EINVAL;
+    if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
+        !out.birth_vertex || !out.death_vertex)
+        return PH_EINVAL;
+    bool any3 = false;
+    for (int i = 0; i < n; ++i) {
+        if (!valid_shape(h_shapes[i])) return PH_EINVAL;
+        any3 |= h_shapes[i].ndim == 3;
+    }
+    if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
+    int rc = device_luts();
+    if (rc != PH_OK) return rc;
+    const Tiles tl = tiles_of(tuning);
+    int64_t t2, t3;
+    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3);
+    if ((int64_t)ws_bytes < need) return PH_ENOMEM;
+    if (t2 >= (1ll << 31) || t3 >= (1ll << 31)) return PH_EINVAL;
+    uint8_t *ws = (uint8_t *)d_ws;
+    const int tile2 = tuning ? tuning->tile2d : 0, tile3 = tuning ? tuning->tile3d : 0;
+
+    // Each launch is checked on its own: the error a failed launch leaves behind would be
+    // overwritten by the next successful call.
+#define FC_LAUNCH(...)                                            \
+    do {                                                          \
+        (void)hipGetLastError();                                  \
+        __VA_ARGS__;                                              \
+        if (hipGetLastError() != hipSuccess) return PH_EHIP;      \
+    } while (0)
+    FC_LAUNCH(hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
+                                 single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
+    if (t2 > 0) {
+        if (tile2 == 1) FC_LAUNCH(launch2d<32, 32>(t2, d_imgs, ws, n, st));
+        else if (tile2 == 2) FC_LAUNCH(launch2d<128, 8>(t2, d_imgs, ws, n, st));
+        else FC_LAUNCH(launch2d<64, 16>(t2, d_imgs, ws, n, st));
+    }
+    if (t3 > 0) {
+        if (tile3 == 1) FC_LAUNCH(launch3d<32, 8, 4>(t3, d_imgs, ws, n, st));
+        else if (tile3 == 2) FC_LAUNCH(launch3d<8, 8, 16>(t3, d_imgs, ws, n, st));
+        else FC_LAUNCH(launch3d<16, 8, 8>(t3, d_imgs, ws, n, st));
+    }
+    const int64_t ml = max_list(h_shapes, n);
+    const unsigned rblocks = (unsigned)((ml + 255) / 256 < 1024 ? (ml + 255) / 256 : 1024);
+    FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 0));
+    if (any3) FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 1));
+    FC_LAUNCH(hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
+    FC_LAUNCH(hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
+    if (flags & PH_HTOP) {
+        FC_LAUNCH(hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
+        FC_LAUNCH(hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
+    }
+    FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 2));
+    FC_LAUNCH(hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
+                                 d_status));
+    return PH_OK;
+}
+
+}  // namespace
+}  // namespace fc
+
+// ====================================================================== C ABI ====
+extern "C" {
+
+int64_t ph_capacity_bound(ph_shape s) {
+    if (!fc::valid_shape(s)) return 0;
+    fc::Inst I;
+    fc::fill_inst(I, s, fc::Tiles{64, 16, 16, 8, 8});
+    return I.N + I.T;
+}
+
+size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
+    (void)flags;
+    if (!h_shapes || n < 1) return 0;
+    for (int i = 0; i < n; ++i)
+        if (!fc::valid_shape(h_shapes[i])) return 0;
+    int64_t t2, t3, best = 0;
+    for (int a = 0; a < 3; ++a)                      // large enough for every tile choice
+        for (int b = 0; b < 3; ++b) {
+            ph_tuning t{a, b};
+            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3);
+            if (need > best) best = need;
+        }
+    return (size_t)best;
+}
+
+int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
+               int64_t *d_count, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
+    if (capacity < 0) return PH_EINVAL;
+    return fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
+                   d_status, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+                     const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
+                     int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
+                     size_t ws_bytes, void *stream) {
+    if (!d_img_off || !d_shapes || !d_out_off) return PH_EINVAL;
+    ph_shape dummy{2, {1, 1, 1}};
+    return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
+                   d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
+                const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
+                const int64_t *d_img_off, int64_t total_voxels, void *stream) {
+    if (n < 1 || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
+        !pairs.birth_vertex || !pairs.death_vertex)
+        return PH_EINVAL;
+    if (!d_out_off || !d_img_off) return PH_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = fc::device_luts();
+    if (rc != PH_OK) return rc;
+    const int64_t zb = (total_voxels + 255) / 256;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(fc::k_zero, dim3((unsigned)(zb < 8192 ? zb : 8192)), dim3(256), 0, st, d_grad_img,
+                       total_voxels);
+    if (hipGetLastError() != hipSuccess) return PH_EHIP;
+    hipLaunchKernelGGL(fc::k_scatter, dim3(64, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
+                       d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
+    return hipGetLastError() == hipSuccess ? PH_OK : PH_EHIP;
+}
+
+int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry) {
+    if (!entry) return PH_EINVAL;
+    int rc = fc::host_luts();
+    if (rc != PH_OK) return rc;
+    if (ndim == 2) {
+        if (raw_mask > 255u) return PH_EINVAL;
+        *entry = fc::g_h_lut2d[raw_mask];
+        return PH_OK;
+    }
+    if (ndim == 3) {
+        if (raw_mask >> 26) return PH_EINVAL;
+        uint32_t cubes;
+        const uint32_t idx1 = fc::canon3d(raw_mask, &cubes);
+        const uint32_t l1 = fc::g_h_l1[idx1];
+        *entry = fc::g_h_l2[(l1 >> 8) + fc::compress8(cubes, l1 & 255u)];
+        return PH_OK;
+    }
+    return PH_EINVAL;
+}
+
+int32_t ph_lut_config_count(int32_t ndim) {
+    if (fc::host_luts() != PH_OK) return -1;
+    return ndim == 2 ? fc::g_cfg2d : ndim == 3 ? fc::g_cfg3d : -1;
+}
+
+const char *ph_version(void) { return "flashcubical-gfx950 0.1"; }
+
+/* Upload the lookup tables to the current device (normally done on first use) and read
+ * them back; returns PH_OK when the device copy equals the host tables. */
+int ph_device_report(char *buf, size_t len) {
+    if (!buf || len == 0) return PH_EINVAL;
+    buf[0] = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return PH_EHIP;
+    return fc::check_kernels(dev, buf, len);
+}
+
+int ph_init_device(void) {
+    int rc = fc::device_luts();
+    if (rc != PH_OK) return rc;
+    std::vector<uint32_t> l2d(256), l1(fc::kL1Size);
+    std::vector<uint64_t> l2(fc::kL3Configs);
+    if (hipMemcpyFromSymbol(l2d.data(), HIP_SYMBOL(fc::c_lut2d), 256 * sizeof(uint32_t)) != hipSuccess) return PH_EHIP;
+    if (hipMemcpyFromSymbol(l1.data(), HIP_SYMBOL(fc::g_l1), l1.size() * sizeof(uint32_t)) != hipSuccess) return PH_EHIP;
+    if (hipMemcpyFromSymbol(l2.data(), HIP_SYMBOL(fc::g_l2), l2.size() * sizeof(uint64_t)) != hipSuccess) return PH_EHIP;
+    if (memcmp(l2d.data(), fc::g_h_lut2d, 256 * sizeof(uint32_t)) || l1 != fc::g_h_l1 || l2 != fc::g_h_l2) return PH_EINTERNAL;
+    return PH_OK;
+}
+
+}  // extern "C"
