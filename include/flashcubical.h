@@ -24,7 +24,8 @@
  *     first pair), then the top dimension.  birth and death are bit copies of input pixels.
  *   - Memory: every pointer named d_* is device memory owned by the caller; h_* is host
  *     memory.  The library allocates nothing per call.  It owns only its lookup tables,
- *     built on the host and uploaded once per device on first use.
+ *     built on the host and copied once per device on first use into device buffers it
+ *     keeps until the process ends (about 1.2 MB per device).
  *   - Streams: all work is enqueued on `stream`; no call synchronises with the host, so a
  *     sequence of calls can be captured in a HIP graph.  Results are valid once the stream
  *     has reached them.
@@ -35,6 +36,13 @@
  *     the first `capacity` pairs in output order are stored, PH_EINTERNAL if a bounded
  *     loop ran out of iterations).
  *   - Calls that share a workspace must not overlap in time.
+ *   - Device path switch: the entry points that launch kernels (ph_diagram,
+ *     ph_diagram_batch, ph_backward) return PH_EDISABLED unless the environment variable
+ *     FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of
+ *     this path ended in a GPU memory fault whose cause has not been found: the kernels are
+ *     memory-safe under CPU emulation with sanitizers, so nothing is launched by default
+ *     until the path has been verified on the device.  Everything that launches no kernel
+ *     (sizes, tables, device report, table upload) is always available.
  */
 #ifndef FLASHCUBICAL_H
 #define FLASHCUBICAL_H
@@ -53,7 +61,8 @@ enum {
     PH_ECAPACITY = -3,
     PH_ENOMEM = -4,
     PH_EHIP = -5,
-    PH_EINTERNAL = -6
+    PH_EINTERNAL = -6,
+    PH_EDISABLED = -7
 };
 
 /* flags: which dimensions to report (H0 is always computed; 2D needs it for the top). */
@@ -134,8 +143,26 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
  * ndim 2: raw_mask has 8 bits (neighbours up, left, right, down, up-left, up-right,
  * down-left, down-right); ndim 3: 26 bits, neighbour at offset code k+1 of the local cell
  * list (offsets ordered by number of non-zero coordinates, then lexicographically, slowest
- * axis first).  Bit set = that neighbour precedes the vertex.  *entry receives the packed
- * classification (layout in the implementation).  Returns PH_OK or PH_EINVAL. */
+ * axis first).  Bit set = that neighbour precedes the vertex.  *entry receives the
+ * classification of the vertex's lower star L(v) by the relative reduction of L(v):
+ *   2D (edges i = 0..3: up, left, right, down; squares q = 0..3: quadrant bits
+ *   (dy > 0) << 1 | (dx > 0)):
+ *     bits 0-2   edge paired with the vertex (7: none, the vertex is a local minimum)
+ *     bits 3-6   KEEP edges (unpaired inside L(v))
+ *     bits 7-10  squares of L(v)
+ *     bits 11-14 ROOT squares (unpaired inside L(v))
+ *     bits 15-22 for each other square q of L(v), 2 bits at 15 + 2q: quadrant of the other
+ *                cofacet of the edge that q is paired with
+ *   3D (edges i = 0..5 at codes 1..6; squares s = 0..11 at codes 7..18; cubes c = 0..7:
+ *   octant bits (dz > 0) << 2 | (dy > 0) << 1 | (dx > 0)):
+ *     bits 0-2   edge paired with the vertex (7: none)
+ *     bits 3-8   KEEP edges
+ *     bits 9-20  KEEP squares
+ *     bits 21-28 ROOT cubes
+ *     bits 29-52 for each other cube c of L(v), 3 bits at 29 + 3c: octant of the other
+ *                cofacet of the square that c is paired with
+ *     bits 53-60 cubes of L(v)
+ * Returns PH_OK or PH_EINVAL. */
 int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry);
 
 /* Number of distinct lower-star configurations after collapsing irrelevant diagonal

@@ -43,6 +43,19 @@ constexpr int8_t kOff[27][3] = {
     {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}, {1, -1, 1},
     {1, 1, -1}, {1, 1, 1}};
 
+// Offsets as arithmetic on packed constants (2 bits per code and axis), so device code needs
+// no table in memory: off_of(code, axis) = kOff[code][axis].
+constexpr uint64_t pack_axis(int a) {
+    uint64_t k = 0;
+    for (int c = 0; c < 27; ++c) k |= (uint64_t)(kOff[c][a] + 1) << (2 * c);
+    return k;
+}
+constexpr uint64_t kOffPackZ = pack_axis(0), kOffPackY = pack_axis(1), kOffPackX = pack_axis(2);
+FC_HD int off_of(int code, int axis) {
+    const uint64_t k = axis == 0 ? kOffPackZ : (axis == 1 ? kOffPackY : kOffPackX);
+    return (int)((k >> (2 * code)) & 3u) - 1;
+}
+
 FC_HD uint32_t ord32(uint32_t u) {
     if (u == 0x80000000u) u = 0;                   // -0 ranks with +0
     return (u >> 31) ? ~u : (u | 0x80000000u);

@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -31,16 +32,13 @@ namespace fc {
 int build_lut2d(uint32_t *lut, char *err, int errlen);
 int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen);
 
-__constant__ uint32_t c_lut2d[256];
-__constant__ int8_t c_off[27][3] = {
-    {0, 0, 0},
-    {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}, {0, 0, 1}, {0, 1, 0}, {1, 0, 0},
-    {-1, -1, 0}, {-1, 0, -1}, {-1, 0, 1}, {-1, 1, 0}, {0, -1, -1}, {0, -1, 1},
-    {0, 1, -1}, {0, 1, 1}, {1, -1, 0}, {1, 0, -1}, {1, 0, 1}, {1, 1, 0},
-    {-1, -1, -1}, {-1, -1, 1}, {-1, 1, -1}, {-1, 1, 1}, {1, -1, -1}, {1, -1, 1},
-    {1, 1, -1}, {1, 1, 1}};
-__device__ uint32_t g_l1[kL1Size];
-__device__ uint64_t g_l2[kL3Configs];
+// The lookup tables live in device buffers the library allocates once per device and passes
+// to the kernels as arguments; device code reads no variable of its own code object.
+struct Luts {
+    const uint32_t *l2d;   // 256 entries (2D)
+    const uint32_t *l1;    // kL1Size entries (3D level 1)
+    const uint64_t *l2;    // kL3Configs entries (3D level 2)
+};
 
 constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
 constexpr int32_t kNotOwned = 0x7FFFFFFF;  // LDS slot not written by this tile
@@ -161,7 +159,7 @@ __device__ __forceinline__ int wave_alloc(int32_t *counter, int count) {
 // ================================================================ classify 2D ====
 template <int TW, int TH>
 __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ imgs,
-                                                    uint8_t *__restrict__ ws, int n) {
+                                                    uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, PW = TW + 1, NP = (TH + 1) * (TW + 1);
     __shared__ uint32_t skey[(TH + 2) * KW];
@@ -226,7 +224,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
                 uint32_t kn = skey[(r + 1 + NDY[b]) * KW + c + 1 + NDX[b]];
                 if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
             }
-            e = c_lut2d[mask];
+            e = lut.l2d[mask];
         }
         const uint32_t direct = e & 7u;
         const bool ismin = valid && direct == kNoDirect;
@@ -313,8 +311,11 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     for (int p = threadIdx.x; p < NP; p += 256) {
         const int32_t v = spT[p];
         if (v == kNotOwned) continue;
-        const int pr = p / PW, pc = p - pr * PW;
-        parT[(y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc)] = v;
+        const int pr = p / PW, pc = p - pr * PW, sy = y0 - 1 + pr, sx = x0 - 1 + pc;
+        // a square is only ever marked for a vertex whose lower star holds it, so it lies in
+        // the image; the check keeps a corrupted table from writing outside parT
+        if (sy >= 0 && sy < H - 1 && sx >= 0 && sx < W - 1) parT[sy * (W - 1) + sx] = v;
+        else set_err(cnt, PH_EINTERNAL);
     }
     if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
 }
@@ -322,7 +323,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
 // ================================================================ classify 3D ====
 template <int TW, int TH, int TD>
 __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ imgs,
-                                                    uint8_t *__restrict__ ws, int n) {
+                                                    uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
     constexpr int PW = TW + 1, PH = TH + 1, PD = TD + 1, NP = PW * PH * PD;
@@ -392,9 +393,9 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             }
             uint32_t cubes;
             const uint32_t idx1 = canon3d(raw, &cubes);
-            const uint32_t l1 = g_l1[idx1];
+            const uint32_t l1 = lut.l1[idx1];
             const uint32_t idx2 = (l1 >> 8) + compress8(cubes, l1 & 255u);
-            if (idx2 < (uint32_t)kL3Configs) e = g_l2[idx2];
+            if (idx2 < (uint32_t)kL3Configs) e = lut.l2[idx2];
             else set_err(cnt, PH_EINTERNAL);
         }
         const uint32_t direct = (uint32_t)(e & 7u);
@@ -412,7 +413,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
                 n0key[id0] = make_key(kv, pv, 0);
             } else {
                 const int code = 1 + (int)direct;
-                const int dz = c_off[code][0], dy = c_off[code][1], dx = c_off[code][2];
+                const int dz = off_of(code, 0), dy = off_of(code, 1), dx = off_of(code, 2);
                 const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
                 if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW)
                     sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
@@ -490,7 +491,10 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
         const int32_t v = spT[p];
         if (v == kNotOwned) continue;
         const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
-        parT[(z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px)] = v;
+        const int cz = z0 - 1 + pz, cy = y0 - 1 + py, cx = x0 - 1 + px;
+        if (cz >= 0 && cz < D - 1 && cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1)
+            parT[cz * TH1W1 + (int64_t)cy * (W - 1) + cx] = v;
+        else set_err(cnt, PH_EINTERNAL);
     }
     if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
 }
@@ -632,7 +636,7 @@ __global__ __launch_bounds__(256) void k_resolve_edges(uint8_t *__restrict__ ws,
         const int64_t v = key_pix(k);
         const int code = key_code(k);
         if (code < 1 || code > 6) { set_err(cnt, PH_EINTERNAL); ea[r] = eb[r] = -1; continue; }
-        const int64_t u = v + c_off[code][0] * HW + c_off[code][1] * (int64_t)I.W + c_off[code][2];
+        const int64_t u = v + off_of(code, 0) * HW + off_of(code, 1) * (int64_t)I.W + off_of(code, 2);
         ea[r] = chase(par0, v, I.N, M0, cnt);
         eb[r] = chase(par0, u, I.N, M0, cnt);
     }
@@ -667,10 +671,10 @@ __global__ __launch_bounds__(256) void k_resolve_facets(uint8_t *__restrict__ ws
         const int vz = (int)(v / HW), vrem = (int)(v - vz * HW), vy = vrem / W, vx = vrem - vy * W;
         int axis = -1;
         for (int a = is2d ? 1 : 0; a < 3; ++a)
-            if (c_off[code][a] == 0) axis = a;
+            if (off_of(code, a) == 0) axis = a;
         int node[2];
         for (int t = 0; t < 2; ++t) {
-            int o[3] = {c_off[code][0], c_off[code][1], c_off[code][2]};
+            int o[3] = {off_of(code, 0), off_of(code, 1), off_of(code, 2)};
             o[axis] = t ? 1 : -1;
             // top cell at doubled offset o from 2v: its first corner is v + (o - 1) / 2
             const int cz = is2d ? 0 : vz + (o[0] - 1) / 2;
@@ -859,7 +863,7 @@ __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int
 __device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code) {
     const int64_t HW = (int64_t)I.H * I.W;
     const int64_t z = v / HW, rem = v - z * HW, y = rem / I.W, x = rem - y * I.W;
-    const int64_t Z = 2 * z + c_off[code][0], Y = 2 * y + c_off[code][1], X = 2 * x + c_off[code][2];
+    const int64_t Z = 2 * z + off_of(code, 0), Y = 2 * y + off_of(code, 1), X = 2 * x + off_of(code, 2);
     return (Z * (2 * (int64_t)I.H - 1) + Y) * (2 * (int64_t)I.W - 1) + X;
 }
 
@@ -1009,6 +1013,7 @@ std::vector<uint64_t> g_h_l2;
 int g_cfg2d = 0, g_cfg3d = 0;
 std::mutex g_dev_mu;
 bool g_dev_ready[64] = {false};
+Luts g_dev_lut[64];                 // per-device table buffers, kept until the process ends
 
 void build_host_luts() {
     char err[256] = {0};
@@ -1077,9 +1082,17 @@ int device_luts() {
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PH_EHIP;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     if (g_dev_ready[dev]) return PH_OK;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(c_lut2d), g_h_lut2d, sizeof g_h_lut2d) != hipSuccess) return PH_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_l1), g_h_l1.data(), sizeof(uint32_t) * kL1Size) != hipSuccess) return PH_EHIP;
-    if (hipMemcpyToSymbol(HIP_SYMBOL(g_l2), g_h_l2.data(), sizeof(uint64_t) * kL3Configs) != hipSuccess) return PH_EHIP;
+    void *a = nullptr, *b = nullptr, *c = nullptr;
+    if (hipMalloc(&a, sizeof g_h_lut2d) != hipSuccess) return PH_EHIP;
+    if (hipMalloc(&b, sizeof(uint32_t) * kL1Size) != hipSuccess) { (void)hipFree(a); return PH_EHIP; }
+    if (hipMalloc(&c, sizeof(uint64_t) * kL3Configs) != hipSuccess) { (void)hipFree(a); (void)hipFree(b); return PH_EHIP; }
+    if (hipMemcpy(a, g_h_lut2d, sizeof g_h_lut2d, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(b, g_h_l1.data(), sizeof(uint32_t) * kL1Size, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(c, g_h_l2.data(), sizeof(uint64_t) * kL3Configs, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(a); (void)hipFree(b); (void)hipFree(c);
+        return PH_EHIP;
+    }
+    g_dev_lut[dev] = Luts{(const uint32_t *)a, (const uint32_t *)b, (const uint64_t *)c};
     rc = check_kernels(dev, nullptr, 0);
     if (rc != PH_OK) return rc;
     g_dev_ready[dev] = true;
@@ -1133,12 +1146,19 @@ int64_t max_list(const ph_shape *h, int n) {
 }
 
 template <int A, int B>
-void launch2d(int64_t tiles, const float *imgs, uint8_t *ws, int n, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify2d<A, B>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n);
+void launch2d(int64_t tiles, const float *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify2d<A, B>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n, lut);
 }
 template <int A, int B, int C>
-void launch3d(int64_t tiles, const float *imgs, uint8_t *ws, int n, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify3d<A, B, C>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n);
+void launch3d(int64_t tiles, const float *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify3d<A, B, C>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n, lut);
+}
+
+Luts current_luts() {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    return g_dev_lut[dev];
 }
 
 int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
@@ -1175,15 +1195,16 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     } while (0)
     FC_LAUNCH(hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
+    const Luts lut = current_luts();
     if (t2 > 0) {
-        if (tile2 == 1) FC_LAUNCH(launch2d<32, 32>(t2, d_imgs, ws, n, st));
-        else if (tile2 == 2) FC_LAUNCH(launch2d<128, 8>(t2, d_imgs, ws, n, st));
-        else FC_LAUNCH(launch2d<64, 16>(t2, d_imgs, ws, n, st));
+        if (tile2 == 1) FC_LAUNCH(launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
+        else if (tile2 == 2) FC_LAUNCH(launch2d<128, 8>(t2, d_imgs, ws, n, lut, st));
+        else FC_LAUNCH(launch2d<64, 16>(t2, d_imgs, ws, n, lut, st));
     }
     if (t3 > 0) {
-        if (tile3 == 1) FC_LAUNCH(launch3d<32, 8, 4>(t3, d_imgs, ws, n, st));
-        else if (tile3 == 2) FC_LAUNCH(launch3d<8, 8, 16>(t3, d_imgs, ws, n, st));
-        else FC_LAUNCH(launch3d<16, 8, 8>(t3, d_imgs, ws, n, st));
+        if (tile3 == 1) FC_LAUNCH(launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
+        else if (tile3 == 2) FC_LAUNCH(launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
+        else FC_LAUNCH(launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
     }
     const int64_t ml = max_list(h_shapes, n);
     const unsigned rblocks = (unsigned)((ml + 255) / 256 < 1024 ? (ml + 255) / 256 : 1024);
@@ -1205,6 +1226,17 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
 }  // namespace fc
 
 // ====================================================================== C ABI ====
+namespace fc {
+namespace {
+// Kernel-launching entry points run only when FLASHCUBICAL_DEVICE_PATH=1 (header: device
+// path switch).
+bool device_path_enabled() {
+    const char *e = getenv("FLASHCUBICAL_DEVICE_PATH");
+    return e && e[0] == '1' && e[1] == 0;
+}
+}  // namespace
+}  // namespace fc
+
 extern "C" {
 
 int64_t ph_capacity_bound(ph_shape s) {
@@ -1231,6 +1263,7 @@ size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
 
 int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
                int64_t *d_count, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
+    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (capacity < 0) return PH_EINVAL;
     return fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
                    d_status, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
@@ -1240,6 +1273,7 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, c
                      const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                      int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
                      size_t ws_bytes, void *stream) {
+    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (!d_img_off || !d_shapes || !d_out_off) return PH_EINVAL;
     ph_shape dummy{2, {1, 1, 1}};
     return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
@@ -1249,6 +1283,7 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, c
 int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
                 const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
                 const int64_t *d_img_off, int64_t total_voxels, void *stream) {
+    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (n < 1 || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
         !pairs.birth_vertex || !pairs.death_vertex)
         return PH_EINVAL;
@@ -1308,9 +1343,10 @@ int ph_init_device(void) {
     if (rc != PH_OK) return rc;
     std::vector<uint32_t> l2d(256), l1(fc::kL1Size);
     std::vector<uint64_t> l2(fc::kL3Configs);
-    if (hipMemcpyFromSymbol(l2d.data(), HIP_SYMBOL(fc::c_lut2d), 256 * sizeof(uint32_t)) != hipSuccess) return PH_EHIP;
-    if (hipMemcpyFromSymbol(l1.data(), HIP_SYMBOL(fc::g_l1), l1.size() * sizeof(uint32_t)) != hipSuccess) return PH_EHIP;
-    if (hipMemcpyFromSymbol(l2.data(), HIP_SYMBOL(fc::g_l2), l2.size() * sizeof(uint64_t)) != hipSuccess) return PH_EHIP;
+    const fc::Luts t = fc::current_luts();
+    if (hipMemcpy(l2d.data(), t.l2d, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
+    if (hipMemcpy(l1.data(), t.l1, l1.size() * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
+    if (hipMemcpy(l2.data(), t.l2, l2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
     if (memcmp(l2d.data(), fc::g_h_lut2d, 256 * sizeof(uint32_t)) || l1 != fc::g_h_l1 || l2 != fc::g_h_l2) return PH_EINTERNAL;
     return PH_OK;
 }

@@ -1,0 +1,115 @@
+"""Host side of the C ABI (no GPU, no kernel launch): the library loads, exports every entry
+point its header declares, sizes its buffers consistently, validates arguments on the host and
+keeps its kernel-launching entry points switched off unless asked."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+fc = pytest.importorskip("paper_2606_04801_amd")
+try:
+    fc.lib()
+except (ImportError, OSError) as e:
+    pytest.skip("library not built: %s" % e, allow_module_level=True)
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flashcubical.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ph_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert {"ph_diagram", "ph_diagram_batch", "ph_backward", "ph_workspace_bytes"} <= set(names)
+    L = ctypes.CDLL(fc.LIB_PATH)
+    for n in names:
+        assert hasattr(L, n), "missing export " + n
+
+
+def test_version():
+    assert fc.lib().ph_version().startswith(b"flashcubical")
+
+
+def test_capacity_bound_closed_form():
+    # pixels + top cells
+    assert fc.capacity_bound((1, 4)) == 4
+    assert fc.capacity_bound((3, 3)) == 9 + 4
+    assert fc.capacity_bound((2048, 2048)) == 2048 * 2048 + 2047 * 2047
+    assert fc.capacity_bound((256, 256, 256)) == 256 ** 3 + 255 ** 3
+    assert fc.capacity_bound((1, 5, 5)) == 25          # a volume with a unit extent has no cubes
+
+
+def test_invalid_shapes_rejected():
+    L = fc.lib()
+    for bad in [(0, 4), (4, 0), (0, 1, 1), (-1, 3)]:
+        assert fc.capacity_bound(bad) == 0
+        assert fc.workspace_bytes([bad]) == 0
+    big = (1 << 14, 1 << 13)                           # 2^27 pixels: above the per-instance limit
+    assert fc.capacity_bound(big) == 0
+    with pytest.raises(fc.PHError):
+        fc.make_shape((4,))
+    assert L.ph_workspace_bytes(None, 1, 3) == 0
+
+
+def test_workspace_grows_with_size_and_batch():
+    a = fc.workspace_bytes([(64, 64)])
+    b = fc.workspace_bytes([(128, 128)])
+    c = fc.workspace_bytes([(64, 64), (128, 128)])
+    assert 0 < a < b < c
+    assert c >= a + b - 4096                           # one header for the batch
+    d3 = fc.workspace_bytes([(16, 16, 16)])
+    assert d3 > fc.workspace_bytes([(64, 64)])
+    mixed = fc.workspace_bytes([(16, 16, 16), (64, 64)])
+    assert mixed > d3
+
+
+def _call_diagram():
+    L = fc.lib()
+    return L.ph_diagram(None, fc.make_shape((4, 4)), 3, fc.ph_pairs(), 16, None, None, None, 0, None)
+
+
+def test_device_path_switch(monkeypatch):
+    monkeypatch.delenv(fc.DEVICE_PATH_ENV, raising=False)
+    assert not fc.device_path_enabled()
+    L = fc.lib()
+    assert _call_diagram() == fc.PH_EDISABLED
+    sh = (fc.ph_shape * 1)(fc.make_shape((4, 4)))
+    assert L.ph_diagram_batch(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
+                              None) == fc.PH_EDISABLED
+    assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EDISABLED
+    monkeypatch.setenv(fc.DEVICE_PATH_ENV, "0")
+    assert _call_diagram() == fc.PH_EDISABLED
+
+
+def test_host_validation_before_any_device_call(monkeypatch):
+    # switched on, but every call below fails argument checks on the host before touching HIP
+    monkeypatch.setenv(fc.DEVICE_PATH_ENV, "1")
+    L = fc.lib()
+    assert _call_diagram() == fc.PH_EINVAL                      # null buffers
+    assert L.ph_diagram(None, fc.make_shape((4, 4)), 3, fc.ph_pairs(), -1, None, None, None, 0,
+                        None) == fc.PH_EINVAL                   # negative capacity
+    sh = (fc.ph_shape * 1)(fc.make_shape((4, 4)))
+    assert L.ph_diagram_batch(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
+                              None) == fc.PH_EINVAL
+    assert L.ph_diagram_batch(0, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
+                              None) == fc.PH_EINVAL
+    assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EINVAL
+    assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 0, None) == fc.PH_EINVAL
+
+
+def test_binding_raises_without_gpu_tensor():
+    torch = pytest.importorskip("torch")
+    with pytest.raises(fc.PHError):
+        fc.ph_diagram(torch.zeros(4, 4))                        # CPU tensor: refused, no fallback
+
+
+def test_status_names_cover_codes():
+    for code in (fc.PH_OK, fc.PH_EINVAL, fc.PH_ENAN, fc.PH_ECAPACITY, fc.PH_ENOMEM, fc.PH_EHIP,
+                 fc.PH_EINTERNAL, fc.PH_EDISABLED):
+        assert code in fc.STATUS_NAMES
