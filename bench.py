@@ -1,0 +1,252 @@
+"""Benchmark: Mvoxels/s to H0 + H_top diagrams, batched forward + backward versus per-image
+plain calls, on one MI355X; prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--traffic-json F]
+
+Workload: 64 volumes 96^3 (random field, sigma 3, seeds 2000+i) and 64 images 512^2 (sigma 6,
+seeds 3000+i) in one batch; loss = sum over finite pairs of (death - birth)^2, so the backward
+scatters -2(d-b) to each birth pixel and +2(d-b) to each death pixel.  A step is one pass of
+the whole path over the batch: forward (ph_diagram_batch), loss gradient, backward
+(ph_backward).  The batched step is captured once in a HIP graph and replayed; the per-image
+form is a plain loop of ph_diagram + ph_backward calls per instance on one stream.  Both forms
+are compared bit for bit before any timing.
+
+roofline: the dominant kernel of the batched step (largest event-timed total over the timed
+profiled steps), its algorithmic bytes per launch divided by its mean launch duration, against
+8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, when a summary
+for this exact library build is given with --traffic-json, else null.
+
+cpu_baseline: the CPU oracle (single-threaded C) on a bounded sample of the same workload (one
+volume and one image, forward + reference gradient, about 30 s), in Mvoxels/s.  The GPU results
+of those two instances are also compared with the oracle's, bit for bit.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import synthetic as S  # noqa: E402
+
+METRIC = "Mvoxels/s to H0+H_top diagrams, batched fwd+bwd vs per-image, bit-exact"
+HBM_PEAK_GBS = 8000.0
+N3, N2 = 64, 64
+SHAPE3, SIG3, SHAPE2, SIG2 = (96, 96, 96), 3.0, (512, 512), 6.0
+
+
+def workload_shapes():
+    return [SHAPE3] * N3 + [SHAPE2] * N2
+
+
+def workload_desc():
+    return "64 x 96^3 field sigma 3 + 64 x 512^2 field sigma 6, H0+H_top, batched fwd+bwd"
+
+
+# instances the CPU baseline runs: (index in the batch, shape, sigma, seed)
+SAMPLE = [(0, SHAPE3, SIG3, 2000), (N3, SHAPE2, SIG2, 3000)]
+
+
+def cpu_baseline():
+    """Oracle (forward + reference gradient) on one volume and one image of the workload.
+
+    Returns the baseline record and {batch index: (pairs, gradient)} for the parity check."""
+    import oracle
+    vox, t = 0, 0.0
+    ref = {}
+    for idx, shape, sig, seed in SAMPLE:
+        img = S.grf(shape, sig, seed)
+        t0 = time.perf_counter()
+        p = oracle.diagram(img)
+        fin = p["death_cell"] >= 0
+        d = np.where(fin, p["death"] - p["birth"], 0).astype(np.float32)
+        g = oracle.gradient(p, -2 * d, 2 * d, img.shape)
+        t += time.perf_counter() - t0
+        vox += img.size
+        ref[idx] = (p, g)
+    rec = {"value": round(vox / t / 1e6, 5), "unit": "Mvoxels/s", "cores": 1, "kind": "oracle",
+           "sample": "one 96^3 volume (seed 2000) + one 512^2 image (seed 3000) of the workload, "
+                     "forward + gradient, single-threaded C, %.1f s" % t}
+    return rec, ref
+
+
+def algorithmic_bytes(name, counts, shapes):
+    """Bytes one launch of `name` must move over the whole batch (model stated in the design doc)."""
+    N = sum(int(np.prod(s)) for s in shapes)
+    T = sum(int(np.prod([e - 1 for e in s])) for s in shapes)
+    K, P = counts["keep"], counts["pairs"]
+    if name.startswith("k_classify"):
+        return 4 * N + 4 * N + 4 * T + 8 * K
+    if name.startswith("k_sort"):
+        return 16 * K
+    if name.startswith("k_resolve") or name.startswith("k_uf"):
+        return 16 * K
+    if name == "k_output":
+        return 8 * K + 32 * P
+    if name == "k_zero":
+        return 4 * N
+    if name == "k_scatter":
+        return 32 * P
+    return 0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only (the batch would shard by instance "
+              "across GPUs; no multi-GPU path is built)", file=sys.stderr)
+        sys.exit(2)
+
+    shapes = workload_shapes()
+    nvox = sum(int(np.prod(s)) for s in shapes)
+    line = {"metric": METRIC, "value": None, "unit": "Mvoxels/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": workload_desc(), "instances": len(shapes), "voxels": nvox}}
+
+    import paper_2606_04801_amd as fc
+    fc.lib()
+    import torch
+    ref = {}
+    if not args.no_cpu_baseline:
+        print("bench: cpu baseline (oracle, about 30 s)", file=sys.stderr, flush=True)
+        line["cpu_baseline"], ref = cpu_baseline()
+    gpu = torch.cuda.is_available()
+    if not gpu or not fc.device_path_enabled():
+        line["status"] = ("no GPU" if not gpu else
+                          "device path switched off (its first launches faulted the GPU and no cause "
+                          "has been shown); set %s=1 to measure" % fc.DEVICE_PATH_ENV)
+    else:
+        line.update(run_gpu(fc, torch, shapes, args, ref))
+    print(json.dumps(line), flush=True)
+
+
+def same_bits(a, b):
+    return len(a) == len(b) and all(np.array_equal(np.asarray(a[f]).view(np.uint8), np.asarray(b[f]).view(np.uint8))
+                                    for f in a.dtype.names)
+
+
+def run_gpu(fc, torch, shapes, args, ref):
+    dev = torch.device("cuda:0")
+    print("bench: generating %d instances" % len(shapes), file=sys.stderr, flush=True)
+    imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
+    rc = fc.lib().ph_init_device()
+    if rc != fc.PH_OK:
+        raise fc.PHError(rc, "ph_init_device")
+    bt = fc.Batch(shapes, device=dev)
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+
+    def batched_step():
+        bt.ph_diagram_batch()
+        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+        bt.ph_backward(-2.0 * diff, 2.0 * diff)
+
+    # per-image plain calls: buffers made once, calls in a loop on the current stream
+    singles = []
+    for i, a in enumerate(imgs):
+        t = bt.image(i)
+        cap = fc.capacity_bound(a.shape)
+        singles.append(dict(img=t, bufs=fc.PairBuffers(cap, dev), ws=fc.Workspace(),
+                            grad=torch.empty(a.shape, dtype=torch.float32, device=dev),
+                            counts=torch.zeros(1, dtype=torch.int64, device=dev),
+                            off=torch.tensor([0, cap], dtype=torch.int64, device=dev),
+                            ioff=torch.zeros(1, dtype=torch.int64, device=dev)))
+
+    def per_image_step():
+        for s in singles:
+            d = fc.ph_diagram(s["img"], capacity=s["bufs"].cap, ws=s["ws"])
+            s["bufs"], s["diag"] = d.bufs, d
+            n = s["bufs"].cap
+            idx = torch.arange(n, device=dev)
+            fin = (idx < d.count_t) & (d.bufs.death_cell >= 0)
+            diff = torch.where(fin, d.bufs.death - d.bufs.birth, 0.0)
+            fc.ph_backward(d.bufs, d.count_t, s["off"], s["ioff"], -2.0 * diff, 2.0 * diff, s["grad"])
+
+    # parity: batched and per-image results must agree bit for bit
+    print("bench: parity", file=sys.stderr, flush=True)
+    batched_step()
+    per_image_step()
+    torch.cuda.synchronize()
+    bt.check()
+    res = bt.results()
+    for i, s in enumerate(singles):
+        if not same_bits(res[i], s["diag"].numpy()):
+            raise SystemExit("bench: batched and per-image diagrams differ on instance %d" % i)
+        g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]]
+        if not torch.allclose(g1, s["grad"].reshape(-1), rtol=1e-6, atol=1e-7):
+            raise SystemExit("bench: batched and per-image gradients differ on instance %d" % i)
+    for i, (p, g) in ref.items():                       # the oracle's own runs of two instances
+        if not same_bits(res[i], p):
+            raise SystemExit("bench: instance %d differs from the oracle" % i)
+        g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]].cpu().numpy()
+        if not np.allclose(g1, g.reshape(-1), rtol=1e-6, atol=1e-7):
+            raise SystemExit("bench: gradient of instance %d differs from the oracle" % i)
+
+    # batched form: one graph per step, replayed
+    for _ in range(args.warmup):
+        batched_step()
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batched_step()
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+
+    for _ in range(args.warmup):
+        per_image_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        per_image_step()
+    torch.cuda.synchronize()
+    t_p = (time.perf_counter() - t0) / args.steps
+
+    # per-kernel event timing of the batched step (eager, same launches as the graph)
+    fc.profile(True)
+    for _ in range(args.steps):
+        batched_step()
+    torch.cuda.synchronize()
+    prof = fc.profile_read()
+    fc.profile(False)
+    cnt = bt.counts.cpu().numpy()
+    counts = {"pairs": int(cnt.sum()), "keep": int(cnt.sum())}
+    name, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
+    mean_s = total_ms / launches / 1e3
+    algo = algorithmic_bytes(name, counts, shapes)
+    achieved = algo / mean_s / 1e9 if mean_s > 0 else 0.0
+    traffic = None
+    if args.traffic_json and os.path.exists(args.traffic_json):
+        traffic = json.load(open(args.traffic_json)).get(name)
+    nvox = sum(int(np.prod(s)) for s in shapes)
+    return {
+        "value": round(nvox / t_b / 1e6, 3),
+        "ms_per_step": round(t_b * 1e3, 4),
+        "per_image": {"value": round(nvox / t_p / 1e6, 3), "ms_per_step": round(t_p * 1e3, 4)},
+        "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},
+        "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
+    }
+
+
+if __name__ == "__main__":
+    main()

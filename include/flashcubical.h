@@ -178,6 +178,20 @@ int ph_init_device(void);
  * fits, PH_EHIP otherwise.  Launches nothing. */
 int ph_device_report(char *buf, size_t len);
 
+/* Per-kernel timing.  ph_profile(1) clears earlier records and makes every following launch
+ * of this library record a pair of HIP events around it on its stream; ph_profile(0) stops
+ * recording.  Not for use while a stream is being captured into a graph.
+ * ph_profile_read waits for the recorded events, writes up to max per-kernel totals (kernels in
+ * launch-pipeline order, only those launched), sets *count to the number of kernels seen, and
+ * clears the records.  Returns PH_OK, PH_EINVAL or PH_EHIP. */
+typedef struct {
+    char name[32];
+    int32_t launches;
+    double total_ms;
+} ph_kernel_time;
+int ph_profile(int32_t enable);
+int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count);
+
 /* Library version string. */
 const char *ph_version(void);
 

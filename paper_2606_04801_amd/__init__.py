@@ -60,6 +60,10 @@ class ph_tuning(ctypes.Structure):
     _fields_ = [("tile2d", ctypes.c_int32), ("tile3d", ctypes.c_int32)]
 
 
+class ph_kernel_time(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int32), ("total_ms", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -90,6 +94,10 @@ def lib():
         L.ph_init_device.restype = ctypes.c_int
         L.ph_device_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.ph_device_report.restype = ctypes.c_int
+        L.ph_profile.argtypes = [i32]
+        L.ph_profile.restype = ctypes.c_int
+        L.ph_profile_read.argtypes = [ctypes.POINTER(ph_kernel_time), i32, ctypes.POINTER(i32)]
+        L.ph_profile_read.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -128,6 +136,22 @@ def device_report():
 
 def lut_config_count(ndim: int) -> int:
     return int(lib().ph_lut_config_count(ndim))
+
+
+def profile(enable: bool) -> None:
+    """Start (clearing earlier records) or stop per-launch event timing (C ABI ph_profile)."""
+    lib().ph_profile(1 if enable else 0)
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} of the launches recorded since profile(True)."""
+    buf = (ph_kernel_time * 32)()
+    cnt = ctypes.c_int32(0)
+    rc = lib().ph_profile_read(buf, 32, ctypes.byref(cnt))
+    if rc != PH_OK:
+        raise PHError(rc, "ph_profile_read")
+    return {buf[k].name.decode(): (int(buf[k].launches), float(buf[k].total_ms))
+            for k in range(min(cnt.value, 32))}
 
 
 # ------------------------------------------------------------------- device side --

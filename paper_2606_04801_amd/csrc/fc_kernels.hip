@@ -1161,6 +1161,44 @@ Luts current_luts() {
     return g_dev_lut[dev];
 }
 
+// ------------------------------------------------------------------- profiling --
+// Optional per-launch timing with HIP events on the launch stream (not for use while the
+// stream is being captured into a graph).
+enum KernelId {
+    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT_EDGES, K_SORT_FACETS, K_SORT_NODES, K_RESOLVE_EDGES,
+    K_UF_H0, K_RESOLVE_FACETS, K_UF_TOP, K_OUTPUT, K_ZERO, K_SCATTER, K_COUNT
+};
+const char *const kKernelNames[K_COUNT] = {
+    "k_plan", "k_classify2d", "k_classify3d", "k_sort(edges)", "k_sort(facets)", "k_sort(nodes)",
+    "k_resolve_edges", "k_uf(h0)", "k_resolve_facets", "k_uf(top)", "k_output", "k_zero", "k_scatter"};
+
+struct ProfRec { int kid; hipEvent_t a, b; };
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+
+hipEvent_t prof_mark(hipStream_t st) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventRecord(e, st) != hipSuccess) { (void)hipEventDestroy(e); return nullptr; }
+    return e;
+}
+
+void prof_push(int kid, hipEvent_t a, hipEvent_t b) {
+    if (!a || !b) {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    g_prof.push_back(ProfRec{kid, a, b});
+}
+
+bool prof_enabled() {
+    std::lock_guard<std::mutex> lk(g_prof_mu);
+    return g_prof_on;
+}
+
 int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
         const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
         const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
@@ -1187,37 +1225,43 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
 
     // Each launch is checked on its own: the error a failed launch leaves behind would be
     // overwritten by the next successful call.
-#define FC_LAUNCH(...)                                            \
-    do {                                                          \
-        (void)hipGetLastError();                                  \
-        __VA_ARGS__;                                              \
-        if (hipGetLastError() != hipSuccess) return PH_EHIP;      \
+    const bool prof = prof_enabled();
+#define FC_LAUNCH(KID, ...)                                                   \
+    do {                                                                      \
+        hipEvent_t ev_a = prof ? prof_mark(st) : nullptr;                     \
+        (void)hipGetLastError();                                              \
+        __VA_ARGS__;                                                          \
+        if (hipGetLastError() != hipSuccess) {                                \
+            if (ev_a) (void)hipEventDestroy(ev_a);                            \
+            return PH_EHIP;                                                   \
+        }                                                                     \
+        if (prof) prof_push(KID, ev_a, prof_mark(st));                        \
     } while (0)
-    FC_LAUNCH(hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
+    FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
     const Luts lut = current_luts();
     if (t2 > 0) {
-        if (tile2 == 1) FC_LAUNCH(launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
-        else if (tile2 == 2) FC_LAUNCH(launch2d<128, 8>(t2, d_imgs, ws, n, lut, st));
-        else FC_LAUNCH(launch2d<64, 16>(t2, d_imgs, ws, n, lut, st));
+        if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
+        else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, d_imgs, ws, n, lut, st));
+        else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, d_imgs, ws, n, lut, st));
     }
     if (t3 > 0) {
-        if (tile3 == 1) FC_LAUNCH(launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
-        else if (tile3 == 2) FC_LAUNCH(launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
-        else FC_LAUNCH(launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
+        if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
+        else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
+        else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
     }
     const int64_t ml = max_list(h_shapes, n);
     const unsigned rblocks = (unsigned)((ml + 255) / 256 < 1024 ? (ml + 255) / 256 : 1024);
-    FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 0));
-    if (any3) FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 1));
-    FC_LAUNCH(hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
-    FC_LAUNCH(hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
+    FC_LAUNCH(K_SORT_EDGES, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 0));
+    if (any3) FC_LAUNCH(K_SORT_FACETS, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 1));
+    FC_LAUNCH(K_RESOLVE_EDGES, hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
+    FC_LAUNCH(K_UF_H0, hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     if (flags & PH_HTOP) {
-        FC_LAUNCH(hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
-        FC_LAUNCH(hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
+        FC_LAUNCH(K_RESOLVE_FACETS, hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
+        FC_LAUNCH(K_UF_TOP, hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
-    FC_LAUNCH(hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 2));
-    FC_LAUNCH(hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
+    FC_LAUNCH(K_SORT_NODES, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 2));
+    FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
                                  d_status));
     return PH_OK;
 }
@@ -1292,13 +1336,22 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
     int rc = fc::device_luts();
     if (rc != PH_OK) return rc;
     const int64_t zb = (total_voxels + 255) / 256;
+    const bool prof = fc::prof_enabled();
+    hipEvent_t z0 = prof ? fc::prof_mark(st) : nullptr;
     (void)hipGetLastError();
     hipLaunchKernelGGL(fc::k_zero, dim3((unsigned)(zb < 8192 ? zb : 8192)), dim3(256), 0, st, d_grad_img,
                        total_voxels);
-    if (hipGetLastError() != hipSuccess) return PH_EHIP;
+    if (hipGetLastError() != hipSuccess) {
+        if (z0) (void)hipEventDestroy(z0);
+        return PH_EHIP;
+    }
+    if (prof) fc::prof_push(fc::K_ZERO, z0, fc::prof_mark(st));
+    hipEvent_t s0 = prof ? fc::prof_mark(st) : nullptr;
     hipLaunchKernelGGL(fc::k_scatter, dim3(64, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
                        d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
-    return hipGetLastError() == hipSuccess ? PH_OK : PH_EHIP;
+    const bool ok = hipGetLastError() == hipSuccess;
+    if (prof) fc::prof_push(fc::K_SCATTER, s0, ok ? fc::prof_mark(st) : nullptr);
+    return ok ? PH_OK : PH_EHIP;
 }
 
 int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry) {
@@ -1327,6 +1380,49 @@ int32_t ph_lut_config_count(int32_t ndim) {
 }
 
 const char *ph_version(void) { return "flashcubical-gfx950 0.1"; }
+
+int ph_profile(int32_t enable) {
+    std::vector<fc::ProfRec> old;
+    {
+        std::lock_guard<std::mutex> lk(fc::g_prof_mu);
+        if (enable) old.swap(fc::g_prof);
+        fc::g_prof_on = enable != 0;
+    }
+    for (auto &r : old) { (void)hipEventDestroy(r.a); (void)hipEventDestroy(r.b); }
+    return PH_OK;
+}
+
+int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count) {
+    if (!count || max < 0 || (max > 0 && !out)) return PH_EINVAL;
+    std::vector<fc::ProfRec> recs;
+    {
+        std::lock_guard<std::mutex> lk(fc::g_prof_mu);
+        recs.swap(fc::g_prof);
+    }
+    double ms[fc::K_COUNT] = {0};
+    int32_t nl[fc::K_COUNT] = {0};
+    int rc = PH_OK;
+    for (auto &r : recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) rc = PH_EHIP;
+        else { ms[r.kid] += t; nl[r.kid] += 1; }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    int32_t k = 0;
+    for (int i = 0; i < fc::K_COUNT; ++i) {
+        if (nl[i] == 0) continue;
+        if (k < max) {
+            memset(&out[k], 0, sizeof out[k]);
+            snprintf(out[k].name, sizeof out[k].name, "%s", fc::kKernelNames[i]);
+            out[k].launches = nl[i];
+            out[k].total_ms = ms[i];
+        }
+        ++k;
+    }
+    *count = k;
+    return rc;
+}
 
 /* Upload the lookup tables to the current device (normally done on first use) and read
  * them back; returns PH_OK when the device copy equals the host tables. */
