@@ -37,7 +37,7 @@
  *     loop ran out of iterations).
  *   - Calls that share a workspace must not overlap in time.
  *   - Device path switch: the entry points that launch kernels (ph_diagram,
- *     ph_diagram_batch, ph_backward) return PH_EDISABLED unless the environment variable
+ *     ph_diagram_batch, ph_autotune, ph_backward) return PH_EDISABLED unless the environment variable
  *     FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of
  *     this path ended in a GPU memory fault whose cause has not been found: the kernels are
  *     memory-safe under CPU emulation with sanitizers, so nothing is launched by default
@@ -85,7 +85,8 @@ typedef struct {
     int32_t *death_vertex;  /* same for the death cell; -1 if essential */
 } ph_pairs;
 
-/* Optional launch tuning; NULL picks defaults (or the autotuned choice for a batch).
+/* Optional launch tuning; NULL picks the autotuned choice for the batch's size class (see
+ * ph_autotune), else the defaults.
  * The choice never changes results, only speed. */
 typedef struct {
     int32_t tile2d;     /* 0: 64x16, 1: 32x32, 2: 128x8 vertices per workgroup */
@@ -125,6 +126,18 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off,
                      ph_pairs out, const int64_t *d_out_off, int64_t *d_counts,
                      int32_t *d_status, const ph_tuning *tuning, void *d_ws, size_t ws_bytes,
                      void *stream);
+
+/* Autotuner (not part of the paper): runs the batch once per candidate tile choice (the 2D
+ * choices if the batch holds images, the 3D ones if it holds volumes), one warm-up and `reps`
+ * timed runs each, writes the fastest to *best and remembers it for the batch's size class
+ * (which dimensions it holds and the binary order of magnitude of its mean instance size):
+ * later ph_diagram_batch calls with tuning == NULL in that class use it.  Arguments as for
+ * ph_diagram_batch; the outputs hold the last run's results.  Waits for the stream (not for
+ * use during graph capture).  Tile choices never change results, only speed. */
+int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+                const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
+                int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
+                ph_tuning *best, void *stream);
 
 /* Gradient of pair values with respect to the pixels (not part of the paper): for every
  * stored pair j of instance i, d_grad_birth[j] is added to the birth pixel and, if the death

@@ -84,6 +84,9 @@ def lib():
         L.ph_diagram_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp,
                                        ctypes.POINTER(ph_tuning), vp, ctypes.c_size_t, vp]
         L.ph_diagram_batch.restype = ctypes.c_int
+        L.ph_autotune.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp, vp,
+                                  ctypes.c_size_t, i32, ctypes.POINTER(ph_tuning), vp]
+        L.ph_autotune.restype = ctypes.c_int
         L.ph_backward.argtypes = [i32, ph_pairs, vp, vp, vp, vp, vp, vp, i64, vp]
         L.ph_backward.restype = ctypes.c_int
         L.ph_lut_entry.argtypes = [i32, u32, ctypes.POINTER(ctypes.c_uint64)]
@@ -313,6 +316,18 @@ class Batch:
                                     _stream_ptr(stream))
         if rc != PH_OK:
             raise PHError(rc, "ph_diagram_batch")
+
+    def ph_autotune(self, reps: int = 3, stream=None):
+        """Time every tile choice on this batch and keep the fastest (C ABI ph_autotune); later
+        ph_diagram_batch calls of this size class use it.  Synchronises the stream."""
+        best = ph_tuning(0, 0)
+        rc = lib().ph_autotune(self.n, _ptr(self.images), _ptr(self.img_off), _ptr(self.d_shapes),
+                               self.h_shapes, self.flags, self.pairs.c(), _ptr(self.out_off),
+                               _ptr(self.counts), _ptr(self.status), _ptr(self.ws), self.ws_bytes,
+                               int(reps), ctypes.byref(best), _stream_ptr(stream))
+        if rc != PH_OK:
+            raise PHError(rc, "ph_autotune")
+        return (int(best.tile2d), int(best.tile3d))
 
     def ph_backward(self, grad_birth, grad_death, stream=None):
         ph_backward(self.pairs, self.counts, self.out_off, self.img_off, grad_birth, grad_death, self.grad,

@@ -141,12 +141,22 @@ enum { CNT_E = 0, CNT_F, CNT_M0, CNT_MT, CNT_ERR, CNT_ROUNDS0, CNT_ROUNDST, CNT_
 
 FC_HD int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+// Unused bytes left after every workspace array (0 in the library; the CPU emulation build of
+// the tests sets it so that a run past the end of an array lands in poisoned memory).
+#ifndef FC_ARRAY_GAP
+#define FC_ARRAY_GAP 0
+#endif
+
 // Fill the array offsets of one instance starting at byte `at`; returns the end offset.
 FC_HD int64_t layout(Inst &I, int64_t at) {
     const int64_t N = I.N, T = I.T, E = I.E, F = I.F, FAC = I.FAC;
     const int64_t L = (E > F ? E : F) > 0 ? (E > F ? E : F) : 1;
     int64_t SCR = L > N ? L : N;
-    auto take = [&](int64_t bytes) { int64_t o = at; at = align256(at + (bytes > 0 ? bytes : 1)); return o; };
+    auto take = [&](int64_t bytes) {
+        int64_t o = at;
+        at = align256(at + (bytes > 0 ? bytes : 1) + FC_ARRAY_GAP);
+        return o;
+    };
     I.o_par0 = take(4 * N);
     I.o_parT = take(4 * T);
     I.o_keyE = take(8 * E);

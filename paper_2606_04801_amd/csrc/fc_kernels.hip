@@ -21,7 +21,9 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "../../include/flashcubical.h"
@@ -1161,6 +1163,37 @@ Luts current_luts() {
     return g_dev_lut[dev];
 }
 
+// ------------------------------------------------------------------ autotuning --
+// Tile choices found fastest by ph_autotune, per size class of a batch: which dimensions it
+// holds and the binary order of magnitude of its mean instance size.  A batch call without an
+// explicit tuning uses the entry of its class, else the defaults.  Tiles never change results.
+using SizeClass = std::tuple<int, int, int>;
+std::mutex g_tune_mu;
+std::map<SizeClass, ph_tuning> g_tune;
+
+SizeClass size_class(const ph_shape *h, int n) {
+    int has2 = 0, has3 = 0;
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        int64_t v = 1;
+        for (int k = 0; k < h[i].ndim; ++k) v *= h[i].ext[k];
+        total += v;
+        (h[i].ndim == 2 ? has2 : has3) = 1;
+    }
+    int64_t mean = total / (n > 0 ? n : 1);
+    int bucket = 0;
+    while (mean > 1) { mean >>= 1; ++bucket; }
+    return SizeClass{has2, has3, bucket};
+}
+
+bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(size_class(h, n));
+    if (it == g_tune.end()) return false;
+    *t = it->second;
+    return true;
+}
+
 // ------------------------------------------------------------------- profiling --
 // Optional per-launch timing with HIP events on the launch stream (not for use while the
 // stream is being captured into a graph).
@@ -1318,10 +1351,51 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, c
                      int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
                      size_t ws_bytes, void *stream) {
     if (!fc::device_path_enabled()) return PH_EDISABLED;
-    if (!d_img_off || !d_shapes || !d_out_off) return PH_EINVAL;
+    if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1) return PH_EINVAL;
     ph_shape dummy{2, {1, 1, 1}};
+    ph_tuning tuned;
+    if (!tuning && fc::tuned_for(h_shapes, n, &tuned)) tuning = &tuned;
     return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
                    d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+                const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
+                int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
+                ph_tuning *best, void *stream) {
+    if (!fc::device_path_enabled()) return PH_EDISABLED;
+    if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1 || reps < 1 || !best) return PH_EINVAL;
+    const fc::SizeClass cls = fc::size_class(h_shapes, n);
+    const int n2 = std::get<0>(cls) ? 3 : 1, n3 = std::get<1>(cls) ? 3 : 1;
+    hipStream_t st = (hipStream_t)stream;
+    ph_shape dummy{2, {1, 1, 1}};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess) return PH_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return PH_EHIP; }
+    float best_ms = -1.f;
+    int rc = PH_OK;
+    for (int a = 0; a < n2 && rc == PH_OK; ++a)
+        for (int b = 0; b < n3 && rc == PH_OK; ++b) {
+            const ph_tuning t{a, b};
+            rc = fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
+                         d_status, &t, d_ws, ws_bytes, st);              // warm-up
+            if (rc != PH_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = PH_EHIP; break; }
+            for (int r = 0; r < reps && rc == PH_OK; ++r)
+                rc = fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0,
+                             d_counts, d_status, &t, d_ws, ws_bytes, st);
+            if (rc != PH_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = PH_EHIP; break; }
+            if (best_ms < 0.f || ms < best_ms) { best_ms = ms; *best = t; }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != PH_OK) return rc;
+    std::lock_guard<std::mutex> lk(fc::g_tune_mu);
+    fc::g_tune[cls] = *best;
+    return PH_OK;
 }
 
 int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,

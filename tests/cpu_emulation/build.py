@@ -1,0 +1,64 @@
+"""Build the CPU emulation of the library's kernels (test infrastructure, never shipped).
+
+The kernels of paper_2606_04801_amd/csrc are compiled as host C++ against the emulated HIP
+runtime in this folder and linked with driver.cpp.  Variants:
+  asan   g++, AddressSanitizer + UBSan (fatal), a redzone around every LDS array
+  poison g++ -O2, LDS refilled with a poison byte before every block
+  msan   clang++, MemorySanitizer (LDS, workspace and outputs start uninitialised)
+Every build leaves 256 unused bytes after each workspace array (FC_ARRAY_GAP), which the driver
+poisons.  Executables go to tests/cpu_emulation/_build/ and are rebuilt when a source changes.
+"""
+from __future__ import annotations
+
+import hashlib
+import os
+import shutil
+import subprocess
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+CSRC = os.path.join(ROOT, "paper_2606_04801_amd", "csrc")
+INC = os.path.join(ROOT, "include")
+OUT = os.path.join(HERE, "_build")
+SOURCES = [os.path.join(CSRC, "fc_kernels.hip"), os.path.join(CSRC, "fc_lut.cpp"), os.path.join(HERE, "driver.cpp")]
+DEPS = SOURCES + [os.path.join(CSRC, "fc_common.h"), os.path.join(INC, "flashcubical.h"),
+                  os.path.join(HERE, "hip", "hip_runtime.h")]
+
+COMMON = ["-std=c++20", "-D__HIPCC__", "-DFC_ARRAY_GAP=256", "-I", HERE, "-I", INC, "-I", CSRC, "-pthread"]
+VARIANTS = {
+    "asan": ("g++", ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                     "-fno-sanitize-recover=undefined", "-DEMU_LDS_REDZONE"]),
+    "poison": ("g++", ["-O2"]),
+    "msan": ("/opt/rocm/llvm/bin/clang++", ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=memory",
+                                            "-fsanitize-memory-track-origins=2"]),
+}
+
+
+def build(variant: str = "asan") -> str:
+    cxx, flags = VARIANTS[variant]
+    if not (os.path.exists(cxx) or shutil.which(cxx)):
+        raise RuntimeError("compiler %s not found" % cxx)
+    h = hashlib.sha256((cxx + " ".join(flags)).encode())
+    for p in DEPS:
+        h.update(open(p, "rb").read())
+    os.makedirs(OUT, exist_ok=True)
+    exe = os.path.join(OUT, "driver_" + variant)
+    stamp = exe + ".sha256"
+    if os.path.exists(exe) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
+        return exe
+    srcs = []
+    for s in SOURCES:
+        srcs += ["-x", "c++", s]
+    cmd = [cxx] + COMMON + flags + srcs + ["-o", exe + ".tmp"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("emulation build failed:\n" + r.stderr[-4000:])
+    os.replace(exe + ".tmp", exe)
+    open(stamp, "w").write(h.hexdigest())
+    return exe
+
+
+if __name__ == "__main__":
+    import sys
+    for v in (sys.argv[1:] or ["asan"]):
+        print(build(v))

@@ -1,0 +1,240 @@
+// Runs the library's kernels on the CPU (through the emulated HIP runtime) for the test suite.
+//
+//   driver in.bin out.bin
+//
+// in.bin (little-endian): int32 n, uint32 flags, int32 mode (0: ph_diagram, n must be 1;
+// 1: ph_diagram_batch; 2: ph_autotune then ph_diagram_batch), int32 tile2d, int32 tile3d
+// (-1: no tuning argument), int32 backward (1: also run ph_backward for the loss
+// sum over finite pairs of (death - birth)^2); then n x (int32 ndim, int32 ext[3]); then the
+// pixels of all instances, float32, concatenated.
+// out.bin: per instance int64 count, int32 status, then the stored pairs as int32 dim,
+// float32 birth, float32 death, int64 birth_cell, int64 death_cell, int32 birth_vertex,
+// int32 death_vertex; then, with backward, the float32 gradient of all pixels.
+//
+// Under AddressSanitizer the workspace gaps between the per-instance arrays (and the unused
+// tail) are poisoned as soon as the plan kernel has written the instance table, so a kernel
+// that runs past the end of one of its arrays is reported even when it stays inside the
+// workspace allocation.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <vector>
+
+#include "flashcubical.h"
+#include "fc_common.h"
+
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define EMU_ASAN 1
+#endif
+#if __has_feature(memory_sanitizer)
+#include <sanitizer/msan_interface.h>
+#define EMU_MSAN_DRIVER 1
+#endif
+#endif
+#ifdef __SANITIZE_ADDRESS__
+#define EMU_ASAN 1
+#endif
+#ifdef EMU_ASAN
+#include <sanitizer/asan_interface.h>
+#endif
+
+dim3 threadIdx, blockIdx, blockDim, gridDim;
+EmuBlock *emu_block = nullptr;
+void (*emu_after_launch)(const void *) = nullptr;
+
+// Fiber switch (x86-64 System V): push the callee-saved registers, save the stack pointer to
+// *save_sp, load next_sp, pop the same registers and return into the other fiber.
+asm(R"(
+    .text
+    .globl emu_ctx_switch
+    .type emu_ctx_switch, @function
+emu_ctx_switch:
+    pushq %rbp
+    pushq %rbx
+    pushq %r12
+    pushq %r13
+    pushq %r14
+    pushq %r15
+    movq %rsp, (%rdi)
+    movq %rsi, %rsp
+    popq %r15
+    popq %r14
+    popq %r13
+    popq %r12
+    popq %rbx
+    popq %rbp
+    ret
+    .size emu_ctx_switch, .-emu_ctx_switch
+)");
+
+namespace {
+
+uint8_t *g_ws = nullptr;
+size_t g_wsb = 0;
+int g_n = 0;
+bool g_guarded = false;
+
+int64_t a256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+void poison(int64_t from, int64_t to) {
+#ifdef EMU_ASAN
+    if (to > from) __asan_poison_memory_region(g_ws + from, (size_t)(to - from));
+#else
+    (void)from;
+    (void)to;
+#endif
+}
+
+// layout of the workspace header and arrays, restated from the header comments of fc_common.h
+void guard_workspace(const void *) {
+    if (g_guarded) return;                        // the first launch of a call is the plan kernel
+    g_guarded = true;
+    const int n = g_n;
+    const int64_t tb2 = a256((int64_t)n * (int64_t)sizeof(fc::Inst));
+    const int64_t tb3 = tb2 + a256((int64_t)(n + 1) * 8), cn = tb3 + a256((int64_t)(n + 1) * 8);
+    const int64_t hdr = cn + a256((int64_t)n * fc::CNT_WORDS * 4);
+    poison((int64_t)n * (int64_t)sizeof(fc::Inst), tb2);
+    poison(tb2 + (int64_t)(n + 1) * 8, tb3);
+    poison(tb3 + (int64_t)(n + 1) * 8, cn);
+    poison(cn + (int64_t)n * fc::CNT_WORDS * 4, hdr);
+    int64_t expect = hdr;
+    for (int i = 0; i < n; ++i) {
+        const fc::Inst &I = ((const fc::Inst *)g_ws)[i];
+        const int64_t N = I.N, T = I.T, E = I.E, F = I.F, FAC = I.FAC;
+        const int64_t L = (E > F ? E : F) > 0 ? (E > F ? E : F) : 1, SCR = L > N ? L : N;
+        const int64_t a[][2] = {{I.o_par0, 4 * N}, {I.o_parT, 4 * T}, {I.o_keyE, 8 * E}, {I.o_ea, 4 * E},
+                                {I.o_eb, 4 * E}, {I.o_neg0, 4 * E}, {I.o_keyF, 8 * F}, {I.o_fa, 4 * FAC},
+                                {I.o_fb, 4 * FAC}, {I.o_killer, 4 * FAC}, {I.o_n0key, 8 * N},
+                                {I.o_n0sorted, 8 * N}, {I.o_nTkey, 8 * (T + 1)}, {I.o_uf0, 4 * N},
+                                {I.o_moe0, 4 * N}, {I.o_death0, 4 * N}, {I.o_ufT, 4 * (T + 1)},
+                                {I.o_moeT, 4 * (T + 1)}, {I.o_live, 4 * L}, {I.o_live2, 4 * L},
+                                {I.o_ra, 4 * L}, {I.o_rb, 4 * L}, {I.o_scratch, 8 * SCR}};
+        const int na = (int)(sizeof a / sizeof a[0]);
+        if (a[0][0] != expect) { fprintf(stderr, "driver: unexpected workspace layout\n"); abort(); }
+        for (int k = 0; k < na; ++k) {
+            const int64_t next = k + 1 < na ? a[k + 1][0] : I.end;
+            poison(a[k][0] + a[k][1], next);
+        }
+        expect = I.end;
+    }
+    poison(expect, (int64_t)g_wsb);
+}
+
+void unguard() {
+#ifdef EMU_ASAN
+    __asan_unpoison_memory_region(g_ws, g_wsb);
+#endif
+    g_guarded = false;
+}
+
+template <typename T> void uninit(std::vector<T> &v) {
+#ifdef EMU_MSAN_DRIVER
+    __msan_poison(v.data(), v.size() * sizeof(T));
+#else
+    (void)v;
+#endif
+}
+
+}  // namespace
+
+int main(int argc, char **argv) {
+    if (argc != 3) { fprintf(stderr, "usage: driver in.bin out.bin\n"); return 2; }
+    FILE *f = fopen(argv[1], "rb");
+    if (!f) return 2;
+    int32_t hdr[6];
+    if (fread(hdr, 4, 6, f) != 6) return 2;
+    const int n = hdr[0], mode = hdr[2], backward = hdr[5];
+    const uint32_t flags = (uint32_t)hdr[1];
+    std::vector<ph_shape> shapes(n);
+    std::vector<int64_t> img_off(n + 1, 0), out_off(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        int32_t s[4];
+        if (fread(s, 4, 4, f) != 4) return 2;
+        shapes[i].ndim = s[0];
+        int64_t nv = 1;
+        for (int k = 0; k < 3; ++k) {
+            shapes[i].ext[k] = s[1 + k];
+            if (k < s[0]) nv *= s[1 + k];
+        }
+        img_off[i + 1] = img_off[i] + nv;
+        out_off[i + 1] = out_off[i] + ph_capacity_bound(shapes[i]);
+    }
+    std::vector<float> img(img_off[n]);
+    if (fread(img.data(), 4, img.size(), f) != img.size()) return 2;
+    fclose(f);
+
+    const int64_t cap = out_off[n];
+    g_wsb = ph_workspace_bytes(shapes.data(), n, flags);
+    std::vector<uint8_t> ws(g_wsb);
+    for (size_t k = 0; k < ws.size(); ++k) ws[k] = (uint8_t)(k * 2654435761u >> 13);   // garbage
+    uninit(ws);
+    g_ws = ws.data();
+    g_n = n;
+    std::vector<int8_t> dim(cap);
+    std::vector<float> birth(cap), death(cap);
+    std::vector<int64_t> bcell(cap), dcell(cap), counts(n);
+    std::vector<int32_t> bvert(cap), dvert(cap), status(n);
+    uninit(dim); uninit(birth); uninit(death); uninit(bcell); uninit(dcell); uninit(bvert); uninit(dvert);
+    uninit(counts); uninit(status);
+    ph_pairs out{dim.data(), birth.data(), death.data(), bcell.data(), dcell.data(), bvert.data(), dvert.data()};
+    ph_tuning tune{hdr[3], hdr[4]};
+    const ph_tuning *tp = hdr[3] >= 0 ? &tune : nullptr;
+    emu_after_launch = guard_workspace;
+    int rc;
+    if (mode == 0) {
+        if (n != 1) return 2;
+        rc = ph_diagram(img.data(), shapes[0], flags, out, cap, counts.data(), status.data(), ws.data(), g_wsb,
+                        nullptr);
+    } else {
+        if (mode == 2) {
+            ph_tuning best{0, 0};
+            rc = ph_autotune(n, img.data(), img_off.data(), shapes.data(), shapes.data(), flags, out,
+                             out_off.data(), counts.data(), status.data(), ws.data(), g_wsb, 1, &best, nullptr);
+            unguard();
+            if (rc != PH_OK) { fprintf(stderr, "driver: autotune rc %d\n", rc); return 3; }
+        }
+        rc = ph_diagram_batch(n, img.data(), img_off.data(), shapes.data(), shapes.data(), flags, out,
+                              out_off.data(), counts.data(), status.data(), tp, ws.data(), g_wsb, nullptr);
+    }
+    unguard();
+    emu_after_launch = nullptr;
+    if (rc != PH_OK) { fprintf(stderr, "driver: rc %d\n", rc); return 3; }
+
+    std::vector<float> grad;
+    if (backward) {
+        std::vector<float> gb(cap, 0.f), gd(cap, 0.f);
+        for (int i = 0; i < n; ++i)
+            for (int64_t j = 0; j < counts[i] && j < out_off[i + 1] - out_off[i]; ++j) {
+                const int64_t k = out_off[i] + j;
+                if (dcell[k] < 0) continue;
+                const float d = death[k] - birth[k];
+                gb[k] = -2.f * d;
+                gd[k] = 2.f * d;
+            }
+        grad.resize(img.size());
+        uninit(grad);
+        rc = ph_backward(n, out, out_off.data(), counts.data(), gb.data(), gd.data(), grad.data(), img_off.data(),
+                         (int64_t)img.size(), nullptr);
+        if (rc != PH_OK) { fprintf(stderr, "driver: backward rc %d\n", rc); return 3; }
+    }
+
+    FILE *o = fopen(argv[2], "wb");
+    if (!o) return 2;
+    for (int i = 0; i < n; ++i) {
+        fwrite(&counts[i], 8, 1, o);
+        fwrite(&status[i], 4, 1, o);
+        const int64_t m = counts[i] < out_off[i + 1] - out_off[i] ? counts[i] : out_off[i + 1] - out_off[i];
+        for (int64_t j = 0; j < m && status[i] == PH_OK; ++j) {
+            const int64_t k = out_off[i] + j;
+            const int32_t dm = dim[k];
+            fwrite(&dm, 4, 1, o); fwrite(&birth[k], 4, 1, o); fwrite(&death[k], 4, 1, o);
+            fwrite(&bcell[k], 8, 1, o); fwrite(&dcell[k], 8, 1, o);
+            fwrite(&bvert[k], 4, 1, o); fwrite(&dvert[k], 4, 1, o);
+        }
+    }
+    if (backward) fwrite(grad.data(), 4, grad.size(), o);
+    fclose(o);
+    return 0;
+}

@@ -1,0 +1,327 @@
+// CPU execution of the library's HIP kernels, for sanitizer runs in the test suite.
+//
+// This header stands in for <hip/hip_runtime.h> when fc_kernels.hip is compiled as plain C++
+// for the host (tests/cpu_emulation/build.py).  It is never part of the library: the gfx950
+// build uses the real HIP runtime.  Semantics modelled:
+//   * every GPU thread of a block is a fiber (its own stack, x86-64 context switch) on the host
+//     thread; blocks of a grid run one after another;
+//   * __syncthreads / __syncthreads_or are block-wide barriers; shuffles and ballots exchange
+//     values between the 64 lanes of a wave through a per-wave barrier, so they must be
+//     reached by every lane of the wave, as on the GPU; a barrier that cannot complete aborts;
+//   * a thread runs until it waits, so the interleaving of threads between barriers is one
+//     fixed order (the GPU may pick any): results that depend on it would not be caught here;
+//   * atomics are plain host atomics;
+//   * __shared__ variables are static; before every block they are overwritten with a poison
+//     byte (or, under MemorySanitizer, marked uninitialised), so reading LDS that the block did
+//     not write shows up.  With EMU_LDS_REDZONE each __shared__ array is an ordinary static,
+//     which AddressSanitizer surrounds with redzones;
+//   * device memory is host memory; launches run synchronously.
+#pragma once
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <vector>
+
+#if defined(__has_feature)
+#if __has_feature(address_sanitizer)
+#define EMU_ASAN_FIBERS 1
+#endif
+#endif
+#ifdef __SANITIZE_ADDRESS__
+#define EMU_ASAN_FIBERS 1
+#endif
+#if EMU_ASAN_FIBERS
+#include <sanitizer/asan_interface.h>
+#include <sanitizer/common_interface_defs.h>
+#endif
+
+#if defined(__has_feature)
+#if __has_feature(memory_sanitizer)
+#include <sanitizer/msan_interface.h>
+#define EMU_MSAN 1
+#endif
+#endif
+
+#define __global__
+#define __device__
+#define __host__
+#define __constant__
+#define __forceinline__ inline
+#define __launch_bounds__(...)
+#define __restrict__
+#ifdef EMU_LDS_REDZONE
+#define __shared__ static
+#else
+#define __shared__ static __attribute__((section("emu_lds")))
+#endif
+
+struct dim3 {
+    unsigned x, y, z;
+    dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
+};
+typedef void *hipStream_t;
+typedef int hipError_t;
+#define hipSuccess 0
+
+// ------------------------------------------------------------------ scheduling --
+// All GPU threads of a block are fibers on the calling host thread, switched cooperatively at
+// barriers (a fiber runs until it waits).  A block in which some live thread can never pass
+// the barrier it waits at is reported as a deadlock, the CPU picture of a hung GPU.
+struct EmuBarrier {
+    int count = 0, arrived = 0;
+    unsigned gen = 0;
+};
+struct EmuBlock {
+    EmuBarrier bar;
+    std::vector<EmuBarrier> wave_bar;
+    std::vector<int64_t> lane_value;
+    int or_acc = 0;
+};
+extern dim3 threadIdx, blockIdx, blockDim, gridDim;
+extern EmuBlock *emu_block;
+extern void (*emu_after_launch)(const void *kernel);
+extern "C" void emu_ctx_switch(void **save_sp, void *next_sp);   // defined in driver.cpp
+
+struct EmuFiber {
+    void *sp = nullptr;
+    char *stack = nullptr;
+    bool done = false;
+    EmuBarrier *wait = nullptr;
+    unsigned wait_gen = 0;
+};
+struct EmuSched {
+    static constexpr size_t kStack = 256 * 1024;
+    static constexpr int kFibers = 1024;
+    std::vector<EmuFiber> fib;
+    void *main_sp = nullptr;
+    const void *main_bottom = nullptr;
+    size_t main_size = 0;
+    int cur = -1;
+    void (*fn)(void *) = nullptr;
+    void *ctx = nullptr;
+};
+inline EmuSched emu_sched;
+
+inline void emu_to_fiber(EmuFiber &f) {
+#if EMU_ASAN_FIBERS
+    void *fake = nullptr;
+    __sanitizer_start_switch_fiber(&fake, f.stack, EmuSched::kStack);
+    emu_ctx_switch(&emu_sched.main_sp, f.sp);
+    __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#else
+    emu_ctx_switch(&emu_sched.main_sp, f.sp);
+#endif
+}
+inline void emu_to_main(EmuFiber &f, bool dying) {
+#if EMU_ASAN_FIBERS
+    void *fake = nullptr;
+    __sanitizer_start_switch_fiber(dying ? nullptr : &fake, emu_sched.main_bottom, emu_sched.main_size);
+    emu_ctx_switch(&f.sp, emu_sched.main_sp);
+    __sanitizer_finish_switch_fiber(fake, nullptr, nullptr);
+#else
+    (void)dying;
+    emu_ctx_switch(&f.sp, emu_sched.main_sp);
+#endif
+}
+[[noreturn]] inline void emu_fiber_main() {
+#if EMU_ASAN_FIBERS
+    __sanitizer_finish_switch_fiber(nullptr, &emu_sched.main_bottom, &emu_sched.main_size);
+#endif
+    EmuFiber &f = emu_sched.fib[emu_sched.cur];
+    emu_sched.fn(emu_sched.ctx);
+    f.done = true;
+    emu_to_main(f, true);
+    abort();                                   // a finished fiber is never resumed
+}
+inline void emu_barrier_wait(EmuBarrier &b) {
+    const unsigned g = b.gen;
+    if (++b.arrived == b.count) {              // the last thread to arrive releases the others
+        b.arrived = 0;
+        ++b.gen;
+        return;
+    }
+    EmuFiber &f = emu_sched.fib[emu_sched.cur];
+    f.wait = &b;
+    f.wait_gen = g;
+    emu_to_main(f, false);
+}
+inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void *), void *ctx) {
+    EmuSched &s = emu_sched;
+    if (s.fib.empty()) {
+        s.fib.resize(EmuSched::kFibers);
+        for (auto &f : s.fib) f.stack = (char *)aligned_alloc(64, EmuSched::kStack);
+    }
+    s.fn = fn;
+    s.ctx = ctx;
+    for (unsigned t = 0; t < nt; ++t) {
+        EmuFiber &f = s.fib[t];
+#if EMU_ASAN_FIBERS
+        __asan_unpoison_memory_region(f.stack, EmuSched::kStack);
+#endif
+        uintptr_t top = ((uintptr_t)f.stack + EmuSched::kStack) & ~(uintptr_t)15;
+        void **sp = (void **)top;
+        *--sp = nullptr;                       // return address of the entry function
+        *--sp = (void *)&emu_fiber_main;       // where the first switch returns to
+        for (int r = 0; r < 6; ++r) *--sp = nullptr;   // rbp rbx r12 r13 r14 r15
+        f.sp = sp;
+        f.done = false;
+        f.wait = nullptr;
+    }
+    unsigned left = nt;
+    while (left > 0) {
+        bool moved = false;
+        for (unsigned t = 0; t < nt; ++t) {
+            EmuFiber &f = s.fib[t];
+            if (f.done || (f.wait && f.wait->gen == f.wait_gen)) continue;
+            f.wait = nullptr;
+            s.cur = (int)t;
+            threadIdx = dim3(t);
+            blockIdx = bid;
+            emu_block = blk;
+            emu_to_fiber(f);
+            moved = true;
+            if (f.done) --left;
+        }
+        if (!moved) {
+            fprintf(stderr, "emulation: deadlock, %u threads wait at a barrier that cannot complete\n", left);
+            abort();
+        }
+    }
+}
+
+inline void __syncthreads() { emu_barrier_wait(emu_block->bar); }
+inline int __syncthreads_or(int x) {
+    EmuBlock *b = emu_block;
+    emu_barrier_wait(b->bar);
+    if (x) b->or_acc = 1;
+    emu_barrier_wait(b->bar);
+    const int r = b->or_acc;
+    emu_barrier_wait(b->bar);
+    if (threadIdx.x == 0) b->or_acc = 0;
+    emu_barrier_wait(b->bar);
+    return r;
+}
+inline int __lane_id() { return (int)(threadIdx.x & 63u); }
+inline int emu_wave() { return (int)(threadIdx.x >> 6); }
+inline int64_t emu_read_lane(int64_t v, int src) {
+    EmuBlock *b = emu_block;
+    EmuBarrier &w = b->wave_bar[emu_wave()];
+    b->lane_value[threadIdx.x] = v;
+    emu_barrier_wait(w);
+    const int64_t got = b->lane_value[(emu_wave() << 6) + src];
+    emu_barrier_wait(w);
+    return got;
+}
+inline int __shfl_up(int v, int d, int = 64) {
+    const int l = __lane_id();
+    return (int)emu_read_lane(v, l - d < 0 ? l : l - d);
+}
+inline int __shfl(int v, int src, int = 64) { return (int)emu_read_lane(v, src & 63); }
+inline unsigned long long __ballot(int pred) {
+    EmuBlock *b = emu_block;
+    EmuBarrier &w = b->wave_bar[emu_wave()];
+    b->lane_value[threadIdx.x] = pred ? 1 : 0;
+    emu_barrier_wait(w);
+    unsigned long long m = 0;
+    for (int l = 0; l < 64 && (emu_wave() << 6) + l < (int)b->lane_value.size(); ++l)
+        if (b->lane_value[(emu_wave() << 6) + l]) m |= 1ull << l;
+    emu_barrier_wait(w);
+    return m;
+}
+inline int __popc(unsigned x) { return __builtin_popcount(x); }
+inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
+inline unsigned __float_as_uint(float f) { unsigned u; memcpy(&u, &f, 4); return u; }
+inline float __int_as_float(int i) { float f; memcpy(&f, &i, 4); return f; }
+
+template <typename T> inline T atomicAdd(T *p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+inline float atomicAdd(float *p, float v) {
+    float old, nw;
+    __atomic_load(p, &old, __ATOMIC_SEQ_CST);
+    do { nw = old + v; } while (!__atomic_compare_exchange(p, &old, &nw, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST));
+    return old;
+}
+template <typename T> inline T atomicMin(T *p, T v) {
+    T old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v < old && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return old;
+}
+template <typename T> inline T atomicCAS(T *p, T cmp, T v) {
+    __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
+    return cmp;
+}
+#ifdef __clang__
+#ifndef __HIP_MEMORY_SCOPE_AGENT
+#define __HIP_MEMORY_SCOPE_WORKGROUP 2
+#define __HIP_MEMORY_SCOPE_AGENT 3
+#endif
+#else
+#define __HIP_MEMORY_SCOPE_WORKGROUP 0
+#define __HIP_MEMORY_SCOPE_AGENT 0
+template <typename T> inline T __hip_atomic_load(T *p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
+template <typename T> inline void __hip_atomic_store(T *p, T v, int, int) { __atomic_store_n(p, v, __ATOMIC_SEQ_CST); }
+#endif
+
+// host API subset
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+enum { hipDeviceAttributeMaxSharedMemoryPerBlock = 1, hipDeviceAttributeMaxThreadsPerBlock = 2 };
+inline hipError_t hipDeviceGetAttribute(int *v, int a, int) { *v = a == 1 ? 163840 : 1024; return hipSuccess; }
+struct hipFuncAttributes { size_t sharedSizeBytes; int numRegs; int maxThreadsPerBlock; };
+inline hipError_t hipFuncGetAttributes(hipFuncAttributes *at, const void *) {
+    at->sharedSizeBytes = 0; at->numRegs = 0; at->maxThreadsPerBlock = 1024;
+    return hipSuccess;
+}
+enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
+inline hipError_t hipMalloc(void **p, size_t n) { *p = malloc(n ? n : 1); return *p ? hipSuccess : 2; }
+inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { memcpy(d, s, n); return hipSuccess; }
+typedef struct EmuEvent { double t; } *hipEvent_t;
+inline double emu_now_ms() {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+inline hipError_t hipEventCreate(hipEvent_t *e) { *e = new EmuEvent{0}; return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t e, hipStream_t) { e->t = emu_now_ms(); return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) { *ms = (float)(b->t - a->t); return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
+
+#ifndef EMU_LDS_REDZONE
+extern "C" char __start_emu_lds[], __stop_emu_lds[];
+#endif
+inline void emu_poison_lds() {
+#ifndef EMU_LDS_REDZONE
+    const char *e = getenv("EMU_POISON");
+    memset(__start_emu_lds, e ? atoi(e) : 0x4F, (size_t)(__stop_emu_lds - __start_emu_lds));
+#ifdef EMU_MSAN
+    __msan_poison(__start_emu_lds, (size_t)(__stop_emu_lds - __start_emu_lds));
+#endif
+#endif
+}
+
+template <typename K, typename... A>
+void emu_launch(K kern, dim3 g, dim3 b, A... args) {
+    gridDim = g;
+    blockDim = b;
+    const unsigned nt = b.x * b.y * b.z;
+    if (nt == 0 || nt > (unsigned)EmuSched::kFibers) { fprintf(stderr, "emulation: bad block size\n"); abort(); }
+    auto call = [&]() { kern(args...); };
+    using Call = decltype(call);
+    for (unsigned bz = 0; bz < g.z; ++bz)
+        for (unsigned by = 0; by < g.y; ++by)
+            for (unsigned bx = 0; bx < g.x; ++bx) {
+                emu_poison_lds();
+                EmuBlock blk;
+                blk.bar.count = (int)nt;
+                blk.wave_bar.resize((nt + 63) / 64);
+                for (unsigned w = 0; w < blk.wave_bar.size(); ++w) blk.wave_bar[w].count = (int)std::min(64u, nt - 64 * w);
+                blk.lane_value.assign(nt, 0);
+                emu_run_block(nt, dim3(bx, by, bz), &blk, [](void *c) { (*(Call *)c)(); }, &call);
+            }
+    if (emu_after_launch) emu_after_launch((const void *)kern);
+}
+#define hipLaunchKernelGGL(K, G, B, SH, ST, ...) emu_launch(K, G, B, __VA_ARGS__)

@@ -1,0 +1,128 @@
+"""The library's kernels run on the CPU against the oracle, under AddressSanitizer and UBSan.
+
+tests/cpu_emulation compiles csrc/fc_kernels.hip as host C++ against an emulated HIP runtime
+(one thread per GPU thread, real barriers and wave exchanges; see its header) with a redzone
+around every LDS array and the workspace gaps between per-instance arrays poisoned.  This
+checks the kernels' indexing and synchronisation, and their results bit for bit, without a GPU.
+It is not a parity claim for the GPU build (compiler and hardware differ) and nothing in the
+library uses it.
+"""
+import os
+import shutil
+import struct
+import subprocess
+import sys
+import tempfile
+
+import numpy as np
+import pytest
+
+import fixtures
+import oracle
+import synthetic as S
+from gpu_util import diff_pairs
+
+sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "cpu_emulation"))
+import build as emu_build  # noqa: E402
+
+pytestmark = pytest.mark.slow
+if shutil.which("g++") is None:
+    pytest.skip("no host C++ compiler", allow_module_level=True)
+
+REC = np.dtype([("dim", "<i4"), ("birth", "<f4"), ("death", "<f4"), ("birth_cell", "<i8"),
+                ("death_cell", "<i8"), ("birth_vertex", "<i4"), ("death_vertex", "<i4")])
+
+
+@pytest.fixture(scope="module")
+def driver():
+    return emu_build.build("asan")
+
+
+def run(exe, imgs, mode=0, tuning=None, backward=False):
+    """(per-instance (pairs, status), gradient or None) from the emulated kernels."""
+    imgs = [np.ascontiguousarray(a, dtype=np.float32) for a in imgs]
+    hdr = struct.pack("<6i", len(imgs), 3, mode, *(tuning if tuning else (-1, -1)), int(backward))
+    for a in imgs:
+        ext = list(a.shape) + [1] * (3 - a.ndim)
+        hdr += struct.pack("<4i", a.ndim, *ext)
+    with tempfile.TemporaryDirectory() as d:
+        fi, fo = os.path.join(d, "in.bin"), os.path.join(d, "out.bin")
+        with open(fi, "wb") as f:
+            f.write(hdr)
+            for a in imgs:
+                f.write(a.tobytes())
+        env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1", ASAN_OPTIONS="detect_leaks=0")
+        r = subprocess.run([exe, fi, fo], capture_output=True, text=True, timeout=600, env=env)
+        assert r.returncode == 0, r.stderr[-4000:]
+        raw = open(fo, "rb").read()
+    out, pos = [], 0
+    for a in imgs:
+        cnt, st = struct.unpack_from("<qi", raw, pos)
+        pos += 12
+        m = cnt if st == 0 else 0
+        rec = np.frombuffer(raw, REC, count=m, offset=pos)
+        pos += m * REC.itemsize
+        res = np.zeros(m, oracle.PAIR_DTYPE)
+        for f in oracle.PAIR_DTYPE.names:
+            res[f] = rec[f]
+        out.append((res, st))
+    grad = None
+    if backward:
+        grad = np.frombuffer(raw, "<f4", offset=pos)
+    return out, grad
+
+
+def test_fixtures(driver):
+    for name, img, _, _ in fixtures.load():
+        (got, st), = run(driver, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, name
+
+
+def test_tiny_sweep(driver):
+    rng = np.random.default_rng(31)
+    for k in range(10):
+        nd = 2 if k % 2 == 0 else 3
+        shape = tuple(int(x) for x in rng.integers(1, 10 if nd == 2 else 6, size=nd))
+        img = S.levels(shape, int(rng.choice([2, 3, 1 << 20])), 7000 + k)
+        (got, st), = run(driver, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, (k, shape)
+
+
+def test_fields_multi_tile(driver):
+    for img in (S.grf((48, 40), 2.0, 7), S.grf((12, 10, 14), 1.5, 8), S.quantize_u8(S.grf((70, 130), 3.0, 2))):
+        (got, st), = run(driver, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
+def mixed_batch():
+    return [S.levels((5, 9), 3, 7100), S.grf((40, 33), 2.0, 7101), S.levels((4, 3, 5), 2, 7102),
+            S.grf((9, 12, 10), 1.5, 7103), S.levels((1, 7), 5, 7104), S.uniform((20, 21), 7105)]
+
+
+@pytest.mark.parametrize("tuning", [None, (1, 2), (2, 1)])
+def test_batch_with_backward(driver, tuning):
+    imgs = mixed_batch()
+    out, grad = run(driver, imgs, mode=1, tuning=tuning, backward=True)
+    off = 0
+    for img, (got, st) in zip(imgs, out):
+        ref = oracle.diagram(img)
+        assert st == 0 and diff_pairs(got, ref) is None, img.shape
+        f = ref["death_cell"] >= 0
+        d = np.where(f, ref["death"] - ref["birth"], 0).astype(np.float32)
+        g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
+        np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
+        off += img.size
+
+
+def test_autotune_then_batch(driver):
+    imgs = mixed_batch()[:4]
+    out, _ = run(driver, imgs, mode=2)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None
+
+
+def test_nan_status(driver):
+    img = S.grf((20, 20), 2.0, 3)
+    img[4, 5] = np.nan
+    (got, st), = run(driver, [img])[0]
+    assert st == -2                                   # PH_ENAN

@@ -1,0 +1,218 @@
+"""GPU tests beyond the small parity sweeps: full-size workloads against stored oracle digests,
+batching (bitwise equal to per-image calls, for every tile choice and after autotuning), graph
+replay, the backward scatter against the oracle's reference gradient and against finite
+differences, and the status words (NaN, capacity).  All go through the C ABI."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from gpu_util import diff_pairs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2606_04801_amd as fc  # noqa: E402
+from golden.make_digests import instances, make, pair_digest, input_digest  # noqa: E402
+
+DEV = torch.device("cuda:0")
+DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
+
+pytestmark = [pytest.mark.gpu, pytest.mark.skipif(
+    not fc.device_path_enabled(),
+    reason="device path switched off: its first launches faulted the GPU and no cause has been "
+           "shown yet; set FLASHCUBICAL_DEVICE_PATH=1 to run")]
+
+
+def gpu(img):
+    print("case", img.shape, flush=True)
+    return fc.ph_diagram(torch.from_numpy(np.ascontiguousarray(img)).to(DEV)).numpy()
+
+
+def digests():
+    if not os.path.exists(DIGESTS):
+        pytest.skip("no stored digests (run tests/golden/make_digests.py)")
+    return json.load(open(DIGESTS))
+
+
+def check_digest(cfg, idx, img, pairs):
+    rec = digests().get(cfg, {}).get(str(idx))
+    if rec is None:
+        pytest.skip("no digest for %s/%d" % (cfg, idx))
+    assert rec["input_sha256"] == input_digest(img), "input generator changed"
+    top = img.ndim - 1
+    assert (int((pairs["dim"] == 0).sum()), int((pairs["dim"] == top).sum())) == (rec["h0"], rec["htop"])
+    assert pair_digest(pairs) == rec["pairs_sha256"]
+
+
+def items(cfg):
+    return [it for it in instances() if it[0] == cfg]
+
+
+@pytest.mark.parametrize("cfg", ["c1", "c2", "c2u8", "c3"])
+def test_single_full_size(cfg):
+    (_, idx, kind, args), = items(cfg)
+    img = make(kind, args)
+    check_digest(cfg, idx, img, gpu(img))
+
+
+def run_batch(imgs, tuning=None, autotune=False):
+    bt = fc.Batch([a.shape for a in imgs], tuning=tuning, device=DEV)
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+    if autotune:
+        bt.ph_autotune(reps=1)
+    bt.ph_diagram_batch()
+    torch.cuda.synchronize()
+    return bt, bt.results()
+
+
+@pytest.mark.parametrize("cfg", ["c4", "c5"])
+def test_batch_full_size(cfg):
+    its = items(cfg)
+    imgs = [make(kind, args) for _, _, kind, args in its]
+    bt, res = run_batch(imgs)
+    for (c, idx, _, _), img, r in zip(its, imgs, res):
+        check_digest(c, idx, img, r)
+
+
+def small_mixed_batch():
+    rng = np.random.default_rng(77)
+    imgs = []
+    for k in range(12):
+        if k % 3 == 2:
+            shape = tuple(int(x) for x in rng.integers(1, 14, size=3))
+        else:
+            shape = tuple(int(x) for x in rng.integers(1, 90, size=2))
+        lev = int(rng.choice([2, 5, 1 << 20]))
+        imgs.append(S.levels(shape, lev, 5000 + k))
+    imgs.append(S.grf((130, 70), 3.0, 5100))
+    imgs.append(S.grf((20, 33, 17), 2.0, 5101))
+    return imgs
+
+
+def test_batch_equals_single_and_oracle():
+    imgs = small_mixed_batch()
+    _, res = run_batch(imgs)
+    for img, r in zip(imgs, res):
+        assert diff_pairs(r, gpu(img)) is None
+        assert diff_pairs(r, oracle.diagram(img)) is None
+
+
+@pytest.mark.parametrize("t2,t3", [(a, b) for a in range(3) for b in range(3)])
+def test_tile_choice_never_changes_results(t2, t3):
+    imgs = small_mixed_batch()
+    _, res = run_batch(imgs, tuning=(t2, t3))
+    for img, r in zip(imgs, res):
+        assert diff_pairs(r, oracle.diagram(img)) is None
+
+
+def test_autotune_then_batch():
+    imgs = small_mixed_batch()
+    _, res = run_batch(imgs, autotune=True)
+    for img, r in zip(imgs, res):
+        assert diff_pairs(r, oracle.diagram(img)) is None
+
+
+def loss_grads(bt):
+    fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+    diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+    return (-2.0 * diff).contiguous(), (2.0 * diff).contiguous()
+
+
+def test_backward_against_reference_gradient():
+    imgs = small_mixed_batch()
+    bt, res = run_batch(imgs)
+    gb, gd = loss_grads(bt)
+    bt.ph_backward(gb, gd)
+    torch.cuda.synchronize()
+    for i, (img, r) in enumerate(zip(imgs, res)):
+        f = r["death_cell"] >= 0
+        d = np.where(f, r["death"] - r["birth"], 0).astype(np.float32)
+        ref = oracle.gradient(oracle.diagram(img), -2 * d, 2 * d, img.shape).reshape(-1)
+        got = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]].cpu().numpy()
+        np.testing.assert_allclose(got, ref, rtol=1e-6, atol=1e-7)
+
+
+def test_graph_replay_matches_eager():
+    imgs = small_mixed_batch()
+    bt, ref = run_batch(imgs)
+    gb, gd = loss_grads(bt)
+    bt.ph_backward(gb, gd)
+    torch.cuda.synchronize()
+    g_ref = bt.grad.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        bt.ph_diagram_batch()
+        gb2, gd2 = loss_grads(bt)
+        bt.ph_backward(gb2, gd2)
+    for rep in range(4):
+        bt.pairs.birth.fill_(float("nan"))
+        bt.grad.fill_(123.0)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        res = bt.results()
+        for a, b in zip(res, ref):
+            assert diff_pairs(a, b) is None, "replay %d" % rep
+        assert torch.equal(bt.grad, g_ref) or torch.allclose(bt.grad, g_ref, rtol=1e-6, atol=1e-7)
+
+
+def test_finite_differences():
+    """dL/dx on tie-free 16x16 inputs, L = sum over finite pairs of (d - b)^2."""
+    Fn = fc.PHDiagramFn
+    for k in range(4):
+        x0 = S.tie_free((16, 16), 4000 + k).astype(np.float64)
+        x = torch.tensor(x0, dtype=torch.float32, device=DEV, requires_grad=True)
+        b, d, dim = Fn.apply(x)
+        fin = torch.isfinite(d)
+        loss = ((d - b)[fin] ** 2).sum()
+        loss.backward()
+        g = x.grad.cpu().numpy().reshape(-1)
+
+        def L(v):
+            p = oracle.diagram(v.astype(np.float32))
+            f = p["death_cell"] >= 0
+            return float(((p["death"][f].astype(np.float64) - p["birth"][f]) ** 2).sum())
+
+        h = 1e-4
+        rng = np.random.default_rng(k)
+        for j in rng.choice(256, size=24, replace=False):
+            xp, xm = x0.reshape(-1).copy(), x0.reshape(-1).copy()
+            xp[j] += h
+            xm[j] -= h
+            step = float(np.float32(xp[j])) - float(np.float32(xm[j]))
+            fd = (L(xp.reshape(16, 16)) - L(xm.reshape(16, 16))) / step
+            assert abs(fd - g[j]) <= 1e-3 * max(1.0, abs(fd)), (k, j, fd, g[j])
+
+
+def test_nan_sets_status():
+    img = S.grf((40, 40), 2.0, 1)
+    img[7, 9] = np.nan
+    d = fc.ph_diagram(torch.from_numpy(img).to(DEV))
+    with pytest.raises(fc.PHError) as e:
+        d.check()
+    assert e.value.code == fc.PH_ENAN
+
+
+def test_capacity_overflow_reports_true_count():
+    img = S.uniform((64, 64), 3)
+    full = gpu(img)
+    d = fc.ph_diagram(torch.from_numpy(img).to(DEV), capacity=10)
+    torch.cuda.synchronize()
+    assert int(d.status_t.item()) == fc.PH_ECAPACITY
+    assert int(d.count_t.item()) == len(full)
+    got = d.bufs.to_numpy(0, 10)
+    assert diff_pairs(got, full[:10]) is None
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (9, 1), (2, 2), (1, 1, 1), (1, 1, 7), (7, 1, 1),
+                                   (1, 6, 6), (6, 1, 6), (2, 2, 2)])
+def test_degenerate_extents(shape):
+    for lev in (2, 1 << 20):
+        img = S.levels(shape, lev, 6000 + sum(shape))
+        assert diff_pairs(gpu(img), oracle.diagram(img)) is None

@@ -83,6 +83,9 @@ def test_device_path_switch(monkeypatch):
     assert L.ph_diagram_batch(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
                               None) == fc.PH_EDISABLED
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EDISABLED
+    best = fc.ph_tuning(0, 0)
+    assert L.ph_autotune(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, 0, 1,
+                         ctypes.byref(best), None) == fc.PH_EDISABLED
     monkeypatch.setenv(fc.DEVICE_PATH_ENV, "0")
     assert _call_diagram() == fc.PH_EDISABLED
 
@@ -101,6 +104,11 @@ def test_host_validation_before_any_device_call(monkeypatch):
                               None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 0, None) == fc.PH_EINVAL
+    best = fc.ph_tuning(0, 0)
+    assert L.ph_autotune(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, 0, 1,
+                         ctypes.byref(best), None) == fc.PH_EINVAL
+    assert L.ph_autotune(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, 0, 1,
+                         None, None) == fc.PH_EINVAL
 
 
 def test_binding_raises_without_gpu_tensor():
