@@ -201,6 +201,16 @@ int main(int argc, char **argv) {
     unguard();
     emu_after_launch = nullptr;
     if (rc != PH_OK) { fprintf(stderr, "driver: rc %d\n", rc); return 3; }
+    if (getenv("EMU_STATS")) {                    // per-instance work counters, for sizing studies
+        const int64_t cn = a256((int64_t)n * (int64_t)sizeof(fc::Inst)) + 2 * a256((int64_t)(n + 1) * 8);
+        for (int i = 0; i < n; ++i) {
+            const int32_t *c = (const int32_t *)(ws.data() + cn) + i * fc::CNT_WORDS;
+            const fc::Inst &I = ((const fc::Inst *)ws.data())[i];
+            fprintf(stderr, "stats %d N %ld keepE %d keepF %d minima %d roots %d rounds0 %d roundsT %d seq %d\n", i,
+                    (long)I.N, c[fc::CNT_E], c[fc::CNT_F], c[fc::CNT_M0], c[fc::CNT_MT], c[fc::CNT_ROUNDS0],
+                    c[fc::CNT_ROUNDST], c[fc::CNT_SEQ]);
+        }
+    }
 
     std::vector<float> grad;
     if (backward) {

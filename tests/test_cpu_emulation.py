@@ -1,8 +1,8 @@
 """The library's kernels run on the CPU against the oracle, under AddressSanitizer and UBSan.
 
 tests/cpu_emulation compiles csrc/fc_kernels.hip as host C++ against an emulated HIP runtime
-(one thread per GPU thread, real barriers and wave exchanges; see its header) with a redzone
-around every LDS array and the workspace gaps between per-instance arrays poisoned.  This
+(one fiber per GPU thread, cooperative barriers and wave exchanges; see its header) with a
+redzone around every LDS array and poisoned gaps after the workspace arrays.  This
 checks the kernels' indexing and synchronisation, and their results bit for bit, without a GPU.
 It is not a parity claim for the GPU build (compiler and hardware differ) and nothing in the
 library uses it.
@@ -126,3 +126,28 @@ def test_nan_status(driver):
     img[4, 5] = np.nan
     (got, st), = run(driver, [img])[0]
     assert st == -2                                   # PH_ENAN
+
+
+@pytest.mark.skipif(os.environ.get("FC_EMULATE_FULL") != "1",
+                    reason="about 9 minutes: set FC_EMULATE_FULL=1 to run every full-size workload")
+def test_full_size_workloads_against_digests():
+    """Every instance of the full-size workloads (2048^2 with and without ties, 256^3, the
+    512-image batch, the 128-instance mixed batch) through the emulated kernels, compared with
+    the oracle's stored digests."""
+    import json
+    sys.path.insert(0, os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden"))
+    from make_digests import instances, make, pair_digest
+    exe = emu_build.build("poison")
+    D = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")))
+    its = instances()
+    for cfg in ("c1", "c2", "c2u8", "c3"):
+        (c, idx, kind, args), = [it for it in its if it[0] == cfg]
+        (got, st), = run(exe, [make(kind, args)])[0]
+        assert st == 0 and pair_digest(got) == D[c][str(idx)]["pairs_sha256"], cfg
+    for cfg, chunk in (("c4", 128), ("c5", 32)):
+        items = [it for it in its if it[0] == cfg]
+        for k in range(0, len(items), chunk):
+            part = items[k:k + chunk]
+            out, _ = run(exe, [make(kind, args) for _, _, kind, args in part], mode=1)
+            for (c, idx, _, _), (got, st) in zip(part, out):
+                assert st == 0 and pair_digest(got) == D[c][str(idx)]["pairs_sha256"], (c, idx)
