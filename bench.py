@@ -16,9 +16,10 @@ profiled steps), its algorithmic bytes per launch divided by its mean launch dur
 8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, when a summary
 for this exact library build is given with --traffic-json, else null.
 
-cpu_baseline: the CPU oracle (single-threaded C) on a bounded sample of the same workload (one
-volume and one image, forward + reference gradient, about 30 s), in Mvoxels/s.  The GPU results
-of those two instances are also compared with the oracle's, bit for bit.
+cpu_baseline: the CPU oracle (single-threaded C, one process per host core, at most 16) on a
+bounded sample of the same workload (one instance per core, half volumes and half images,
+forward + reference gradient, about 30 s), in Mvoxels/s.  The GPU results of those instances
+are also compared with the oracle's, bit for bit.
 """
 from __future__ import annotations
 
@@ -50,30 +51,39 @@ def workload_desc():
     return "64 x 96^3 field sigma 3 + 64 x 512^2 field sigma 6, H0+H_top, batched fwd+bwd"
 
 
-# instances the CPU baseline runs: (index in the batch, shape, sigma, seed)
-SAMPLE = [(0, SHAPE3, SIG3, 2000), (N3, SHAPE2, SIG2, 3000)]
-
-
-def cpu_baseline():
-    """Oracle (forward + reference gradient) on one volume and one image of the workload.
-
-    Returns the baseline record and {batch index: (pairs, gradient)} for the parity check."""
+def _oracle_instance(item):
+    """One workload instance through the oracle: forward + reference gradient, timed."""
     import oracle
-    vox, t = 0, 0.0
-    ref = {}
-    for idx, shape, sig, seed in SAMPLE:
-        img = S.grf(shape, sig, seed)
-        t0 = time.perf_counter()
-        p = oracle.diagram(img)
-        fin = p["death_cell"] >= 0
-        d = np.where(fin, p["death"] - p["birth"], 0).astype(np.float32)
-        g = oracle.gradient(p, -2 * d, 2 * d, img.shape)
-        t += time.perf_counter() - t0
-        vox += img.size
-        ref[idx] = (p, g)
-    rec = {"value": round(vox / t / 1e6, 5), "unit": "Mvoxels/s", "cores": 1, "kind": "oracle",
-           "sample": "one 96^3 volume (seed 2000) + one 512^2 image (seed 3000) of the workload, "
-                     "forward + gradient, single-threaded C, %.1f s" % t}
+    idx, shape, sig, seed = item
+    img = S.grf(shape, sig, seed)
+    t0 = time.perf_counter()
+    p = oracle.diagram(img)
+    fin = p["death_cell"] >= 0
+    d = np.where(fin, p["death"] - p["birth"], 0).astype(np.float32)
+    g = oracle.gradient(p, -2 * d, 2 * d, img.shape)
+    return idx, img.size, time.perf_counter() - t0, p, g
+
+
+def cpu_baseline(workers: int):
+    """The oracle on a bounded sample of the workload, one instance per host core.
+
+    The sample is `workers` instances, half volumes and half images (first seeds of each),
+    each run single-threaded in its own process; the rate is sample voxels over wall time.
+    Returns the baseline record and {batch index: (pairs, gradient)} for the parity check."""
+    from multiprocessing import get_context
+    n3 = (workers + 1) // 2
+    items = [(i, SHAPE3, SIG3, 2000 + i) for i in range(n3)] + \
+            [(N3 + i, SHAPE2, SIG2, 3000 + i) for i in range(workers - n3)]
+    t0 = time.perf_counter()
+    with get_context("fork").Pool(workers) as pool:
+        res = pool.map(_oracle_instance, items, chunksize=1)
+    wall = time.perf_counter() - t0
+    vox = sum(r[1] for r in res)
+    ref = {r[0]: (r[3], r[4]) for r in res}
+    rec = {"value": round(vox / wall / 1e6, 5), "unit": "Mvoxels/s", "cores": workers, "kind": "oracle",
+           "sample": "%d x 96^3 volumes (seeds 2000..) + %d x 512^2 images (seeds 3000..) of the workload, "
+                     "forward + gradient, one single-threaded C process per core, %.1f s wall "
+                     "(single-process sum %.1f s)" % (n3, workers - n3, wall, sum(r[2] for r in res))}
     return rec, ref
 
 
@@ -103,6 +113,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
     ap.add_argument("--traffic-json", default=None)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -122,8 +133,9 @@ def main():
     import torch
     ref = {}
     if not args.no_cpu_baseline:
-        print("bench: cpu baseline (oracle, about 30 s)", file=sys.stderr, flush=True)
-        line["cpu_baseline"], ref = cpu_baseline()
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
+        line["cpu_baseline"], ref = cpu_baseline(workers)
     gpu = torch.cuda.is_available()
     if not gpu or not fc.device_path_enabled():
         line["status"] = ("no GPU" if not gpu else

@@ -36,6 +36,8 @@
  *     the first `capacity` pairs in output order are stored, PH_EINTERNAL if a bounded
  *     loop ran out of iterations).
  *   - Calls that share a workspace must not overlap in time.
+ *   - FLASHCUBICAL_TRACE=1 in the environment names every kernel launch on stderr and waits
+ *     for it (a debugging aid: it synchronises, so it must not be set during graph capture).
  *   - Device path switch: the entry points that launch kernels (ph_diagram,
  *     ph_diagram_batch, ph_autotune, ph_backward) return PH_EDISABLED unless the environment variable
  *     FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of

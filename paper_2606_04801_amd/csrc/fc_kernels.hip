@@ -1232,6 +1232,29 @@ bool prof_enabled() {
     return g_prof_on;
 }
 
+// FLASHCUBICAL_TRACE=1: name every launch on stderr before it is made and wait for it after,
+// so that a failing kernel is the last one named.
+bool trace_enabled() {
+    static const bool on = [] {
+        const char *e = getenv("FLASHCUBICAL_TRACE");
+        return e && e[0] == '1' && e[1] == 0;
+    }();
+    return on;
+}
+
+int trace_before(int kid) {
+    fprintf(stderr, "flashcubical: launch %s\n", kKernelNames[kid]);
+    fflush(stderr);
+    return PH_OK;
+}
+
+int trace_after(int kid, hipStream_t st) {
+    const hipError_t e = hipStreamSynchronize(st);
+    fprintf(stderr, "flashcubical: %s %s\n", kKernelNames[kid], e == hipSuccess ? "done" : "FAILED");
+    fflush(stderr);
+    return e == hipSuccess ? PH_OK : PH_EHIP;
+}
+
 int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
         const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
         const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
@@ -1258,9 +1281,10 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
 
     // Each launch is checked on its own: the error a failed launch leaves behind would be
     // overwritten by the next successful call.
-    const bool prof = prof_enabled();
+    const bool prof = prof_enabled(), trace = trace_enabled();
 #define FC_LAUNCH(KID, ...)                                                   \
     do {                                                                      \
+        if (trace) trace_before(KID);                                         \
         hipEvent_t ev_a = prof ? prof_mark(st) : nullptr;                     \
         (void)hipGetLastError();                                              \
         __VA_ARGS__;                                                          \
@@ -1269,6 +1293,7 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
             return PH_EHIP;                                                   \
         }                                                                     \
         if (prof) prof_push(KID, ev_a, prof_mark(st));                        \
+        if (trace && trace_after(KID, st) != PH_OK) return PH_EHIP;           \
     } while (0)
     FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
@@ -1410,7 +1435,8 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
     int rc = fc::device_luts();
     if (rc != PH_OK) return rc;
     const int64_t zb = (total_voxels + 255) / 256;
-    const bool prof = fc::prof_enabled();
+    const bool prof = fc::prof_enabled(), trace = fc::trace_enabled();
+    if (trace) fc::trace_before(fc::K_ZERO);
     hipEvent_t z0 = prof ? fc::prof_mark(st) : nullptr;
     (void)hipGetLastError();
     hipLaunchKernelGGL(fc::k_zero, dim3((unsigned)(zb < 8192 ? zb : 8192)), dim3(256), 0, st, d_grad_img,
@@ -1420,11 +1446,14 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
         return PH_EHIP;
     }
     if (prof) fc::prof_push(fc::K_ZERO, z0, fc::prof_mark(st));
+    if (trace && fc::trace_after(fc::K_ZERO, st) != PH_OK) return PH_EHIP;
+    if (trace) fc::trace_before(fc::K_SCATTER);
     hipEvent_t s0 = prof ? fc::prof_mark(st) : nullptr;
     hipLaunchKernelGGL(fc::k_scatter, dim3(64, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
                        d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
     const bool ok = hipGetLastError() == hipSuccess;
     if (prof) fc::prof_push(fc::K_SCATTER, s0, ok ? fc::prof_mark(st) : nullptr);
+    if (ok && trace && fc::trace_after(fc::K_SCATTER, st) != PH_OK) return PH_EHIP;
     return ok ? PH_OK : PH_EHIP;
 }
 

@@ -269,6 +269,7 @@ template <typename T> inline void __hip_atomic_store(T *p, T v, int, int) { __at
 // host API subset
 inline hipError_t hipGetLastError() { return hipSuccess; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 enum { hipDeviceAttributeMaxSharedMemoryPerBlock = 1, hipDeviceAttributeMaxThreadsPerBlock = 2 };
 inline hipError_t hipDeviceGetAttribute(int *v, int a, int) { *v = a == 1 ? 163840 : 1024; return hipSuccess; }
 struct hipFuncAttributes { size_t sharedSizeBytes; int numRegs; int maxThreadsPerBlock; };
