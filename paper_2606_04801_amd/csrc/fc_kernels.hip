@@ -126,6 +126,17 @@ __device__ __forceinline__ bool block_failed(const int32_t *cnt) {
     return __syncthreads_or(failed(cnt) ? 1 : 0) != 0;
 }
 
+// Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup w runs on XCD w % 8),
+// and each XCD has its own L2.  Tiles are renumbered so that every XCD gets one contiguous run
+// of tiles: neighbouring tiles share halo rows, which then hit the same L2.  A bijection of
+// [0, g) for any grid size g.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t g) {
+    const int64_t base = g / kXcds, rem = g % kXcds;
+    const int64_t x = w % kXcds, local = w / kXcds;
+    return x * base + (x < rem ? x : rem) + local;
+}
+
 __device__ __forceinline__ int find_inst(const int64_t *tb, int n, int64_t tile) {
     int lo = 0, hi = n - 1;                        // largest i with tb[i] <= tile < tb[i+1]
     while (lo < hi) {
@@ -170,12 +181,13 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ int s_nan;
 
     const Inst *tab = (const Inst *)ws;
-    const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, blockIdx.x);
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
     const int H = I.H, W = I.W;
-    const int lt = (int)(blockIdx.x - I.tile_base);
+    const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
     const int y0 = ty * TH, x0 = tx * TW;
     const float *img = imgs + I.img_off;
@@ -336,12 +348,13 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __shared__ int s_nan;
 
     const Inst *tab = (const Inst *)ws;
-    const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, blockIdx.x);
+    const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
     const int D = I.D, H = I.H, W = I.W;
-    const int lt = (int)(blockIdx.x - I.tile_base);
+    const int lt = (int)(tile - I.tile_base);
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
     const int ty = rem / I.tx, tx = rem - ty * I.tx;
     const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
