@@ -87,23 +87,37 @@ def cpu_baseline(workers: int):
     return rec, ref
 
 
-def algorithmic_bytes(name, counts, shapes):
-    """Bytes one launch of `name` must move over the whole batch (model stated in the design doc)."""
+def algorithmic_bytes(name, wc, npairs, shapes):
+    """Bytes one launch of `name` must move over the whole batch (model stated in the design doc).
+
+    wc: per-instance work counters (KEEP edges, KEEP squares, H0 nodes, dual nodes, ...)."""
+    is3 = np.array([len(s) == 3 for s in shapes])
     N = sum(int(np.prod(s)) for s in shapes)
     T = sum(int(np.prod([e - 1 for e in s])) for s in shapes)
-    K, P = counts["keep"], counts["pairs"]
-    if name.startswith("k_classify"):
-        return 4 * N + 4 * N + 4 * T + 8 * K
-    if name.startswith("k_sort"):
-        return 16 * K
-    if name.startswith("k_resolve") or name.startswith("k_uf"):
-        return 16 * K
+    ke, kf, m0, mt = (int(wc[:, k].sum()) for k in range(4))
+    facets = int(wc[~is3, 0].sum()) + kf                 # 2D walks the KEEP edges, 3D the KEEP squares
+    if name == "k_classify2d" or name == "k_classify3d":
+        sel = is3 if name == "k_classify3d" else ~is3
+        n = sum(int(np.prod(s)) for s, k in zip(shapes, sel) if k)
+        t = sum(int(np.prod([e - 1 for e in s])) for s, k in zip(shapes, sel) if k)
+        return 4 * n + 4 * n + 4 * t + 8 * (int(wc[sel, 0].sum()) + int(wc[sel, 1].sum())
+                                            + int(wc[sel, 2].sum()) + int(wc[sel, 3].sum()))
+    if name == "k_sort(edges)":
+        return 16 * ke
+    if name == "k_sort(facets)":
+        return 16 * kf
+    if name == "k_sort(nodes)":
+        return 16 * m0
+    if name in ("k_resolve_edges", "k_uf(h0)"):
+        return 16 * ke
+    if name in ("k_resolve_facets", "k_uf(top)"):
+        return 16 * facets
     if name == "k_output":
-        return 8 * K + 32 * P
+        return 8 * (m0 + facets) + 32 * npairs
     if name == "k_zero":
         return 4 * N
     if name == "k_scatter":
-        return 32 * P
+        return 32 * npairs
     return 0
 
 
@@ -240,11 +254,11 @@ def run_gpu(fc, torch, shapes, args, ref):
     torch.cuda.synchronize()
     prof = fc.profile_read()
     fc.profile(False)
-    cnt = bt.counts.cpu().numpy()
-    counts = {"pairs": int(cnt.sum()), "keep": int(cnt.sum())}
+    npairs = int(bt.counts.cpu().numpy().sum())
+    wc = bt.work_counters()
     name, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
     mean_s = total_ms / launches / 1e3
-    algo = algorithmic_bytes(name, counts, shapes)
+    algo = algorithmic_bytes(name, wc, npairs, shapes)
     achieved = algo / mean_s / 1e9 if mean_s > 0 else 0.0
     traffic = None
     if args.traffic_json and os.path.exists(args.traffic_json):
@@ -257,6 +271,9 @@ def run_gpu(fc, torch, shapes, args, ref):
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},
         "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
+        "work": {"keep_edges": int(wc[:, 0].sum()), "keep_squares": int(wc[:, 1].sum()),
+                 "h0_nodes": int(wc[:, 2].sum()), "dual_nodes": int(wc[:, 3].sum()),
+                 "max_rounds": int(wc[:, 4:6].max()), "sequential_edges": int(wc[:, 6].sum())},
     }
 
 

@@ -207,6 +207,13 @@ typedef struct {
 int ph_profile(int32_t enable);
 int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count);
 
+/* Work counters of the last call that used workspace d_ws for n instances (the same n), for
+ * sizing and diagnostics: 8 int32 per instance written to h_out (host), in order KEEP edges,
+ * KEEP squares (3D), H0 nodes (local minima), dual nodes (ROOT top cells + the cell at
+ * infinity), H0 union-find rounds, dual union-find rounds, edges finished sequentially, and
+ * the instance's error word.  Copies synchronously; PH_OK, PH_EINVAL or PH_EHIP. */
+int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out);
+
 /* Library version string. */
 const char *ph_version(void);
 

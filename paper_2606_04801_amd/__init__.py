@@ -97,6 +97,8 @@ def lib():
         L.ph_init_device.restype = ctypes.c_int
         L.ph_device_report.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
         L.ph_device_report.restype = ctypes.c_int
+        L.ph_work_counters.argtypes = [vp, i32, ctypes.POINTER(i32)]
+        L.ph_work_counters.restype = ctypes.c_int
         L.ph_profile.argtypes = [i32]
         L.ph_profile.restype = ctypes.c_int
         L.ph_profile_read.argtypes = [ctypes.POINTER(ph_kernel_time), i32, ctypes.POINTER(i32)]
@@ -332,6 +334,16 @@ class Batch:
     def ph_backward(self, grad_birth, grad_death, stream=None):
         ph_backward(self.pairs, self.counts, self.out_off, self.img_off, grad_birth, grad_death, self.grad,
                     stream)
+
+    def work_counters(self):
+        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 8) array:
+        KEEP edges, KEEP squares, H0 nodes, dual nodes, H0 rounds, dual rounds, sequential
+        edges, error word.  Synchronises."""
+        out = (ctypes.c_int32 * (8 * self.n))()
+        rc = lib().ph_work_counters(_ptr(self.ws), self.n, out)
+        if rc != PH_OK:
+            raise PHError(rc, "ph_work_counters")
+        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 8).copy()
 
     def valid_mask(self):
         """Device bool mask over the packed pair slots holding a stored pair (no sync)."""

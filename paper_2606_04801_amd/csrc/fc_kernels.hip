@@ -1497,6 +1497,19 @@ int32_t ph_lut_config_count(int32_t ndim) {
 
 const char *ph_version(void) { return "flashcubical-gfx950 0.1"; }
 
+int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out) {
+    if (!d_ws || n < 1 || !h_out) return PH_EINVAL;
+    std::vector<int32_t> c((size_t)n * fc::CNT_WORDS);
+    if (hipMemcpy(c.data(), (const uint8_t *)d_ws + fc::off_cnt(n), c.size() * sizeof(int32_t),
+                  hipMemcpyDeviceToHost) != hipSuccess)
+        return PH_EHIP;
+    const int pick[8] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
+                         fc::CNT_SEQ, fc::CNT_ERR};
+    for (int i = 0; i < n; ++i)
+        for (int k = 0; k < 8; ++k) h_out[i * 8 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
+    return PH_OK;
+}
+
 int ph_profile(int32_t enable) {
     std::vector<fc::ProfRec> old;
     {

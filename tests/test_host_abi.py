@@ -121,3 +121,11 @@ def test_status_names_cover_codes():
     for code in (fc.PH_OK, fc.PH_EINVAL, fc.PH_ENAN, fc.PH_ECAPACITY, fc.PH_ENOMEM, fc.PH_EHIP,
                  fc.PH_EINTERNAL, fc.PH_EDISABLED):
         assert code in fc.STATUS_NAMES
+
+
+def test_work_counters_validation():
+    L = fc.lib()
+    out = (ctypes.c_int32 * 8)()
+    assert L.ph_work_counters(None, 1, out) == fc.PH_EINVAL
+    assert L.ph_work_counters(ctypes.c_void_p(1), 0, out) == fc.PH_EINVAL
+    assert L.ph_work_counters(ctypes.c_void_p(1), 1, None) == fc.PH_EINVAL
