@@ -5,8 +5,9 @@
 // in.bin (little-endian): int32 n, uint32 flags, int32 mode (0: ph_diagram, n must be 1;
 // 1: ph_diagram_batch; 2: ph_autotune then ph_diagram_batch), int32 tile2d, int32 tile3d
 // (-1: no tuning argument), int32 backward (1: also run ph_backward for the loss
-// sum over finite pairs of (death - birth)^2); then n x (int32 ndim, int32 ext[3]); then the
-// pixels of all instances, float32, concatenated.
+// sum over finite pairs of (death - birth)^2), int32 capacity per instance (-1: the bound);
+// then n x (int32 ndim, int32 ext[3]); then the pixels of all instances, float32,
+// concatenated.
 // out.bin: per instance int64 count, int32 status, then the stored pairs as int32 dim,
 // float32 birth, float32 death, int64 birth_cell, int64 death_cell, int32 birth_vertex,
 // int32 death_vertex; then, with backward, the float32 gradient of all pixels.
@@ -143,8 +144,8 @@ int main(int argc, char **argv) {
     if (argc != 3) { fprintf(stderr, "usage: driver in.bin out.bin\n"); return 2; }
     FILE *f = fopen(argv[1], "rb");
     if (!f) return 2;
-    int32_t hdr[6];
-    if (fread(hdr, 4, 6, f) != 6) return 2;
+    int32_t hdr[7];
+    if (fread(hdr, 4, 7, f) != 7) return 2;
     const int n = hdr[0], mode = hdr[2], backward = hdr[5];
     const uint32_t flags = (uint32_t)hdr[1];
     std::vector<ph_shape> shapes(n);
@@ -159,7 +160,7 @@ int main(int argc, char **argv) {
             if (k < s[0]) nv *= s[1 + k];
         }
         img_off[i + 1] = img_off[i] + nv;
-        out_off[i + 1] = out_off[i] + ph_capacity_bound(shapes[i]);
+        out_off[i + 1] = out_off[i] + (hdr[6] >= 0 ? hdr[6] : ph_capacity_bound(shapes[i]));
     }
     std::vector<float> img(img_off[n]);
     if (fread(img.data(), 4, img.size(), f) != img.size()) return 2;
@@ -236,7 +237,7 @@ int main(int argc, char **argv) {
         fwrite(&counts[i], 8, 1, o);
         fwrite(&status[i], 4, 1, o);
         const int64_t m = counts[i] < out_off[i + 1] - out_off[i] ? counts[i] : out_off[i + 1] - out_off[i];
-        for (int64_t j = 0; j < m && status[i] == PH_OK; ++j) {
+        for (int64_t j = 0; j < m && (status[i] == PH_OK || status[i] == PH_ECAPACITY); ++j) {
             const int64_t k = out_off[i] + j;
             const int32_t dm = dim[k];
             fwrite(&dm, 4, 1, o); fwrite(&birth[k], 4, 1, o); fwrite(&death[k], 4, 1, o);

@@ -38,10 +38,11 @@ def driver():
     return emu_build.build("asan")
 
 
-def run(exe, imgs, mode=0, tuning=None, backward=False):
-    """(per-instance (pairs, status), gradient or None) from the emulated kernels."""
+def run(exe, imgs, mode=0, tuning=None, backward=False, capacity=-1, with_count=False):
+    """(per-instance (pairs, status), gradient or None) from the emulated kernels.  With
+    with_count, each instance gives (pairs, status, count) instead."""
     imgs = [np.ascontiguousarray(a, dtype=np.float32) for a in imgs]
-    hdr = struct.pack("<6i", len(imgs), 3, mode, *(tuning if tuning else (-1, -1)), int(backward))
+    hdr = struct.pack("<7i", len(imgs), 3, mode, *(tuning if tuning else (-1, -1)), int(backward), capacity)
     for a in imgs:
         ext = list(a.shape) + [1] * (3 - a.ndim)
         hdr += struct.pack("<4i", a.ndim, *ext)
@@ -59,13 +60,13 @@ def run(exe, imgs, mode=0, tuning=None, backward=False):
     for a in imgs:
         cnt, st = struct.unpack_from("<qi", raw, pos)
         pos += 12
-        m = cnt if st == 0 else 0
+        m = cnt if st == 0 else (min(cnt, capacity) if st == -3 and capacity >= 0 else 0)
         rec = np.frombuffer(raw, REC, count=m, offset=pos)
         pos += m * REC.itemsize
         res = np.zeros(m, oracle.PAIR_DTYPE)
         for f in oracle.PAIR_DTYPE.names:
             res[f] = rec[f]
-        out.append((res, st))
+        out.append((res, st, cnt) if with_count else (res, st))
     grad = None
     if backward:
         grad = np.frombuffer(raw, "<f4", offset=pos)
@@ -151,3 +152,34 @@ def test_full_size_workloads_against_digests():
             out, _ = run(exe, [make(kind, args) for _, _, kind, args in part], mode=1)
             for (c, idx, _, _), (got, st) in zip(part, out):
                 assert st == 0 and pair_digest(got) == D[c][str(idx)]["pairs_sha256"], (c, idx)
+
+
+def staircase(n):
+    """1 x (2n+1) row: minima decreasing to the right, saddles increasing.  Every H0 merge waits
+    for the previous one, so the parallel rounds run out and the sequential finish is used."""
+    a = np.zeros(2 * n + 1, np.float32)
+    a[0::2] = np.linspace(0.5, 0.1, n + 1).astype(np.float32)
+    a[1::2] = np.linspace(1.0, 2.0, n).astype(np.float32)
+    return a.reshape(1, -1)
+
+
+def test_edge_cases(driver):
+    rng = np.random.default_rng(5)
+    cb = (np.indices((33, 47)).sum(axis=0) % 2).astype(np.float32)          # checkerboard, all ties
+    specials = np.array([[np.inf, -np.inf, -0.0, 0.0, 1e-45, -1e-45, 3.4e38, -3.4e38]] * 5, np.float32)
+    specials[2:] = specials[2:, ::-1]
+    cases = [staircase(150), staircase(150)[:, ::-1].copy(), np.zeros((17, 23), np.float32), cb,
+             S.levels((1, 5000), 7, 1), S.levels((5000, 1), 7, 2), S.levels((1, 1, 3000), 5, 3),
+             S.levels((3000, 1, 1), 5, 4), S.levels((2, 2, 700), 3, 5), specials,
+             rng.permutation(64 * 64).reshape(64, 64).astype(np.float32)]
+    for img in cases:
+        (got, st), = run(driver, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
+def test_capacity_overflow_keeps_true_count(driver):
+    img = S.uniform((40, 40), 9)
+    ref = oracle.diagram(img)
+    (got, st, cnt), = run(driver, [img], capacity=25, with_count=True)[0]
+    assert st == -3 and cnt == len(ref)                                     # PH_ECAPACITY
+    assert diff_pairs(got, ref[:25]) is None
