@@ -168,6 +168,8 @@ def _torch():
 
 def _stream_ptr(stream):
     torch = _torch()
+    if stream is None and not torch.cuda.is_available():
+        return ctypes.c_void_p(None)             # no device: the library reports it, not the binding
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
 

@@ -5,6 +5,7 @@ runtime in this folder and linked with driver.cpp.  Variants:
   asan   g++, AddressSanitizer + UBSan (fatal), a redzone around every LDS array
   poison g++ -O2, LDS refilled with a poison byte before every block
   msan   clang++, MemorySanitizer (LDS, workspace and outputs start uninitialised)
+  so     the library's C ABI as a host shared object (no driver), for the binding tests
 Every build leaves 256 unused bytes after each workspace array (FC_ARRAY_GAP), which the driver
 poisons.  Executables go to tests/cpu_emulation/_build/ and are rebuilt when a source changes.
 """
@@ -20,8 +21,8 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 CSRC = os.path.join(ROOT, "paper_2606_04801_amd", "csrc")
 INC = os.path.join(ROOT, "include")
 OUT = os.path.join(HERE, "_build")
-SOURCES = [os.path.join(CSRC, "fc_kernels.hip"), os.path.join(CSRC, "fc_lut.cpp"), os.path.join(HERE, "driver.cpp")]
-DEPS = SOURCES + [os.path.join(CSRC, "fc_common.h"), os.path.join(INC, "flashcubical.h"),
+SOURCES = [os.path.join(CSRC, "fc_kernels.hip"), os.path.join(CSRC, "fc_lut.cpp"), os.path.join(HERE, "runtime.cpp")]
+DEPS = SOURCES + [os.path.join(HERE, "driver.cpp"), os.path.join(CSRC, "fc_common.h"), os.path.join(INC, "flashcubical.h"),
                   os.path.join(HERE, "hip", "hip_runtime.h")]
 
 COMMON = ["-std=c++20", "-D__HIPCC__", "-DFC_ARRAY_GAP=256", "-I", HERE, "-I", INC, "-I", CSRC, "-pthread"]
@@ -31,6 +32,8 @@ VARIANTS = {
     "poison": ("g++", ["-O2"]),
     "msan": ("/opt/rocm/llvm/bin/clang++", ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=memory",
                                             "-fsanitize-memory-track-origins=2"]),
+    # the library's C ABI as a host shared object, for driving the Python binding on the CPU
+    "so": ("g++", ["-O2", "-g", "-fPIC", "-shared"]),
 }
 
 
@@ -47,8 +50,13 @@ def build(variant: str = "asan") -> str:
     if os.path.exists(exe) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
         return exe
     srcs = []
-    for s in SOURCES:
+    for s in SOURCES + ([] if variant == "so" else [os.path.join(HERE, "driver.cpp")]):
         srcs += ["-x", "c++", s]
+    if variant == "so":
+        exe = os.path.join(OUT, "libflashcubical_emulated.so")
+        stamp = exe + ".sha256"
+        if os.path.exists(exe) and os.path.exists(stamp) and open(stamp).read() == h.hexdigest():
+            return exe
     cmd = [cxx] + COMMON + flags + srcs + ["-o", exe + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:

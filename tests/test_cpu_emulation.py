@@ -183,3 +183,12 @@ def test_capacity_overflow_keeps_true_count(driver):
     (got, st, cnt), = run(driver, [img], capacity=25, with_count=True)[0]
     assert st == -3 and cnt == len(ref)                                     # PH_ECAPACITY
     assert diff_pairs(got, ref[:25]) is None
+
+
+def test_binding_batch_end_to_end():
+    """The Python binding's Batch (offsets, buffers, autotune, counters, profiling, backward)
+    against the host build of the C ABI, in a separate process."""
+    so = emu_build.build("so")
+    script = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cpu_emulation", "binding_check.py")
+    r = subprocess.run([sys.executable, script, so], capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0 and "binding ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
