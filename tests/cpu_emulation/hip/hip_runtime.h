@@ -9,7 +9,7 @@
 //     values between the 64 lanes of a wave through a per-wave barrier, so they must be
 //     reached by every lane of the wave, as on the GPU; a barrier that cannot complete aborts;
 //   * a thread runs until it waits, so the interleaving of threads between barriers is one
-//     fixed order (the GPU may pick any): results that depend on it would not be caught here;
+//     fixed order (the GPU may pick any), unless EMU_SHUFFLE is set (see below);
 //   * atomics are plain host atomics;
 //   * __shared__ variables are static; before every block they are overwritten with a poison
 //     byte (or, under MemorySanitizer, marked uninitialised), so reading LDS that the block did
@@ -106,6 +106,24 @@ struct EmuSched {
 };
 inline EmuSched emu_sched;
 
+// EMU_SHUFFLE=<seed>: threads are resumed in a random order on every scheduling pass, and a
+// thread may give up its turn at any atomic operation, so that other interleavings between
+// barriers are tried as well.
+inline uint64_t emu_shuffle_state() {
+    static uint64_t seed = [] {
+        const char *e = getenv("EMU_SHUFFLE");
+        return e ? (uint64_t)strtoull(e, nullptr, 10) * 2654435761ull + 1 : 0ull;
+    }();
+    return seed;
+}
+inline uint64_t emu_rand() {
+    static uint64_t x = emu_shuffle_state();
+    x ^= x << 13;
+    x ^= x >> 7;
+    x ^= x << 17;
+    return x;
+}
+
 inline void emu_to_fiber(EmuFiber &f) {
 #if EMU_ASAN_FIBERS
     void *fake = nullptr;
@@ -136,6 +154,12 @@ inline void emu_to_main(EmuFiber &f, bool dying) {
     f.done = true;
     emu_to_main(f, true);
     abort();                                   // a finished fiber is never resumed
+}
+inline void emu_maybe_yield() {
+    if (!emu_shuffle_state() || emu_sched.cur < 0 || (emu_rand() & 3) != 0) return;
+    EmuFiber &f = emu_sched.fib[emu_sched.cur];
+    f.wait = nullptr;
+    emu_to_main(f, false);
 }
 inline void emu_barrier_wait(EmuBarrier &b) {
     const unsigned g = b.gen;
@@ -172,9 +196,13 @@ inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void 
         f.wait = nullptr;
     }
     unsigned left = nt;
+    std::vector<unsigned> order(nt);
+    for (unsigned t = 0; t < nt; ++t) order[t] = t;
     while (left > 0) {
         bool moved = false;
-        for (unsigned t = 0; t < nt; ++t) {
+        if (emu_shuffle_state())
+            for (unsigned k = nt; k > 1; --k) std::swap(order[k - 1], order[emu_rand() % k]);
+        for (unsigned t : order) {
             EmuFiber &f = s.fib[t];
             if (f.done || (f.wait && f.wait->gen == f.wait_gen)) continue;
             f.wait = nullptr;
@@ -186,6 +214,7 @@ inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void 
             moved = true;
             if (f.done) --left;
         }
+        s.cur = -1;
         if (!moved) {
             fprintf(stderr, "emulation: deadlock, %u threads wait at a barrier that cannot complete\n", left);
             abort();
@@ -237,20 +266,26 @@ inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline unsigned __float_as_uint(float f) { unsigned u; memcpy(&u, &f, 4); return u; }
 inline float __int_as_float(int i) { float f; memcpy(&f, &i, 4); return f; }
 
-template <typename T> inline T atomicAdd(T *p, T v) { return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST); }
+template <typename T> inline T atomicAdd(T *p, T v) {
+    emu_maybe_yield();
+    return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
+}
 inline float atomicAdd(float *p, float v) {
+    emu_maybe_yield();
     float old, nw;
     __atomic_load(p, &old, __ATOMIC_SEQ_CST);
     do { nw = old + v; } while (!__atomic_compare_exchange(p, &old, &nw, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST));
     return old;
 }
 template <typename T> inline T atomicMin(T *p, T v) {
+    emu_maybe_yield();
     T old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
     while (v < old && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
     }
     return old;
 }
 template <typename T> inline T atomicCAS(T *p, T cmp, T v) {
+    emu_maybe_yield();
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
 }
@@ -262,8 +297,14 @@ template <typename T> inline T atomicCAS(T *p, T cmp, T v) {
 #else
 #define __HIP_MEMORY_SCOPE_WORKGROUP 0
 #define __HIP_MEMORY_SCOPE_AGENT 0
-template <typename T> inline T __hip_atomic_load(T *p, int, int) { return __atomic_load_n(p, __ATOMIC_SEQ_CST); }
-template <typename T> inline void __hip_atomic_store(T *p, T v, int, int) { __atomic_store_n(p, v, __ATOMIC_SEQ_CST); }
+template <typename T> inline T __hip_atomic_load(T *p, int, int) {
+    emu_maybe_yield();
+    return __atomic_load_n(p, __ATOMIC_SEQ_CST);
+}
+template <typename T> inline void __hip_atomic_store(T *p, T v, int, int) {
+    emu_maybe_yield();
+    __atomic_store_n(p, v, __ATOMIC_SEQ_CST);
+}
 #endif
 
 // host API subset

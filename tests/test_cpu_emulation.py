@@ -192,3 +192,21 @@ def test_binding_batch_end_to_end():
     script = os.path.join(os.path.dirname(os.path.abspath(__file__)), "cpu_emulation", "binding_check.py")
     r = subprocess.run([sys.executable, script, so], capture_output=True, text=True, timeout=600)
     assert r.returncode == 0 and "binding ok" in r.stdout, r.stdout[-2000:] + r.stderr[-4000:]
+
+
+@pytest.mark.parametrize("seed", [1, 2])
+def test_random_interleavings(driver, monkeypatch, seed):
+    """Threads resumed in random order, with turns given up at atomics: the results must not
+    depend on the interleaving between barriers."""
+    monkeypatch.setenv("EMU_SHUFFLE", str(seed))
+    imgs = mixed_batch() + [staircase(60), S.uniform((48, 48), 11)]
+    out, grad = run(driver, imgs, mode=1, backward=True)
+    off = 0
+    for img, (got, st) in zip(imgs, out):
+        ref = oracle.diagram(img)
+        assert st == 0 and diff_pairs(got, ref) is None, img.shape
+        f = ref["death_cell"] >= 0
+        d = np.where(f, ref["death"] - ref["birth"], 0).astype(np.float32)
+        g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
+        np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
+        off += img.size
