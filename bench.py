@@ -14,7 +14,8 @@ are compared bit for bit before any timing.
 roofline: the dominant kernel of the batched step (largest event-timed total over the timed
 profiled steps), its algorithmic bytes per launch divided by its mean launch duration, against
 8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, when a summary
-for this exact library build is given with --traffic-json, else null.
+for this exact library build is given with --traffic-json, else null (see --profile-steps and
+--traffic-from).
 
 cpu_baseline: the CPU oracle (single-threaded C, one process per host core, at most 16) on a
 bounded sample of the same workload (one instance per core, half volumes and half images,
@@ -121,6 +122,73 @@ def algorithmic_bytes(name, wc, npairs, shapes):
     return 0
 
 
+# ------------------------------------------------------------------ HBM traffic --
+# Under `rocprofv3 --pmc FETCH_SIZE` (then `--pmc WRITE_SIZE`) run `bench.py --profile-steps K`:
+# K eager batched steps, then one elementwise kernel (torch.neg) over COPY_BYTES, which must read
+# and write exactly COPY_BYTES.  --traffic-from reads the two counter CSVs, scales each counter
+# by what it reads for that kernel and writes bytes per launch per kernel for --traffic-json.
+COPY_BYTES = 1 << 30
+KERNEL_KEYS = ["k_classify2d", "k_classify3d", "k_sort", "k_resolve_edges", "k_resolve_facets", "k_uf<false>",
+               "k_uf<true>", "k_output", "k_plan", "k_zero", "k_scatter"]
+PROFILE_NAMES = {"k_uf<false>": "k_uf(h0)", "k_uf<true>": "k_uf(top)"}
+
+
+def profile_steps(steps):
+    import torch
+    import paper_2606_04801_amd as fc
+    shapes = workload_shapes()
+    bt = fc.Batch(shapes, device="cuda:0")
+    imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+    for k in range(steps):
+        bt.ph_diagram_batch()
+        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+        bt.ph_backward(-2.0 * diff, 2.0 * diff)
+        torch.cuda.synchronize()
+        print("bench: profile step %d done" % k, file=sys.stderr, flush=True)
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    torch.neg(a, out=b)                          # one elementwise kernel: reads and writes COPY_BYTES
+    torch.cuda.synchronize()
+    bt.check()
+    print("bench: profile run done", file=sys.stderr, flush=True)
+
+
+def _counter_means(path, counter):
+    """{kernel key: mean counter value (KiB) per dispatch}, plus the copy kernel's under 'copy'."""
+    import csv
+    acc = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            name = row.get("Kernel_Name", "")
+            key = "copy" if "neg_kernel" in name else next((k for k in KERNEL_KEYS if k in name), None)
+            if key is None:
+                continue
+            v = acc.setdefault(key, [0.0, 0])
+            v[0] += float(row["Counter_Value"])
+            v[1] += 1
+    return {k: v[0] / v[1] for k, v in acc.items()}
+
+
+def traffic_from(fetch_csv, write_csv, out_json):
+    fetch, write = _counter_means(fetch_csv, "FETCH_SIZE"), _counter_means(write_csv, "WRITE_SIZE")
+    if "copy" not in fetch or "copy" not in write:
+        raise SystemExit("bench: no copy kernel in the counter files")
+    fs, ws = COPY_BYTES / (fetch["copy"] * 1024), COPY_BYTES / (write["copy"] * 1024)
+    res = {"_scale": {"fetch": fs, "write": ws}}
+    for k in fetch:
+        if k == "copy" or k not in write:
+            continue
+        res[PROFILE_NAMES.get(k, k)] = round(fetch[k] * 1024 * fs + write[k] * 1024 * ws)
+    with open(out_json, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,7 +197,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
     ap.add_argument("--traffic-json", default=None)
+    ap.add_argument("--profile-steps", type=int, default=0, help="only run K eager steps and a calibration copy")
+    ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from(*args.traffic_from)
+        return
+    if args.profile_steps:
+        profile_steps(args.profile_steps)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the batch would shard by instance "
               "across GPUs; no multi-GPU path is built)", file=sys.stderr)
