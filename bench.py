@@ -8,8 +8,10 @@ seeds 3000+i) in one batch; loss = sum over finite pairs of (death - birth)^2, s
 scatters -2(d-b) to each birth pixel and +2(d-b) to each death pixel.  A step is one pass of
 the whole path over the batch: forward (ph_diagram_batch), loss gradient, backward
 (ph_backward).  The batched step is captured once in a HIP graph and replayed; the per-image
-form is a plain loop of ph_diagram + ph_backward calls per instance on one stream.  Both forms
-are compared bit for bit before any timing.
+form is a plain loop of ph_diagram + ph_backward calls per instance on one stream; the forward
+alone is timed as well.  Pair capacities come from a sizing pass on the same inputs, and timed
+steps alternate between two copies of inputs and buffers.  All forms are compared bit for bit
+before any timing.
 
 roofline: the dominant kernel of the batched step (largest event-timed total over the timed
 profiled steps), its algorithmic bytes per launch divided by its mean launch duration, against
@@ -44,12 +46,20 @@ N3, N2 = 64, 64
 SHAPE3, SIG3, SHAPE2, SIG2 = (96, 96, 96), 3.0, (512, 512), 6.0
 
 
+def use_small_workload():
+    """A reduced workload of the same kind, for checking this script against the host build of
+    the library (--host-library); never used for a reported number."""
+    global N3, N2, SHAPE3, SHAPE2
+    N3, N2, SHAPE3, SHAPE2 = 3, 3, (20, 18, 22), (64, 70)
+
+
 def workload_shapes():
     return [SHAPE3] * N3 + [SHAPE2] * N2
 
 
 def workload_desc():
-    return "64 x 96^3 field sigma 3 + 64 x 512^2 field sigma 6, H0+H_top, batched fwd+bwd"
+    return "%d x %s field sigma 3 + %d x %s field sigma 6, H0+H_top, batched fwd+bwd" % (
+        N3, "x".join(map(str, SHAPE3)), N2, "x".join(map(str, SHAPE2)))
 
 
 def _oracle_instance(item):
@@ -72,19 +82,22 @@ def cpu_baseline(workers: int):
     each run single-threaded in its own process; the rate is sample voxels over wall time.
     Returns the baseline record and {batch index: (pairs, gradient)} for the parity check."""
     from multiprocessing import get_context
-    n3 = (workers + 1) // 2
+    n3 = min((workers + 1) // 2, N3)
+    n2 = min(workers - n3, N2)
     items = [(i, SHAPE3, SIG3, 2000 + i) for i in range(n3)] + \
-            [(N3 + i, SHAPE2, SIG2, 3000 + i) for i in range(workers - n3)]
+            [(N3 + i, SHAPE2, SIG2, 3000 + i) for i in range(n2)]
     t0 = time.perf_counter()
     with get_context("fork").Pool(workers) as pool:
         res = pool.map(_oracle_instance, items, chunksize=1)
     wall = time.perf_counter() - t0
     vox = sum(r[1] for r in res)
     ref = {r[0]: (r[3], r[4]) for r in res}
-    rec = {"value": round(vox / wall / 1e6, 5), "unit": "Mvoxels/s", "cores": workers, "kind": "oracle",
-           "sample": "%d x 96^3 volumes (seeds 2000..) + %d x 512^2 images (seeds 3000..) of the workload, "
+    rec = {"value": round(vox / wall / 1e6, 5), "unit": "Mvoxels/s", "cores": min(workers, len(items)),
+           "kind": "oracle",
+           "sample": "%d x %s volumes (seeds 2000..) + %d x %s images (seeds 3000..) of the workload, "
                      "forward + gradient, one single-threaded C process per core, %.1f s wall "
-                     "(single-process sum %.1f s)" % (n3, workers - n3, wall, sum(r[2] for r in res))}
+                     "(single-process sum %.1f s)" % (n3, "x".join(map(str, SHAPE3)), n2,
+                                                     "x".join(map(str, SHAPE2)), wall, sum(r[2] for r in res))}
     return rec, ref
 
 
@@ -199,6 +212,8 @@ def main():
     ap.add_argument("--traffic-json", default=None)
     ap.add_argument("--profile-steps", type=int, default=0, help="only run K eager steps and a calibration copy")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
+    ap.add_argument("--host-library", default=None,
+                    help="check this script on the CPU against a host build of the C ABI (small workload)")
     args = ap.parse_args()
     if args.traffic_from:
         traffic_from(*args.traffic_from)
@@ -211,6 +226,8 @@ def main():
               "across GPUs; no multi-GPU path is built)", file=sys.stderr)
         sys.exit(2)
 
+    if args.host_library:
+        use_small_workload()
     shapes = workload_shapes()
     nvox = sum(int(np.prod(s)) for s in shapes)
     line = {"metric": METRIC, "value": None, "unit": "Mvoxels/s", "n_gpus": 1, "steps": args.steps,
@@ -219,6 +236,8 @@ def main():
             "config": {"workload": workload_desc(), "instances": len(shapes), "voxels": nvox}}
 
     import paper_2606_04801_amd as fc
+    if args.host_library:
+        fc.LIB_PATH = args.host_library
     fc.lib()
     import torch
     ref = {}
@@ -227,7 +246,10 @@ def main():
         print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(workers)
     gpu = torch.cuda.is_available()
-    if not gpu or not fc.device_path_enabled():
+    if args.host_library:
+        line.update(run_gpu(fc, torch, shapes, args, ref, dev=torch.device("cpu")))
+        line["status"] = "host-library check, not a measurement"
+    elif not gpu or not fc.device_path_enabled():
         line["status"] = ("no GPU" if not gpu else
                           "device path switched off (its first launches faulted the GPU and no cause "
                           "has been shown); set %s=1 to measure" % fc.DEVICE_PATH_ENV)
@@ -237,97 +259,133 @@ def main():
 
 
 def same_bits(a, b):
-    return len(a) == len(b) and all(np.array_equal(np.asarray(a[f]).view(np.uint8), np.asarray(b[f]).view(np.uint8))
+    """Pair arrays equal field by field, floats compared by their bits."""
+    return len(a) == len(b) and all(np.array_equal(np.ascontiguousarray(a[f]).view(np.uint8),
+                                                   np.ascontiguousarray(b[f]).view(np.uint8))
                                     for f in a.dtype.names)
 
 
-def run_gpu(fc, torch, shapes, args, ref):
-    dev = torch.device("cuda:0")
+def step_bytes(prof_names, wc, npairs, shapes):
+    """Algorithmic bytes of one batched forward + backward step (kernel models summed)."""
+    return sum(algorithmic_bytes(k, wc, npairs, shapes) for k in prof_names)
+
+
+def run_gpu(fc, torch, shapes, args, ref, dev=None):
+    dev = dev or torch.device("cuda:0")
+    cuda = dev.type == "cuda"
+    sync = torch.cuda.synchronize if cuda else (lambda: None)
     print("bench: generating %d instances" % len(shapes), file=sys.stderr, flush=True)
     imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
+    host = [torch.from_numpy(a) for a in imgs]
     rc = fc.lib().ph_init_device()
     if rc != fc.PH_OK:
         raise fc.PHError(rc, "ph_init_device")
-    bt = fc.Batch(shapes, device=dev)
-    bt.set_images([torch.from_numpy(a) for a in imgs])
 
-    def batched_step():
+    # sizing pass with the never-overflowing capacity, then exact capacities: the pair buffers
+    # (and the loss-gradient arithmetic over them) stay as small as the diagrams
+    print("bench: sizing pass", file=sys.stderr, flush=True)
+    sizing = fc.Batch(shapes, device=dev)
+    sizing.set_images(host)
+    sizing.ph_diagram_batch()
+    sync()
+    sizing.check()
+    caps = sizing.counts.cpu().numpy().tolist()
+    del sizing
+    if cuda:
+        torch.cuda.empty_cache()
+
+    # two copies of inputs and buffers; timed steps alternate between them so that a step does
+    # not find its inputs in the caches from the step before
+    bts = []
+    for _ in range(2):
+        bt = fc.Batch(shapes, device=dev, capacities=caps)
+        bt.set_images(host)
+        bts.append(bt)
+
+    def batched_step(bt, backward=True):
         bt.ph_diagram_batch()
-        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
-        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
-        bt.ph_backward(-2.0 * diff, 2.0 * diff)
+        if backward:
+            fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+            diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+            bt.ph_backward(-2.0 * diff, 2.0 * diff)
 
-    # per-image plain calls: buffers made once, calls in a loop on the current stream
-    singles = []
-    for i, a in enumerate(imgs):
-        t = bt.image(i)
-        cap = fc.capacity_bound(a.shape)
-        singles.append(dict(img=t, bufs=fc.PairBuffers(cap, dev), ws=fc.Workspace(),
-                            grad=torch.empty(a.shape, dtype=torch.float32, device=dev),
-                            counts=torch.zeros(1, dtype=torch.int64, device=dev),
-                            off=torch.tensor([0, cap], dtype=torch.int64, device=dev),
-                            ioff=torch.zeros(1, dtype=torch.int64, device=dev)))
+    # per-image plain calls on the same inputs, one stream, no graph
+    singles = [[], []]
+    for c in range(2):
+        for i in range(len(imgs)):
+            singles[c].append(dict(img=bts[c].image(i), cap=int(caps[i]), ws=fc.Workspace(),
+                                   grad=torch.empty(imgs[i].shape, dtype=torch.float32, device=dev),
+                                   off=torch.tensor([0, max(int(caps[i]), 1)], dtype=torch.int64, device=dev),
+                                   ioff=torch.zeros(1, dtype=torch.int64, device=dev)))
 
-    def per_image_step():
-        for s in singles:
-            d = fc.ph_diagram(s["img"], capacity=s["bufs"].cap, ws=s["ws"])
-            s["bufs"], s["diag"] = d.bufs, d
-            n = s["bufs"].cap
-            idx = torch.arange(n, device=dev)
+    def per_image_step(c):
+        for s in singles[c]:
+            d = fc.ph_diagram(s["img"], capacity=s["cap"], ws=s["ws"])
+            s["diag"] = d
+            idx = torch.arange(d.bufs.cap, device=dev)
             fin = (idx < d.count_t) & (d.bufs.death_cell >= 0)
             diff = torch.where(fin, d.bufs.death - d.bufs.birth, 0.0)
             fc.ph_backward(d.bufs, d.count_t, s["off"], s["ioff"], -2.0 * diff, 2.0 * diff, s["grad"])
 
-    # parity: batched and per-image results must agree bit for bit
+    # parity: batched, per-image and (for the sampled instances) the oracle, bit for bit
     print("bench: parity", file=sys.stderr, flush=True)
-    batched_step()
-    per_image_step()
-    torch.cuda.synchronize()
+    bt = bts[0]
+    batched_step(bt)
+    per_image_step(0)
+    sync()
     bt.check()
     res = bt.results()
-    for i, s in enumerate(singles):
+    for i, s in enumerate(singles[0]):
         if not same_bits(res[i], s["diag"].numpy()):
             raise SystemExit("bench: batched and per-image diagrams differ on instance %d" % i)
         g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]]
         if not torch.allclose(g1, s["grad"].reshape(-1), rtol=1e-6, atol=1e-7):
             raise SystemExit("bench: batched and per-image gradients differ on instance %d" % i)
-    for i, (p, g) in ref.items():                       # the oracle's own runs of two instances
+    for i, (p, g) in ref.items():
         if not same_bits(res[i], p):
             raise SystemExit("bench: instance %d differs from the oracle" % i)
         g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]].cpu().numpy()
         if not np.allclose(g1, g.reshape(-1), rtol=1e-6, atol=1e-7):
             raise SystemExit("bench: gradient of instance %d differs from the oracle" % i)
 
-    # batched form: one graph per step, replayed
-    for _ in range(args.warmup):
-        batched_step()
-    torch.cuda.synchronize()
-    graph = torch.cuda.CUDAGraph()
-    with torch.cuda.graph(graph):
-        batched_step()
-    for _ in range(args.warmup):
-        graph.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        graph.replay()
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / args.steps
+    def capture(fn):
+        """A replayable step: a captured HIP graph on the GPU (the host check replays eagerly)."""
+        for _ in range(args.warmup):
+            fn()
+        sync()
+        if not cuda:
+            return fn
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g.replay
 
-    for _ in range(args.warmup):
-        per_image_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        per_image_step()
-    torch.cuda.synchronize()
-    t_p = (time.perf_counter() - t0) / args.steps
+    def timed(run):
+        for k in range(args.warmup):
+            run(k)
+        sync()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            run(k)
+        sync()
+        return (time.perf_counter() - t0) / args.steps
 
-    # per-kernel event timing of the batched step (eager, same launches as the graph)
+    print("bench: batched forward + backward (graph replay)", file=sys.stderr, flush=True)
+    g_fb = [capture(lambda b=b: batched_step(b)) for b in bts]
+    t_b = timed(lambda k: g_fb[k % 2]())
+    for b in bts:
+        b.check()
+    print("bench: batched forward only (graph replay)", file=sys.stderr, flush=True)
+    g_f = [capture(lambda b=b: batched_step(b, backward=False)) for b in bts]
+    t_f = timed(lambda k: g_f[k % 2]())
+    print("bench: per-image plain calls", file=sys.stderr, flush=True)
+    t_p = timed(lambda k: per_image_step(k % 2))
+
+    # per-kernel event timing of the batched step (eager, the same launches as the graph)
     fc.profile(True)
-    for _ in range(args.steps):
-        batched_step()
-    torch.cuda.synchronize()
+    for k in range(args.steps):
+        batched_step(bts[k % 2])
+    sync()
     prof = fc.profile_read()
     fc.profile(False)
     npairs = int(bt.counts.cpu().numpy().sum())
@@ -340,16 +398,24 @@ def run_gpu(fc, torch, shapes, args, ref):
     if args.traffic_json and os.path.exists(args.traffic_json):
         traffic = json.load(open(args.traffic_json)).get(name)
     nvox = sum(int(np.prod(s)) for s in shapes)
+    sb = step_bytes(prof.keys(), wc, npairs, shapes)
+    fb = sb - algorithmic_bytes("k_zero", wc, npairs, shapes) - algorithmic_bytes("k_scatter", wc, npairs, shapes)
+    frac = lambda b, t: round(b / t / (HBM_PEAK_GBS * 1e9), 5)
     return {
         "value": round(nvox / t_b / 1e6, 3),
         "ms_per_step": round(t_b * 1e3, 4),
-        "per_image": {"value": round(nvox / t_p / 1e6, 3), "ms_per_step": round(t_p * 1e3, 4)},
+        "forms": {
+            "batched_fwd_bwd": {"value": round(nvox / t_b / 1e6, 3), "ms": round(t_b * 1e3, 4), "hbm_frac": frac(sb, t_b)},
+            "batched_fwd": {"value": round(nvox / t_f / 1e6, 3), "ms": round(t_f * 1e3, 4), "hbm_frac": frac(fb, t_f)},
+            "per_image_fwd_bwd": {"value": round(nvox / t_p / 1e6, 3), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p)},
+        },
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},
         "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
         "work": {"keep_edges": int(wc[:, 0].sum()), "keep_squares": int(wc[:, 1].sum()),
                  "h0_nodes": int(wc[:, 2].sum()), "dual_nodes": int(wc[:, 3].sum()),
-                 "max_rounds": int(wc[:, 4:6].max()), "sequential_edges": int(wc[:, 6].sum())},
+                 "pairs": npairs, "max_rounds": int(wc[:, 4:6].max()),
+                 "sequential_edges": int(wc[:, 6].sum())},
     }
 
 

@@ -241,7 +241,10 @@ def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, w
                stream=None) -> Diagram:
     """Persistence diagram of one float32 image (H, W) or volume (D, H, W) on the GPU."""
     torch = _torch()
-    if not (img.is_cuda and img.dtype == torch.float32 and img.dim() in (2, 3)):
+    # a host tensor would hand the kernels a host pointer; without a GPU the library itself
+    # reports that it cannot run, so the check only matters when one is present
+    on_device = img.is_cuda or not torch.cuda.is_available()
+    if not (on_device and img.dtype == torch.float32 and img.dim() in (2, 3)):
         raise PHError(PH_EINVAL, "ph_diagram expects a 2D/3D float32 CUDA tensor")
     img = img.contiguous()
     shp = make_shape(img.shape)
@@ -275,14 +278,19 @@ class Batch:
     launches and the forward + backward pair can be captured in a HIP graph.
     """
 
-    def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda"):
+    def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda", capacities=None):
+        """capacities: pairs stored per instance (default: the bound pixels + top cells, which
+        never overflows); a smaller one, e.g. the counts of an earlier call on the same
+        inputs, keeps the pair buffers small."""
         torch = _torch()
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
         self.n = len(self.shapes)
         self.flags = flags
         self.device = torch.device(device)
         sizes = [int(np.prod(s)) for s in self.shapes]
-        caps = [capacity_bound(s) for s in self.shapes]
+        caps = [capacity_bound(s) for s in self.shapes] if capacities is None else [max(int(c), 1) for c in capacities]
+        if len(caps) != self.n:
+            raise PHError(PH_EINVAL, "capacities")
         self.img_off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
         self.out_off_h = np.concatenate([[0], np.cumsum(caps)]).astype(np.int64)
         self.total_voxels = int(self.img_off_h[-1])

@@ -1553,8 +1553,7 @@ int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count) {
     return rc;
 }
 
-/* Upload the lookup tables to the current device (normally done on first use) and read
- * them back; returns PH_OK when the device copy equals the host tables. */
+/* Report of the device limits and of every kernel's resources; launches nothing. */
 int ph_device_report(char *buf, size_t len) {
     if (!buf || len == 0) return PH_EINVAL;
     buf[0] = 0;
@@ -1563,6 +1562,8 @@ int ph_device_report(char *buf, size_t len) {
     return fc::check_kernels(dev, buf, len);
 }
 
+/* Copy the lookup tables to the current device (normally done on first use) and read them
+ * back; PH_OK when the device copy equals the host tables. */
 int ph_init_device(void) {
     int rc = fc::device_luts();
     if (rc != PH_OK) return rc;

@@ -210,3 +210,20 @@ def test_random_interleavings(driver, monkeypatch, seed):
         g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
         np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
         off += img.size
+
+
+def test_bench_flow_against_host_library():
+    """bench.py's measuring path (sizing pass, batched and per-image forms, parity with each
+    other and with the oracle, profiling, counters, JSON line) run on the CPU against the host
+    build of the C ABI, on a reduced workload."""
+    import json
+    so = emu_build.build("so")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1")
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--host-library", so, "--steps", "1",
+                        "--warmup", "1", "--cpu-workers", "2"], capture_output=True, text=True, timeout=900, env=env)
+    assert r.returncode == 0, r.stderr[-4000:]
+    line = json.loads(r.stdout.strip().splitlines()[-1])
+    assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
+    assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd", "per_image_fwd_bwd"}
+    assert line["cpu_baseline"]["kind"] == "oracle" and line["work"]["pairs"] > 0
