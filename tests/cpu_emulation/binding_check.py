@@ -57,6 +57,31 @@ def main(so):
     bt2.ph_diagram_batch()
     for r, ref in zip(bt2.results(), refs):
         assert diff_pairs(r, ref) is None
+    # autograd: PHDiagramFn forward + backward against finite differences of the oracle's loss
+    Fn = fc.PHDiagramFn
+    for k in range(2):
+        x0 = S.tie_free((16, 16), 4000 + k).astype(np.float64)
+        x = torch.tensor(x0, dtype=torch.float32, requires_grad=True)
+        b, d, dim = Fn.apply(x)
+        ref = oracle.diagram(x0.astype(np.float32))
+        assert torch.equal(b, torch.from_numpy(ref["birth"].copy()))
+        fin = torch.isfinite(d)
+        ((d - b)[fin] ** 2).sum().backward()
+        g = x.grad.numpy().reshape(-1)
+
+        def loss(v):
+            p = oracle.diagram(v.astype(np.float32))
+            f = p["death_cell"] >= 0
+            return float(((p["death"][f].astype(np.float64) - p["birth"][f]) ** 2).sum())
+
+        h = 1e-4
+        for j in np.random.default_rng(k).choice(256, size=20, replace=False):
+            xp, xm = x0.reshape(-1).copy(), x0.reshape(-1).copy()
+            xp[j] += h
+            xm[j] -= h
+            step = float(np.float32(xp[j])) - float(np.float32(xm[j]))
+            fd = (loss(xp.reshape(16, 16)) - loss(xm.reshape(16, 16))) / step
+            assert abs(fd - g[j]) <= 1e-3 * max(1.0, abs(fd)), (k, j, fd, g[j])
     print("binding ok")
 
 
