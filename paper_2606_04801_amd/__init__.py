@@ -8,8 +8,11 @@ fallback.
 Entry points (same names as the C ABI):
   ph_diagram(img)                 one image or volume -> Diagram (device tensors)
   Batch(shapes).ph_diagram_batch  many instances of uneven sizes in one set of launches
+  Batch.ph_autotune               tile choice timed on the batch, kept for its size class
   Batch.ph_backward / ph_backward gradient scatter to the critical pixels
   PHDiagramFn                     torch.autograd.Function around ph_diagram / ph_backward
+  Batch.work_counters, profile / profile_read, device_report: inspection
+The kernel-launching entry points are off unless FLASHCUBICAL_DEVICE_PATH=1 (see the header).
 """
 from __future__ import annotations
 
@@ -411,7 +414,13 @@ def _autograd():
     return PHDiagramFn
 
 
+_fn_cache = []
+
+
 def __getattr__(name):
+    # the autograd class is made on first use so that importing this module needs no torch
     if name == "PHDiagramFn":
-        return _autograd()
+        if not _fn_cache:
+            _fn_cache.append(_autograd())
+        return _fn_cache[0]
     raise AttributeError(name)
