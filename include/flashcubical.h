@@ -11,7 +11,8 @@
  *   - lookup-table classification and pruning of each vertex's lower star (Sec. 3.2, 3.3),
  *     union-find for H0 and union-find on the dual graph with a cell at infinity for the top
  *     dimension (Sec. 3.1, Appendix A), as assembled in Sec. 4.1 (2D) and Sec. 4.2 steps 1-3
- *     (3D).  H1 of a volume (Sec. 4.2 steps 4-5) is not computed by this library.
+ *     (3D).  H1 of a volume (Sec. 4.2 steps 4-5) is not computed by this library; a volume
+ *     with an extent of 1 is still a volume (empty H2, no H1): pass it as an image for H1.
  *
  * Conventions shared by every entry point:
  *   - Pixel layout: row-major, last axis fastest.  2D extents are (H, W), 3D (D, H, W); every
