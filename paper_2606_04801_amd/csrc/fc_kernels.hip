@@ -51,6 +51,10 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
 constexpr int32_t kInf = 0x7FFFFFFF;
+// Halo key of a pixel outside the image.  Pixel keys are capped one below it (only the NaN bit
+// pattern 0x7FFFFFFF would reach it, and NaN input is an error), so an outside neighbour never
+// precedes a vertex and the stencil needs no bounds checks.
+constexpr uint32_t kOutside = 0xFFFFFFFFu;
 
 // ------------------------------------------------------------------ workspace map --
 FC_HD int64_t off_tb2(int n) { return align256((int64_t)n * (int64_t)sizeof(Inst)); }
@@ -153,8 +157,10 @@ __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
     atomicCAS(&cnt[CNT_ERR], 0, code);
 }
 
-// wave-aggregated reservation: returns this lane's first slot; all lanes must call it
+// wave-aggregated reservation: returns this lane's first slot; all lanes must call it.  Most
+// waves reserve nothing (kept cells are rare), so they skip the scan.
 __device__ __forceinline__ int wave_alloc(int32_t *counter, int count) {
+    if (__ballot(count != 0) == 0) return 0;
     const int lane = __lane_id();
     int x = count;
 #pragma unroll
@@ -201,11 +207,12 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     int nan = 0;
     for (int l = threadIdx.x; l < (TH + 2) * KW; l += 256) {
         int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
-        uint32_t k = 0;
+        uint32_t k = kOutside;
         if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
             float f = img[(int64_t)gy * W + gx];
             nan |= (f != f);
-            k = ord32(__float_as_uint(f));
+            const uint32_t o = ord32(__float_as_uint(f));
+            k = o < kOutside ? o : kOutside - 1u;
         }
         skey[l] = k;
     }
@@ -232,9 +239,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
         if (valid) {
             uint32_t mask = 0;
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {
-                int ny = gy + NDY[b], nx = gx + NDX[b];
-                if (ny < 0 || ny >= H || nx < 0 || nx >= W) continue;
+            for (int b = 0; b < 8; ++b) {               // outside neighbours hold kOutside
                 uint32_t kn = skey[(r + 1 + NDY[b]) * KW + c + 1 + NDX[b]];
                 if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
             }
@@ -373,11 +378,12 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     for (int l = threadIdx.x; l < KD * KH * KW; l += 256) {
         int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
         int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-        uint32_t k = 0;
+        uint32_t k = kOutside;
         if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
             float f = img[gz * HW + (int64_t)gy * W + gx];
             nan |= (f != f);
-            k = ord32(__float_as_uint(f));
+            const uint32_t o = ord32(__float_as_uint(f));
+            k = o < kOutside ? o : kOutside - 1u;
         }
         skey[l] = k;
     }
@@ -398,11 +404,9 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
         if (valid) {
             uint32_t raw = 0;
 #pragma unroll
-            for (int code = 1; code < 27; ++code) {
+            for (int code = 1; code < 27; ++code) {     // outside neighbours hold kOutside
                 const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
                 const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                const int nz = gz + dz, ny = gy + dy, nx = gx + dx;
-                if (nz < 0 || nz >= D || ny < 0 || ny >= H || nx < 0 || nx >= W) continue;
                 const uint32_t kn = skey[((lz + 1 + dz) * KH + ly + 1 + dy) * KW + lx + 1 + dx];
                 if (kn < kv || (kn == kv && before)) raw |= 1u << (code - 1);
             }
