@@ -227,3 +227,29 @@ def test_bench_flow_against_host_library():
     assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
     assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd", "per_image_fwd_bwd"}
     assert line["cpu_baseline"]["kind"] == "oracle" and line["work"]["pairs"] > 0
+
+
+def test_random_shapes_and_ties_hypothesis(driver):
+    """Random extents (1..12 per axis, 2D and 3D), value counts (2 levels to all distinct),
+    +-0 and infinities, in batches of 16 through the emulated kernels against the oracle."""
+    hyp = pytest.importorskip("hypothesis")
+    from hypothesis import strategies as st
+
+    @hyp.settings(max_examples=12, deadline=None, derandomize=True)
+    @hyp.given(st.lists(st.tuples(st.lists(st.integers(1, 12), min_size=2, max_size=3),
+                                  st.sampled_from([2, 3, 7, 1 << 20]), st.integers(0, 2 ** 31 - 1),
+                                  st.booleans()), min_size=1, max_size=16))
+    def check(spec):
+        imgs = []
+        for shape, lev, seed, specials in spec:
+            a = S.levels(tuple(shape), lev, seed)
+            if specials and a.size > 2:
+                r = np.random.default_rng(seed)
+                flat = a.reshape(-1)
+                flat[r.integers(0, a.size, 2)] = np.array([-0.0, np.inf], np.float32)
+            imgs.append(a)
+        out, _ = run(driver, imgs, mode=1)
+        for a, (got, status) in zip(imgs, out):
+            assert status == 0 and diff_pairs(got, oracle.diagram(a)) is None, a.shape
+
+    check()
