@@ -115,7 +115,7 @@ int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
                int64_t capacity, int64_t *d_count, int32_t *d_status, void *d_ws,
                size_t ws_bytes, void *stream);
 
-/* Diagrams of n instances of uneven sizes and mixed 2D/3D in one set of launches:
+/* Diagrams of n instances (1 <= n <= 65535) of uneven sizes and mixed 2D/3D in one set of launches:
  * persistent kernels walk a per-instance table built on the device from d_shapes.
  *   d_imgs     : all pixels concatenated; instance i starts at element d_img_off[i].
  *   d_shapes   : device copy of h_shapes (n entries); h_shapes sizes the launch grids.
@@ -142,7 +142,7 @@ int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const 
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
                 ph_tuning *best, void *stream);
 
-/* Gradient of pair values with respect to the pixels (not part of the paper): for every
+/* Gradient of pair values with respect to the pixels (not part of the paper; 1 <= n <= 65535): for every
  * stored pair j of instance i, d_grad_birth[j] is added to the birth pixel and, if the death
  * is finite, d_grad_death[j] to the death pixel; all other pixels get 0.
  *   pairs, d_counts : as written by ph_diagram(_batch) for n instances.

@@ -51,6 +51,7 @@ constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
 constexpr int32_t kInf = 0x7FFFFFFF;
+constexpr int kMaxInstances = 65535;       // instances of one call: the y extent of a grid
 // Halo key of a pixel outside the image.  Pixel keys are capped one below it (only the NaN bit
 // pattern 0x7FFFFFFF would reach it, and NaN input is an error), so an outside neighbour never
 // precedes a vertex and the stencil needs no bounds checks.
@@ -1276,7 +1277,7 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
         const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
         const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
         const ph_tuning *tuning, void *d_ws, size_t ws_bytes, hipStream_t st) {
-    if (n < 1 || !d_imgs || !h_shapes || !d_counts || !d_status || !d_ws) return PH_EINVAL;
+    if (n < 1 || n > kMaxInstances || !d_imgs || !h_shapes || !d_counts || !d_status || !d_ws) return PH_EINVAL;
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
         return PH_EINVAL;
@@ -1444,7 +1445,7 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
                 const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
                 const int64_t *d_img_off, int64_t total_voxels, void *stream) {
     if (!fc::device_path_enabled()) return PH_EDISABLED;
-    if (n < 1 || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
+    if (n < 1 || n > fc::kMaxInstances || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
         !pairs.birth_vertex || !pairs.death_vertex)
         return PH_EINVAL;
     if (!d_out_off || !d_img_off) return PH_EINVAL;

@@ -102,6 +102,10 @@ def test_host_validation_before_any_device_call(monkeypatch):
                               None) == fc.PH_EINVAL
     assert L.ph_diagram_batch(0, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
                               None) == fc.PH_EINVAL
+    many = (fc.ph_shape * 65536)(*([fc.make_shape((2, 2))] * 65536))
+    one = ctypes.c_void_p(1)                                    # never dereferenced: rejected first
+    assert L.ph_diagram_batch(65536, one, one, one, many, 3, fc.ph_pairs(one, one, one, one, one, one, one),
+                              one, one, one, None, one, 1 << 30, None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 0, None) == fc.PH_EINVAL
     best = fc.ph_tuning(0, 0)
