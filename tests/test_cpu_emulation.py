@@ -253,3 +253,17 @@ def test_random_shapes_and_ties_hypothesis(driver):
             assert status == 0 and diff_pairs(got, oracle.diagram(a)) is None, a.shape
 
     check()
+
+
+def test_gpu_suites_against_host_library():
+    """The GPU test modules themselves, run against the host build of the C ABI on host tensors
+    (graph capture and the full-size workloads excepted), in a separate process."""
+    so = emu_build.build("so")
+    tests = os.path.dirname(os.path.abspath(__file__))
+    env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1", FC_TEST_HOST_LIBRARY=so)
+    env.pop("FC_EMULATE_FULL", None)
+    r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-m", "gpu", "-p", "no:cacheprovider",
+                        os.path.join(tests, "test_gpu_parity.py"), os.path.join(tests, "test_gpu_full.py")],
+                       capture_output=True, text=True, timeout=1200, env=env, cwd=os.path.dirname(tests))
+    assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
+    assert " passed" in r.stdout and " failed" not in r.stdout

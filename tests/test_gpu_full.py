@@ -14,19 +14,28 @@ from gpu_util import diff_pairs
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
-if not torch.cuda.is_available():
-    pytest.skip("no GPU", allow_module_level=True)
 
 import paper_2606_04801_amd as fc  # noqa: E402
 from golden.make_digests import instances, make, pair_digest, input_digest  # noqa: E402
+from gpu_util import device_for_tests  # noqa: E402
 
-DEV = torch.device("cuda:0")
+DEV, HOST_MODE = device_for_tests(fc, torch)
+if DEV is None:
+    pytest.skip("no GPU", allow_module_level=True)
+# against the host build, the full-size workloads take minutes: only with FC_EMULATE_FULL=1
+full_size = pytest.mark.skipif(HOST_MODE and os.environ.get("FC_EMULATE_FULL") != "1",
+                               reason="full size against the host build: set FC_EMULATE_FULL=1")
 DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
 
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(
     not fc.device_path_enabled(),
     reason="device path switched off: its first launches faulted the GPU and no cause has been "
            "shown yet; set FLASHCUBICAL_DEVICE_PATH=1 to run")]
+
+
+def sync():
+    if not HOST_MODE:
+        torch.cuda.synchronize()
 
 
 def gpu(img):
@@ -54,6 +63,7 @@ def items(cfg):
     return [it for it in instances() if it[0] == cfg]
 
 
+@full_size
 @pytest.mark.parametrize("cfg", ["c1", "c2", "c2u8", "c3"])
 def test_single_full_size(cfg):
     (_, idx, kind, args), = items(cfg)
@@ -67,10 +77,11 @@ def run_batch(imgs, tuning=None, autotune=False):
     if autotune:
         bt.ph_autotune(reps=1)
     bt.ph_diagram_batch()
-    torch.cuda.synchronize()
+    sync()
     return bt, bt.results()
 
 
+@full_size
 @pytest.mark.parametrize("cfg", ["c4", "c5"])
 def test_batch_full_size(cfg):
     its = items(cfg)
@@ -129,7 +140,7 @@ def test_backward_against_reference_gradient():
     bt, res = run_batch(imgs)
     gb, gd = loss_grads(bt)
     bt.ph_backward(gb, gd)
-    torch.cuda.synchronize()
+    sync()
     for i, (img, r) in enumerate(zip(imgs, res)):
         f = r["death_cell"] >= 0
         d = np.where(f, r["death"] - r["birth"], 0).astype(np.float32)
@@ -139,11 +150,13 @@ def test_backward_against_reference_gradient():
 
 
 def test_graph_replay_matches_eager():
+    if HOST_MODE:
+        pytest.skip("graph capture needs the GPU")
     imgs = small_mixed_batch()
     bt, ref = run_batch(imgs)
     gb, gd = loss_grads(bt)
     bt.ph_backward(gb, gd)
-    torch.cuda.synchronize()
+    sync()
     g_ref = bt.grad.clone()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph):
@@ -153,9 +166,9 @@ def test_graph_replay_matches_eager():
     for rep in range(4):
         bt.pairs.birth.fill_(float("nan"))
         bt.grad.fill_(123.0)
-        torch.cuda.synchronize()
+        sync()
         graph.replay()
-        torch.cuda.synchronize()
+        sync()
         res = bt.results()
         for a, b in zip(res, ref):
             assert diff_pairs(a, b) is None, "replay %d" % rep
@@ -203,7 +216,7 @@ def test_capacity_overflow_reports_true_count():
     img = S.uniform((64, 64), 3)
     full = gpu(img)
     d = fc.ph_diagram(torch.from_numpy(img).to(DEV), capacity=10)
-    torch.cuda.synchronize()
+    sync()
     assert int(d.status_t.item()) == fc.PH_ECAPACITY
     assert int(d.count_t.item()) == len(full)
     got = d.bufs.to_numpy(0, 10)
