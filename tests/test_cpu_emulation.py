@@ -267,3 +267,15 @@ def test_gpu_suites_against_host_library():
                        capture_output=True, text=True, timeout=1200, env=env, cwd=os.path.dirname(tests))
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     assert " passed" in r.stdout and " failed" not in r.stdout
+
+
+def test_smoke_diagram_checks_against_host_library():
+    """The diagram half of __graft_entry__.smoke() on host tensors against the host build."""
+    so = emu_build.build("so")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys, torch; sys.path.insert(0, %r); import paper_2606_04801_amd as fc; "
+            "fc.LIB_PATH = %r; import __graft_entry__ as g; g.diagram_checks(torch.device('cpu')); "
+            "print('checks ok')" % (root, so))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1"), cwd=root)
+    assert r.returncode == 0 and "checks ok" in r.stdout, r.stdout[-2000:] + r.stderr[-3000:]
