@@ -27,9 +27,10 @@
  *     memory.  The library allocates nothing per call.  It owns only its lookup tables,
  *     built on the host and copied once per device on first use into device buffers it
  *     keeps until the process ends (about 1.2 MB per device).
- *   - Streams: all work is enqueued on `stream`; no call synchronises with the host, so a
- *     sequence of calls can be captured in a HIP graph.  Results are valid once the stream
- *     has reached them.
+ *   - Streams: all work is enqueued on `stream`.  ph_diagram, ph_diagram_batch and
+ *     ph_backward never synchronise with the host, so a sequence of them can be captured in a
+ *     HIP graph; results are valid once the stream has reached them.  ph_autotune and the
+ *     inspection helpers do wait.
  *   - Errors: argument errors found on the host are returned synchronously (PH_EINVAL,
  *     PH_ENOMEM for a too-small workspace, PH_EHIP for a failed HIP call).  Errors found
  *     by the kernels are written to the per-instance status word (PH_ENAN for a NaN pixel,
@@ -40,8 +41,8 @@
  *   - FLASHCUBICAL_TRACE=1 in the environment names every kernel launch on stderr and waits
  *     for it (a debugging aid: it synchronises, so it must not be set during graph capture).
  *   - Device path switch: the entry points that launch kernels (ph_diagram,
- *     ph_diagram_batch, ph_autotune, ph_backward) return PH_EDISABLED unless the environment variable
- *     FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of
+ *     ph_diagram_batch, ph_autotune, ph_backward) return PH_EDISABLED unless the
+ *     environment variable FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of
  *     this path ended in a GPU memory fault whose cause has not been found: the kernels are
  *     memory-safe under CPU emulation with sanitizers, so nothing is launched by default
  *     until the path has been verified on the device.  Everything that launches no kernel
