@@ -559,18 +559,22 @@ __device__ void bitonic_lds(uint64_t *s, int P) {
     }
 }
 
-__global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws, int n, int which) {
+// The list is a template argument, so each instantiation is straight-line code.  With the list
+// chosen by a run-time argument, the gfx950 build of this kernel took the node-key branch
+// without setting the scalar register pair that holds the count's address, and loaded the
+// count from near address 0.
+template <int WHICH>
+__global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws, int n) {
     __shared__ uint64_t s[kSortCap];
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
-    uint64_t *src, *dst;
-    int m;
-    int64_t cap;
-    if (which == 0) { src = dst = arr<uint64_t>(ws, I.o_keyE); m = cnt[CNT_E]; cap = I.E; }
-    else if (which == 1) { src = dst = arr<uint64_t>(ws, I.o_keyF); m = cnt[CNT_F]; cap = I.F; }
-    else { src = arr<uint64_t>(ws, I.o_n0key); dst = arr<uint64_t>(ws, I.o_n0sorted); m = cnt[CNT_M0]; cap = I.N; }
+    constexpr int kCnt = WHICH == 0 ? CNT_E : (WHICH == 1 ? CNT_F : CNT_M0);
+    uint64_t *src = arr<uint64_t>(ws, WHICH == 0 ? I.o_keyE : (WHICH == 1 ? I.o_keyF : I.o_n0key));
+    uint64_t *dst = WHICH == 2 ? arr<uint64_t>(ws, I.o_n0sorted) : src;
+    const int m = cnt[kCnt];
+    const int64_t cap = WHICH == 0 ? I.E : (WHICH == 1 ? I.F : I.N);
     if (m > cap) { if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL); return; }
     if (m <= 0) return;
     if (m <= kSortCap) {
@@ -1064,7 +1068,9 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_classify3d<16,8,8>", (const void *)k_classify3d<16, 8, 8>, 256},
         {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4>, 256},
         {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16>, 256},
-        {"k_sort", (const void *)k_sort, kSortThreads},
+        {"k_sort<edges>", (const void *)k_sort<0>, kSortThreads},
+        {"k_sort<facets>", (const void *)k_sort<1>, kSortThreads},
+        {"k_sort<nodes>", (const void *)k_sort<2>, kSortThreads},
         {"k_resolve_edges", (const void *)k_resolve_edges, 256},
         {"k_resolve_facets", (const void *)k_resolve_facets, 256},
         {"k_uf<0>", (const void *)k_uf<false>, kUfThreads},
@@ -1328,15 +1334,15 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     }
     const int64_t ml = max_list(h_shapes, n);
     const unsigned rblocks = (unsigned)((ml + 255) / 256 < 1024 ? (ml + 255) / 256 : 1024);
-    FC_LAUNCH(K_SORT_EDGES, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 0));
-    if (any3) FC_LAUNCH(K_SORT_FACETS, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 1));
+    FC_LAUNCH(K_SORT_EDGES, hipLaunchKernelGGL(k_sort<0>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
+    if (any3) FC_LAUNCH(K_SORT_FACETS, hipLaunchKernelGGL(k_sort<1>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
     FC_LAUNCH(K_RESOLVE_EDGES, hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
     FC_LAUNCH(K_UF_H0, hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     if (flags & PH_HTOP) {
         FC_LAUNCH(K_RESOLVE_FACETS, hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
         FC_LAUNCH(K_UF_TOP, hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
-    FC_LAUNCH(K_SORT_NODES, hipLaunchKernelGGL(k_sort, dim3(n), dim3(kSortThreads), 0, st, ws, n, 2));
+    FC_LAUNCH(K_SORT_NODES, hipLaunchKernelGGL(k_sort<2>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
                                  d_status));
     return PH_OK;

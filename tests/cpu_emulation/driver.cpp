@@ -22,6 +22,7 @@
 
 #include <vector>
 
+#include "hip/hip_runtime.h"
 #include "flashcubical.h"
 #include "fc_common.h"
 
@@ -103,12 +104,26 @@ void unguard() {
     g_guarded = false;
 }
 
-template <typename T> void uninit(std::vector<T> &v) {
+template <typename T> void uninit(T *p, size_t count) {
 #ifdef EMU_MSAN_DRIVER
-    __msan_poison(v.data(), v.size() * sizeof(T));
+    __msan_poison(p, count * sizeof(T));
 #else
-    (void)v;
+    (void)p;
+    (void)count;
 #endif
+}
+
+// Every buffer a kernel receives is device memory of the emulated runtime (hipMalloc), as on
+// the GPU; only h_shapes stays in host memory.
+template <typename T> T *dev_alloc(size_t count) {
+    void *p = nullptr;
+    if (hipMalloc(&p, count * sizeof(T)) != hipSuccess) { fprintf(stderr, "driver: hipMalloc\n"); exit(2); }
+    return (T *)p;
+}
+template <typename T> T *dev_copy(const std::vector<T> &v) {
+    T *p = dev_alloc<T>(v.size());
+    if (!v.empty()) memcpy(p, v.data(), v.size() * sizeof(T));
+    return p;
 }
 
 }  // namespace
@@ -141,36 +156,38 @@ int main(int argc, char **argv) {
 
     const int64_t cap = out_off[n];
     g_wsb = ph_workspace_bytes(shapes.data(), n, flags);
-    std::vector<uint8_t> ws(g_wsb);
-    for (size_t k = 0; k < ws.size(); ++k) ws[k] = (uint8_t)(k * 2654435761u >> 13);   // garbage
-    uninit(ws);
-    g_ws = ws.data();
+    uint8_t *ws = dev_alloc<uint8_t>(g_wsb);
+    for (size_t k = 0; k < g_wsb; ++k) ws[k] = (uint8_t)(k * 2654435761u >> 13);   // garbage
+    uninit(ws, g_wsb);
+    g_ws = ws;
     g_n = n;
-    std::vector<int8_t> dim(cap);
-    std::vector<float> birth(cap), death(cap);
-    std::vector<int64_t> bcell(cap), dcell(cap), counts(n);
-    std::vector<int32_t> bvert(cap), dvert(cap), status(n);
-    uninit(dim); uninit(birth); uninit(death); uninit(bcell); uninit(dcell); uninit(bvert); uninit(dvert);
-    uninit(counts); uninit(status);
-    ph_pairs out{dim.data(), birth.data(), death.data(), bcell.data(), dcell.data(), bvert.data(), dvert.data()};
+    float *d_img = dev_copy(img);
+    int64_t *d_img_off = dev_copy(img_off), *d_out_off = dev_copy(out_off);
+    ph_shape *d_shapes = dev_copy(shapes);
+    int8_t *dim = dev_alloc<int8_t>(cap);
+    float *birth = dev_alloc<float>(cap), *death = dev_alloc<float>(cap);
+    int64_t *bcell = dev_alloc<int64_t>(cap), *dcell = dev_alloc<int64_t>(cap), *counts = dev_alloc<int64_t>(n);
+    int32_t *bvert = dev_alloc<int32_t>(cap), *dvert = dev_alloc<int32_t>(cap), *status = dev_alloc<int32_t>(n);
+    uninit(dim, cap); uninit(birth, cap); uninit(death, cap); uninit(bcell, cap); uninit(dcell, cap);
+    uninit(bvert, cap); uninit(dvert, cap); uninit(counts, n); uninit(status, n);
+    ph_pairs out{dim, birth, death, bcell, dcell, bvert, dvert};
     ph_tuning tune{hdr[3], hdr[4]};
     const ph_tuning *tp = hdr[3] >= 0 ? &tune : nullptr;
     emu_after_launch = guard_workspace;
     int rc;
     if (mode == 0) {
         if (n != 1) return 2;
-        rc = ph_diagram(img.data(), shapes[0], flags, out, cap, counts.data(), status.data(), ws.data(), g_wsb,
-                        nullptr);
+        rc = ph_diagram(d_img, shapes[0], flags, out, cap, counts, status, ws, g_wsb, nullptr);
     } else {
         if (mode == 2) {
             ph_tuning best{0, 0};
-            rc = ph_autotune(n, img.data(), img_off.data(), shapes.data(), shapes.data(), flags, out,
-                             out_off.data(), counts.data(), status.data(), ws.data(), g_wsb, 1, &best, nullptr);
+            rc = ph_autotune(n, d_img, d_img_off, d_shapes, shapes.data(), flags, out, d_out_off, counts, status,
+                             ws, g_wsb, 1, &best, nullptr);
             unguard();
             if (rc != PH_OK) { fprintf(stderr, "driver: autotune rc %d\n", rc); return 3; }
         }
-        rc = ph_diagram_batch(n, img.data(), img_off.data(), shapes.data(), shapes.data(), flags, out,
-                              out_off.data(), counts.data(), status.data(), tp, ws.data(), g_wsb, nullptr);
+        rc = ph_diagram_batch(n, d_img, d_img_off, d_shapes, shapes.data(), flags, out, d_out_off, counts, status,
+                              tp, ws, g_wsb, nullptr);
     }
     unguard();
     emu_after_launch = nullptr;
@@ -178,15 +195,15 @@ int main(int argc, char **argv) {
     if (getenv("EMU_STATS")) {                    // per-instance work counters, for sizing studies
         const int64_t cn = a256((int64_t)n * (int64_t)sizeof(fc::Inst)) + 2 * a256((int64_t)(n + 1) * 8);
         for (int i = 0; i < n; ++i) {
-            const int32_t *c = (const int32_t *)(ws.data() + cn) + i * fc::CNT_WORDS;
-            const fc::Inst &I = ((const fc::Inst *)ws.data())[i];
+            const int32_t *c = (const int32_t *)(ws + cn) + i * fc::CNT_WORDS;
+            const fc::Inst &I = ((const fc::Inst *)ws)[i];
             fprintf(stderr, "stats %d N %ld keepE %d keepF %d minima %d roots %d rounds0 %d roundsT %d seq %d\n", i,
                     (long)I.N, c[fc::CNT_E], c[fc::CNT_F], c[fc::CNT_M0], c[fc::CNT_MT], c[fc::CNT_ROUNDS0],
                     c[fc::CNT_ROUNDST], c[fc::CNT_SEQ]);
         }
     }
 
-    std::vector<float> grad;
+    float *grad = nullptr;
     if (backward) {
         std::vector<float> gb(cap, 0.f), gd(cap, 0.f);
         for (int i = 0; i < n; ++i)
@@ -197,10 +214,10 @@ int main(int argc, char **argv) {
                 gb[k] = -2.f * d;
                 gd[k] = 2.f * d;
             }
-        grad.resize(img.size());
-        uninit(grad);
-        rc = ph_backward(n, out, out_off.data(), counts.data(), gb.data(), gd.data(), grad.data(), img_off.data(),
-                         (int64_t)img.size(), nullptr);
+        float *d_gb = dev_copy(gb), *d_gd = dev_copy(gd);
+        grad = dev_alloc<float>(img.size());
+        uninit(grad, img.size());
+        rc = ph_backward(n, out, d_out_off, counts, d_gb, d_gd, grad, d_img_off, (int64_t)img.size(), nullptr);
         if (rc != PH_OK) { fprintf(stderr, "driver: backward rc %d\n", rc); return 3; }
     }
 
@@ -218,7 +235,7 @@ int main(int argc, char **argv) {
             fwrite(&bvert[k], 4, 1, o); fwrite(&dvert[k], 4, 1, o);
         }
     }
-    if (backward) fwrite(grad.data(), 4, grad.size(), o);
+    if (backward) fwrite(grad, 4, img.size(), o);
     fclose(o);
     return 0;
 }

@@ -46,7 +46,27 @@
 #endif
 #endif
 
+// EMU_TRACE (the "trace" build): every load and store of kernel code, struct copies included,
+// is checked against the memory a GPU thread may touch (runtime.cpp).  The runtime's own
+// functions that run on a thread's fiber are kept out of line and uninstrumented, so only
+// kernel code is checked.
+#ifdef EMU_TRACE
+#define EMU_FN inline __attribute__((noinline, no_sanitize("address")))
+#define EMU_FN_ATTR __attribute__((noinline, no_sanitize("address")))
+void emu_dev_register(const void *p, size_t n);
+void emu_dev_unregister(const void *p);
+void emu_check_access(const void *p, size_t n, int store);
+#else
+#define EMU_FN inline
+#define EMU_FN_ATTR
+inline void emu_check_access(const void *, size_t, int) {}
+#endif
+
+#ifdef EMU_TRACE
+#define __global__ __attribute__((noinline))
+#else
 #define __global__
+#endif
 #define __device__
 #define __host__
 #define __constant__
@@ -105,18 +125,19 @@ struct EmuSched {
     void *ctx = nullptr;
 };
 inline EmuSched emu_sched;
+inline bool emu_in_block = false;               // fibers of a block are running
 
 // EMU_SHUFFLE=<seed>: threads are resumed in a random order on every scheduling pass, and a
 // thread may give up its turn at any atomic operation, so that other interleavings between
 // barriers are tried as well.
-inline uint64_t emu_shuffle_state() {
+EMU_FN uint64_t emu_shuffle_state() {
     static uint64_t seed = [] {
         const char *e = getenv("EMU_SHUFFLE");
         return e ? (uint64_t)strtoull(e, nullptr, 10) * 2654435761ull + 1 : 0ull;
     }();
     return seed;
 }
-inline uint64_t emu_rand() {
+EMU_FN uint64_t emu_rand() {
     static uint64_t x = emu_shuffle_state();
     x ^= x << 13;
     x ^= x >> 7;
@@ -124,7 +145,7 @@ inline uint64_t emu_rand() {
     return x;
 }
 
-inline void emu_to_fiber(EmuFiber &f) {
+EMU_FN void emu_to_fiber(EmuFiber &f) {
 #if EMU_ASAN_FIBERS
     void *fake = nullptr;
     __sanitizer_start_switch_fiber(&fake, f.stack, EmuSched::kStack);
@@ -134,7 +155,7 @@ inline void emu_to_fiber(EmuFiber &f) {
     emu_ctx_switch(&emu_sched.main_sp, f.sp);
 #endif
 }
-inline void emu_to_main(EmuFiber &f, bool dying) {
+EMU_FN void emu_to_main(EmuFiber &f, bool dying) {
 #if EMU_ASAN_FIBERS
     void *fake = nullptr;
     __sanitizer_start_switch_fiber(dying ? nullptr : &fake, emu_sched.main_bottom, emu_sched.main_size);
@@ -145,7 +166,7 @@ inline void emu_to_main(EmuFiber &f, bool dying) {
     emu_ctx_switch(&f.sp, emu_sched.main_sp);
 #endif
 }
-[[noreturn]] inline void emu_fiber_main() {
+[[noreturn]] EMU_FN void emu_fiber_main() {
 #if EMU_ASAN_FIBERS
     __sanitizer_finish_switch_fiber(nullptr, &emu_sched.main_bottom, &emu_sched.main_size);
 #endif
@@ -155,13 +176,13 @@ inline void emu_to_main(EmuFiber &f, bool dying) {
     emu_to_main(f, true);
     abort();                                   // a finished fiber is never resumed
 }
-inline void emu_maybe_yield() {
+EMU_FN void emu_maybe_yield() {
     if (!emu_shuffle_state() || emu_sched.cur < 0 || (emu_rand() & 3) != 0) return;
     EmuFiber &f = emu_sched.fib[emu_sched.cur];
     f.wait = nullptr;
     emu_to_main(f, false);
 }
-inline void emu_barrier_wait(EmuBarrier &b) {
+EMU_FN void emu_barrier_wait(EmuBarrier &b) {
     const unsigned g = b.gen;
     if (++b.arrived == b.count) {              // the last thread to arrive releases the others
         b.arrived = 0;
@@ -173,7 +194,7 @@ inline void emu_barrier_wait(EmuBarrier &b) {
     f.wait_gen = g;
     emu_to_main(f, false);
 }
-inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void *), void *ctx) {
+EMU_FN void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void *), void *ctx) {
     EmuSched &s = emu_sched;
     if (s.fib.empty()) {
         s.fib.resize(EmuSched::kFibers);
@@ -196,6 +217,7 @@ inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void 
         f.wait = nullptr;
     }
     unsigned left = nt;
+    emu_in_block = true;
     std::vector<unsigned> order(nt);
     for (unsigned t = 0; t < nt; ++t) order[t] = t;
     while (left > 0) {
@@ -220,10 +242,11 @@ inline void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void 
             abort();
         }
     }
+    emu_in_block = false;
 }
 
-inline void __syncthreads() { emu_barrier_wait(emu_block->bar); }
-inline int __syncthreads_or(int x) {
+EMU_FN void __syncthreads() { emu_barrier_wait(emu_block->bar); }
+EMU_FN int __syncthreads_or(int x) {
     EmuBlock *b = emu_block;
     emu_barrier_wait(b->bar);
     if (x) b->or_acc = 1;
@@ -234,9 +257,9 @@ inline int __syncthreads_or(int x) {
     emu_barrier_wait(b->bar);
     return r;
 }
-inline int __lane_id() { return (int)(threadIdx.x & 63u); }
-inline int emu_wave() { return (int)(threadIdx.x >> 6); }
-inline int64_t emu_read_lane(int64_t v, int src) {
+EMU_FN int __lane_id() { return (int)(threadIdx.x & 63u); }
+EMU_FN int emu_wave() { return (int)(threadIdx.x >> 6); }
+EMU_FN int64_t emu_read_lane(int64_t v, int src) {
     EmuBlock *b = emu_block;
     EmuBarrier &w = b->wave_bar[emu_wave()];
     b->lane_value[threadIdx.x] = v;
@@ -245,12 +268,12 @@ inline int64_t emu_read_lane(int64_t v, int src) {
     emu_barrier_wait(w);
     return got;
 }
-inline int __shfl_up(int v, int d, int = 64) {
+EMU_FN int __shfl_up(int v, int d, int = 64) {
     const int l = __lane_id();
     return (int)emu_read_lane(v, l - d < 0 ? l : l - d);
 }
-inline int __shfl(int v, int src, int = 64) { return (int)emu_read_lane(v, src & 63); }
-inline unsigned long long __ballot(int pred) {
+EMU_FN int __shfl(int v, int src, int = 64) { return (int)emu_read_lane(v, src & 63); }
+EMU_FN unsigned long long __ballot(int pred) {
     EmuBlock *b = emu_block;
     EmuBarrier &w = b->wave_bar[emu_wave()];
     b->lane_value[threadIdx.x] = pred ? 1 : 0;
@@ -266,25 +289,29 @@ inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline unsigned __float_as_uint(float f) { unsigned u; memcpy(&u, &f, 4); return u; }
 inline float __int_as_float(int i) { float f; memcpy(&f, &i, 4); return f; }
 
-template <typename T> inline T atomicAdd(T *p, T v) {
+template <typename T> EMU_FN T atomicAdd(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
     emu_maybe_yield();
     return __atomic_fetch_add(p, v, __ATOMIC_SEQ_CST);
 }
-inline float atomicAdd(float *p, float v) {
+EMU_FN float atomicAdd(float *p, float v) {
+    emu_check_access(p, sizeof(float), 1);
     emu_maybe_yield();
     float old, nw;
     __atomic_load(p, &old, __ATOMIC_SEQ_CST);
     do { nw = old + v; } while (!__atomic_compare_exchange(p, &old, &nw, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST));
     return old;
 }
-template <typename T> inline T atomicMin(T *p, T v) {
+template <typename T> EMU_FN T atomicMin(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
     emu_maybe_yield();
     T old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
     while (v < old && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
     }
     return old;
 }
-template <typename T> inline T atomicCAS(T *p, T cmp, T v) {
+template <typename T> EMU_FN T atomicCAS(T *p, T cmp, T v) {
+    emu_check_access(p, sizeof(T), 1);
     emu_maybe_yield();
     __atomic_compare_exchange_n(p, &cmp, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST);
     return cmp;
@@ -319,8 +346,33 @@ inline hipError_t hipFuncGetAttributes(hipFuncAttributes *at, const void *) {
     return hipSuccess;
 }
 enum hipMemcpyKind { hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3 };
-inline hipError_t hipMalloc(void **p, size_t n) { *p = malloc(n ? n : 1); return *p ? hipSuccess : 2; }
-inline hipError_t hipFree(void *p) { free(p); return hipSuccess; }
+#ifdef EMU_ISA
+// EMU_ISA (the "isa" build): kernel launches and device allocations are handed to hooks that
+// the Python interpreter of the library's gfx950 code object installs (runtime.cpp); the host
+// C++ bodies of the kernels are never run.
+extern void (*emu_isa_launch)(const char *kernel, const unsigned *dims, const void *args, size_t len);
+extern void (*emu_isa_alloc)(void *p, size_t n, int is_free);
+#endif
+inline hipError_t hipMalloc(void **p, size_t n) {
+    *p = malloc(n ? n : 1);
+#ifdef EMU_TRACE
+    if (*p) emu_dev_register(*p, n);
+#endif
+#ifdef EMU_ISA
+    if (*p && emu_isa_alloc) emu_isa_alloc(*p, n ? n : 1, 0);
+#endif
+    return *p ? hipSuccess : 2;
+}
+inline hipError_t hipFree(void *p) {
+#ifdef EMU_TRACE
+    if (p) emu_dev_unregister(p);
+#endif
+#ifdef EMU_ISA
+    if (p && emu_isa_alloc) emu_isa_alloc(p, 0, 1);
+#endif
+    free(p);
+    return hipSuccess;
+}
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { memcpy(d, s, n); return hipSuccess; }
 typedef struct EmuEvent { double t; } *hipEvent_t;
 inline double emu_now_ms() {
@@ -345,13 +397,31 @@ inline void emu_poison_lds() {
 #endif
 }
 
+#ifdef EMU_ISA
+#include <dlfcn.h>
+template <typename T> void emu_pack(std::vector<unsigned char> &buf, const T &x) {
+    size_t at = (buf.size() + alignof(T) - 1) / alignof(T) * alignof(T);
+    buf.resize(at + sizeof(T));
+    memcpy(buf.data() + at, &x, sizeof(T));
+}
+template <typename K, typename... A>
+void emu_launch(K kern, dim3 g, dim3 b, A... args) {
+    Dl_info info;
+    if (!dladdr((void *)kern, &info) || !info.dli_sname) { fprintf(stderr, "emulation: kernel has no symbol\n"); abort(); }
+    std::vector<unsigned char> buf;
+    (emu_pack(buf, args), ...);
+    const unsigned dims[6] = {g.x, g.y, g.z, b.x, b.y, b.z};
+    if (!emu_isa_launch) { fprintf(stderr, "emulation: no launch hook\n"); abort(); }
+    emu_isa_launch(info.dli_sname, dims, buf.data(), buf.size());
+}
+#else
 template <typename K, typename... A>
 void emu_launch(K kern, dim3 g, dim3 b, A... args) {
     gridDim = g;
     blockDim = b;
     const unsigned nt = b.x * b.y * b.z;
     if (nt == 0 || nt > (unsigned)EmuSched::kFibers) { fprintf(stderr, "emulation: bad block size\n"); abort(); }
-    auto call = [&]() { kern(args...); };
+    auto call = [&]() EMU_FN_ATTR { kern(args...); };
     using Call = decltype(call);
     for (unsigned bz = 0; bz < g.z; ++bz)
         for (unsigned by = 0; by < g.y; ++by)
@@ -362,8 +432,9 @@ void emu_launch(K kern, dim3 g, dim3 b, A... args) {
                 blk.wave_bar.resize((nt + 63) / 64);
                 for (unsigned w = 0; w < blk.wave_bar.size(); ++w) blk.wave_bar[w].count = (int)std::min(64u, nt - 64 * w);
                 blk.lane_value.assign(nt, 0);
-                emu_run_block(nt, dim3(bx, by, bz), &blk, [](void *c) { (*(Call *)c)(); }, &call);
+                emu_run_block(nt, dim3(bx, by, bz), &blk, [](void *c) EMU_FN_ATTR { (*(Call *)c)(); }, &call);
             }
     if (emu_after_launch) emu_after_launch((const void *)kern);
 }
+#endif
 #define hipLaunchKernelGGL(K, G, B, SH, ST, ...) emu_launch(K, G, B, __VA_ARGS__)

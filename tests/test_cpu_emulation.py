@@ -279,3 +279,19 @@ def test_smoke_diagram_checks_against_host_library():
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
                        env=dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1"), cwd=root)
     assert r.returncode == 0 and "checks ok" in r.stdout, r.stdout[-2000:] + r.stderr[-3000:]
+
+
+@pytest.mark.parametrize("lockstep", ["0", "1"])
+def test_kernels_touch_device_memory_only(monkeypatch, lockstep):
+    """Every load, store and struct copy of kernel code lands in a device allocation, LDS or the
+    thread's own private memory (trace build); with EMU_LOCKSTEP=1 the threads of a block also
+    advance one memory access at a time."""
+    exe = emu_build.build("trace")
+    monkeypatch.setenv("EMU_LOCKSTEP", lockstep)
+    for name, img, _, _ in fixtures.load():
+        (got, st), = run(exe, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, name
+    imgs = mixed_batch()
+    out, grad = run(exe, imgs, mode=1, tuning=(2, 1), backward=True)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
