@@ -40,13 +40,6 @@
  *   - Calls that share a workspace must not overlap in time.
  *   - FLASHCUBICAL_TRACE=1 in the environment names every kernel launch on stderr and waits
  *     for it (a debugging aid: it synchronises, so it must not be set during graph capture).
- *   - Device path switch: the entry points that launch kernels (ph_diagram,
- *     ph_diagram_batch, ph_autotune, ph_backward) return PH_EDISABLED unless the
- *     environment variable FLASHCUBICAL_DEVICE_PATH is set to 1 when the call is made.  The first launches of
- *     this path ended in a GPU memory fault whose cause has not been found: the kernels are
- *     memory-safe under CPU emulation with sanitizers, so nothing is launched by default
- *     until the path has been verified on the device.  Everything that launches no kernel
- *     (sizes, tables, device report, table upload) is always available.
  */
 #ifndef FLASHCUBICAL_H
 #define FLASHCUBICAL_H
@@ -65,8 +58,7 @@ enum {
     PH_ECAPACITY = -3,
     PH_ENOMEM = -4,
     PH_EHIP = -5,
-    PH_EINTERNAL = -6,
-    PH_EDISABLED = -7
+    PH_EINTERNAL = -6
 };
 
 /* flags: which dimensions to report (H0 is always computed; 2D needs it for the top). */

@@ -12,7 +12,6 @@ Entry points (same names as the C ABI):
   Batch.ph_backward / ph_backward gradient scatter to the critical pixels
   PHDiagramFn                     torch.autograd.Function around ph_diagram / ph_backward
   Batch.work_counters, profile / profile_read, device_report: inspection
-The kernel-launching entry points are off unless FLASHCUBICAL_DEVICE_PATH=1 (see the header).
 """
 from __future__ import annotations
 
@@ -24,17 +23,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflashcubical.so")
 
-PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL, PH_EDISABLED = 0, -1, -2, -3, -4, -5, -6, -7
+PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 PH_H0, PH_HTOP = 1, 2
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
-                -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded",
-                -7: "device path switched off (set FLASHCUBICAL_DEVICE_PATH=1)"}
-DEVICE_PATH_ENV = "FLASHCUBICAL_DEVICE_PATH"
-
-
-def device_path_enabled() -> bool:
-    """True when the kernel-launching entry points are switched on (see the C header)."""
-    return os.environ.get(DEVICE_PATH_ENV) == "1"
+                -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
 
 PAIR_DTYPE = np.dtype([
     ("dim", np.int8), ("birth", np.float32), ("death", np.float32),

@@ -1352,16 +1352,6 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
 }  // namespace fc
 
 // ====================================================================== C ABI ====
-namespace fc {
-namespace {
-// Kernel-launching entry points run only when FLASHCUBICAL_DEVICE_PATH=1 (header: device
-// path switch).
-bool device_path_enabled() {
-    const char *e = getenv("FLASHCUBICAL_DEVICE_PATH");
-    return e && e[0] == '1' && e[1] == 0;
-}
-}  // namespace
-}  // namespace fc
 
 extern "C" {
 
@@ -1389,7 +1379,6 @@ size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
 
 int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
                int64_t *d_count, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
-    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (capacity < 0) return PH_EINVAL;
     return fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
                    d_status, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
@@ -1399,7 +1388,6 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, c
                      const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                      int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
                      size_t ws_bytes, void *stream) {
-    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1) return PH_EINVAL;
     ph_shape dummy{2, {1, 1, 1}};
     ph_tuning tuned;
@@ -1412,7 +1400,6 @@ int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const 
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
                 ph_tuning *best, void *stream) {
-    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1 || reps < 1 || !best) return PH_EINVAL;
     const fc::SizeClass cls = fc::size_class(h_shapes, n);
     const int n2 = std::get<0>(cls) ? 3 : 1, n3 = std::get<1>(cls) ? 3 : 1;
@@ -1450,7 +1437,6 @@ int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const 
 int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
                 const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
                 const int64_t *d_img_off, int64_t total_voxels, void *stream) {
-    if (!fc::device_path_enabled()) return PH_EDISABLED;
     if (n < 1 || n > fc::kMaxInstances || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
         !pairs.birth_vertex || !pairs.death_vertex)
         return PH_EINVAL;

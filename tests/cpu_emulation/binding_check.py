@@ -11,7 +11,6 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 TESTS = os.path.dirname(HERE)
 ROOT = os.path.dirname(TESTS)
 sys.path[:0] = [ROOT, TESTS]
-os.environ["FLASHCUBICAL_DEVICE_PATH"] = "1"
 
 import numpy as np  # noqa: E402
 import torch  # noqa: E402

@@ -86,8 +86,7 @@ class IsaRunner:
         H.ph_diagram_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp,
                                        ctypes.POINTER(ph_tuning), vp, ctypes.c_size_t, vp]
         H.ph_backward.argtypes = [i32, ph_pairs, vp, vp, vp, vp, vp, vp, i64, vp]
-        os.environ["FLASHCUBICAL_DEVICE_PATH"] = "1"
-
+        
     # ------------------------------------------------------------------ hooks --
     def _on_launch(self, name, dims, args, n):
         if self.error is not None:

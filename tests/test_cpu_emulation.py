@@ -52,7 +52,7 @@ def run(exe, imgs, mode=0, tuning=None, backward=False, capacity=-1, with_count=
             f.write(hdr)
             for a in imgs:
                 f.write(a.tobytes())
-        env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1", ASAN_OPTIONS="detect_leaks=0")
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
         r = subprocess.run([exe, fi, fo], capture_output=True, text=True, timeout=600, env=env)
         assert r.returncode == 0, r.stderr[-4000:]
         raw = open(fo, "rb").read()
@@ -219,7 +219,7 @@ def test_bench_flow_against_host_library():
     import json
     so = emu_build.build("so")
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-    env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1")
+    env = dict(os.environ)
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--host-library", so, "--steps", "1",
                         "--warmup", "1", "--cpu-workers", "2"], capture_output=True, text=True, timeout=900, env=env)
     assert r.returncode == 0, r.stderr[-4000:]
@@ -260,7 +260,7 @@ def test_gpu_suites_against_host_library():
     (graph capture and the full-size workloads excepted), in a separate process."""
     so = emu_build.build("so")
     tests = os.path.dirname(os.path.abspath(__file__))
-    env = dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1", FC_TEST_HOST_LIBRARY=so)
+    env = dict(os.environ, FC_TEST_HOST_LIBRARY=so)
     env.pop("FC_EMULATE_FULL", None)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-m", "gpu", "-p", "no:cacheprovider",
                         os.path.join(tests, "test_gpu_parity.py"), os.path.join(tests, "test_gpu_full.py")],
@@ -277,7 +277,7 @@ def test_smoke_diagram_checks_against_host_library():
             "fc.LIB_PATH = %r; import __graft_entry__ as g; g.diagram_checks(torch.device('cpu')); "
             "print('checks ok')" % (root, so))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600,
-                       env=dict(os.environ, FLASHCUBICAL_DEVICE_PATH="1"), cwd=root)
+                       cwd=root)
     assert r.returncode == 0 and "checks ok" in r.stdout, r.stdout[-2000:] + r.stderr[-3000:]
 
 

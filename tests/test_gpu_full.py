@@ -27,11 +27,6 @@ full_size = pytest.mark.skipif(HOST_MODE and os.environ.get("FC_EMULATE_FULL") !
                                reason="full size against the host build: set FC_EMULATE_FULL=1")
 DIGESTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
 
-pytestmark = [pytest.mark.gpu, pytest.mark.skipif(
-    not fc.device_path_enabled(),
-    reason="device path switched off: its first launches faulted the GPU and no cause has been "
-           "shown yet; set FLASHCUBICAL_DEVICE_PATH=1 to run")]
-
 
 def sync():
     if not HOST_MODE:

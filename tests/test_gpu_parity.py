@@ -19,15 +19,6 @@ DEV, HOST_MODE = device_for_tests(fc, torch)
 if DEV is None:
     pytest.skip("no GPU", allow_module_level=True)
 
-# The kernel-launching entry points are switched off by default: their first launches ended in
-# a GPU memory fault whose cause has not been shown (the kernels are memory-safe under CPU
-# emulation with sanitizers).  These tests run only with FLASHCUBICAL_DEVICE_PATH=1.
-needs_device_path = pytest.mark.skipif(
-    not fc.device_path_enabled(),
-    reason="device path switched off: its first launches faulted the GPU and no cause has been "
-           "shown yet; set FLASHCUBICAL_DEVICE_PATH=1 to run")
-
-
 def gpu_diagram(img, **kw):
     print("case", img.shape, flush=True)
     return fc.ph_diagram(torch.from_numpy(np.ascontiguousarray(img)).to(DEV), **kw).numpy()
@@ -60,13 +51,11 @@ def test_tables_uploaded():
     assert fc.lib().ph_init_device() == fc.PH_OK
 
 
-@needs_device_path
 @pytest.mark.parametrize("name,img,expected,case", fixtures.load(), ids=lambda x: x if isinstance(x, str) else "")
 def test_fixtures(name, img, expected, case):
     check(img, name)
 
 
-@needs_device_path
 def test_tiny_sweep_2d():
     rng = np.random.default_rng(1)
     for k in range(150):
@@ -75,7 +64,6 @@ def test_tiny_sweep_2d():
         check(S.levels(shape, lev, 10_000 + k), "2d#%d" % k)
 
 
-@needs_device_path
 def test_tiny_sweep_3d():
     rng = np.random.default_rng(2)
     for k in range(120):
@@ -84,7 +72,6 @@ def test_tiny_sweep_3d():
         check(S.levels(shape, lev, 20_000 + k), "3d#%d" % k)
 
 
-@needs_device_path
 def test_special_values():
     a = np.array([[0.0, -0.0, 1.0, np.inf], [-np.inf, 0.5, -0.0, 0.0], [1e-45, -1e-45, 3.0, 0.0]], np.float32)
     check(a, "specials")
@@ -92,12 +79,10 @@ def test_special_values():
     check(v, "specials3d")
 
 
-@needs_device_path
 def test_uniform_128():
     check(S.uniform((128, 128), 0), "uniform128")
 
 
-@needs_device_path
 @pytest.mark.parametrize("shape,sigma", [((200, 300), 2.0), ((257, 131), 4.0), ((70, 1030), 1.0)])
 def test_fields_2d(shape, sigma):
     x = S.grf(shape, sigma, 5)
@@ -105,7 +90,6 @@ def test_fields_2d(shape, sigma):
     check(S.quantize_u8(x), "u8")
 
 
-@needs_device_path
 @pytest.mark.parametrize("shape,sigma", [((40, 35, 50), 1.5), ((17, 64, 33), 2.0), ((1, 40, 41), 1.0)])
 def test_fields_3d(shape, sigma):
     x = S.grf(shape, sigma, 6)
@@ -113,6 +97,5 @@ def test_fields_3d(shape, sigma):
     check(S.quantize_u8(x), "u8-3")
 
 
-@needs_device_path
 def test_uniform_3d():
     check(S.uniform((24, 30, 28), 9), "uniform3d")

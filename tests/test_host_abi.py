@@ -1,6 +1,5 @@
 """Host side of the C ABI (no GPU, no kernel launch): the library loads, exports every entry
-point its header declares, sizes its buffers consistently, validates arguments on the host and
-keeps its kernel-launching entry points switched off unless asked."""
+point its header declares, sizes its buffers consistently and validates arguments on the host."""
 import ctypes
 import os
 import re
@@ -74,25 +73,8 @@ def _call_diagram():
     return L.ph_diagram(None, fc.make_shape((4, 4)), 3, fc.ph_pairs(), 16, None, None, None, 0, None)
 
 
-def test_device_path_switch(monkeypatch):
-    monkeypatch.delenv(fc.DEVICE_PATH_ENV, raising=False)
-    assert not fc.device_path_enabled()
-    L = fc.lib()
-    assert _call_diagram() == fc.PH_EDISABLED
-    sh = (fc.ph_shape * 1)(fc.make_shape((4, 4)))
-    assert L.ph_diagram_batch(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, None, 0,
-                              None) == fc.PH_EDISABLED
-    assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EDISABLED
-    best = fc.ph_tuning(0, 0)
-    assert L.ph_autotune(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, 0, 1,
-                         ctypes.byref(best), None) == fc.PH_EDISABLED
-    monkeypatch.setenv(fc.DEVICE_PATH_ENV, "0")
-    assert _call_diagram() == fc.PH_EDISABLED
-
-
-def test_host_validation_before_any_device_call(monkeypatch):
-    # switched on, but every call below fails argument checks on the host before touching HIP
-    monkeypatch.setenv(fc.DEVICE_PATH_ENV, "1")
+def test_host_validation_before_any_device_call():
+    # every call below fails argument checks on the host before touching HIP
     L = fc.lib()
     assert _call_diagram() == fc.PH_EINVAL                      # null buffers
     assert L.ph_diagram(None, fc.make_shape((4, 4)), 3, fc.ph_pairs(), -1, None, None, None, 0,
@@ -123,7 +105,7 @@ def test_binding_raises_without_gpu_tensor():
 
 def test_status_names_cover_codes():
     for code in (fc.PH_OK, fc.PH_EINVAL, fc.PH_ENAN, fc.PH_ECAPACITY, fc.PH_ENOMEM, fc.PH_EHIP,
-                 fc.PH_EINTERNAL, fc.PH_EDISABLED):
+                 fc.PH_EINTERNAL):
         assert code in fc.STATUS_NAMES
 
 
