@@ -87,7 +87,7 @@ def cpu_baseline(workers: int):
     items = [(i, SHAPE3, SIG3, 2000 + i) for i in range(n3)] + \
             [(N3 + i, SHAPE2, SIG2, 3000 + i) for i in range(n2)]
     t0 = time.perf_counter()
-    with get_context("fork").Pool(workers) as pool:
+    with get_context("spawn").Pool(workers) as pool:     # fresh processes: no HIP state is forked
         res = pool.map(_oracle_instance, items, chunksize=1)
     wall = time.perf_counter() - t0
     vox = sum(r[1] for r in res)
@@ -235,16 +235,16 @@ def main():
             "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": workload_desc(), "instances": len(shapes), "voxels": nvox}}
 
+    ref = {}
+    if not args.no_cpu_baseline:                 # before this process loads HIP
+        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
+        print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
+        line["cpu_baseline"], ref = cpu_baseline(workers)
     import paper_2606_04801_amd as fc
     if args.host_library:
         fc.LIB_PATH = args.host_library
     fc.lib()
     import torch
-    ref = {}
-    if not args.no_cpu_baseline:
-        workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
-        print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
-        line["cpu_baseline"], ref = cpu_baseline(workers)
     gpu = torch.cuda.is_available()
     if args.host_library:
         line.update(run_gpu(fc, torch, shapes, args, ref, dev=torch.device("cpu")))
@@ -275,6 +275,8 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
     print("bench: generating %d instances" % len(shapes), file=sys.stderr, flush=True)
     imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
     host = [torch.from_numpy(a) for a in imgs]
+    if cuda:
+        torch.zeros(1, device=dev)               # the device context exists before the library's first call
     rc = fc.lib().ph_init_device()
     if rc != fc.PH_OK:
         raise fc.PHError(rc, "ph_init_device")

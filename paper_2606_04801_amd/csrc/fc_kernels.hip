@@ -1059,6 +1059,13 @@ int host_luts() {
 // kernels reading unwritten workspace, so the library refuses to run instead.
 struct KInfo { const char *name; const void *fn; int threads; };
 
+// A failed HIP call of the set-up path is named on stderr: the caller only sees PH_EHIP.
+bool hip_ok(hipError_t e, const char *what) {
+    if (e == hipSuccess) return true;
+    fprintf(stderr, "flashcubical: %s failed: %s\n", what, hipGetErrorString(e));
+    return false;
+}
+
 int check_kernels(int dev, char *report, size_t len) {
     const KInfo ks[] = {
         {"k_plan", (const void *)k_plan, 64},
@@ -1080,8 +1087,9 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_scatter", (const void *)k_scatter, 256},
     };
     int maxsh = 0, maxthr = 0;
-    if (hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return PH_EHIP;
-    if (hipDeviceGetAttribute(&maxthr, hipDeviceAttributeMaxThreadsPerBlock, dev) != hipSuccess) return PH_EHIP;
+    if (!hip_ok(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute") ||
+        !hip_ok(hipDeviceGetAttribute(&maxthr, hipDeviceAttributeMaxThreadsPerBlock, dev), "hipDeviceGetAttribute"))
+        return PH_EHIP;
     size_t used = 0;
     auto put = [&](const char *fmt, auto... a) {
         if (!report || used >= len) return;
@@ -1092,7 +1100,7 @@ int check_kernels(int dev, char *report, size_t len) {
     int rc = PH_OK;
     for (const KInfo &k : ks) {
         hipFuncAttributes at;
-        if (hipFuncGetAttributes(&at, k.fn) != hipSuccess) { put("%s: attributes unavailable\n", k.name); rc = PH_EHIP; continue; }
+        if (!hip_ok(hipFuncGetAttributes(&at, k.fn), k.name)) { put("%s: attributes unavailable\n", k.name); rc = PH_EHIP; continue; }
         const bool ok = (int)at.sharedSizeBytes <= maxsh && at.maxThreadsPerBlock >= k.threads && k.threads <= maxthr;
         put("%s: lds %d B, regs %d, max threads %d, launch %d %s\n", k.name, (int)at.sharedSizeBytes,
             at.numRegs, at.maxThreadsPerBlock, k.threads, ok ? "ok" : "DOES NOT FIT");
@@ -1105,16 +1113,16 @@ int device_luts() {
     int rc = host_luts();
     if (rc != PH_OK) return rc;
     int dev = 0;
-    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PH_EHIP;
+    if (!hip_ok(hipGetDevice(&dev), "hipGetDevice") || dev < 0 || dev >= 64) return PH_EHIP;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     if (g_dev_ready[dev]) return PH_OK;
     void *a = nullptr, *b = nullptr, *c = nullptr;
-    if (hipMalloc(&a, sizeof g_h_lut2d) != hipSuccess) return PH_EHIP;
-    if (hipMalloc(&b, sizeof(uint32_t) * kL1Size) != hipSuccess) { (void)hipFree(a); return PH_EHIP; }
-    if (hipMalloc(&c, sizeof(uint64_t) * kL3Configs) != hipSuccess) { (void)hipFree(a); (void)hipFree(b); return PH_EHIP; }
-    if (hipMemcpy(a, g_h_lut2d, sizeof g_h_lut2d, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(b, g_h_l1.data(), sizeof(uint32_t) * kL1Size, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(c, g_h_l2.data(), sizeof(uint64_t) * kL3Configs, hipMemcpyHostToDevice) != hipSuccess) {
+    if (!hip_ok(hipMalloc(&a, sizeof g_h_lut2d), "hipMalloc (tables)")) return PH_EHIP;
+    if (!hip_ok(hipMalloc(&b, sizeof(uint32_t) * kL1Size), "hipMalloc (tables)")) { (void)hipFree(a); return PH_EHIP; }
+    if (!hip_ok(hipMalloc(&c, sizeof(uint64_t) * kL3Configs), "hipMalloc (tables)")) { (void)hipFree(a); (void)hipFree(b); return PH_EHIP; }
+    if (!hip_ok(hipMemcpy(a, g_h_lut2d, sizeof g_h_lut2d, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(b, g_h_l1.data(), sizeof(uint32_t) * kL1Size, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(c, g_h_l2.data(), sizeof(uint64_t) * kL3Configs, hipMemcpyHostToDevice), "hipMemcpy (tables)")) {
         (void)hipFree(a); (void)hipFree(b); (void)hipFree(c);
         return PH_EHIP;
     }
@@ -1567,9 +1575,10 @@ int ph_init_device(void) {
     std::vector<uint32_t> l2d(256), l1(fc::kL1Size);
     std::vector<uint64_t> l2(fc::kL3Configs);
     const fc::Luts t = fc::current_luts();
-    if (hipMemcpy(l2d.data(), t.l2d, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
-    if (hipMemcpy(l1.data(), t.l1, l1.size() * sizeof(uint32_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
-    if (hipMemcpy(l2.data(), t.l2, l2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost) != hipSuccess) return PH_EHIP;
+    if (!fc::hip_ok(hipMemcpy(l2d.data(), t.l2d, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
+        !fc::hip_ok(hipMemcpy(l1.data(), t.l1, l1.size() * sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
+        !fc::hip_ok(hipMemcpy(l2.data(), t.l2, l2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)"))
+        return PH_EHIP;
     if (memcmp(l2d.data(), fc::g_h_lut2d, 256 * sizeof(uint32_t)) || l1 != fc::g_h_l1 || l2 != fc::g_h_l2) return PH_EINTERNAL;
     return PH_OK;
 }

@@ -336,6 +336,7 @@ template <typename T> inline void __hip_atomic_store(T *p, T v, int, int) {
 
 // host API subset
 inline hipError_t hipGetLastError() { return hipSuccess; }
+inline const char *hipGetErrorString(hipError_t e) { return e == hipSuccess ? "no error" : "emulated error"; }
 inline hipError_t hipGetDevice(int *d) { *d = 0; return hipSuccess; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
 enum { hipDeviceAttributeMaxSharedMemoryPerBlock = 1, hipDeviceAttributeMaxThreadsPerBlock = 2 };
