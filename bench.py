@@ -240,11 +240,11 @@ def main():
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(workers)
+    import torch
     import paper_2606_04801_amd as fc
     if args.host_library:
         fc.LIB_PATH = args.host_library
     fc.lib()
-    import torch
     gpu = torch.cuda.is_available()
     if args.host_library:
         line.update(run_gpu(fc, torch, shapes, args, ref, dev=torch.device("cpu")))

@@ -62,13 +62,35 @@ class ph_kernel_time(ctypes.Structure):
 _lib = None
 
 
+def _hip_runtimes():
+    """Paths of the HIP runtime libraries mapped into this process."""
+    try:
+        with open("/proc/self/maps") as f:
+            return sorted({ln.split()[-1] for ln in f if "libamdhip64" in ln and "/" in ln})
+    except OSError:
+        return []
+
+
 def lib():
-    """The loaded C library; raises when it is missing (build it first)."""
+    """The loaded C library; raises when it is missing (build it first).
+
+    The library must share the HIP runtime of torch, which provides the device memory and
+    streams: torch is imported first, so the loader binds the library to torch's copy of the
+    runtime.  Loaded the other way round, the process would hold two runtimes, and the
+    library's would not see torch's allocations."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libflashcubical.so is not built: run `python -m paper_2606_04801_amd.build`")
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
+        runtimes = _hip_runtimes()
+        if len(runtimes) > 1:
+            raise ImportError("two HIP runtimes are loaded (%s): import torch before this library is "
+                              "loaded" % ", ".join(runtimes))
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         L.ph_capacity_bound.argtypes = [ph_shape]
         L.ph_capacity_bound.restype = i64

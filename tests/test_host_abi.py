@@ -115,3 +115,23 @@ def test_work_counters_validation():
     assert L.ph_work_counters(None, 1, out) == fc.PH_EINVAL
     assert L.ph_work_counters(ctypes.c_void_p(1), 0, out) == fc.PH_EINVAL
     assert L.ph_work_counters(ctypes.c_void_p(1), 1, None) == fc.PH_EINVAL
+
+
+def test_one_hip_runtime_shared_with_torch():
+    """The library binds to torch's HIP runtime: one libamdhip64 in the process (a second
+    copy would not see torch's device allocations)."""
+    pytest.importorskip("torch")
+    fc.lib()
+    assert len(fc._hip_runtimes()) <= 1, fc._hip_runtimes()
+
+
+def test_library_loaded_before_torch_still_shares_its_runtime():
+    """In a fresh process, the first use of the binding without importing torch still ends with
+    one runtime: lib() imports torch before loading the library."""
+    import subprocess
+    import sys
+    pytest.importorskip("torch")
+    code = ("import sys; sys.path.insert(0, %r); import paper_2606_04801_amd as fc; fc.lib(); "
+            "print(len(fc._hip_runtimes()))" % ROOT)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().splitlines()[-1] in ("0", "1"), r.stdout + r.stderr[-2000:]
