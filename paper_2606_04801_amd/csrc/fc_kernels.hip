@@ -80,46 +80,81 @@ FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
     I.pad = 0;
 }
 
-__global__ void k_plan(int n, const ph_shape *__restrict__ d_shapes, ph_shape single,
+// One thread per instance, in chunks of the block: each instance's table entry, with its
+// workspace offset and first tile found by a block-wide prefix sum over the chunk.  An
+// instance's arrays start on a 256-byte boundary, so its layout is its size-only layout
+// shifted by its offset.
+constexpr int kPlanThreads = 1024;
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__restrict__ d_shapes, ph_shape single,
                        const int64_t *__restrict__ d_img_off, const int64_t *__restrict__ d_out_off,
                        int64_t single_cap, Tiles tl, uint8_t *__restrict__ ws,
                        int64_t *__restrict__ d_counts, int32_t *__restrict__ d_status,
                        int64_t want_t2, int64_t want_t3, int64_t ws_bytes) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    __shared__ int64_t s_scan[2][3][kPlanThreads];   // bytes, 2D tiles, 3D tiles (double buffer)
+    __shared__ int64_t s_run[3];
+    if (blockIdx.x != 0) return;
+    const int t = threadIdx.x;
     Inst *tab = (Inst *)ws;
     int64_t *tb2 = (int64_t *)(ws + off_tb2(n));
     int64_t *tb3 = (int64_t *)(ws + off_tb3(n));
     int32_t *cnt = (int32_t *)(ws + off_cnt(n));
-    int64_t at = header_bytes(n), t2 = 0, t3 = 0;
-    for (int i = 0; i < n; ++i) {
-        ph_shape s = d_shapes ? d_shapes[i] : single;
-        bool ok = s.ndim == 2 || s.ndim == 3;
-        for (int k = 0; k < 3 && ok; ++k) ok = k >= s.ndim || s.ext[k] >= 1;
-        if (!ok) s = ph_shape{2, {1, 1, 1}};
+    if (t == 0) { s_run[0] = header_bytes(n); s_run[1] = 0; s_run[2] = 0; }
+    __syncthreads();
+    for (int c0 = 0; c0 < n; c0 += kPlanThreads) {
+        const int i = c0 + t;
         Inst I;
-        fill_inst(I, s, tl);
-        if (I.N >= (1ll << kPixBits)) { ok = false; s = ph_shape{2, {1, 1, 1}}; fill_inst(I, s, tl); }
-        I.img_off = d_img_off ? d_img_off[i] : 0;
-        I.out_off = d_out_off ? d_out_off[i] : 0;
-        I.out_cap = d_out_off ? d_out_off[i + 1] - d_out_off[i] : single_cap;
-        tb2[i] = t2;
-        tb3[i] = t3;
-        if (I.ndim == 2) { I.tile_base = t2; t2 += (int64_t)I.tx * I.ty; }
-        else { I.tile_base = t3; t3 += (int64_t)I.tx * I.ty * I.tz; }
-        at = layout(I, at);
-        tab[i] = I;
-        for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
-        cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
-        if (!ok || I.out_cap < 0) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
-        d_counts[i] = 0;
-        d_status[i] = PH_OK;
+        bool ok = true;
+        int64_t v[3] = {0, 0, 0};
+        if (i < n) {
+            ph_shape s = d_shapes ? d_shapes[i] : single;
+            ok = (s.ndim == 2 || s.ndim == 3) && s.ext[0] >= 1 && s.ext[1] >= 1 && (s.ndim == 2 || s.ext[2] >= 1);
+            if (!ok) s = ph_shape{2, {1, 1, 1}};
+            fill_inst(I, s, tl);
+            if (I.N >= (1ll << kPixBits)) { ok = false; s = ph_shape{2, {1, 1, 1}}; fill_inst(I, s, tl); }
+            v[0] = layout(I, 0);
+            if (I.ndim == 2) v[1] = (int64_t)I.tx * I.ty;
+            else v[2] = (int64_t)I.tx * I.ty * I.tz;
+        }
+        // inclusive Hillis-Steele scan of the three sizes over the block
+        int b = 0;
+        for (int k = 0; k < 3; ++k) s_scan[0][k][t] = v[k];
+        __syncthreads();
+        for (int off = 1; off < kPlanThreads; off <<= 1) {
+            for (int k = 0; k < 3; ++k)
+                s_scan[b ^ 1][k][t] = s_scan[b][k][t] + (t >= off ? s_scan[b][k][t - off] : 0);
+            b ^= 1;
+            __syncthreads();
+        }
+        if (i < n) {
+            const int64_t at = s_run[0] + s_scan[b][0][t] - v[0];
+            I.img_off = d_img_off ? d_img_off[i] : 0;
+            I.out_off = d_out_off ? d_out_off[i] : 0;
+            I.out_cap = d_out_off ? d_out_off[i + 1] - d_out_off[i] : single_cap;
+            tb2[i] = s_run[1] + s_scan[b][1][t] - v[1];
+            tb3[i] = s_run[2] + s_scan[b][2][t] - v[2];
+            I.tile_base = I.ndim == 2 ? tb2[i] : tb3[i];
+            layout(I, at);
+            tab[i] = I;
+            for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
+            cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
+            if (!ok || I.out_cap < 0) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
+            d_counts[i] = 0;
+            d_status[i] = PH_OK;
+        }
+        __syncthreads();
+        if (t == kPlanThreads - 1)
+            for (int k = 0; k < 3; ++k) s_run[k] += s_scan[b][k][t];
+        __syncthreads();
     }
-    tb2[n] = t2;
-    tb3[n] = t3;
+    if (t == 0) {
+        tb2[n] = s_run[1];
+        tb3[n] = s_run[2];
+    }
     // the launch grids were sized from the host shapes: a device table that disagrees with
     // them (or outgrows the workspace) disables every instance
-    if (t2 != want_t2 || t3 != want_t3 || at > ws_bytes)
-        for (int i = 0; i < n; ++i) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
+    if (s_run[1] != want_t2 || s_run[2] != want_t3 || s_run[0] > ws_bytes)
+        for (int i = t; i < n; i += kPlanThreads) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
 }
 
 // true when an earlier kernel recorded an error for this instance: later kernels skip it
@@ -158,22 +193,45 @@ __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
     atomicCAS(&cnt[CNT_ERR], 0, code);
 }
 
-// wave-aggregated reservation: returns this lane's first slot; all lanes must call it.  Most
-// waves reserve nothing (kept cells are rare), so they skip the scan.
-__device__ __forceinline__ int wave_alloc(int32_t *counter, int count) {
-    if (__ballot(count != 0) == 0) return 0;
-    const int lane = __lane_id();
-    int x = count;
+// Block-wide reservation of slots in up to four per-instance lists at once.  Each thread
+// passes its counts packed 16 bits per list (every block total stays below 2^16: a tile has
+// 1024 vertices and at most 12 kept cells each of one kind); the block scans them once and
+// one thread reserves each list's block total with a single atomic, so a tile costs one
+// atomic per non-empty list instead of one per wave and pass.  Returns the thread's
+// exclusive prefix (packed the same way); the lists' first slots are left in s_base.  All
+// threads call it.
+__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
+    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
+    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int NLIST>
+__device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[NLIST], uint64_t packed,
+                                                uint64_t *s_scan, int32_t *s_base) {
+    const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    uint64_t x = packed;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
-        int y = __shfl_up(x, off, 64);
+        const uint64_t y = shfl_up64(x, off);
         if (lane >= off) x += y;
     }
-    int total = __shfl(x, 63, 64);
-    int base = 0;
-    if (lane == 0 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 0, 64);
-    return base + x - count;
+    if (lane == 63) s_scan[wid] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint64_t tot = 0;
+        for (int w = 0; w < nw; ++w) {
+            const uint64_t v = s_scan[w];
+            s_scan[w] = tot;
+            tot += v;
+        }
+        for (int k = 0; k < NLIST; ++k) {
+            const int t = (int)((tot >> (16 * k)) & 0xFFFFu);
+            s_base[k] = t ? atomicAdd(&cnt[list[k]], t) : 0;
+        }
+    }
+    __syncthreads();
+    return s_scan[wid] + x - packed;
 }
 
 // ================================================================ classify 2D ====
@@ -186,6 +244,8 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ int32_t sp0[TH * TW];
     __shared__ int32_t spT[NP];
     __shared__ int s_nan;
+    __shared__ uint64_t s_scan[4];
+    __shared__ int32_t s_base[4];
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -229,53 +289,70 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     constexpr int NDX[8] = {0, -1, 1, 0, -1, 1, -1, 1};
     constexpr bool NBEFORE[8] = {true, true, false, false, true, true, false, false};
 
-#pragma unroll 1
-    for (int it = 0; it < TH * TW / 256; ++it) {
+    // pass 1: every vertex of the thread through the table; counts of the cells it keeps
+    constexpr int NIT = TH * TW / 256;
+    constexpr uint32_t kValid = 1u << 31;           // above every field of a 2D entry
+    uint32_t ev[NIT];
+    uint64_t packed = 0;                            // minima | KEEP edges << 16 | ROOT squares << 32
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
         const int l = threadIdx.x + it * 256;
         const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
-        const bool valid = gy < H && gx < W;
-        const uint32_t kv = skey[(r + 1) * KW + c + 1];
-        const uint32_t pv = (uint32_t)(gy * W + gx);
-        uint32_t e = kNoDirect;
-        if (valid) {
+        uint32_t e = 0;
+        if (gy < H && gx < W) {
+            const uint32_t kv = skey[(r + 1) * KW + c + 1];
             uint32_t mask = 0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {               // outside neighbours hold kOutside
                 uint32_t kn = skey[(r + 1 + NDY[b]) * KW + c + 1 + NDX[b]];
                 if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
             }
-            e = lut.l2d[mask];
+            e = lut.l2d[mask] | kValid;
+            packed += (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((e >> kL2Keep) & 15u) << 16) |
+                      ((uint64_t)__popc((e >> kL2Root) & 15u) << 32);
         }
+        ev[it] = e;
+    }
+    const int lists[3] = {CNT_M0, CNT_E, CNT_MT};
+    const uint64_t pre = block_alloc<3>(cnt, lists, packed, s_scan, s_base);
+    int id0 = s_base[0] + (int)(pre & 0xFFFFu);
+    int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
+    int rb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
+
+    // pass 2: forest links, node keys and compact lists at the reserved slots
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint32_t e = ev[it];
+        if (!(e & kValid)) continue;
+        const int l = threadIdx.x + it * 256;
+        const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        const uint32_t kv = skey[(r + 1) * KW + c + 1];
+        const uint32_t pv = (uint32_t)(gy * W + gx);
         const uint32_t direct = e & 7u;
-        const bool ismin = valid && direct == kNoDirect;
-        const uint32_t keep = valid ? (e >> kL2Keep) & 15u : 0u;
-        const uint32_t present = valid ? (e >> kL2Present) & 15u : 0u;
-        const uint32_t root = valid ? (e >> kL2Root) & 15u : 0u;
+        const uint32_t keep = (e >> kL2Keep) & 15u;
+        const uint32_t present = (e >> kL2Present) & 15u;
+        const uint32_t root = (e >> kL2Root) & 15u;
 
         // H0 forest: link to the other end of the DIRECT edge, or become a node
-        int id0 = wave_alloc(&cnt[CNT_M0], ismin ? 1 : 0);
-        if (ismin && id0 >= I.N) { set_err(cnt, PH_EINTERNAL); id0 = 0; }
-        if (valid) {
-            if (ismin) {
-                sp0[l] = -(id0 + 1);
-                n0key[id0] = make_key(kv, pv, 0);
-            } else {
-                const int dy = direct == 0 ? -1 : (direct == 3 ? 1 : 0);
-                const int dx = direct == 1 ? -1 : (direct == 2 ? 1 : 0);
-                const int rr = r + dy, cc = c + dx;
-                if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) sp0[l] = kLocal | (rr * TW + cc);
-                else sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
-            }
+        if (direct == kNoDirect) {
+            int id = id0++;
+            if (id >= I.N) { set_err(cnt, PH_EINTERNAL); id = 0; }
+            sp0[l] = -(id + 1);
+            n0key[id] = make_key(kv, pv, 0);
+        } else {
+            const int dy = direct == 0 ? -1 : (direct == 3 ? 1 : 0);
+            const int dx = direct == 1 ? -1 : (direct == 2 ? 1 : 0);
+            const int rr = r + dy, cc = c + dx;
+            if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) sp0[l] = kLocal | (rr * TW + cc);
+            else sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
         }
         // KEEP edges -> compact list
-        int kb = wave_alloc(&cnt[CNT_E], __popc(keep));
         for (int b = 0; b < 4; ++b)
             if ((keep >> b) & 1u) {
                 if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
                 ++kb;
             }
         // squares of L(v): ROOT -> dual node, LOCAL -> dual link
-        int rb = wave_alloc(&cnt[CNT_MT], __popc(root));
         for (int q = 0; q < 4; ++q) {
             if (!((present >> q) & 1u)) continue;
             const int sy = gy - 1 + (q >> 1), sx = gx - 1 + (q & 1);
@@ -352,6 +429,8 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __shared__ int32_t sp0[NV];
     __shared__ int32_t spT[NP];
     __shared__ int s_nan;
+    __shared__ uint64_t s_scan[4];
+    __shared__ int32_t s_base[4];
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -393,16 +472,19 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __syncthreads();
     if (nan) s_nan = 1;
 
-#pragma unroll 1
-    for (int it = 0; it < NV / 256; ++it) {
+    // pass 1: every vertex of the thread through the table; counts of the cells it keeps
+    constexpr int NIT = NV / 256;
+    constexpr uint64_t kValid = 1ull << 63;         // above every field of a 3D entry
+    uint64_t ev[NIT];
+    uint64_t packed = 0;              // minima | KEEP edges << 16 | KEEP squares << 32 | ROOT cubes << 48
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
         const int l = threadIdx.x + it * 256;
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
-        const bool valid = gz < D && gy < H && gx < W;
-        const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
-        const uint32_t pv = (uint32_t)(gz * HW + (int64_t)gy * W + gx);
-        uint64_t e = kNoDirect;
-        if (valid) {
+        uint64_t e = 0;
+        if (gz < D && gy < H && gx < W) {
+            const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
             uint32_t raw = 0;
 #pragma unroll
             for (int code = 1; code < 27; ++code) {     // outside neighbours hold kOutside
@@ -415,45 +497,63 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             const uint32_t idx1 = canon3d(raw, &cubes);
             const uint32_t l1 = lut.l1[idx1];
             const uint32_t idx2 = (l1 >> 8) + compress8(cubes, l1 & 255u);
+            e = kNoDirect;
             if (idx2 < (uint32_t)kL3Configs) e = lut.l2[idx2];
             else set_err(cnt, PH_EINTERNAL);
+            e |= kValid;
+            packed += (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((uint32_t)(e >> kL3Keep) & 63u) << 16) |
+                      ((uint64_t)__popc((uint32_t)(e >> kL3KeepSq) & 4095u) << 32) |
+                      ((uint64_t)__popc((uint32_t)(e >> kL3Root) & 255u) << 48);
         }
-        const uint32_t direct = (uint32_t)(e & 7u);
-        const bool ismin = valid && direct == kNoDirect;
-        const uint32_t keep = valid ? (uint32_t)((e >> kL3Keep) & 63u) : 0u;
-        const uint32_t keepsq = valid ? (uint32_t)((e >> kL3KeepSq) & 4095u) : 0u;
-        const uint32_t root = valid ? (uint32_t)((e >> kL3Root) & 255u) : 0u;
-        const uint32_t present = valid ? (uint32_t)((e >> kL3Present) & 255u) : 0u;
+        ev[it] = e;
+    }
+    const int lists[4] = {CNT_M0, CNT_E, CNT_F, CNT_MT};
+    const uint64_t pre = block_alloc<4>(cnt, lists, packed, s_scan, s_base);
+    int id0 = s_base[0] + (int)(pre & 0xFFFFu);
+    int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
+    int fb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
+    int rb = s_base[3] + (int)((pre >> 48) & 0xFFFFu);
 
-        int id0 = wave_alloc(&cnt[CNT_M0], ismin ? 1 : 0);
-        if (ismin && id0 >= I.N) { set_err(cnt, PH_EINTERNAL); id0 = 0; }
-        if (valid) {
-            if (ismin) {
-                sp0[l] = -(id0 + 1);
-                n0key[id0] = make_key(kv, pv, 0);
-            } else {
-                const int code = 1 + (int)direct;
-                const int dz = off_of(code, 0), dy = off_of(code, 1), dx = off_of(code, 2);
-                const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
-                if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW)
-                    sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
-                else
-                    sp0[l] = (int32_t)((gz + dz) * HW + (int64_t)(gy + dy) * W + gx + dx);
-            }
+    // pass 2: forest links, node keys and compact lists at the reserved slots
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const uint64_t e = ev[it];
+        if (!(e & kValid)) continue;
+        const int l = threadIdx.x + it * 256;
+        const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
+        const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+        const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
+        const uint32_t pv = (uint32_t)(gz * HW + (int64_t)gy * W + gx);
+        const uint32_t direct = (uint32_t)(e & 7u);
+        const uint32_t keep = (uint32_t)((e >> kL3Keep) & 63u);
+        const uint32_t keepsq = (uint32_t)((e >> kL3KeepSq) & 4095u);
+        const uint32_t root = (uint32_t)((e >> kL3Root) & 255u);
+        const uint32_t present = (uint32_t)((e >> kL3Present) & 255u);
+
+        if (direct == kNoDirect) {
+            int id = id0++;
+            if (id >= I.N) { set_err(cnt, PH_EINTERNAL); id = 0; }
+            sp0[l] = -(id + 1);
+            n0key[id] = make_key(kv, pv, 0);
+        } else {
+            const int code = 1 + (int)direct;
+            const int dz = off_of(code, 0), dy = off_of(code, 1), dx = off_of(code, 2);
+            const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
+            if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW)
+                sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
+            else
+                sp0[l] = (int32_t)((gz + dz) * HW + (int64_t)(gy + dy) * W + gx + dx);
         }
-        int kb = wave_alloc(&cnt[CNT_E], __popc(keep));
         for (int b = 0; b < 6; ++b)
             if ((keep >> b) & 1u) {
                 if (kb < I.E) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
                 ++kb;
             }
-        int fb = wave_alloc(&cnt[CNT_F], __popc(keepsq));
-        for (int s = 0; s < 12; ++s)
-            if ((keepsq >> s) & 1u) {
-                if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + s); else set_err(cnt, PH_EINTERNAL);
+        for (int q = 0; q < 12; ++q)
+            if ((keepsq >> q) & 1u) {
+                if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
                 ++fb;
             }
-        int rb = wave_alloc(&cnt[CNT_MT], __popc(root));
         for (int b = 0; b < 8; ++b) {
             if (!((present >> b) & 1u)) continue;
             const int sz = gz - 1 + (b >> 2), sy = gy - 1 + ((b >> 1) & 1), sx = gx - 1 + (b & 1);
@@ -1068,7 +1168,7 @@ bool hip_ok(hipError_t e, const char *what) {
 
 int check_kernels(int dev, char *report, size_t len) {
     const KInfo ks[] = {
-        {"k_plan", (const void *)k_plan, 64},
+        {"k_plan", (const void *)k_plan, kPlanThreads},
         {"k_classify2d<64,16>", (const void *)k_classify2d<64, 16>, 256},
         {"k_classify2d<32,32>", (const void *)k_classify2d<32, 32>, 256},
         {"k_classify2d<128,8>", (const void *)k_classify2d<128, 8>, 256},
@@ -1327,7 +1427,7 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
         if (prof) prof_push(KID, ev_a, prof_mark(st));                        \
         if (trace && trace_after(KID, st) != PH_OK) return PH_EHIP;           \
     } while (0)
-    FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, st, n, d_shapes, single, d_img_off, d_out_off,
+    FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, n, d_shapes, single, d_img_off, d_out_off,
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
     const Luts lut = current_luts();
     if (t2 > 0) {

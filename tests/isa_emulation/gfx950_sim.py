@@ -401,6 +401,7 @@ VALU2 = {   # D = f(S0, S1)
     "v_lshrrev_b32": lambda a, b: vec(b) >> (vec(a) & U32(31)),
     "v_ashrrev_i32": lambda a, b: (s32(b) >> (vec(a) & U32(31)).astype(I32)).view(U32),
     "v_max_i32": lambda a, b: np.maximum(s32(a), s32(b)).view(U32),
+    "v_min_i32": lambda a, b: np.minimum(s32(a), s32(b)).view(U32),
     "v_max_u32": lambda a, b: np.maximum(vec(a), vec(b)),
     "v_min_u32": lambda a, b: np.minimum(vec(a), vec(b)),
     "v_mul_lo_u32": lambda a, b: ((vec(a).astype(U64) * vec(b).astype(U64)) & U64(M32)).astype(U32),
@@ -1131,8 +1132,8 @@ def _compile_ds(op, O, mods, nxt):
                         (what, w.pc, int(addrs[bad][0]), int(addrs[bad][0]) + n, lim))
         return w.wg.lds
 
-    if kind in ("read_b32", "read_b64", "read_b128", "read_u16", "read_u8"):
-        n = {"read_b32": 4, "read_b64": 8, "read_b128": 16, "read_u16": 2, "read_u8": 1}[kind]
+    if kind in ("read_b32", "read_b64", "read_b96", "read_b128", "read_u16", "read_u8"):
+        n = {"read_b32": 4, "read_b64": 8, "read_b96": 12, "read_b128": 16, "read_u16": 2, "read_u8": 1}[kind]
         di, va = O[0].idx, r32(O[1])
 
         def f(w):
@@ -1150,9 +1151,11 @@ def _compile_ds(op, O, mods, nxt):
                 w.v[di][e] = raw.view("<u2" if n == 2 else "<u1").reshape(-1).astype(U32)
             return nxt
         return f
-    if kind == "read2_b32":
+    if kind in ("read2_b32", "read2_b64", "read2st64_b32", "read2st64_b64"):
+        esz = 8 if kind.endswith("b64") else 4
+        unit = esz * (64 if "st64" in kind else 1)
         di, va = O[0].idx, r32(O[1])
-        o0, o1 = int(mods.get("offset0", "0"), 0) * 4, int(mods.get("offset1", "0"), 0) * 4
+        o0, o1 = int(mods.get("offset0", "0"), 0) * unit, int(mods.get("offset1", "0"), 0) * unit
 
         def f(w):
             e = w.exec()
@@ -1161,12 +1164,14 @@ def _compile_ds(op, O, mods, nxt):
             base = vec(va(w)).astype(np.int64)[e]
             for k, o in enumerate((o0, o1)):
                 addrs = (base + o) & M32
-                mem = lds(w, addrs, 4, op)
-                w.v[di + k][e] = mem[addrs[:, None] + np.arange(4)].view("<u4").reshape(-1)
+                mem = lds(w, addrs, esz, op)
+                vals = mem[addrs[:, None] + np.arange(esz)].view("<u4").reshape(len(addrs), esz // 4)
+                for j in range(esz // 4):
+                    w.v[di + k * (esz // 4) + j][e] = vals[:, j]
             return nxt
         return f
-    if kind in ("write_b32", "write_b64", "write_b128", "write_b16", "write_b8"):
-        n = {"write_b32": 4, "write_b64": 8, "write_b128": 16, "write_b16": 2, "write_b8": 1}[kind]
+    if kind in ("write_b32", "write_b64", "write_b96", "write_b128", "write_b16", "write_b8"):
+        n = {"write_b32": 4, "write_b64": 8, "write_b96": 12, "write_b128": 16, "write_b16": 2, "write_b8": 1}[kind]
         va, si = r32(O[0]), O[1].idx
 
         def f(w):
@@ -1184,9 +1189,11 @@ def _compile_ds(op, O, mods, nxt):
                 mem[addrs[k]:addrs[k] + n] = data[k]
             return nxt
         return f
-    if kind == "write2_b32":
+    if kind in ("write2_b32", "write2_b64", "write2st64_b32", "write2st64_b64"):
+        esz = 8 if kind.endswith("b64") else 4
+        unit = esz * (64 if "st64" in kind else 1)
         va, s0, s1 = r32(O[0]), O[1].idx, O[2].idx
-        o0, o1 = int(mods.get("offset0", "0"), 0) * 4, int(mods.get("offset1", "0"), 0) * 4
+        o0, o1 = int(mods.get("offset0", "0"), 0) * unit, int(mods.get("offset1", "0"), 0) * unit
 
         def f(w):
             e = w.exec()
@@ -1195,10 +1202,11 @@ def _compile_ds(op, O, mods, nxt):
             base = vec(va(w)).astype(np.int64)[e]
             for o, si in ((o0, s0), (o1, s1)):
                 addrs = (base + o) & M32
-                mem = lds(w, addrs, 4, op)
-                data = w.v[si][e].astype("<u4").view(U8).reshape(len(addrs), 4)
+                mem = lds(w, addrs, esz, op)
+                data = np.stack([w.v[si + j][e] for j in range(esz // 4)], axis=1).astype("<u4").view(U8)
+                data = data.reshape(len(addrs), esz)
                 for k in range(len(addrs)):
-                    mem[addrs[k]:addrs[k] + 4] = data[k]
+                    mem[addrs[k]:addrs[k] + esz] = data[k]
             return nxt
         return f
     if kind == "bpermute_b32":

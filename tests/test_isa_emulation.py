@@ -113,3 +113,17 @@ def test_access_outside_device_memory_is_reported(isa):
             d.run()
         finally:
             d.done()
+
+
+def test_interpreter_covers_every_instruction(isa):
+    """Every instruction of the code object parses into an implemented operation, so no
+    path of any kernel can stop on an unknown one."""
+    from gfx950_sim import Unsupported, compile_instr
+    missing = {}
+    pcs = sorted(isa.prog.text)
+    for k, pc in enumerate(pcs):
+        try:
+            compile_instr(pc, isa.prog.text[pc], pcs[k + 1] if k + 1 < len(pcs) else None)
+        except Unsupported as e:
+            missing.setdefault(isa.prog.text[pc].split()[0], str(e))
+    assert not missing, missing
