@@ -177,13 +177,41 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t w, int64_t g) {
     return x * base + (x < rem ? x : rem) + local;
 }
 
+// Instance owning `tile`: the largest i with tb[i] <= tile (tb ascending, tb[0] = 0,
+// tb[n] = all tiles).  Every wave searches on its own, 64 probes per step, so a batch of up to
+// 64 instances costs one dependent load and 65535 instances three.
 __device__ __forceinline__ int find_inst(const int64_t *tb, int n, int64_t tile) {
-    int lo = 0, hi = n - 1;                        // largest i with tb[i] <= tile < tb[i+1]
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (tb[mid] <= tile) lo = mid; else hi = mid - 1;
+    const int lane = __lane_id();
+    int lo = 0, hi = n;                            // tb[lo] <= tile < tb[hi]
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) >> 6;
+        const int probe = lo + lane * step;
+        const bool le = probe < hi && tb[probe] <= tile;
+        const uint64_t m = __ballot(le);           // lanes 0.. set up to the owner's step
+        const int last = 63 - __builtin_clzll(m);  // lane 0 always qualifies (tb[lo] <= tile)
+        lo += last * step;
+        hi = lo + step < hi ? lo + step : hi;
     }
-    return lo;                                     // tb[lo+1] > tile: instance lo owns the tile
+    return lo;
+}
+
+// Barrier for LDS traffic only.  The global stores of a block are read by later kernels,
+// never by the block's other threads, so the barrier does not wait for them to complete.
+__device__ __forceinline__ void lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// OR of a flag over the block with one LDS-only barrier.  Successive calls alternate between
+// the two halves of s_any (parity), so a call never overwrites flags still being read.
+__device__ __forceinline__ bool block_any(int flag, int *s_any, int parity) {
+    const bool w = __ballot(flag) != 0;
+    if (__lane_id() == 0) s_any[parity * 16 + (threadIdx.x >> 6)] = w ? 1 : 0;
+    lds_barrier();
+    int r = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r |= s_any[parity * 16 + k];
+    return r != 0;
 }
 
 template <typename T>
@@ -217,7 +245,7 @@ __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[
         if (lane >= off) x += y;
     }
     if (lane == 63) s_scan[wid] = x;
-    __syncthreads();
+    lds_barrier();
     if (threadIdx.x == 0) {
         uint64_t tot = 0;
         for (int w = 0; w < nw; ++w) {
@@ -230,7 +258,7 @@ __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[
             s_base[k] = t ? atomicAdd(&cnt[list[k]], t) : 0;
         }
     }
-    __syncthreads();
+    lds_barrier();
     return s_scan[wid] + x - packed;
 }
 
@@ -246,6 +274,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
+    __shared__ int s_any[32];
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -266,22 +295,37 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
 
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
-    for (int l = threadIdx.x; l < (TH + 2) * KW; l += 256) {
-        int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
-        uint32_t k = kOutside;
-        if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            float f = img[(int64_t)gy * W + gx];
-            nan |= (f != f);
-            const uint32_t o = ord32(__float_as_uint(f));
-            k = o < kOutside ? o : kOutside - 1u;
+    {
+        // every halo load of the thread is issued before the first is used: the addresses
+        // are clamped into the image and outside pixels replaced afterwards
+        constexpr int NS = (TH + 2) * KW, NL = (NS + 255) / 256;
+        float f[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int l = threadIdx.x + 256 * k;
+            const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
+            const int cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy), cx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
+            f[k] = img[(int64_t)cy * W + cx];
         }
-        skey[l] = k;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int l = threadIdx.x + 256 * k;
+            const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
+            if (l >= NS) break;
+            uint32_t key = kOutside;
+            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                nan |= (f[k] != f[k]);
+                const uint32_t o = ord32(__float_as_uint(f[k]));
+                key = o < kOutside ? o : kOutside - 1u;
+            }
+            skey[l] = key;
+        }
     }
     for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
     // every link slot starts final (0 is never followed); slots of vertices outside the
     // image keep it, so the pointer jumping below never reads an uninitialised slot
     for (int l = threadIdx.x; l < TH * TW; l += 256) sp0[l] = 0;
-    __syncthreads();
+    lds_barrier();
     if (nan) s_nan = 1;
 
     // neighbours in mask-bit order: up, left, right, down, UL, UR, DL, DR
@@ -372,7 +416,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     // resolve links inside the tile by pointer jumping
     for (int round = 0; round < 32; ++round) {
@@ -398,7 +442,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
                 changed = 1;
             }
         }
-        if (!__syncthreads_or(changed)) break;
+        if (!block_any(changed, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < TH * TW; l += 256) {
@@ -431,6 +475,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
+    __shared__ int s_any[32];
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -455,21 +500,37 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
 
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
-    for (int l = threadIdx.x; l < KD * KH * KW; l += 256) {
-        int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
-        int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-        uint32_t k = kOutside;
-        if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
-            float f = img[gz * HW + (int64_t)gy * W + gx];
-            nan |= (f != f);
-            const uint32_t o = ord32(__float_as_uint(f));
-            k = o < kOutside ? o : kOutside - 1u;
+    {
+        // every halo load of the thread is issued before the first is used (see the 2D kernel)
+        constexpr int NS = KD * KH * KW, NL = (NS + 255) / 256;
+        float f[NL];
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int l = threadIdx.x + 256 * k;
+            const int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
+            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+            const int cz = gz < 0 ? 0 : (gz >= D ? D - 1 : gz), cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy),
+                      cx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
+            f[k] = img[cz * HW + (int64_t)cy * W + cx];
         }
-        skey[l] = k;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int l = threadIdx.x + 256 * k;
+            if (l >= NS) break;
+            const int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
+            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
+            uint32_t key = kOutside;
+            if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
+                nan |= (f[k] != f[k]);
+                const uint32_t o = ord32(__float_as_uint(f[k]));
+                key = o < kOutside ? o : kOutside - 1u;
+            }
+            skey[l] = key;
+        }
     }
     for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
     for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;      // see the 2D kernel
-    __syncthreads();
+    lds_barrier();
     if (nan) s_nan = 1;
 
     // pass 1: every vertex of the thread through the table; counts of the cells it keeps
@@ -574,7 +635,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             }
         }
     }
-    __syncthreads();
+    lds_barrier();
 
     for (int round = 0; round < 32; ++round) {
         int changed = 0;
@@ -599,7 +660,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
                 changed = 1;
             }
         }
-        if (!__syncthreads_or(changed)) break;
+        if (!block_any(changed, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < NV; l += 256) {

@@ -246,6 +246,9 @@ EMU_FN void emu_run_block(unsigned nt, dim3 bid, EmuBlock *blk, void (*fn)(void 
 }
 
 EMU_FN void __syncthreads() { emu_barrier_wait(emu_block->bar); }
+// the gfx950 barrier and fence builtins: every emulated barrier orders all memory
+#define __builtin_amdgcn_s_barrier() __syncthreads()
+#define __builtin_amdgcn_fence(...) ((void)0)
 EMU_FN int __syncthreads_or(int x) {
     EmuBlock *b = emu_block;
     emu_barrier_wait(b->bar);

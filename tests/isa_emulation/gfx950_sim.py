@@ -630,7 +630,8 @@ def _compile_salu(op, O, mods, nxt):
     if op in ("s_mov_b32", "s_mov_b64"):
         a = rs64(O[1]) if is64 else rs(O[1])
         return lambda w: (d(w, a(w)), nxt)[1]
-    if op in ("s_not_b32", "s_brev_b32", "s_abs_i32", "s_ff1_i32_b64", "s_bcnt1_i32_b64"):
+    if op in ("s_not_b32", "s_brev_b32", "s_abs_i32", "s_ff1_i32_b64", "s_bcnt1_i32_b64", "s_flbit_i32_b64",
+              "s_flbit_i32_b32", "s_ff1_i32_b32", "s_bcnt1_i32_b32"):
         a = rs64(O[1]) if op.endswith("b64") else rs(O[1])
         if op == "s_not_b32":
             return lambda w: (d(w, _scc_nz(w, ~a(w) & M32)), nxt)[1]
@@ -643,13 +644,23 @@ def _compile_salu(op, O, mods, nxt):
                 d(w, _scc_nz(w, abs(x) & M32))
                 return nxt
             return f
-        if op == "s_ff1_i32_b64":
+        if op in ("s_ff1_i32_b64", "s_ff1_i32_b32"):
             def f(w):
                 x = a(w)
                 d(w, ((x & -x).bit_length() - 1) & M32 if x else M32)
                 return nxt
             return f
+        if op in ("s_flbit_i32_b64", "s_flbit_i32_b32"):   # leading zeros, -1 for zero
+            width = 64 if op.endswith("64") else 32
+
+            def f(w):
+                x = a(w)
+                d(w, (width - x.bit_length()) if x else M32)
+                return nxt
+            return f
         return lambda w: (d(w, _scc_nz(w, bin(a(w)).count("1"))), nxt)[1]
+    if len(O) < 3:
+        raise Unsupported(op)
     a, b = O[1], O[2]
     if op in ("s_lshl_b64", "s_lshr_b64"):
         ra, rb = rs64(a), rs(b)

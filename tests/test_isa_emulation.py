@@ -124,6 +124,6 @@ def test_interpreter_covers_every_instruction(isa):
     for k, pc in enumerate(pcs):
         try:
             compile_instr(pc, isa.prog.text[pc], pcs[k + 1] if k + 1 < len(pcs) else None)
-        except Unsupported as e:
-            missing.setdefault(isa.prog.text[pc].split()[0], str(e))
+        except (Unsupported, IndexError, ValueError, KeyError) as e:
+            missing.setdefault(isa.prog.text[pc].split()[0], "%s: %s" % (type(e).__name__, e))
     assert not missing, missing
