@@ -88,9 +88,10 @@ constexpr int kL3Keep = 3, kL3KeepSq = 9, kL3Root = 21, kL3Link = 29, kL3Present
 constexpr int kL3Configs = 15935;
 constexpr int kL2Configs = 47;
 
-// 3D two-level index.  Level 1 is indexed by (6 face bits | 12 present-square bits << 6)
-// and holds (base << 8 | possible-cube mask); level 2 at base + (present cubes compressed
-// through the possible mask) holds the entry.
+// 3D two-level index.  Level 1 is indexed by (6 face bits | 12 square bits << 6) of the raw
+// neighbour mask and holds (base << 8 | possible-cube mask) of the canonical configuration
+// (squares kept only where both faces are present); level 2 at base + (the raw cube bits
+// compressed through the possible mask) holds the entry.
 constexpr int kL1Size = 1 << 18;
 
 // square index s = code-7: the two face (edge) indices it spans

@@ -203,6 +203,13 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+template <typename T>
+__device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + off); }
+
+__device__ __forceinline__ void set_err(int32_t *cnt, int code) {
+    atomicCAS(&cnt[CNT_ERR], 0, code);
+}
+
 // OR of a flag over the block with one LDS-only barrier.  Successive calls alternate between
 // the two halves of s_any (parity), so a call never overwrites flags still being read.
 __device__ __forceinline__ bool block_any(int flag, int *s_any, int parity) {
@@ -214,12 +221,13 @@ __device__ __forceinline__ bool block_any(int flag, int *s_any, int parity) {
     return r != 0;
 }
 
-template <typename T>
-__device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + off); }
-
-__device__ __forceinline__ void set_err(int32_t *cnt, int code) {
-    atomicCAS(&cnt[CNT_ERR], 0, code);
-}
+// Links inside a classify tile.  A slot holds a final value (a node, a link out of the tile,
+// the cell at infinity) or kLocal | s, a link to slot s of the same tile.  Pointer jumping
+// replaces every local link by its target's value until none is left; chains at least halve
+// every round.  A thread owns the slots threadIdx.x + 256 k and keeps in a bit mask those that
+// still hold a local link, so a finished slot costs nothing in later rounds.  Updates within a
+// round may already see other slots' new values: a value only ever moves along its own chain.
+__device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal && v != kNotOwned; }
 
 // Block-wide reservation of slots in up to four per-instance lists at once.  Each thread
 // passes its counts packed 16 bits per list (every block total stays below 2^16: a tile has
@@ -275,6 +283,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
     __shared__ int s_any[32];
+
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -364,6 +373,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     int rb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
+    uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const uint32_t e = ev[it];
@@ -387,18 +397,22 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             const int dy = direct == 0 ? -1 : (direct == 3 ? 1 : 0);
             const int dx = direct == 1 ? -1 : (direct == 2 ? 1 : 0);
             const int rr = r + dy, cc = c + dx;
-            if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) sp0[l] = kLocal | (rr * TW + cc);
-            else sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
+            if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) {
+                sp0[l] = kLocal | (rr * TW + cc);
+                act0 |= 1u << it;
+            } else {
+                sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
+            }
         }
         // KEEP edges -> compact list
-        for (int b = 0; b < 4; ++b)
-            if ((keep >> b) & 1u) {
-                if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
-                ++kb;
-            }
+        for (uint32_t m = keep; m; m &= m - 1) {
+            const int b = __builtin_ctz(m);
+            if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
+            ++kb;
+        }
         // squares of L(v): ROOT -> dual node, LOCAL -> dual link
-        for (int q = 0; q < 4; ++q) {
-            if (!((present >> q) & 1u)) continue;
+        for (uint32_t m = present; m; m &= m - 1) {
+            const int q = __builtin_ctz(m);
             const int sy = gy - 1 + (q >> 1), sx = gx - 1 + (q & 1);
             const int pos = (sy - y0 + 1) * PW + (sx - x0 + 1);
             if ((root >> q) & 1u) {
@@ -418,31 +432,30 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     }
     lds_barrier();
 
-    // resolve links inside the tile by pointer jumping
+    // resolve links inside the tile by pointer jumping (see is_local)
+    uint32_t actT = 0;
+    for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
+        if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
     for (int round = 0; round < 32; ++round) {
-        int changed = 0;
-        for (int l = threadIdx.x; l < TH * TW; l += 256) {
-            int32_t v = sp0[l];
-            if (v >= kLocal && v != kNotOwned) {
-                const int t = v - kLocal;                 // links only ever name slots of this tile
-                sp0[l] = t < TH * TW ? sp0[t] : 0;
-                changed = 1;
-            }
+        for (uint32_t m = act0; m; m &= m - 1) {
+            const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
+            const int t = sp0[l] - kLocal;               // links only ever name slots of this tile
+            const int32_t w = t < TH * TW ? sp0[t] : 0;
+            sp0[l] = w;
+            if (!is_local(w)) act0 &= ~(1u << k);
         }
-        for (int p = threadIdx.x; p < NP; p += 256) {
-            int32_t v = spT[p];
-            if (v >= kLocal && v != kNotOwned) {
-                const int tp = v - kLocal < NP ? v - kLocal : 0;
-                int32_t w = spT[tp];
-                if (w == kNotOwned) {
-                    const int pr = tp / PW, pc = tp - pr * PW;
-                    w = (int32_t)((y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc));
-                }
-                spT[p] = w;
-                changed = 1;
+        for (uint32_t m = actT; m; m &= m - 1) {
+            const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
+            const int tp = spT[p] - kLocal < NP ? spT[p] - kLocal : 0;
+            int32_t w = spT[tp];
+            if (w == kNotOwned) {                        // a square of another tile
+                const int pr = tp / PW, pc = tp - pr * PW;
+                w = (int32_t)((y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc));
             }
+            spT[p] = w;
+            if (!is_local(w)) actT &= ~(1u << k);
         }
-        if (!block_any(changed, s_any, round & 1)) break;
+        if (!block_any((act0 | actT) != 0, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < TH * TW; l += 256) {
@@ -476,6 +489,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
     __shared__ int s_any[32];
+
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -554,10 +568,9 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
                 const uint32_t kn = skey[((lz + 1 + dz) * KH + ly + 1 + dy) * KW + lx + 1 + dx];
                 if (kn < kv || (kn == kv && before)) raw |= 1u << (code - 1);
             }
-            uint32_t cubes;
-            const uint32_t idx1 = canon3d(raw, &cubes);
-            const uint32_t l1 = lut.l1[idx1];
-            const uint32_t idx2 = (l1 >> 8) + compress8(cubes, l1 & 255u);
+            // level 1 holds the canonical configuration for every raw square set
+            const uint32_t l1 = lut.l1[raw & (uint32_t)(kL1Size - 1)];
+            const uint32_t idx2 = (l1 >> 8) + compress8(raw >> 18, l1 & 255u);
             e = kNoDirect;
             if (idx2 < (uint32_t)kL3Configs) e = lut.l2[idx2];
             else set_err(cnt, PH_EINTERNAL);
@@ -576,6 +589,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     int rb = s_base[3] + (int)((pre >> 48) & 0xFFFFu);
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
+    uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const uint64_t e = ev[it];
@@ -600,23 +614,25 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             const int code = 1 + (int)direct;
             const int dz = off_of(code, 0), dy = off_of(code, 1), dx = off_of(code, 2);
             const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
-            if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW)
+            if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW) {
                 sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
-            else
+                act0 |= 1u << it;
+            } else {
                 sp0[l] = (int32_t)((gz + dz) * HW + (int64_t)(gy + dy) * W + gx + dx);
+            }
         }
-        for (int b = 0; b < 6; ++b)
-            if ((keep >> b) & 1u) {
-                if (kb < I.E) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
-                ++kb;
-            }
-        for (int q = 0; q < 12; ++q)
-            if ((keepsq >> q) & 1u) {
-                if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
-                ++fb;
-            }
-        for (int b = 0; b < 8; ++b) {
-            if (!((present >> b) & 1u)) continue;
+        for (uint32_t m = keep; m; m &= m - 1) {
+            const int b = __builtin_ctz(m);
+            if (kb < I.E) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
+            ++kb;
+        }
+        for (uint32_t m = keepsq; m; m &= m - 1) {
+            const int q = __builtin_ctz(m);
+            if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
+            ++fb;
+        }
+        for (uint32_t m = present; m; m &= m - 1) {
+            const int b = __builtin_ctz(m);
             const int sz = gz - 1 + (b >> 2), sy = gy - 1 + ((b >> 1) & 1), sx = gx - 1 + (b & 1);
             const int pos = ((sz - z0 + 1) * PH + (sy - y0 + 1)) * PW + (sx - x0 + 1);
             if ((root >> b) & 1u) {
@@ -637,30 +653,29 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     }
     lds_barrier();
 
+    uint32_t actT = 0;
+    for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
+        if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
     for (int round = 0; round < 32; ++round) {
-        int changed = 0;
-        for (int l = threadIdx.x; l < NV; l += 256) {
-            int32_t v = sp0[l];
-            if (v >= kLocal && v != kNotOwned) {
-                const int t = v - kLocal;
-                sp0[l] = t < NV ? sp0[t] : 0;
-                changed = 1;
-            }
+        for (uint32_t m = act0; m; m &= m - 1) {
+            const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
+            const int t = sp0[l] - kLocal;
+            const int32_t w = t < NV ? sp0[t] : 0;
+            sp0[l] = w;
+            if (!is_local(w)) act0 &= ~(1u << k);
         }
-        for (int p = threadIdx.x; p < NP; p += 256) {
-            int32_t v = spT[p];
-            if (v >= kLocal && v != kNotOwned) {
-                const int tp = v - kLocal < NP ? v - kLocal : 0;
-                int32_t w = spT[tp];
-                if (w == kNotOwned) {
-                    const int pz = tp / (PH * PW), pr = tp - pz * PH * PW, py = pr / PW, px = pr - py * PW;
-                    w = (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px));
-                }
-                spT[p] = w;
-                changed = 1;
+        for (uint32_t m = actT; m; m &= m - 1) {
+            const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
+            const int tp = spT[p] - kLocal < NP ? spT[p] - kLocal : 0;
+            int32_t w = spT[tp];
+            if (w == kNotOwned) {
+                const int pz = tp / (PH * PW), pr = tp - pz * PH * PW, py = pr / PW, px = pr - py * PW;
+                w = (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px));
             }
+            spT[p] = w;
+            if (!is_local(w)) actT &= ~(1u << k);
         }
-        if (!block_any(changed, s_any, round & 1)) break;
+        if (!block_any((act0 | actT) != 0, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < NV; l += 256) {

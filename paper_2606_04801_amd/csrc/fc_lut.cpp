@@ -224,6 +224,17 @@ int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen) {
             next += n2;
         }
     }
+    // every other square set maps to the entry of its canonical set (the squares whose two
+    // faces are present), so the kernels index level 1 with the raw face and square bits
+    for (uint32_t face = 0; face < 64; ++face) {
+        uint32_t relsq = 0;
+        for (int s = 0; s < 12; ++s) {
+            uint32_t need = (1u << kSqFace[s][0]) | (1u << kSqFace[s][1]);
+            if ((face & need) == need) relsq |= 1u << s;
+        }
+        for (uint32_t sq = 0; sq < 4096; ++sq)
+            if (sq & ~relsq) l1[face | (sq << 6)] = l1[face | ((sq & relsq) << 6)];
+    }
     return (int)next;
 }
 

@@ -426,7 +426,23 @@ VALU1 = {   # D = f(S0)
     "v_rcp_iflag_f32": _rcp,
     "v_rcp_f32": _rcp,
     "v_trunc_f32": lambda a: bits(np.trunc(f32(a))),
+    "v_ffbl_b32": lambda a: _ffbl(vec(a)),          # lowest set bit, -1 for zero
+    "v_ffbh_u32": lambda a: _ffbh(vec(a)),          # leading zeros, -1 for zero
 }
+
+
+def _ffbl(x):
+    r = np.full(LANES, M32, dtype=U32)
+    for k in range(31, -1, -1):
+        r = np.where((x >> U32(k)) & U32(1), U32(k), r)
+    return r
+
+
+def _ffbh(x):
+    r = np.full(LANES, M32, dtype=U32)
+    for k in range(32):
+        r = np.where((x >> U32(k)) & U32(1), U32(31 - k), r)
+    return r
 VALU3 = {   # D = f(S0, S1, S2)
     "v_add3_u32": lambda a, b, c: vec(a) + b + c,
     "v_add_lshl_u32": lambda a, b, c: (vec(a) + b) << (vec(c) & U32(31)),
