@@ -15,9 +15,9 @@ before any timing.
 
 roofline: the dominant kernel of the batched step (largest event-timed total over the timed
 profiled steps), its algorithmic bytes per launch divided by its mean launch duration, against
-8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, when a summary
-for this exact library build is given with --traffic-json, else null (see --profile-steps and
---traffic-from).
+8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, read from
+profiles/hbm_traffic.json (or --traffic-json) only when it was taken on the library build that
+is loaded (its sha256 is recorded), else null (see --profile-steps and --traffic-from).
 
 cpu_baseline: the CPU oracle (single-threaded C, one process per host core, at most 16) on a
 bounded sample of the same workload (one instance per core, half volumes and half images,
@@ -187,12 +187,20 @@ def _counter_means(path, counter):
     return {k: v[0] / v[1] for k, v in acc.items()}
 
 
+def library_sha256():
+    import hashlib
+    import paper_2606_04801_amd as fc
+    with open(fc.LIB_PATH, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
 def traffic_from(fetch_csv, write_csv, out_json):
     fetch, write = _counter_means(fetch_csv, "FETCH_SIZE"), _counter_means(write_csv, "WRITE_SIZE")
     if "copy" not in fetch or "copy" not in write:
         raise SystemExit("bench: no copy kernel in the counter files")
     fs, ws = COPY_BYTES / (fetch["copy"] * 1024), COPY_BYTES / (write["copy"] * 1024)
-    res = {"_scale": {"fetch": fs, "write": ws}}
+    # the counters belong to this library build: bench.py uses them only while it is loaded
+    res = {"_library_sha256": library_sha256(), "_scale": {"fetch": fs, "write": ws}}
     for k in fetch:
         if k == "copy" or k not in write:
             continue
@@ -209,7 +217,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
-    ap.add_argument("--traffic-json", default=None)
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"),
+                    help="HBM bytes per launch from the counter passes (used only for the library build they were taken on)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run K eager steps and a calibration copy")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
     ap.add_argument("--host-library", default=None,
@@ -396,7 +405,9 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
     achieved = algo / mean_s / 1e9 if mean_s > 0 else 0.0
     traffic = None
     if args.traffic_json and os.path.exists(args.traffic_json):
-        traffic = json.load(open(args.traffic_json)).get(name)
+        tj = json.load(open(args.traffic_json))
+        if tj.get("_library_sha256") == library_sha256():
+            traffic = tj.get(name)
     nvox = sum(int(np.prod(s)) for s in shapes)
     sb = step_bytes(prof.keys(), wc, npairs, shapes)
     fb = sb - algorithmic_bytes("k_zero", wc, npairs, shapes) - algorithmic_bytes("k_scatter", wc, npairs, shapes)
