@@ -374,7 +374,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
     uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
-#pragma unroll
+#pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint32_t e = ev[it];
         if (!(e & kValid)) continue;
@@ -589,8 +589,9 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     int rb = s_base[3] + (int)((pre >> 48) & 0xFFFFu);
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
+    const int64_t capN = I.N, capE = I.E, capF = I.F, capT = I.T;
     uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
-#pragma unroll
+#pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint64_t e = ev[it];
         if (!(e & kValid)) continue;
@@ -598,56 +599,69 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
         const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
-        const uint32_t pv = (uint32_t)(gz * HW + (int64_t)gy * W + gx);
+        const uint32_t pv = (uint32_t)gz * (uint32_t)HW + (uint32_t)(gy * W + gx);   // < 2^27
         const uint32_t direct = (uint32_t)(e & 7u);
         const uint32_t keep = (uint32_t)((e >> kL3Keep) & 63u);
         const uint32_t keepsq = (uint32_t)((e >> kL3KeepSq) & 4095u);
         const uint32_t root = (uint32_t)((e >> kL3Root) & 255u);
         const uint32_t present = (uint32_t)((e >> kL3Present) & 255u);
+        const uint32_t links = (uint32_t)(e >> kL3Link) & 0xFFFFFFu;
 
         if (direct == kNoDirect) {
-            int id = id0++;
-            if (id >= I.N) { set_err(cnt, PH_EINTERNAL); id = 0; }
-            sp0[l] = -(id + 1);
+            int64_t id = id0++;
+            if (id >= capN) { set_err(cnt, PH_EINTERNAL); id = 0; }
+            sp0[l] = -(int32_t)(id + 1);
             n0key[id] = make_key(kv, pv, 0);
         } else {
-            const int code = 1 + (int)direct;
-            const int dz = off_of(code, 0), dy = off_of(code, 1), dx = off_of(code, 2);
-            const int z2 = lz + dz, y2 = ly + dy, x2 = lx + dx;
-            if (z2 >= 0 && z2 < TD && y2 >= 0 && y2 < TH && x2 >= 0 && x2 < TW) {
-                sp0[l] = kLocal | ((z2 * TH + y2) * TW + x2);
+            // edge code 1 + direct: -z, -y, -x, +x, +y, +z
+            const int axis = direct < 3 ? (int)direct : 5 - (int)direct;
+            const int sgn = direct < 3 ? -1 : 1;
+            const int lc = axis == 0 ? lz : (axis == 1 ? ly : lx);
+            const int lim = axis == 0 ? TD : (axis == 1 ? TH : TW);
+            const int sdel = axis == 0 ? TH * TW : (axis == 1 ? TW : 1);
+            const int gdel = axis == 0 ? (int)HW : (axis == 1 ? W : 1);
+            if ((unsigned)(lc + sgn) < (unsigned)lim) {
+                sp0[l] = kLocal | (l + sgn * sdel);
                 act0 |= 1u << it;
             } else {
-                sp0[l] = (int32_t)((gz + dz) * HW + (int64_t)(gy + dy) * W + gx + dx);
+                sp0[l] = (int32_t)pv + sgn * gdel;
             }
         }
         for (uint32_t m = keep; m; m &= m - 1) {
             const int b = __builtin_ctz(m);
-            if (kb < I.E) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
+            if (kb < capE) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
             ++kb;
         }
         for (uint32_t m = keepsq; m; m &= m - 1) {
             const int q = __builtin_ctz(m);
-            if (fb < I.F) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
+            if (fb < capF) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
             ++fb;
         }
-        for (uint32_t m = present; m; m &= m - 1) {
-            const int b = __builtin_ctz(m);
-            const int sz = gz - 1 + (b >> 2), sy = gy - 1 + ((b >> 1) & 1), sx = gx - 1 + (b & 1);
-            const int pos = ((sz - z0 + 1) * PH + (sy - y0 + 1)) * PW + (sx - x0 + 1);
-            if ((root >> b) & 1u) {
-                if (rb > I.T) { set_err(cnt, PH_EINTERNAL); rb = 0; }
-                spT[pos] = -(rb + 1);
-                nTkey[rb] = make_key(kv, pv, 19 + b);
-                ++rb;
-            } else {
-                const uint32_t t = (uint32_t)((e >> (kL3Link + 3 * b)) & 7u);
-                const int tz2 = gz - 1 + (int)(t >> 2), ty2 = gy - 1 + (int)((t >> 1) & 1),
-                          tx2 = gx - 1 + (int)(t & 1);
-                if (tz2 >= 0 && tz2 < D - 1 && ty2 >= 0 && ty2 < H - 1 && tx2 >= 0 && tx2 < W - 1)
-                    spT[pos] = kLocal | (((tz2 - z0 + 1) * PH + (ty2 - y0 + 1)) * PW + (tx2 - x0 + 1));
-                else
-                    spT[pos] = -1;
+        if (present) {
+            // the eight cubes around v: octant t = (z y x bits) has its first corner at
+            // v - (1,1,1) + t, its slot at pos0 + the octant's slot offset, and lies inside the
+            // image when every corner coordinate does
+            const int pos0 = (lz * PH + ly) * PW + lx;
+            const uint32_t okx = (gx >= 1 ? 1u : 0u) | (gx <= W - 2 ? 2u : 0u);
+            const uint32_t oky = (gy >= 1 ? 1u : 0u) | (gy <= H - 2 ? 2u : 0u);
+            const uint32_t okz = (gz >= 1 ? 1u : 0u) | (gz <= D - 2 ? 2u : 0u);
+            const uint32_t inimg = ((okx & 1u ? 0x55u : 0u) | (okx & 2u ? 0xAAu : 0u)) &
+                                   ((oky & 1u ? 0x33u : 0u) | (oky & 2u ? 0xCCu : 0u)) &
+                                   ((okz & 1u ? 0x0Fu : 0u) | (okz & 2u ? 0xF0u : 0u));
+            for (uint32_t m = present; m; m &= m - 1) {
+                const int b = __builtin_ctz(m);
+                const int pos = pos0 + (b >> 2) * (PH * PW) + ((b >> 1) & 1) * PW + (b & 1);
+                if ((root >> b) & 1u) {
+                    if (rb > capT) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                    spT[pos] = -(rb + 1);
+                    nTkey[rb] = make_key(kv, pv, 19 + b);
+                    ++rb;
+                } else {
+                    const uint32_t t = (links >> (3 * b)) & 7u;
+                    spT[pos] = (inimg >> t) & 1u
+                                   ? kLocal | (pos0 + (int)(t >> 2) * (PH * PW) + (int)((t >> 1) & 1u) * PW + (int)(t & 1u))
+                                   : -1;                // the cell at infinity
+                }
             }
         }
     }
