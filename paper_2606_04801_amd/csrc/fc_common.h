@@ -137,8 +137,13 @@ struct Inst {
     int64_t end;
 };
 
-// counters per instance (int32 each)
-enum { CNT_E = 0, CNT_F, CNT_M0, CNT_MT, CNT_ERR, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ, CNT_WORDS = 16 };
+// counters per instance (int32 each).  The four list counters that every classify tile
+// advances with an atomic each sit on cache lines of their own (128 B apart), so the atomics
+// of one tile, and of the tiles of one instance, do not queue behind each other on one line.
+enum {
+    CNT_E = 0, CNT_F = 32, CNT_M0 = 64, CNT_MT = 96,
+    CNT_ERR = 128, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ, CNT_WORDS = 160
+};
 
 FC_HD int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 

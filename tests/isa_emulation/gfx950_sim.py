@@ -414,6 +414,8 @@ VALU2 = {   # D = f(S0, S1)
     "v_mbcnt_hi_u32_b32": _mbcnt(False),
     "v_mul_f32": lambda a, b: bits(f32(a) * f32(b)),
     "v_add_u16": lambda a, b: ((vec(a) + vec(b)) & U32(0xFFFF)),
+    "v_mul_lo_u16": lambda a, b: (((vec(a) & U32(0xFFFF)) * (vec(b) & U32(0xFFFF))) & U32(0xFFFF)),
+    "v_sub_u16": lambda a, b: ((vec(a) - vec(b)) & U32(0xFFFF)),
     "v_lshrrev_b16": lambda a, b: ((vec(b) & U32(0xFFFF)) >> (vec(a) & U32(15))),
     "v_ashrrev_i16": lambda a, b: ((_sx(b, 16) >> (vec(a) & U32(15)).astype(np.int64)) & 0xFFFF).astype(U32),
 }
@@ -422,6 +424,7 @@ VALU1 = {   # D = f(S0)
     "v_not_b32": lambda a: ~vec(a),
     "v_bfrev_b32": lambda a: _brev32(vec(a)),
     "v_cvt_f32_u32": lambda a: bits(vec(a).astype(np.float64).astype(F32)),
+    "v_cvt_f32_i32": lambda a: bits(s32(a).astype(np.float64).astype(F32)),
     "v_cvt_u32_f32": _cvt_u32_f32,
     "v_rcp_iflag_f32": _rcp,
     "v_rcp_f32": _rcp,
