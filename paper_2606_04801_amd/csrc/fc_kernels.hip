@@ -210,24 +210,21 @@ __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
     atomicCAS(&cnt[CNT_ERR], 0, code);
 }
 
-// OR of a flag over the block with one LDS-only barrier.  Successive calls alternate between
-// the two halves of s_any (parity), so a call never overwrites flags still being read.
-__device__ __forceinline__ bool block_any(int flag, int *s_any, int parity) {
-    const bool w = __ballot(flag) != 0;
-    if (__lane_id() == 0) s_any[parity * 16 + (threadIdx.x >> 6)] = w ? 1 : 0;
-    lds_barrier();
-    int r = 0;
-    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) r |= s_any[parity * 16 + k];
-    return r != 0;
-}
-
 // Links inside a classify tile.  A slot holds a final value (a node, a link out of the tile,
 // the cell at infinity) or kLocal | s, a link to slot s of the same tile.  Pointer jumping
-// replaces every local link by its target's value until none is left; chains at least halve
-// every round.  A thread owns the slots threadIdx.x + 256 k and keeps in a bit mask those that
-// still hold a local link, so a finished slot costs nothing in later rounds.  Updates within a
-// round may already see other slots' new values: a value only ever moves along its own chain.
+// replaces every local link by its target's value until none is left.  A thread owns the slots
+// threadIdx.x + 256 k, keeps in a bit mask those that still hold a local link, and jumps them
+// until they are final, with no barrier: the other threads jump their slots at the same time,
+// so a chain shortens from many places at once, and a read that finds an older value still
+// advances one step, since a value only ever moves along its own chain.  The write-out reads
+// only the thread's own slots.  Slots are read and written whole, as relaxed atomics.
 __device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal && v != kNotOwned; }
+__device__ __forceinline__ int32_t slot_get(const int32_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void slot_put(int32_t *p, int32_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
 
 // Block-wide reservation of slots in up to four per-instance lists at once.  Each thread
 // passes its counts packed 16 bits per list (every block total stays below 2^16: a tile has
@@ -282,7 +279,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
-    __shared__ int s_any[32];
+
 
 
     const Inst *tab = (const Inst *)ws;
@@ -436,26 +433,25 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     uint32_t actT = 0;
     for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
         if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
-    for (int round = 0; round < 32; ++round) {
+    for (int round = 0; (act0 | actT) != 0 && round < TH * TW + NP; ++round) {
         for (uint32_t m = act0; m; m &= m - 1) {
             const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
-            const int t = sp0[l] - kLocal;               // links only ever name slots of this tile
-            const int32_t w = t < TH * TW ? sp0[t] : 0;
-            sp0[l] = w;
+            const int t = slot_get(&sp0[l]) - kLocal;    // links only ever name slots of this tile
+            const int32_t w = t < TH * TW ? slot_get(&sp0[t]) : 0;
+            slot_put(&sp0[l], w);
             if (!is_local(w)) act0 &= ~(1u << k);
         }
         for (uint32_t m = actT; m; m &= m - 1) {
             const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
-            const int tp = spT[p] - kLocal < NP ? spT[p] - kLocal : 0;
-            int32_t w = spT[tp];
+            const int tp = slot_get(&spT[p]) - kLocal < NP ? slot_get(&spT[p]) - kLocal : 0;
+            int32_t w = slot_get(&spT[tp]);
             if (w == kNotOwned) {                        // a square of another tile
                 const int pr = tp / PW, pc = tp - pr * PW;
                 w = (int32_t)((y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc));
             }
-            spT[p] = w;
+            slot_put(&spT[p], w);
             if (!is_local(w)) actT &= ~(1u << k);
         }
-        if (!block_any((act0 | actT) != 0, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < TH * TW; l += 256) {
@@ -488,7 +484,7 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
-    __shared__ int s_any[32];
+
 
 
     const Inst *tab = (const Inst *)ws;
@@ -670,26 +666,25 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     uint32_t actT = 0;
     for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
         if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
-    for (int round = 0; round < 32; ++round) {
+    for (int round = 0; (act0 | actT) != 0 && round < NV + NP; ++round) {
         for (uint32_t m = act0; m; m &= m - 1) {
             const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
-            const int t = sp0[l] - kLocal;
-            const int32_t w = t < NV ? sp0[t] : 0;
-            sp0[l] = w;
+            const int t = slot_get(&sp0[l]) - kLocal;
+            const int32_t w = t < NV ? slot_get(&sp0[t]) : 0;
+            slot_put(&sp0[l], w);
             if (!is_local(w)) act0 &= ~(1u << k);
         }
         for (uint32_t m = actT; m; m &= m - 1) {
             const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
-            const int tp = spT[p] - kLocal < NP ? spT[p] - kLocal : 0;
-            int32_t w = spT[tp];
+            const int tp = slot_get(&spT[p]) - kLocal < NP ? slot_get(&spT[p]) - kLocal : 0;
+            int32_t w = slot_get(&spT[tp]);
             if (w == kNotOwned) {
                 const int pz = tp / (PH * PW), pr = tp - pz * PH * PW, py = pr / PW, px = pr - py * PW;
                 w = (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px));
             }
-            spT[p] = w;
+            slot_put(&spT[p], w);
             if (!is_local(w)) actT &= ~(1u << k);
         }
-        if (!block_any((act0 | actT) != 0, s_any, round & 1)) break;
     }
 
     for (int l = threadIdx.x; l < NV; l += 256) {
