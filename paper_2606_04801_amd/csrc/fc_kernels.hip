@@ -43,7 +43,6 @@ struct Luts {
 };
 
 constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
-constexpr int32_t kNotOwned = 0x7FFFFFFF;  // LDS slot not written by this tile
 constexpr int kMaxChase = 1 << 22;         // bound of every pointer walk
 constexpr int kUfThreads = 1024;
 constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS (2 x 20 KiB)
@@ -211,19 +210,65 @@ __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
 }
 
 // Links inside a classify tile.  A slot holds a final value (a node, a link out of the tile,
-// the cell at infinity) or kLocal | s, a link to slot s of the same tile.  Pointer jumping
-// replaces every local link by its target's value until none is left.  A thread owns the slots
-// threadIdx.x + 256 k, keeps in a bit mask those that still hold a local link, and jumps them
-// until they are final, with no barrier: the other threads jump their slots at the same time,
-// so a chain shortens from many places at once, and a read that finds an older value still
-// advances one step, since a value only ever moves along its own chain.  The write-out reads
-// only the thread's own slots.  Slots are read and written whole, as relaxed atomics.
-__device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal && v != kNotOwned; }
+// the cell at infinity) or kLocal | s, a link to slot s of the same tile.  A top-cell slot that
+// no vertex of the tile writes keeps its initial value, the cell's own global index: a link
+// that reaches it ends there, at a cell of another tile.  Pointer jumping (jump_links) replaces
+// every local link by its target's value until none is left.
+__device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal; }
 __device__ __forceinline__ int32_t slot_get(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void slot_put(int32_t *p, int32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// OR of a flag over the block with one LDS-only barrier.  Successive calls alternate between
+// the two halves of s_any[8] (parity): every wave rewrites its flag on each call, and a wave can
+// only rewrite a half after every wave has passed the barrier of the call in between, so no
+// flag is overwritten while still being read.
+__device__ __forceinline__ bool block_any(bool flag, int *s_any, int parity) {
+    static_assert(256 / 64 <= 4, "one flag per wave of the block");
+    const bool w = __ballot(flag) != 0;
+    if (__lane_id() == 0) s_any[parity * 4 + (threadIdx.x >> 6)] = w ? 1 : 0;
+    lds_barrier();
+    const int *a = s_any + parity * 4;
+    return (a[0] | a[1] | a[2] | a[3]) != 0;
+}
+
+// Pointer jumping over a tile's vertex slots sp0[256 N0] and top-cell slots spT[256 NT].  A
+// thread owns the slots threadIdx.x + 256 k of each array and holds their values in v0, vT;
+// it alone writes them.  Every round it replaces each local value by its target's value and
+// publishes it; a barrier ends the round, so chains at least halve every round.  Reads within
+// a round may already see other slots' new values, which only helps: a value only ever moves
+// along its own chain.  Slots are read and written whole, as relaxed atomics.  A chain visits
+// each slot at most once, which bounds the rounds.  All threads of the block must call it.
+template <int N0, int NT>
+__device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (&v0)[N0], int32_t (&vT)[NT],
+                                           int *s_any, int32_t *cnt) {
+    const int tid = threadIdx.x;
+    for (int round = 0; round <= 256 * (N0 + NT); ++round) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < N0; ++k) {
+            if (is_local(v0[k])) {
+                const uint32_t d = (uint32_t)(v0[k] - kLocal), t = d < 256u * N0 ? d : 256u * N0 - 1u;
+                v0[k] = slot_get(&sp0[t]);
+                slot_put(&sp0[tid + 256 * k], v0[k]);
+                any |= is_local(v0[k]);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            if (is_local(vT[k])) {
+                const uint32_t d = (uint32_t)(vT[k] - kLocal), t = d < 256u * NT ? d : 256u * NT - 1u;
+                vT[k] = slot_get(&spT[t]);
+                slot_put(&spT[tid + 256 * k], vT[k]);
+                any |= is_local(vT[k]);
+            }
+        }
+        if (!block_any(any, s_any, round & 1)) return;
+    }
+    set_err(cnt, PH_EINTERNAL);
 }
 
 // Block-wide reservation of slots in up to four per-instance lists at once.  Each thread
@@ -273,12 +318,14 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, PW = TW + 1, NP = (TH + 1) * (TW + 1);
+    constexpr int NIT = TH * TW / 256, NKT = (NP + 255) / 256;
     __shared__ uint32_t skey[(TH + 2) * KW];
     __shared__ int32_t sp0[TH * TW];
-    __shared__ int32_t spT[NP];
+    __shared__ int32_t spT[256 * NKT];           // padded to whole rounds of the block
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
+    __shared__ int s_any[8];
 
 
 
@@ -327,7 +374,10 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             skey[l] = key;
         }
     }
-    for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
+    for (int p = threadIdx.x; p < 256 * NKT; p += 256) {
+        const int pr = p / PW, pc = p - pr * PW;
+        spT[p] = p < NP ? (y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc) : 0;
+    }
     // every link slot starts final (0 is never followed); slots of vertices outside the
     // image keep it, so the pointer jumping below never reads an uninitialised slot
     for (int l = threadIdx.x; l < TH * TW; l += 256) sp0[l] = 0;
@@ -340,21 +390,25 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     constexpr bool NBEFORE[8] = {true, true, false, false, true, true, false, false};
 
     // pass 1: every vertex of the thread through the table; counts of the cells it keeps
-    constexpr int NIT = TH * TW / 256;
     constexpr uint32_t kValid = 1u << 31;           // above every field of a 2D entry
     uint32_t ev[NIT];
     uint64_t packed = 0;                            // minima | KEEP edges << 16 | ROOT squares << 32
+    // the 3x3 neighbourhood of vertex threadIdx.x + 256 it starts at skey[nb0 + it * kRows * KW]
+    static_assert(256 % TW == 0, "a block covers whole tile rows");
+    constexpr int kRows = 256 / TW;
+    const int nb0 = (threadIdx.x / TW) * KW + threadIdx.x % TW;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int l = threadIdx.x + it * 256;
         const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        const uint32_t *nb = skey + nb0 + it * kRows * KW;
         uint32_t e = 0;
         if (gy < H && gx < W) {
-            const uint32_t kv = skey[(r + 1) * KW + c + 1];
+            const uint32_t kv = nb[KW + 1];
             uint32_t mask = 0;
 #pragma unroll
             for (int b = 0; b < 8; ++b) {               // outside neighbours hold kOutside
-                uint32_t kn = skey[(r + 1 + NDY[b]) * KW + c + 1 + NDX[b]];
+                uint32_t kn = nb[(1 + NDY[b]) * KW + 1 + NDX[b]];
                 if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
             }
             e = lut.l2d[mask] | kValid;
@@ -370,7 +424,6 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     int rb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
-    uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
 #pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint32_t e = ev[it];
@@ -396,7 +449,6 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             const int rr = r + dy, cc = c + dx;
             if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) {
                 sp0[l] = kLocal | (rr * TW + cc);
-                act0 |= 1u << it;
             } else {
                 sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
             }
@@ -429,39 +481,25 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     }
     lds_barrier();
 
-    // resolve links inside the tile by pointer jumping (see is_local)
-    uint32_t actT = 0;
-    for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
-        if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
-    for (int round = 0; (act0 | actT) != 0 && round < TH * TW + NP; ++round) {
-        for (uint32_t m = act0; m; m &= m - 1) {
-            const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
-            const int t = slot_get(&sp0[l]) - kLocal;    // links only ever name slots of this tile
-            const int32_t w = t < TH * TW ? slot_get(&sp0[t]) : 0;
-            slot_put(&sp0[l], w);
-            if (!is_local(w)) act0 &= ~(1u << k);
-        }
-        for (uint32_t m = actT; m; m &= m - 1) {
-            const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
-            const int tp = slot_get(&spT[p]) - kLocal < NP ? slot_get(&spT[p]) - kLocal : 0;
-            int32_t w = slot_get(&spT[tp]);
-            if (w == kNotOwned) {                        // a square of another tile
-                const int pr = tp / PW, pc = tp - pr * PW;
-                w = (int32_t)((y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc));
-            }
-            slot_put(&spT[p], w);
-            if (!is_local(w)) actT &= ~(1u << k);
-        }
-    }
+    // resolve links inside the tile (see jump_links)
+    int32_t v0[NIT], vT[NKT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < NKT; ++k) vT[k] = spT[threadIdx.x + 256 * k];
+    jump_links(sp0, spT, v0, vT, s_any, cnt);
 
-    for (int l = threadIdx.x; l < TH * TW; l += 256) {
-        const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
-        if (gy < H && gx < W) par0[gy * W + gx] = sp0[l];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int l = threadIdx.x + 256 * k, r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        if (gy < H && gx < W) par0[gy * W + gx] = v0[k];
     }
-    for (int p = threadIdx.x; p < NP; p += 256) {
-        const int32_t v = spT[p];
-        if (v == kNotOwned) continue;
+#pragma unroll
+    for (int k = 0; k < NKT; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        const int32_t v = vT[k];
         const int pr = p / PW, pc = p - pr * PW, sy = y0 - 1 + pr, sx = x0 - 1 + pc;
+        if (p >= NP || v == sy * (W - 1) + sx) continue;     // not a square of this tile
         // a square is only ever marked for a vertex whose lower star holds it, so it lies in
         // the image; the check keeps a corrupted table from writing outside parT
         if (sy >= 0 && sy < H - 1 && sx >= 0 && sx < W - 1) parT[sy * (W - 1) + sx] = v;
@@ -477,13 +515,14 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
     constexpr int PW = TW + 1, PH = TH + 1, PD = TD + 1, NP = PW * PH * PD;
-    constexpr int NV = TW * TH * TD;
+    constexpr int NV = TW * TH * TD, NIT = NV / 256, NKT = (NP + 255) / 256;
     __shared__ uint32_t skey[KD * KH * KW];
     __shared__ int32_t sp0[NV];
-    __shared__ int32_t spT[NP];
+    __shared__ int32_t spT[256 * NKT];           // padded to whole rounds of the block
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
+    __shared__ int s_any[8];
 
 
 
@@ -538,31 +577,40 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             skey[l] = key;
         }
     }
-    for (int p = threadIdx.x; p < NP; p += 256) spT[p] = kNotOwned;
-    for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;      // see the 2D kernel
+    for (int p = threadIdx.x; p < 256 * NKT; p += 256) {         // see the 2D kernel
+        const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
+        spT[p] = p < NP ? (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px)) : 0;
+    }
+    for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;
     lds_barrier();
     if (nan) s_nan = 1;
 
     // pass 1: every vertex of the thread through the table; counts of the cells it keeps
-    constexpr int NIT = NV / 256;
     constexpr uint64_t kValid = 1ull << 63;         // above every field of a 3D entry
     uint64_t ev[NIT];
     uint64_t packed = 0;              // minima | KEEP edges << 16 | KEEP squares << 32 | ROOT cubes << 48
+    // the 3x3x3 neighbourhood of vertex threadIdx.x + 256 it starts at skey[nb0 + it * kLayers * KH * KW]
+    static_assert(256 % (TH * TW) == 0, "a block covers whole tile layers");
+    constexpr int kLayers = 256 / (TH * TW);
+    const int nb0 = ((threadIdx.x / (TH * TW)) * KH + (threadIdx.x / TW) % TH) * KW + threadIdx.x % TW;
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int l = threadIdx.x + it * 256;
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+        const uint32_t *nb = skey + nb0 + it * kLayers * KH * KW;
         uint64_t e = 0;
         if (gz < D && gy < H && gx < W) {
-            const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
+            const uint32_t kv = nb[(KH + 1) * KW + 1];
+            // bit code - 1 of raw: the neighbour at kOff[code] comes before v (ties by position);
+            // shifted in from the top code down
             uint32_t raw = 0;
 #pragma unroll
-            for (int code = 1; code < 27; ++code) {     // outside neighbours hold kOutside
+            for (int code = 26; code >= 1; --code) {    // outside neighbours hold kOutside
                 const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
                 const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                const uint32_t kn = skey[((lz + 1 + dz) * KH + ly + 1 + dy) * KW + lx + 1 + dx];
-                if (kn < kv || (kn == kv && before)) raw |= 1u << (code - 1);
+                const uint32_t kn = nb[((1 + dz) * KH + 1 + dy) * KW + 1 + dx];
+                raw = raw + raw + (uint32_t)(before ? kn <= kv : kn < kv);
             }
             // level 1 holds the canonical configuration for every raw square set
             const uint32_t l1 = lut.l1[raw & (uint32_t)(kL1Size - 1)];
@@ -586,7 +634,6 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
     const int64_t capN = I.N, capE = I.E, capF = I.F, capT = I.T;
-    uint32_t act0 = 0;                              // this thread's vertex slots holding a local link
 #pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint64_t e = ev[it];
@@ -618,7 +665,6 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             const int gdel = axis == 0 ? (int)HW : (axis == 1 ? W : 1);
             if ((unsigned)(lc + sgn) < (unsigned)lim) {
                 sp0[l] = kLocal | (l + sgn * sdel);
-                act0 |= 1u << it;
             } else {
                 sp0[l] = (int32_t)pv + sgn * gdel;
             }
@@ -663,40 +709,27 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     }
     lds_barrier();
 
-    uint32_t actT = 0;
-    for (int k = 0; threadIdx.x + 256 * k < NP; ++k)
-        if (is_local(spT[threadIdx.x + 256 * k])) actT |= 1u << k;
-    for (int round = 0; (act0 | actT) != 0 && round < NV + NP; ++round) {
-        for (uint32_t m = act0; m; m &= m - 1) {
-            const int k = __builtin_ctz(m), l = threadIdx.x + 256 * k;
-            const int t = slot_get(&sp0[l]) - kLocal;
-            const int32_t w = t < NV ? slot_get(&sp0[t]) : 0;
-            slot_put(&sp0[l], w);
-            if (!is_local(w)) act0 &= ~(1u << k);
-        }
-        for (uint32_t m = actT; m; m &= m - 1) {
-            const int k = __builtin_ctz(m), p = threadIdx.x + 256 * k;
-            const int tp = slot_get(&spT[p]) - kLocal < NP ? slot_get(&spT[p]) - kLocal : 0;
-            int32_t w = slot_get(&spT[tp]);
-            if (w == kNotOwned) {
-                const int pz = tp / (PH * PW), pr = tp - pz * PH * PW, py = pr / PW, px = pr - py * PW;
-                w = (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px));
-            }
-            slot_put(&spT[p], w);
-            if (!is_local(w)) actT &= ~(1u << k);
-        }
-    }
+    int32_t v0[NIT], vT[NKT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+#pragma unroll
+    for (int k = 0; k < NKT; ++k) vT[k] = spT[threadIdx.x + 256 * k];
+    jump_links(sp0, spT, v0, vT, s_any, cnt);
 
-    for (int l = threadIdx.x; l < NV; l += 256) {
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+        const int l = threadIdx.x + 256 * k;
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
-        if (gz < D && gy < H && gx < W) par0[gz * HW + (int64_t)gy * W + gx] = sp0[l];
+        if (gz < D && gy < H && gx < W) par0[gz * HW + (int64_t)gy * W + gx] = v0[k];
     }
-    for (int p = threadIdx.x; p < NP; p += 256) {
-        const int32_t v = spT[p];
-        if (v == kNotOwned) continue;
+#pragma unroll
+    for (int k = 0; k < NKT; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        const int32_t v = vT[k];
         const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
         const int cz = z0 - 1 + pz, cy = y0 - 1 + py, cx = x0 - 1 + px;
+        if (p >= NP || v == (int32_t)(cz * TH1W1 + (int64_t)cy * (W - 1) + cx)) continue;
         if (cz >= 0 && cz < D - 1 && cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1)
             parT[cz * TH1W1 + (int64_t)cy * (W - 1) + cx] = v;
         else set_err(cnt, PH_EINTERNAL);

@@ -408,6 +408,7 @@ VALU2 = {   # D = f(S0, S1)
     "v_mul_hi_u32": lambda a, b: ((vec(a).astype(U64) * vec(b).astype(U64)) >> U64(32)).astype(U32),
     "v_mul_hi_i32": lambda a, b: ((s32(a).astype(I64) * s32(b).astype(I64)) >> 32).astype(I64).astype(U32),
     "v_mul_u32_u24": lambda a, b: (((vec(a) & U32(0xFFFFFF)).astype(U64) * (vec(b) & U32(0xFFFFFF)).astype(U64)) & U64(M32)).astype(U32),
+    "v_mul_hi_u32_u24": lambda a, b: (((vec(a) & U32(0xFFFFFF)).astype(U64) * (vec(b) & U32(0xFFFFFF)).astype(U64)) >> U64(32)).astype(U32),
     "v_mul_i32_i24": lambda a, b: ((_sx(a, 24) * _sx(b, 24)) & M32).astype(U32),
     "v_bcnt_u32_b32": lambda a, b: _popc32(a) + vec(b),
     "v_mbcnt_lo_u32_b32": _mbcnt(True),
@@ -693,9 +694,11 @@ def _compile_salu(op, O, mods, nxt):
         ra, rb = rs(a), rs(b)
         M = M32
     base = op[2:op.rindex("_")]
-    if base in ("and", "or", "xor", "andn2", "orn2"):
+    if base in ("and", "or", "xor", "andn2", "orn2", "nand", "nor", "xnor"):
         fn = {"and": lambda x, y: x & y, "or": lambda x, y: x | y, "xor": lambda x, y: x ^ y,
-              "andn2": lambda x, y: x & ~y & M, "orn2": lambda x, y: (x | ~y) & M}[base]
+              "andn2": lambda x, y: x & ~y & M, "orn2": lambda x, y: (x | ~y) & M,
+              "nand": lambda x, y: ~(x & y) & M, "nor": lambda x, y: ~(x | y) & M,
+              "xnor": lambda x, y: ~(x ^ y) & M}[base]
         return lambda w: (d(w, _scc_nz(w, fn(ra(w), rb(w)))), nxt)[1]
     if op == "s_add_u32":
         def f(w):
