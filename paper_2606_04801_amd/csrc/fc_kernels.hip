@@ -43,6 +43,7 @@ struct Luts {
 };
 
 constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
+constexpr int32_t kUnset = 0x7FFFFFFF;     // LDS cube slot not yet written
 constexpr int kMaxChase = 1 << 22;         // bound of every pointer walk
 constexpr int kUfThreads = 1024;
 constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS (2 x 20 KiB)
@@ -215,6 +216,27 @@ __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
 // that reaches it ends there, at a cell of another tile.  Pointer jumping (jump_links) replaces
 // every local link by its target's value until none is left.
 __device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal; }
+
+// Offset of octant t = (z y x bits) of the eight cubes around a vertex from the slot of the
+// first (t = 0), in a slot box of rows PW and layers PW * PH.  When every offset fits a byte
+// the eight are picked with one byte permute.
+template <int PW, int PH>
+__device__ __forceinline__ int oct_slot(uint32_t t) {
+    constexpr uint32_t L = PH * PW;
+    if constexpr (L + PW + 1 < 256) {
+        constexpr uint32_t lo = 0u | 1u << 8 | (uint32_t)PW << 16 | (uint32_t)(PW + 1) << 24;
+        constexpr uint32_t hi = L | (L + 1) << 8 | (L + PW) << 16 | (L + PW + 1) << 24;
+        return (int)__builtin_amdgcn_perm(hi, lo, t | 0x0C0C0C00u);
+    } else {
+        return (int)((t >> 2) * L + ((t >> 1) & 1u) * PW + (t & 1u));
+    }
+}
+
+// v clamped into [0, hi]
+__device__ __forceinline__ int clamp0(int v, int hi) {
+    const int a = v > 0 ? v : 0;
+    return a < hi ? a : hi;
+}
 __device__ __forceinline__ int32_t slot_get(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -235,14 +257,15 @@ __device__ __forceinline__ bool block_any(bool flag, int *s_any, int parity) {
     return (a[0] | a[1] | a[2] | a[3]) != 0;
 }
 
-// Pointer jumping over a tile's vertex slots sp0[256 N0] and top-cell slots spT[256 NT].  A
-// thread owns the slots threadIdx.x + 256 k of each array and holds their values in v0, vT;
-// it alone writes them.  Every round it replaces each local value by its target's value and
+// Pointer jumping over a tile's vertex slots sp0[256 N0] and top-cell slots spT[ST NT].  A
+// thread owns the vertex slots threadIdx.x + 256 k and the top-cell slots threadIdx.x + ST k
+// and holds their values in v0, vT (a thread without top-cell slots holds finals there); it
+// alone writes them.  Every round it replaces each local value by its target's value and
 // publishes it; a barrier ends the round, so chains at least halve every round.  Reads within
 // a round may already see other slots' new values, which only helps: a value only ever moves
 // along its own chain.  Slots are read and written whole, as relaxed atomics.  A chain visits
 // each slot at most once, which bounds the rounds.  All threads of the block must call it.
-template <int N0, int NT>
+template <int N0, int NT, int ST>
 __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (&v0)[N0], int32_t (&vT)[NT],
                                            int *s_any, int32_t *cnt) {
     const int tid = threadIdx.x;
@@ -251,7 +274,7 @@ __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (
 #pragma unroll
         for (int k = 0; k < N0; ++k) {
             if (is_local(v0[k])) {
-                const uint32_t d = (uint32_t)(v0[k] - kLocal), t = d < 256u * N0 ? d : 256u * N0 - 1u;
+                const uint32_t d = (uint32_t)(v0[k] - kLocal), t = d < 256u * N0 - 1u ? d : 256u * N0 - 1u;
                 v0[k] = slot_get(&sp0[t]);
                 slot_put(&sp0[tid + 256 * k], v0[k]);
                 any |= is_local(v0[k]);
@@ -260,9 +283,9 @@ __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (
 #pragma unroll
         for (int k = 0; k < NT; ++k) {
             if (is_local(vT[k])) {
-                const uint32_t d = (uint32_t)(vT[k] - kLocal), t = d < 256u * NT ? d : 256u * NT - 1u;
+                const uint32_t d = (uint32_t)(vT[k] - kLocal), t = d < ST * NT - 1u ? d : ST * NT - 1u;
                 vT[k] = slot_get(&spT[t]);
-                slot_put(&spT[tid + 256 * k], vT[k]);
+                slot_put(&spT[tid + ST * k], vT[k]);
                 any |= is_local(vT[k]);
             }
         }
@@ -487,7 +510,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
 #pragma unroll
     for (int k = 0; k < NKT; ++k) vT[k] = spT[threadIdx.x + 256 * k];
-    jump_links(sp0, spT, v0, vT, s_any, cnt);
+    jump_links<NIT, NKT, 256>(sp0, spT, v0, vT, s_any, cnt);
 
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
@@ -515,14 +538,20 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
     constexpr int PW = TW + 1, PH = TH + 1, PD = TD + 1, NP = PW * PH * PD;
-    constexpr int NV = TW * TH * TD, NIT = NV / 256, NKT = (NP + 255) / 256;
+    constexpr int NV = TW * TH * TD, NIT = NV / 256;
+    // Cube slots: the slot box is PD * PH rows of PW.  A group of PW consecutive threads owns
+    // one row, GT rows at a time (slots threadIdx.x + k STT of the thread), so a thread keeps
+    // its column and steps its row, and the row's global cube index, by constants.
+    constexpr int GT = 256 / PW, STT = GT * PW, NRT = PD * PH, NKT = (NRT + GT - 1) / GT;
+    static_assert(NKT * STT >= NP, "cube slots cover the box");
     __shared__ uint32_t skey[KD * KH * KW];
     __shared__ int32_t sp0[NV];
-    __shared__ int32_t spT[256 * NKT];           // padded to whole rounds of the block
+    __shared__ int32_t spT[NKT * STT];
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
     __shared__ int s_any[8];
+    __shared__ uint8_t s_pext[256];              // [mask nibble << 4 | bits nibble]: compress8 of the two
 
 
 
@@ -550,38 +579,45 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
     {
-        // every halo load of the thread is issued before the first is used (see the 2D kernel)
-        constexpr int NS = KD * KH * KW, NL = (NS + 255) / 256;
+        // The halo box is KD * KH rows of KW keys.  A group of KW consecutive threads loads
+        // one row, kGroups rows at a time, so a thread keeps its column and steps its row by a
+        // constant.  Every load of the thread is issued before the first is used: addresses
+        // are clamped into the volume (offsets fit 32 bits: an instance has < 2^27 voxels)
+        // and outside voxels replaced afterwards.
+        constexpr int kGroups = 256 / KW, NR = KD * KH, NL = (NR + kGroups - 1) / kGroups;
+        const int g = threadIdx.x / KW, c = threadIdx.x - g * KW;
+        const int gx = x0 - 1 + c, cx = clamp0(gx, W - 1);
+        const bool inx = (unsigned)gx < (unsigned)W && g < kGroups;
         float f[NL];
+        uint32_t inside = 0;                                // bit k: row g + k kGroups, in the volume
+        int zz = g / KH, yy = g - zz * KH;
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int l = threadIdx.x + 256 * k;
-            const int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
-            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-            const int cz = gz < 0 ? 0 : (gz >= D ? D - 1 : gz), cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy),
-                      cx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
-            f[k] = img[cz * HW + (int64_t)cy * W + cx];
+            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
+            const int cz = clamp0(gz, D - 1), cy = clamp0(gy, H - 1);
+            f[k] = img[(uint32_t)(cz * (int)HW + cy * W + cx)];
+            if (inx && (unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H) inside |= 1u << k;
+            yy += kGroups % KH;
+            zz += kGroups / KH;
+            if (yy >= KH) { yy -= KH; ++zz; }
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
-            const int l = threadIdx.x + 256 * k;
-            if (l >= NS) break;
-            const int zz = l / (KH * KW), r2 = l - zz * KH * KW, yy = r2 / KW, xx = r2 - yy * KW;
-            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy, gx = x0 - 1 + xx;
-            uint32_t key = kOutside;
-            if (gz >= 0 && gz < D && gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                nan |= (f[k] != f[k]);
-                const uint32_t o = ord32(__float_as_uint(f[k]));
-                key = o < kOutside ? o : kOutside - 1u;
-            }
-            skey[l] = key;
+            if (g >= kGroups || g + k * kGroups >= NR) break;   // threads past the last group load only
+            const uint32_t o = ord32(__float_as_uint(f[k]));
+            const bool in = (inside >> k) & 1u;
+            nan |= in && f[k] != f[k];
+            skey[threadIdx.x + k * kGroups * KW] = in ? (o < kOutside ? o : kOutside - 1u) : kOutside;
         }
     }
-    for (int p = threadIdx.x; p < 256 * NKT; p += 256) {         // see the 2D kernel
-        const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
-        spT[p] = p < NP ? (int32_t)((z0 - 1 + pz) * TH1W1 + (int64_t)(y0 - 1 + py) * (W - 1) + (x0 - 1 + px)) : 0;
-    }
+    // cube slots start unset (padding rows final); after pass 2 the slots no vertex of the
+    // tile wrote get their cube's global index (see is_local)
+    const int gT = threadIdx.x / PW;
+#pragma unroll
+    for (int k = 0; k < NKT; ++k)
+        if (gT < GT) spT[threadIdx.x + k * STT] = gT + k * GT < NRT ? kUnset : 0;
     for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;
+    s_pext[threadIdx.x] = (uint8_t)compress8(threadIdx.x & 15u, threadIdx.x >> 4);
     lds_barrier();
     if (nan) s_nan = 1;
 
@@ -612,9 +648,13 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
                 const uint32_t kn = nb[((1 + dz) * KH + 1 + dy) * KW + 1 + dx];
                 raw = raw + raw + (uint32_t)(before ? kn <= kv : kn < kv);
             }
-            // level 1 holds the canonical configuration for every raw square set
+            // level 1 holds the canonical configuration for every raw square set; the cube
+            // bits are compressed through its possible-cube mask one nibble at a time
             const uint32_t l1 = lut.l1[raw & (uint32_t)(kL1Size - 1)];
-            const uint32_t idx2 = (l1 >> 8) + compress8(raw >> 18, l1 & 255u);
+            const uint32_t cb = raw >> 18;
+            const uint32_t lo = s_pext[((l1 & 15u) << 4) | (cb & 15u)];
+            const uint32_t hi = s_pext[(l1 & 0xF0u) | (cb >> 4)];
+            const uint32_t idx2 = (l1 >> 8) + lo + (hi << __popc(l1 & 15u));
             e = kNoDirect;
             if (idx2 < (uint32_t)kL3Configs) e = lut.l2[idx2];
             else set_err(cnt, PH_EINTERNAL);
@@ -690,31 +730,45 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
             const uint32_t inimg = ((okx & 1u ? 0x55u : 0u) | (okx & 2u ? 0xAAu : 0u)) &
                                    ((oky & 1u ? 0x33u : 0u) | (oky & 2u ? 0xCCu : 0u)) &
                                    ((okz & 1u ? 0x0Fu : 0u) | (okz & 2u ? 0xF0u : 0u));
-            for (uint32_t m = present; m; m &= m - 1) {
+            // root cubes become dual nodes, every other cube of L(v) a dual link (two loops:
+            // roots are rare, so most waves skip the first)
+            for (uint32_t m = root & present; m; m &= m - 1) {
                 const int b = __builtin_ctz(m);
-                const int pos = pos0 + (b >> 2) * (PH * PW) + ((b >> 1) & 1) * PW + (b & 1);
-                if ((root >> b) & 1u) {
-                    if (rb > capT) { set_err(cnt, PH_EINTERNAL); rb = 0; }
-                    spT[pos] = -(rb + 1);
-                    nTkey[rb] = make_key(kv, pv, 19 + b);
-                    ++rb;
-                } else {
-                    const uint32_t t = (links >> (3 * b)) & 7u;
-                    spT[pos] = (inimg >> t) & 1u
-                                   ? kLocal | (pos0 + (int)(t >> 2) * (PH * PW) + (int)((t >> 1) & 1u) * PW + (int)(t & 1u))
-                                   : -1;                // the cell at infinity
-                }
+                if (rb > capT) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                spT[pos0 + oct_slot<PW, PH>(b)] = -(rb + 1);
+                nTkey[rb] = make_key(kv, pv, 19 + b);
+                ++rb;
+            }
+            for (uint32_t m = present & ~root; m; m &= m - 1) {
+                const int b = __builtin_ctz(m);
+                const uint32_t t = (links >> (3 * b)) & 7u;
+                spT[pos0 + oct_slot<PW, PH>(b)] = (inimg >> t) & 1u ? kLocal | (pos0 + oct_slot<PW, PH>(t))
+                                                                     : -1;   // the cell at infinity
             }
         }
     }
     lds_barrier();
 
+    // the thread's cube slots, row by row: walk state (row z, row y, cube index), left one
+    // step past the last row, from where the write-out walks back
+    const int cT = threadIdx.x - gT * PW;
+    const int pz0 = gT / PH, py0 = gT - pz0 * PH;
+    const int dRow = (GT / PH) * (int)TH1W1 + (GT % PH) * (W - 1), dWrap = (int)TH1W1 - PH * (W - 1);
+    int pzw = pz0, pyw = py0, gw = (z0 - 1 + pz0) * (int)TH1W1 + (y0 - 1 + py0) * (W - 1) + (x0 - 1 + cT);
     int32_t v0[NIT], vT[NKT];
 #pragma unroll
-    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+    for (int k = 0; k < NKT; ++k) {
+        vT[k] = gT < GT ? spT[threadIdx.x + STT * k] : 0;
+        if (vT[k] == kUnset) spT[threadIdx.x + STT * k] = vT[k] = gw;
+        gw += dRow;
+        pyw += GT % PH;
+        pzw += GT / PH;
+        if (pyw >= PH) { pyw -= PH; ++pzw; gw += dWrap; }
+    }
 #pragma unroll
-    for (int k = 0; k < NKT; ++k) vT[k] = spT[threadIdx.x + 256 * k];
-    jump_links(sp0, spT, v0, vT, s_any, cnt);
+    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+    lds_barrier();
+    jump_links<NIT, NKT, STT>(sp0, spT, v0, vT, s_any, cnt);
 
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
@@ -723,16 +777,23 @@ __global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ im
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
         if (gz < D && gy < H && gx < W) par0[gz * HW + (int64_t)gy * W + gx] = v0[k];
     }
+    {
+        // the thread's cube slots again, last row first; a slot still holding its own index
+        // belongs to another tile
+        const bool inx = (unsigned)(x0 - 1 + cT) < (unsigned)(W - 1);
 #pragma unroll
-    for (int k = 0; k < NKT; ++k) {
-        const int p = threadIdx.x + 256 * k;
-        const int32_t v = vT[k];
-        const int pz = p / (PH * PW), pr = p - pz * PH * PW, py = pr / PW, px = pr - py * PW;
-        const int cz = z0 - 1 + pz, cy = y0 - 1 + py, cx = x0 - 1 + px;
-        if (p >= NP || v == (int32_t)(cz * TH1W1 + (int64_t)cy * (W - 1) + cx)) continue;
-        if (cz >= 0 && cz < D - 1 && cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1)
-            parT[cz * TH1W1 + (int64_t)cy * (W - 1) + cx] = v;
-        else set_err(cnt, PH_EINTERNAL);
+        for (int k = NKT - 1; k >= 0; --k) {
+            gw -= dRow;
+            pyw -= GT % PH;
+            pzw -= GT / PH;
+            if (pyw < 0) { pyw += PH; --pzw; gw -= dWrap; }
+            const int32_t v = vT[k];
+            if (gT < GT && gT + k * GT < NRT && v != gw) {
+                if (inx && (unsigned)(z0 - 1 + pzw) < (unsigned)(D - 1) && (unsigned)(y0 - 1 + pyw) < (unsigned)(H - 1))
+                    parT[gw] = v;
+                else set_err(cnt, PH_EINTERNAL);
+            }
+        }
     }
     if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
 }

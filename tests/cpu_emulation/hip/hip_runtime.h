@@ -288,6 +288,21 @@ EMU_FN unsigned long long __ballot(int pred) {
     return m;
 }
 inline int __popc(unsigned x) { return __builtin_popcount(x); }
+// v_perm_b32: byte i of the result is chosen by byte i of sel from the eight bytes of
+// {hi, lo}: 0..7 a byte, 8..11 the sign of bytes 1, 3, 5, 7 replicated, 12 zero, 13.. 0xFF
+inline unsigned __builtin_amdgcn_perm(unsigned hi, unsigned lo, unsigned sel) {
+    const unsigned long long d = ((unsigned long long)hi << 32) | lo;
+    unsigned out = 0;
+    for (int i = 0; i < 4; ++i) {
+        const unsigned s = (sel >> (8 * i)) & 0xFFu;
+        unsigned b;
+        if (s < 8) b = (unsigned)(d >> (8 * s)) & 0xFFu;
+        else if (s < 12) b = ((d >> (16 * (s - 8) + 15)) & 1u) ? 0xFFu : 0u;
+        else b = s == 12 ? 0u : 0xFFu;
+        out |= b << (8 * i);
+    }
+    return out;
+}
 inline int __popcll(unsigned long long x) { return __builtin_popcountll(x); }
 inline unsigned __float_as_uint(float f) { unsigned u; memcpy(&u, &f, 4); return u; }
 inline float __int_as_float(int i) { float f; memcpy(&f, &i, 4); return f; }

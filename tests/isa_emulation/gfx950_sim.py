@@ -457,6 +457,8 @@ VALU3 = {   # D = f(S0, S1, S2)
     "v_xad_u32": lambda a, b, c: (vec(a) ^ b) + c,
     "v_bfe_u32": lambda a, b, c: _bfe_u(vec(a), b, c),
     "v_bfe_i32": lambda a, b, c: _bfe_i(vec(a), b, c),
+    "v_perm_b32": lambda a, b, c: _perm_b32(vec(a), vec(b), vec(c)),
+    "v_bfi_b32": lambda a, b, c: (vec(a) & vec(b)) | (~vec(a) & vec(c)),
     "v_alignbit_b32": lambda a, b, c: (((vec(a).astype(U64) << U64(32)) | vec(b).astype(U64)) >> (vec(c) & U32(31)).astype(U64)).astype(U64).__and__(U64(M32)).astype(U32),
     "v_mad_u32_u24": lambda a, b, c: ((((vec(a) & U32(0xFFFFFF)).astype(U64) * (vec(b) & U32(0xFFFFFF)).astype(U64)) + vec(c).astype(U64)) & U64(M32)).astype(U32),
     "v_mad_i32_i24": lambda a, b, c: ((_sx(a, 24) * _sx(b, 24) + vec(c).astype(np.int64)) & M32).astype(U32),
@@ -472,6 +474,21 @@ def _brev32(x):
 
 CMP = {"lt": np.less, "le": np.less_equal, "gt": np.greater, "ge": np.greater_equal,
        "eq": np.equal, "ne": np.not_equal, "lg": np.not_equal}
+
+
+def _perm_b32(a, b, c):
+    """v_perm_b32: byte i of the result is chosen by byte i of c from the eight bytes of
+    {a (high), b (low)}; 8..11 replicate the sign bit of bytes 1, 3, 5, 7, 12 gives 0, 13.. 0xFF"""
+    data = (a.astype(U64) << U64(32)) | b.astype(U64)
+    out = np.zeros(a.shape, U32)
+    for i in range(4):
+        sel = ((c >> U32(8 * i)) & U32(0xFF)).astype(U64)
+        byte = (data >> (U64(8) * np.minimum(sel, U64(7)))) & U64(0xFF)
+        for s_, bit in ((8, 15), (9, 31), (10, 47), (11, 63)):
+            byte = np.where(sel == s_, np.where((data >> U64(bit)) & U64(1), U64(0xFF), U64(0)), byte)
+        byte = np.where(sel == 12, U64(0), np.where(sel >= 13, U64(0xFF), byte))
+        out |= (byte.astype(U32) << U32(8 * i))
+    return out
 
 
 def _cmp_vals(ty, o):
@@ -490,6 +507,12 @@ def _cmp_vals(ty, o):
     if ty == "f32":
         f = r32(o)
         return lambda w: f32(f(w))
+    if ty == "u16":
+        f = r32(o)
+        return lambda w: vec(f(w)) & U32(0xFFFF)
+    if ty == "i16":
+        f = r32(o)
+        return lambda w: ((vec(f(w)) & U32(0xFFFF)).astype(I64) ^ 0x8000) - 0x8000
     raise Unsupported("compare type " + ty)
 
 
@@ -1015,6 +1038,26 @@ def _sdwa_sel(x, sel, sext):
 
 
 def _compile_sdwa(op, O, mods, nxt):
+    if op.startswith("v_cmp_"):
+        # VOPC with operand selects: compare the selected fields, write the lane mask
+        _, _, cmpop, ty = op.split("_")
+        if ty not in ("u16", "i16", "u32", "i32") or cmpop not in CMP:
+            raise Unsupported("sdwa compare " + op)
+        dst = ws(O[0])
+        a, b = r32(O[1]), r32(O[2])
+        s0, s1 = mods.get("src0_sel", "DWORD"), mods.get("src1_sel", "DWORD")
+        x0, x1 = O[1].sext, O[2].sext
+        c = CMP[cmpop]
+        nb = 16 if ty.endswith("16") else 32
+
+        def val(x):
+            x = vec(x).astype(I64) & ((1 << nb) - 1)
+            return ((x ^ (1 << (nb - 1))) - (1 << (nb - 1))) if ty[0] == "i" else x
+
+        def f(w):
+            dst(w, mask_of(c(val(_sdwa_sel(a(w), s0, x0)), val(_sdwa_sel(b(w), s1, x1))) & w.exec()))
+            return nxt
+        return f
     fn = VALU2.get(op)
     if fn is None:
         raise Unsupported("sdwa op " + op)
