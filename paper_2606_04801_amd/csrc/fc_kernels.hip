@@ -532,8 +532,10 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
 }
 
 // ================================================================ classify 3D ====
+// 256 threads, at least seven workgroups (28 waves) per compute unit: the register budget
+// (72) costs a few spilled registers, cheaper than losing a wave per SIMD
 template <int TW, int TH, int TD>
-__global__ __launch_bounds__(256) void k_classify3d(const float *__restrict__ imgs,
+__global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;

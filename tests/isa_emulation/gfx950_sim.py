@@ -193,7 +193,7 @@ def split_ops(rest: str):
 
 
 class Wave:
-    __slots__ = ("s", "v", "scc", "pc", "done", "barrier", "wid", "wg", "lds", "_em", "_eb")
+    __slots__ = ("s", "v", "scc", "pc", "done", "barrier", "wid", "wg", "lds", "_em", "_eb", "priv")
 
     def __init__(self, nvgpr):
         self.s = [0] * 128
@@ -204,6 +204,7 @@ class Wave:
         self.barrier = False
         self._em = None
         self._eb = None
+        self.priv = None          # (64, private segment bytes): each lane's scratch memory
 
     def exec(self) -> np.ndarray:
         m = self.s[126] | (self.s[127] << 32)
@@ -575,6 +576,8 @@ def _compile(op, parts, mods, pc, nxt):
         return _compile_salu(op, O, mods, nxt)
     if op.startswith(("global_", "flat_")):
         return _compile_global(op, O, mods, nxt)
+    if op.startswith("scratch_"):
+        return _compile_scratch(op, O, mods, nxt)
     if op.startswith("ds_"):
         return _compile_ds(op, O, mods, nxt)
     if op.startswith("v_"):
@@ -1092,6 +1095,40 @@ def _offset(mods):
     return int(mods.get("offset", "0"), 0)
 
 
+def _compile_scratch(op, O, mods, nxt):
+    """Private (scratch) memory: every lane has its own bytes, w.priv[lane]; the address is
+    vaddr + saddr + offset (either may be off), checked against the private segment size."""
+    off = _offset(mods)
+    kind = op.split("_", 1)[1]
+    load = kind.startswith("load_")
+    nbytes = {"dword": 4, "dwordx2": 8, "dwordx3": 12, "dwordx4": 16}.get(kind.split("_", 1)[1])
+    if nbytes is None:
+        raise Unsupported(op)
+    vo, so = (O[1], O[2]) if load else (O[0], O[2])
+    va = (lambda w: np.zeros(LANES, np.int64)) if vo.kind == "off" else (lambda w, r=r32(vo): vec(r(w)).astype(np.int64))
+    sa = (lambda w: 0) if so.kind == "off" else (lambda w, r=rs(so): int(r(w)))
+    reg = (O[0] if load else O[1]).idx
+
+    def f(w):
+        e = w.exec()
+        if not e.any():
+            return nxt
+        addr = va(w) + sa(w) + off
+        lanes = np.nonzero(e)[0]
+        a = addr[lanes]
+        if (a < 0).any() or (a + nbytes > w.priv.shape[1]).any():
+            raise Fault("%s at pc 0x%x: outside the private segment (%d bytes)" % (op, w.pc, w.priv.shape[1]))
+        for k in range(nbytes // 4):
+            for j, ln in enumerate(lanes):
+                p = int(a[j]) + 4 * k
+                if load:
+                    w.v[reg + k][ln] = w.priv[ln, p:p + 4].view("<u4")[0]
+                else:
+                    w.priv[ln, p:p + 4] = np.frombuffer(np.uint32(w.v[reg + k][ln]).tobytes(), U8)
+        return nxt
+    return f
+
+
 def _compile_global(op, O, mods, nxt):
     off = _offset(mods)
     flat = op.startswith("flat_")
@@ -1398,8 +1435,10 @@ class Dispatch:
         self.kcp = struct.unpack_from("<H", d, 56)[0]
         if struct.unpack_from("<H", d, 58)[0]:
             raise Unsupported("kernarg preload")
-        if self.rsrc2 & 1 or self.kcp & 1 or self.kcp & 0x20:
-            raise Unsupported("private segment")
+        # a private segment is only supported with architected flat scratch (scratch_* with no
+        # buffer descriptor or flat-scratch SGPRs); every lane's bytes live in Wave.priv
+        if self.kcp & 1 or self.kcp & 0x20:
+            raise Unsupported("private segment buffer / flat scratch init SGPRs")
         self.nvgpr = 512
 
     def done(self):
@@ -1433,6 +1472,9 @@ class Dispatch:
                 k += 1
         if self.rsrc2 & (1 << 10):
             raise Unsupported("workgroup info SGPR")
+        if self.rsrc2 & 1:                         # private segment wave offset: scratch is per wave here
+            s[k] = 0
+            k += 1
         bx, by, bz = self.block
         t = wid * 64 + LANE
         tx, ty, tz = t % bx, (t // bx) % by, t // (bx * by)
@@ -1459,6 +1501,7 @@ class Dispatch:
                     waves = [self._init_wave(i, (x, y, z), nthreads) for i in range(nwaves)]
                     for w in waves:
                         w.wg = wg
+                        w.priv = np.full((LANES, max(self.k.private_segment, 4)), 0x5A, U8)
                     count += self._run_group(waves, max_instr - count, (x, y, z))
         return count
 

@@ -1,7 +1,8 @@
 """Audit of the library's own gfx950 machine code (built here), read back from the shared
-library with the ROCm LLVM tools: no scratch memory, no packed FP32 arithmetic, no stores or
-atomics through the scalar data cache, no PC-relative data references, and every kernel's
-static LDS within the device limit.  No GPU needed."""
+library with the ROCm LLVM tools: no packed FP32 arithmetic, no stores or atomics through the
+scalar data cache, no PC-relative data references, every kernel's static LDS within the device
+limit, and no scratch memory except a bounded register spill in the 3D classify kernels (built
+for seven workgroups per compute unit).  No GPU needed."""
 import os
 import re
 import shutil
@@ -16,7 +17,7 @@ if not (os.path.exists(fc.LIB_PATH) and os.path.exists(os.path.join(LLVM, "llvm-
     pytest.skip("library or ROCm LLVM tools missing", allow_module_level=True)
 
 FORBIDDEN = [
-    r"^scratch_", r"^buffer_",                                    # private (scratch) memory
+    r"^buffer_",                                                  # buffer-descriptor memory
     r"^v_pk_(add|mul|fma)_f32",                                   # packed FP32 arithmetic
     r"^s_(buffer_)?store", r"^s_(buffer_)?atomic", r"^s_dcache_(wb|discard)",   # scalar-cache writes
     r"^s_getpc",                                                  # PC-relative addressing
@@ -44,14 +45,32 @@ def test_no_forbidden_instructions(code_object):
     assert not bad, bad
 
 
+def test_scratch_only_in_classify3d(code_object):
+    """Private memory appears only as the 3D classify kernels' spill, through architected flat
+    scratch (no buffer descriptor)."""
+    dis = subprocess.run([os.path.join(LLVM, "llvm-objdump"), "-d", "--mcpu=gfx950", code_object],
+                         check=True, capture_output=True, text=True).stdout
+    fn, users = None, set()
+    for line in dis.splitlines():
+        m = re.match(r"^[0-9a-f]+ <(\S+)>:", line)
+        if m:
+            fn = m.group(1)
+        elif re.match(r"^\s+scratch_", line):
+            users.add(fn)
+    assert all("k_classify3d" in f for f in users), users
+
+
 def test_kernel_descriptors(code_object):
     out = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--notes", code_object], check=True,
                          capture_output=True, text=True).stdout
     lds = [int(x) for x in re.findall(r"\.group_segment_fixed_size:\s+(\d+)", out)]
     priv = [int(x) for x in re.findall(r"\.private_segment_fixed_size:\s+(\d+)", out)]
-    assert len(lds) >= 15 and len(priv) == len(lds)
+    names = re.findall(r"^\s+\.name:\s+(\S+)", out, flags=re.M)
+    names = [n for n in names if n.startswith("_Z") or n.startswith("k_")]
+    assert len(lds) >= 15 and len(priv) == len(lds) == len(names)
     assert max(lds) <= 64 * 1024            # well inside the 160 KiB a gfx950 workgroup may use
-    assert max(priv) == 0
+    for n, p in zip(names, priv):           # a spill of a few registers at most
+        assert p == 0 or ("k_classify3d" in n and p <= 32), (n, p)
     assert "uses_dynamic_stack: true" not in out.replace(".", "")
 
 
