@@ -554,6 +554,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
     __shared__ int32_t s_base[4];
     __shared__ int s_any[8];
     __shared__ uint8_t s_pext[256];              // [mask nibble << 4 | bits nibble]: compress8 of the two
+    __shared__ int2 s_row[NKT * GT];
 
 
 
@@ -613,11 +614,17 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
         }
     }
     // cube slots start unset (padding rows final); after pass 2 the slots no vertex of the
-    // tile wrote get their cube's global index (see is_local)
+    // tile wrote get their cube's global index (see is_local).  s_row[r]: global index of the
+    // first cube of slot row r (x = x0 - 1) and whether the row lies in the image.
     const int gT = threadIdx.x / PW;
 #pragma unroll
     for (int k = 0; k < NKT; ++k)
         if (gT < GT) spT[threadIdx.x + k * STT] = gT + k * GT < NRT ? kUnset : 0;
+    for (int r = threadIdx.x; r < NKT * GT; r += 256) {
+        const int pz = r / PH, py = r - pz * PH, cz = z0 - 1 + pz, cy = y0 - 1 + py;
+        s_row[r] = make_int2(cz * (int)TH1W1 + cy * (W - 1) + x0 - 1,
+                             r < NRT && (unsigned)cz < (unsigned)(D - 1) && (unsigned)cy < (unsigned)(H - 1));
+    }
     for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;
     s_pext[threadIdx.x] = (uint8_t)compress8(threadIdx.x & 15u, threadIdx.x >> 4);
     lds_barrier();
@@ -751,21 +758,13 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
     }
     lds_barrier();
 
-    // the thread's cube slots, row by row: walk state (row z, row y, cube index), left one
-    // step past the last row, from where the write-out walks back
+    // the thread's cube slots (column cT of rows gT + k GT)
     const int cT = threadIdx.x - gT * PW;
-    const int pz0 = gT / PH, py0 = gT - pz0 * PH;
-    const int dRow = (GT / PH) * (int)TH1W1 + (GT % PH) * (W - 1), dWrap = (int)TH1W1 - PH * (W - 1);
-    int pzw = pz0, pyw = py0, gw = (z0 - 1 + pz0) * (int)TH1W1 + (y0 - 1 + py0) * (W - 1) + (x0 - 1 + cT);
     int32_t v0[NIT], vT[NKT];
 #pragma unroll
     for (int k = 0; k < NKT; ++k) {
         vT[k] = gT < GT ? spT[threadIdx.x + STT * k] : 0;
-        if (vT[k] == kUnset) spT[threadIdx.x + STT * k] = vT[k] = gw;
-        gw += dRow;
-        pyw += GT % PH;
-        pzw += GT / PH;
-        if (pyw >= PH) { pyw -= PH; ++pzw; gw += dWrap; }
+        if (vT[k] == kUnset) spT[threadIdx.x + STT * k] = vT[k] = s_row[gT + k * GT].x + cT;
     }
 #pragma unroll
     for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
@@ -777,22 +776,19 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
         const int l = threadIdx.x + 256 * k;
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
-        if (gz < D && gy < H && gx < W) par0[gz * HW + (int64_t)gy * W + gx] = v0[k];
+        if (gz < D && gy < H && gx < W) par0[(uint32_t)(gz * (int)HW + gy * W + gx)] = v0[k];
     }
     {
-        // the thread's cube slots again, last row first; a slot still holding its own index
-        // belongs to another tile
+        // the thread's cube slots again; a slot still holding its own index belongs to
+        // another tile
         const bool inx = (unsigned)(x0 - 1 + cT) < (unsigned)(W - 1);
 #pragma unroll
-        for (int k = NKT - 1; k >= 0; --k) {
-            gw -= dRow;
-            pyw -= GT % PH;
-            pzw -= GT / PH;
-            if (pyw < 0) { pyw += PH; --pzw; gw -= dWrap; }
+        for (int k = 0; k < NKT; ++k) {
             const int32_t v = vT[k];
-            if (gT < GT && gT + k * GT < NRT && v != gw) {
-                if (inx && (unsigned)(z0 - 1 + pzw) < (unsigned)(D - 1) && (unsigned)(y0 - 1 + pyw) < (unsigned)(H - 1))
-                    parT[gw] = v;
+            const int2 row = s_row[gT + k * GT];
+            const int32_t gidx = row.x + cT;
+            if (gT < GT && gT + k * GT < NRT && v != gidx) {
+                if (inx && row.y) parT[gidx] = v;
                 else set_err(cnt, PH_EINTERNAL);
             }
         }

@@ -79,6 +79,9 @@ inline void emu_check_access(const void *, size_t, int) {}
 #define __shared__ static __attribute__((section("emu_lds")))
 #endif
 
+struct int2 { int x, y; };
+inline int2 make_int2(int x, int y) { return int2{x, y}; }
+
 struct dim3 {
     unsigned x, y, z;
     dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {}
