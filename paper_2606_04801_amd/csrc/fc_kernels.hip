@@ -232,6 +232,18 @@ __device__ __forceinline__ int oct_slot(uint32_t t) {
     }
 }
 
+// Offset of square q = (y x bits) of the four squares around a vertex from the slot of the
+// first (q = 0), in rows of PW slots; picked with a byte permute when every offset fits a byte.
+template <int PW>
+__device__ __forceinline__ int quad_slot(uint32_t q) {
+    if constexpr (PW + 1 < 256) {
+        return (int)__builtin_amdgcn_perm(0u, 0u | 1u << 8 | (uint32_t)PW << 16 | (uint32_t)(PW + 1) << 24,
+                                          q | 0x0C0C0C00u);
+    } else {
+        return (int)((q >> 1) * PW + (q & 1u));
+    }
+}
+
 // v clamped into [0, hi]
 __device__ __forceinline__ int clamp0(int v, int hi) {
     const int a = v > 0 ? v : 0;
@@ -345,6 +357,8 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     __shared__ uint32_t skey[(TH + 2) * KW];
     __shared__ int32_t sp0[TH * TW];
     __shared__ int32_t spT[256 * NKT];           // padded to whole rounds of the block
+    constexpr int NRT = (256 * NKT + PW - 1) / PW;   // slot rows, padding included
+    __shared__ int2 s_row[NRT];
     __shared__ int s_nan;
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
@@ -397,9 +411,13 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             skey[l] = key;
         }
     }
-    for (int p = threadIdx.x; p < 256 * NKT; p += 256) {
-        const int pr = p / PW, pc = p - pr * PW;
-        spT[p] = p < NP ? (y0 - 1 + pr) * (W - 1) + (x0 - 1 + pc) : 0;
+    // square slots start unset (padding final); after pass 2 the slots no vertex of the tile
+    // wrote get their square's global index (see is_local).  s_row[r]: global index of the
+    // first square of slot row r (x = x0 - 1) and whether the row lies in the image.
+    for (int p = threadIdx.x; p < 256 * NKT; p += 256) spT[p] = p < NP ? kUnset : 0;
+    for (int r = threadIdx.x; r < NRT; r += 256) {
+        const int sy = y0 - 1 + r;
+        s_row[r] = make_int2(sy * (W - 1) + x0 - 1, r <= TH && (unsigned)sy < (unsigned)(H - 1));
     }
     // every link slot starts final (0 is never followed); slots of vertices outside the
     // image keep it, so the pointer jumping below never reads an uninitialised slot
@@ -482,23 +500,25 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
             ++kb;
         }
-        // squares of L(v): ROOT -> dual node, LOCAL -> dual link
-        for (uint32_t m = present; m; m &= m - 1) {
-            const int q = __builtin_ctz(m);
-            const int sy = gy - 1 + (q >> 1), sx = gx - 1 + (q & 1);
-            const int pos = (sy - y0 + 1) * PW + (sx - x0 + 1);
-            if ((root >> q) & 1u) {
+        // squares of L(v): ROOT -> dual node, the others -> dual link.  Square q = (y x bits)
+        // has its first corner at v - (1,1) + q and its slot at pos0 + quad_slot(q); it lies in
+        // the image when both corner coordinates do.
+        if (present) {
+            const int pos0 = r * PW + c;
+            const uint32_t inimg = ((gy >= 1 ? 0x3u : 0u) | (gy <= H - 2 ? 0xCu : 0u)) &
+                                   ((gx >= 1 ? 0x5u : 0u) | (gx <= W - 2 ? 0xAu : 0u));
+            for (uint32_t m = root & present; m; m &= m - 1) {
+                const int q = __builtin_ctz(m);
                 if (rb > I.T) { set_err(cnt, PH_EINTERNAL); rb = 0; }
-                spT[pos] = -(rb + 1);
+                spT[pos0 + quad_slot<PW>(q)] = -(rb + 1);
                 nTkey[rb] = make_key(kv, pv, 11 + q);
                 ++rb;
-            } else {
+            }
+            for (uint32_t m = present & ~root; m; m &= m - 1) {
+                const int q = __builtin_ctz(m);
                 const uint32_t t = (e >> (kL2Link + 2 * q)) & 3u;
-                const int ty2 = gy - 1 + (int)(t >> 1), tx2 = gx - 1 + (int)(t & 1);
-                if (ty2 >= 0 && ty2 < H - 1 && tx2 >= 0 && tx2 < W - 1)
-                    spT[pos] = kLocal | ((ty2 - y0 + 1) * PW + (tx2 - x0 + 1));
-                else
-                    spT[pos] = -1;                       // the cell at infinity
+                spT[pos0 + quad_slot<PW>(q)] = (inimg >> t) & 1u ? kLocal | (pos0 + quad_slot<PW>(t))
+                                                                 : -1;    // the cell at infinity
             }
         }
     }
@@ -507,25 +527,31 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     // resolve links inside the tile (see jump_links)
     int32_t v0[NIT], vT[NKT];
 #pragma unroll
-    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+    for (int k = 0; k < NKT; ++k) {
+        const int p = threadIdx.x + 256 * k, pr = p / PW, pc = p - pr * PW;
+        vT[k] = spT[p];
+        if (vT[k] == kUnset) spT[p] = vT[k] = s_row[pr].x + pc;
+    }
 #pragma unroll
-    for (int k = 0; k < NKT; ++k) vT[k] = spT[threadIdx.x + 256 * k];
+    for (int k = 0; k < NIT; ++k) v0[k] = sp0[threadIdx.x + 256 * k];
+    lds_barrier();
     jump_links<NIT, NKT, 256>(sp0, spT, v0, vT, s_any, cnt);
 
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
         const int l = threadIdx.x + 256 * k, r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
-        if (gy < H && gx < W) par0[gy * W + gx] = v0[k];
+        if (gy < H && gx < W) par0[(uint32_t)(gy * W + gx)] = v0[k];
     }
 #pragma unroll
     for (int k = 0; k < NKT; ++k) {
-        const int p = threadIdx.x + 256 * k;
+        const int p = threadIdx.x + 256 * k, pr = p / PW, pc = p - pr * PW;
         const int32_t v = vT[k];
-        const int pr = p / PW, pc = p - pr * PW, sy = y0 - 1 + pr, sx = x0 - 1 + pc;
-        if (p >= NP || v == sy * (W - 1) + sx) continue;     // not a square of this tile
+        const int2 row = s_row[pr];
+        const int32_t gidx = row.x + pc;
+        if (p >= NP || v == gidx) continue;          // not a square of this tile
         // a square is only ever marked for a vertex whose lower star holds it, so it lies in
         // the image; the check keeps a corrupted table from writing outside parT
-        if (sy >= 0 && sy < H - 1 && sx >= 0 && sx < W - 1) parT[sy * (W - 1) + sx] = v;
+        if (row.y && (unsigned)(x0 - 1 + pc) < (unsigned)(W - 1)) parT[gidx] = v;
         else set_err(cnt, PH_EINTERNAL);
     }
     if (threadIdx.x == 0 && s_nan) set_err(cnt, PH_ENAN);
@@ -784,10 +810,11 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
         const bool inx = (unsigned)(x0 - 1 + cT) < (unsigned)(W - 1);
 #pragma unroll
         for (int k = 0; k < NKT; ++k) {
+            if (gT >= GT || gT + k * GT >= NRT) continue;   // no slot, or a padding row
             const int32_t v = vT[k];
             const int2 row = s_row[gT + k * GT];
             const int32_t gidx = row.x + cT;
-            if (gT < GT && gT + k * GT < NRT && v != gidx) {
+            if (v != gidx) {
                 if (inx && row.y) parT[gidx] = v;
                 else set_err(cnt, PH_EINTERNAL);
             }
