@@ -929,22 +929,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws,
 }
 
 // ===================================================================== resolve ====
-// Follow forest links from entry x to its root node id; -1 (and an error) if a link leaves
-// [0, size) or a node id is not below nodes.
-__device__ __forceinline__ int chase(const int32_t *__restrict__ p, int64_t x, int64_t size, int nodes,
-                                     int32_t *cnt) {
-    for (int it = 0; it < kMaxChase; ++it) {
-        if (x < 0 || x >= size) break;
-        const int32_t v = p[x];
-        if (v < 0) {
-            const int id = -(v + 1);
-            if (id >= nodes) break;
-            return id;
+// Follow forest links from entries x0 and x1 to their root node ids, both walks at once so
+// their loads are in flight together; -1 (and an error) if a link leaves [0, size) or a node
+// id is not below nodes; a walk not run yields 0.
+__device__ __forceinline__ void chase2(const int32_t *__restrict__ p, int64_t x0, int64_t x1, bool run0, bool run1,
+                                       int64_t size, int nodes, int32_t *cnt, int &r0, int &r1) {
+    r0 = 0;
+    r1 = 0;
+    bool a0 = run0, a1 = run1;
+    for (int it = 0; (a0 || a1) && it < kMaxChase; ++it) {
+        if (a0 && (x0 < 0 || x0 >= size)) { set_err(cnt, PH_EINTERNAL); r0 = -1; a0 = false; }
+        if (a1 && (x1 < 0 || x1 >= size)) { set_err(cnt, PH_EINTERNAL); r1 = -1; a1 = false; }
+        const int32_t v0 = a0 ? p[x0] : 0, v1 = a1 ? p[x1] : 0;
+        if (a0) {
+            if (v0 >= 0) x0 = v0;
+            else {
+                a0 = false;
+                r0 = -(v0 + 1);
+                if (r0 >= nodes) { set_err(cnt, PH_EINTERNAL); r0 = -1; }
+            }
         }
-        x = v;
+        if (a1) {
+            if (v1 >= 0) x1 = v1;
+            else {
+                a1 = false;
+                r1 = -(v1 + 1);
+                if (r1 >= nodes) { set_err(cnt, PH_EINTERNAL); r1 = -1; }
+            }
+        }
     }
-    set_err(cnt, PH_EINTERNAL);
-    return -1;
+    if (a0) { set_err(cnt, PH_EINTERNAL); r0 = -1; }
+    if (a1) { set_err(cnt, PH_EINTERNAL); r1 = -1; }
 }
 
 // H0: the two endpoints of every sorted KEEP edge, as H0 nodes (local minima).
@@ -965,8 +980,10 @@ __global__ __launch_bounds__(256) void k_resolve_edges(uint8_t *__restrict__ ws,
         const int code = key_code(k);
         if (code < 1 || code > 6) { set_err(cnt, PH_EINTERNAL); ea[r] = eb[r] = -1; continue; }
         const int64_t u = v + off_of(code, 0) * HW + off_of(code, 1) * (int64_t)I.W + off_of(code, 2);
-        ea[r] = chase(par0, v, I.N, M0, cnt);
-        eb[r] = chase(par0, u, I.N, M0, cnt);
+        int a, b;
+        chase2(par0, v, u, true, true, I.N, M0, cnt, a, b);
+        ea[r] = a;
+        eb[r] = b;
     }
 }
 
@@ -1000,21 +1017,22 @@ __global__ __launch_bounds__(256) void k_resolve_facets(uint8_t *__restrict__ ws
         int axis = -1;
         for (int a = is2d ? 1 : 0; a < 3; ++a)
             if (off_of(code, a) == 0) axis = a;
-        int node[2];
+        int64_t top[2];
+        bool in[2];
         for (int t = 0; t < 2; ++t) {
             int o[3] = {off_of(code, 0), off_of(code, 1), off_of(code, 2)};
             o[axis] = t ? 1 : -1;
-            // top cell at doubled offset o from 2v: its first corner is v + (o - 1) / 2
+            // top cell at doubled offset o from 2v: its first corner is v + (o - 1) / 2; a
+            // cofacet outside the image is the cell at infinity (node 0)
             const int cz = is2d ? 0 : vz + (o[0] - 1) / 2;
             const int cy = vy + (o[1] - 1) / 2, cx = vx + (o[2] - 1) / 2;
-            const bool in = cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1 &&
-                            (is2d || (cz >= 0 && cz < D - 1));
-            if (!in) { node[t] = 0; continue; }
-            const int64_t top = ((int64_t)cz * (H - 1) + cy) * (W - 1) + cx;
-            node[t] = chase(parT, top, I.T, MT, cnt);
+            in[t] = cy >= 0 && cy < H - 1 && cx >= 0 && cx < W - 1 && (is2d || (cz >= 0 && cz < D - 1));
+            top[t] = ((int64_t)cz * (H - 1) + cy) * (W - 1) + cx;
         }
-        fa[r] = node[0];
-        fb[r] = node[1];
+        int a, b;
+        chase2(parT, top[0], top[1], in[0], in[1], I.T, MT, cnt, a, b);
+        fa[r] = a;
+        fb[r] = b;
     }
 }
 
@@ -1472,6 +1490,16 @@ int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_
     return at;
 }
 
+int64_t max_voxels(const ph_shape *h, int n) {
+    int64_t m = 1;
+    for (int i = 0; i < n; ++i) {
+        int64_t v = 1;
+        for (int a = 0; a < h[i].ndim; ++a) v *= h[i].ext[a];
+        if (v > m) m = v;
+    }
+    return m;
+}
+
 int64_t max_list(const ph_shape *h, int n) {
     int64_t m = 1;
     for (int i = 0; i < n; ++i) {
@@ -1644,8 +1672,12 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
         else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
         else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
     }
-    const int64_t ml = max_list(h_shapes, n);
-    const unsigned rblocks = (unsigned)((ml + 255) / 256 < 1024 ? (ml + 255) / 256 : 1024);
+    // resolve grid: the lists are a small share of the voxels for any field that is not noise,
+    // so 256 threads per 64Ki voxels of the largest instance; the loops stride over the rest
+    const int64_t ml = max_list(h_shapes, n), mv = max_voxels(h_shapes, n);
+    int64_t rb = (mv + 65535) / 65536;
+    if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
+    const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
     FC_LAUNCH(K_SORT_EDGES, hipLaunchKernelGGL(k_sort<0>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
     if (any3) FC_LAUNCH(K_SORT_FACETS, hipLaunchKernelGGL(k_sort<1>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
     FC_LAUNCH(K_RESOLVE_EDGES, hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
