@@ -116,12 +116,8 @@ def algorithmic_bytes(name, wc, npairs, shapes):
         t = sum(int(np.prod([e - 1 for e in s])) for s, k in zip(shapes, sel) if k)
         return 4 * n + 4 * n + 4 * t + 8 * (int(wc[sel, 0].sum()) + int(wc[sel, 1].sum())
                                             + int(wc[sel, 2].sum()) + int(wc[sel, 3].sum()))
-    if name == "k_sort(edges)":
-        return 16 * ke
-    if name == "k_sort(facets)":
-        return 16 * kf
-    if name == "k_sort(nodes)":
-        return 16 * m0
+    if name == "k_sort":
+        return 16 * (ke + kf + m0)
     if name in ("k_resolve_edges", "k_uf(h0)"):
         return 16 * ke
     if name in ("k_resolve_facets", "k_uf(top)"):

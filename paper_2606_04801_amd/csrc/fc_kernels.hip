@@ -863,21 +863,16 @@ __device__ void bitonic_lds(uint64_t *s, int P) {
     }
 }
 
-// The list is a template argument, so each instantiation is straight-line code.  With the list
-// chosen by a run-time argument, the gfx950 build of this kernel took the node-key branch
-// without setting the scalar register pair that holds the count's address, and loaded the
-// count from near address 0.
+// Sort of one list of instance I (WHICH: 0 KEEP edges, 1 KEEP squares, 2 node keys), m keys,
+// by the whole block.  The list is a template argument, so each instantiation is straight-line
+// code: with the list chosen by a run-time argument, the gfx950 build of an earlier sort kernel
+// took the node-key branch without setting the scalar register pair that holds the count's
+// address, and loaded the count from near address 0.  The caller loads every count first.
 template <int WHICH>
-__global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws, int n) {
-    __shared__ uint64_t s[kSortCap];
-    const int i = blockIdx.x;
-    const Inst &I = ((const Inst *)ws)[i];
-    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed(cnt)) return;
-    constexpr int kCnt = WHICH == 0 ? CNT_E : (WHICH == 1 ? CNT_F : CNT_M0);
+__device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &I, int32_t *cnt, int m,
+                                          uint64_t *s) {
     uint64_t *src = arr<uint64_t>(ws, WHICH == 0 ? I.o_keyE : (WHICH == 1 ? I.o_keyF : I.o_n0key));
     uint64_t *dst = WHICH == 2 ? arr<uint64_t>(ws, I.o_n0sorted) : src;
-    const int m = cnt[kCnt];
     const int64_t cap = WHICH == 0 ? I.E : (WHICH == 1 ? I.F : I.N);
     if (m > cap) { if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL); return; }
     if (m <= 0) return;
@@ -888,6 +883,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws,
         __syncthreads();
         bitonic_lds(s, P);
         for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = s[t];
+        __syncthreads();                         // s is free for the caller's next sort
         return;
     }
     // long list: chunks in LDS, then merge passes dst <-> scratch
@@ -926,6 +922,31 @@ __global__ __launch_bounds__(kSortThreads) void k_sort(uint8_t *__restrict__ ws,
     }
     if (a != dst)
         for (int64_t t = threadIdx.x; t < m; t += blockDim.x) dst[t] = a[t];
+    __syncthreads();
+}
+
+// The three sorts of every instance in one launch: block (i, w) sorts list w of instance i, so
+// the lists of all instances are sorted side by side.  A list longer than the LDS merges through
+// the instance's one scratch buffer; when any list of the instance is that long, block (i, 0)
+// sorts all three in turn and the other two leave.
+__global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict__ ws, int n) {
+    __shared__ uint64_t s[kSortCap];
+    const int i = blockIdx.x, w = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (block_failed(cnt)) return;
+    const int mE = cnt[CNT_E], mF = cnt[CNT_F], mN = cnt[CNT_M0];
+    const bool serial = mE > kSortCap || mF > kSortCap || mN > kSortCap;
+    if (w == 0) {
+        sort_list<0>(ws, I, cnt, mE, s);
+        if (serial) {
+            sort_list<1>(ws, I, cnt, mF, s);
+            sort_list<2>(ws, I, cnt, mN, s);
+        }
+    } else if (!serial) {
+        if (w == 1) sort_list<1>(ws, I, cnt, mF, s);
+        else sort_list<2>(ws, I, cnt, mN, s);
+    }
 }
 
 // ===================================================================== resolve ====
@@ -1397,9 +1418,7 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_classify3d<16,8,8>", (const void *)k_classify3d<16, 8, 8>, 256},
         {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4>, 256},
         {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16>, 256},
-        {"k_sort<edges>", (const void *)k_sort<0>, kSortThreads},
-        {"k_sort<facets>", (const void *)k_sort<1>, kSortThreads},
-        {"k_sort<nodes>", (const void *)k_sort<2>, kSortThreads},
+        {"k_sort_lists", (const void *)k_sort_lists, kSortThreads},
         {"k_resolve_edges", (const void *)k_resolve_edges, 256},
         {"k_resolve_facets", (const void *)k_resolve_facets, 256},
         {"k_uf<0>", (const void *)k_uf<false>, kUfThreads},
@@ -1562,11 +1581,11 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // Optional per-launch timing with HIP events on the launch stream (not for use while the
 // stream is being captured into a graph).
 enum KernelId {
-    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT_EDGES, K_SORT_FACETS, K_SORT_NODES, K_RESOLVE_EDGES,
+    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE_EDGES,
     K_UF_H0, K_RESOLVE_FACETS, K_UF_TOP, K_OUTPUT, K_ZERO, K_SCATTER, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
-    "k_plan", "k_classify2d", "k_classify3d", "k_sort(edges)", "k_sort(facets)", "k_sort(nodes)",
+    "k_plan", "k_classify2d", "k_classify3d", "k_sort",
     "k_resolve_edges", "k_uf(h0)", "k_resolve_facets", "k_uf(top)", "k_output", "k_zero", "k_scatter"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
@@ -1627,11 +1646,8 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
         return PH_EINVAL;
-    bool any3 = false;
-    for (int i = 0; i < n; ++i) {
+    for (int i = 0; i < n; ++i)
         if (!valid_shape(h_shapes[i])) return PH_EINVAL;
-        any3 |= h_shapes[i].ndim == 3;
-    }
     if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
     int rc = device_luts();
     if (rc != PH_OK) return rc;
@@ -1678,15 +1694,13 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     int64_t rb = (mv + 65535) / 65536;
     if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
-    FC_LAUNCH(K_SORT_EDGES, hipLaunchKernelGGL(k_sort<0>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
-    if (any3) FC_LAUNCH(K_SORT_FACETS, hipLaunchKernelGGL(k_sort<1>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
+    FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n));
     FC_LAUNCH(K_RESOLVE_EDGES, hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
     FC_LAUNCH(K_UF_H0, hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     if (flags & PH_HTOP) {
         FC_LAUNCH(K_RESOLVE_FACETS, hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
         FC_LAUNCH(K_UF_TOP, hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
-    FC_LAUNCH(K_SORT_NODES, hipLaunchKernelGGL(k_sort<2>, dim3(n), dim3(kSortThreads), 0, st, ws, n));
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
                                  d_status));
     return PH_OK;

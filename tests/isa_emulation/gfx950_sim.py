@@ -455,6 +455,11 @@ VALU3 = {   # D = f(S0, S1, S2)
     "v_lshl_or_b32": lambda a, b, c: (vec(a) << (vec(b) & U32(31))) | c,
     "v_and_or_b32": lambda a, b, c: (vec(a) & b) | c,
     "v_or3_b32": lambda a, b, c: vec(a) | b | c,
+    "v_max3_i32": lambda a, b, c: np.maximum(np.maximum(s32(a), s32(b)), s32(c)).astype(U32),
+    "v_min3_i32": lambda a, b, c: np.minimum(np.minimum(s32(a), s32(b)), s32(c)).astype(U32),
+    "v_max3_u32": lambda a, b, c: np.maximum(np.maximum(vec(a), vec(b)), vec(c)),
+    "v_min3_u32": lambda a, b, c: np.minimum(np.minimum(vec(a), vec(b)), vec(c)),
+    "v_med3_i32": lambda a, b, c: np.median(np.stack(np.broadcast_arrays(s32(a), s32(b), s32(c))), axis=0).astype(np.int64).astype(U32),
     "v_xad_u32": lambda a, b, c: (vec(a) ^ b) + c,
     "v_bfe_u32": lambda a, b, c: _bfe_u(vec(a), b, c),
     "v_bfe_i32": lambda a, b, c: _bfe_i(vec(a), b, c),

@@ -6,7 +6,7 @@ a workgroup interleaved between barriers, every global access checked against th
 device buffers and every LDS access against the kernel's LDS segment.  The library's own host
 code issues the launches (tests/cpu_emulation, variant "isa").  Results must equal the
 oracle's bit for bit.  This is how the node-key sort was found to load its count through a
-scalar register pair that its branch never set (see k_sort).
+scalar register pair that its branch never set (see sort_list).
 """
 import os
 import shutil
@@ -51,7 +51,7 @@ def test_every_kernel_of_a_diagram_runs(isa):
     isa.launches = []
     isa.diagram(S.grf((12, 10, 14), 1.5, 8))
     names = {n for n, _, _ in isa.launches}
-    for k in ("k_plan", "k_classify3d", "k_sortILi0", "k_sortILi1", "k_sortILi2", "k_resolve_edges",
+    for k in ("k_plan", "k_classify3d", "k_sort_lists", "k_resolve_edges",
               "k_resolve_facets", "k_ufILb0", "k_ufILb1", "k_output"):
         assert any(k in n for n in names), k
 
