@@ -47,6 +47,7 @@ constexpr int32_t kUnset = 0x7FFFFFFF;     // LDS cube slot not yet written
 constexpr int kMaxChase = 1 << 22;         // bound of every pointer walk
 constexpr int kUfThreads = 1024;
 constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS (2 x 20 KiB)
+constexpr int kUfLdsEdges = 4096;          // union-find live edges kept in LDS (3 x 16 KiB)
 constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
@@ -1082,9 +1083,13 @@ __device__ __forceinline__ void st_node(int32_t *p, int32_t v) {
     else __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-template <bool DUAL, bool GLOBAL>
+// The round loop.  GN: the node arrays (par, moe) live in global memory, else in LDS; GL: the
+// live-edge arrays (walk position q, and the current roots A, B of the edge's two ends) live in
+// global memory, else in LDS.  A fired edge is marked by complementing its q; compaction keeps
+// the edges whose ends still lie in different components and moves them down in place.
+template <bool DUAL, bool GN, bool GL>
 __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t *par, int32_t *moe,
-                                        int *s_wsum) {
+                                        int32_t *live, int32_t *A, int32_t *B, int *s_wsum) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1097,8 +1102,6 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
     int32_t *death0 = arr<int32_t>(ws, I.o_death0);
     int32_t *killer = arr<int32_t>(ws, I.o_killer);
-    int32_t *live = arr<int32_t>(ws, I.o_live), *live2 = arr<int32_t>(ws, I.o_live2);
-    int32_t *RA = arr<int32_t>(ws, I.o_ra), *RB = arr<int32_t>(ws, I.o_rb);
 
     // elder(x, y): x entered earlier in the walk order
     auto elder = [&](int x, int y) -> bool {
@@ -1107,18 +1110,23 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     };
     auto find = [&](int x) -> int {
         for (int it = 0; it < kMaxChase; ++it) {
-            const int p = ld_node<GLOBAL>(&par[x]);
+            const int p = ld_node<GN>(&par[x]);
             if (p == x) return x;
-            const int g = ld_node<GLOBAL>(&par[p]);
-            if (g != p) st_node<GLOBAL>(&par[x], g);   // path halving (any ancestor is valid)
+            const int g = ld_node<GN>(&par[p]);
+            if (g != p) st_node<GN>(&par[x], g);       // path halving (any ancestor is valid)
             x = g;
         }
         set_err(cnt, PH_EINTERNAL);
         return x;
     };
     auto edge_of = [&](int q) { return DUAL ? m - 1 - q : q; };
+    auto fire = [&](int dead, int into, int r) {
+        st_node<GN>(&par[dead], into);
+        if (DUAL) killer[r] = dead;
+        else { death0[dead] = r; neg0[r] = 1; }
+    };
 
-    for (int x = threadIdx.x; x < M; x += blockDim.x) { st_node<GLOBAL>(&par[x], x); st_node<GLOBAL>(&moe[x], kInf); }
+    for (int x = threadIdx.x; x < M; x += blockDim.x) { st_node<GN>(&par[x], x); st_node<GN>(&moe[x], kInf); }
     if (DUAL) { for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1; }
     else {
         for (int r = threadIdx.x; r < m; r += blockDim.x) neg0[r] = 0;
@@ -1130,15 +1138,16 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     int L = 0;
     for (int base = 0; base < m; base += blockDim.x) {
         const int q = base + threadIdx.x;
-        int flag = 0;
+        int flag = 0, a = 0, b = 0;
         if (q < m) {
             const int r = edge_of(q);
-            const int a = ea[r], b = eb[r];
+            a = ea[r];
+            b = eb[r];
             flag = a >= 0 && b >= 0 && a < M && b < M && a != b;
         }
         int tot;
         const int pos = block_flag_scan(flag, s_wsum, &tot);
-        if (flag) live[L + pos] = q;
+        if (flag) { live[L + pos] = q; A[L + pos] = a; B[L + pos] = b; }
         L += tot;
     }
     __syncthreads();
@@ -1146,70 +1155,69 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     int round = 0;
     for (; round < kMaxRounds && L > 0; ++round) {
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
-            const int q = live[t], r = edge_of(q);
-            const int x = find(ea[r]), y = find(eb[r]);
-            RA[t] = x;
-            RB[t] = y;
+            const int q = live[t];
+            const int x = find(A[t]), y = find(B[t]);
+            A[t] = x;
+            B[t] = y;
             if (x != y) { atomicMin(&moe[x], q); atomicMin(&moe[y], q); }
         }
         __syncthreads();
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
-            const int x = RA[t], y = RB[t];
+            const int x = A[t], y = B[t];
             if (x == y) continue;
-            const int q = live[t], r = edge_of(q);
+            const int q = live[t];
             int dead = -1, into = -1;
-            if (ld_node<GLOBAL>(&moe[x]) == q && elder(y, x)) { dead = x; into = y; }
-            else if (ld_node<GLOBAL>(&moe[y]) == q && elder(x, y)) { dead = y; into = x; }
+            if (ld_node<GN>(&moe[x]) == q && elder(y, x)) { dead = x; into = y; }
+            else if (ld_node<GN>(&moe[y]) == q && elder(x, y)) { dead = y; into = x; }
             if (dead >= 0) {
-                st_node<GLOBAL>(&par[dead], into);
-                if (DUAL) killer[r] = dead;
-                else { death0[dead] = r; neg0[r] = 1; }
+                fire(dead, into, edge_of(q));
+                live[t] = ~q;
             }
         }
         __syncthreads();
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
-            st_node<GLOBAL>(&moe[RA[t]], kInf);
-            st_node<GLOBAL>(&moe[RB[t]], kInf);
+            st_node<GN>(&moe[A[t]], kInf);
+            st_node<GN>(&moe[B[t]], kInf);
         }
         __syncthreads();
         int L2 = 0;
         for (int base = 0; base < L; base += blockDim.x) {
             const int t = base + threadIdx.x;
-            int flag = 0, q = 0;
+            int flag = 0, q = 0, a = 0, b = 0;
             if (t < L) {
                 q = live[t];
-                const int r = edge_of(q);
-                const bool fired = DUAL ? killer[r] >= 0 : neg0[r] != 0;
-                flag = RA[t] != RB[t] && !fired;
+                a = A[t];
+                b = B[t];
+                flag = a != b && q >= 0;
             }
             int tot;
-            const int pos = block_flag_scan(flag, s_wsum, &tot);
-            if (flag) live2[L2 + pos] = q;
+            const int pos = block_flag_scan(flag, s_wsum, &tot);   // every read of the chunk is done
+            if (flag) { live[L2 + pos] = q; A[L2 + pos] = a; B[L2 + pos] = b; }
             L2 += tot;
         }
         __syncthreads();
-        int32_t *tmp = live; live = live2; live2 = tmp;
         L = L2;
     }
     if (threadIdx.x == 0) {
         cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] = round;
         if (L > 0) cnt[CNT_SEQ] += L;
         for (int t = 0; t < L; ++t) {               // sequential finish, walk order
-            const int q = live[t], r = edge_of(q);
-            const int x = find(ea[r]), y = find(eb[r]);
+            const int q = live[t];
+            const int x = find(A[t]), y = find(B[t]);
             if (x == y) continue;
             const int dead = elder(y, x) ? x : y, into = dead == x ? y : x;
-            st_node<GLOBAL>(&par[dead], into);
-            if (DUAL) killer[r] = dead;
-            else { death0[dead] = r; neg0[r] = 1; }
+            fire(dead, into, edge_of(q));
         }
     }
 }
 
+// Instances with at most kUfLdsNodes nodes keep par and moe in LDS, and with at most
+// kUfLdsEdges edges their live-edge arrays too; larger ones use the workspace.
 template <bool DUAL>
 __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int n) {
     __shared__ int32_t s_par[kUfLdsNodes];
     __shared__ int32_t s_moe[kUfLdsNodes];
+    __shared__ int32_t s_live[kUfLdsEdges], s_a[kUfLdsEdges], s_b[kUfLdsEdges];
     __shared__ int s_wsum[kUfThreads / 64];
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
@@ -1221,9 +1229,11 @@ __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int
         if (threadIdx.x == 0) set_err((int32_t *)cnt, PH_EINTERNAL);
         return;
     }
-    if (M <= kUfLdsNodes) uf_body<DUAL, false>(ws, n, s_par, s_moe, s_wsum);
-    else uf_body<DUAL, true>(ws, n, arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0),
-                             arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0), s_wsum);
+    int32_t *gpar = arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0), *gmoe = arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0);
+    int32_t *glive = arr<int32_t>(ws, I.o_live), *ga = arr<int32_t>(ws, I.o_ra), *gb = arr<int32_t>(ws, I.o_rb);
+    if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_wsum);
+    else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_wsum);
+    else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, s_wsum);
 }
 
 // ====================================================================== output ====
