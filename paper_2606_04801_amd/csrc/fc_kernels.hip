@@ -827,12 +827,21 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
 // ===================================================================== block scan ==
 // Exclusive scan of a 0/1 flag over a block of kUfThreads threads; returns the prefix and
 // writes the block total to *total.  All threads must call it.
+// Barrier of the block; LDS_ONLY: orders LDS accesses only, for phases that exchange nothing
+// through global memory (their global stores are not read back inside the kernel).
+template <bool LDS_ONLY>
+__device__ __forceinline__ void block_sync() {
+    if (LDS_ONLY) lds_barrier();
+    else __syncthreads();
+}
+
+template <bool LDS_ONLY = false>
 __device__ __forceinline__ int block_flag_scan(int flag, int *s_wsum, int *total) {
     const int lane = __lane_id(), wid = threadIdx.x >> 6;
     const uint64_t b = __ballot(flag);
     const int pre = __popcll(b & ((1ull << lane) - 1ull));
     if (lane == 0) s_wsum[wid] = __popcll(b);
-    __syncthreads();
+    block_sync<LDS_ONLY>();
     const int nw = blockDim.x >> 6;
     int base = 0, tot = 0;
     for (int w = 0; w < nw; ++w) {
@@ -840,7 +849,7 @@ __device__ __forceinline__ int block_flag_scan(int flag, int *s_wsum, int *total
         if (w < wid) base += v;
         tot += v;
     }
-    __syncthreads();
+    block_sync<LDS_ONLY>();
     *total = tot;
     return base + pre;
 }
@@ -1089,7 +1098,7 @@ __device__ __forceinline__ void st_node(int32_t *p, int32_t v) {
 // the edges whose ends still lie in different components and moves them down in place.
 template <bool DUAL, bool GN, bool GL>
 __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t *par, int32_t *moe,
-                                        int32_t *live, int32_t *A, int32_t *B, int *s_wsum) {
+                                        int32_t *live, int32_t *A, int32_t *B, uint64_t *s_key, int *s_wsum) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1098,7 +1107,8 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
     const int32_t *ea = arr<int32_t>(ws, DUAL ? I.o_fa : I.o_ea);
     const int32_t *eb = arr<int32_t>(ws, DUAL ? I.o_fb : I.o_eb);
-    const uint64_t *nkey = arr<uint64_t>(ws, DUAL ? I.o_nTkey : I.o_n0key);
+    const uint64_t *gkey = arr<uint64_t>(ws, DUAL ? I.o_nTkey : I.o_n0key);
+    const uint64_t *nkey = GN ? gkey : s_key;       // node keys, copied to LDS with the nodes
     int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
     int32_t *death0 = arr<int32_t>(ws, I.o_death0);
     int32_t *killer = arr<int32_t>(ws, I.o_killer);
@@ -1120,19 +1130,26 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
         return x;
     };
     auto edge_of = [&](int q) { return DUAL ? m - 1 - q : q; };
+    // all state in LDS: the round barriers order LDS only (the rounds' global stores, the
+    // deaths and killers, are each written once and read after the kernel)
+    constexpr bool kLds = !GN && !GL;
     auto fire = [&](int dead, int into, int r) {
         st_node<GN>(&par[dead], into);
         if (DUAL) killer[r] = dead;
         else { death0[dead] = r; neg0[r] = 1; }
     };
 
-    for (int x = threadIdx.x; x < M; x += blockDim.x) { st_node<GN>(&par[x], x); st_node<GN>(&moe[x], kInf); }
+    for (int x = threadIdx.x; x < M; x += blockDim.x) {
+        st_node<GN>(&par[x], x);
+        st_node<GN>(&moe[x], kInf);
+        if (!GN) s_key[x] = gkey[x];
+    }
     if (DUAL) { for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1; }
     else {
         for (int r = threadIdx.x; r < m; r += blockDim.x) neg0[r] = 0;
         for (int x = threadIdx.x; x < M; x += blockDim.x) death0[x] = -1;
     }
-    __syncthreads();
+    __syncthreads();                                // the init stores land before any round's
 
     // live list: walk positions q whose edge joins two different nodes
     int L = 0;
@@ -1146,11 +1163,11 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
             flag = a >= 0 && b >= 0 && a < M && b < M && a != b;
         }
         int tot;
-        const int pos = block_flag_scan(flag, s_wsum, &tot);
+        const int pos = block_flag_scan<kLds>(flag, s_wsum, &tot);
         if (flag) { live[L + pos] = q; A[L + pos] = a; B[L + pos] = b; }
         L += tot;
     }
-    __syncthreads();
+    block_sync<kLds>();
 
     int round = 0;
     for (; round < kMaxRounds && L > 0; ++round) {
@@ -1161,7 +1178,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
             B[t] = y;
             if (x != y) { atomicMin(&moe[x], q); atomicMin(&moe[y], q); }
         }
-        __syncthreads();
+        block_sync<kLds>();
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
             const int x = A[t], y = B[t];
             if (x == y) continue;
@@ -1174,12 +1191,12 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
                 live[t] = ~q;
             }
         }
-        __syncthreads();
+        block_sync<kLds>();
         for (int t = threadIdx.x; t < L; t += blockDim.x) {
             st_node<GN>(&moe[A[t]], kInf);
             st_node<GN>(&moe[B[t]], kInf);
         }
-        __syncthreads();
+        block_sync<kLds>();
         int L2 = 0;
         for (int base = 0; base < L; base += blockDim.x) {
             const int t = base + threadIdx.x;
@@ -1191,11 +1208,11 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
                 flag = a != b && q >= 0;
             }
             int tot;
-            const int pos = block_flag_scan(flag, s_wsum, &tot);   // every read of the chunk is done
+            const int pos = block_flag_scan<kLds>(flag, s_wsum, &tot);   // every read of the chunk is done
             if (flag) { live[L2 + pos] = q; A[L2 + pos] = a; B[L2 + pos] = b; }
             L2 += tot;
         }
-        __syncthreads();
+        block_sync<kLds>();
         L = L2;
     }
     if (threadIdx.x == 0) {
@@ -1211,13 +1228,14 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     }
 }
 
-// Instances with at most kUfLdsNodes nodes keep par and moe in LDS, and with at most
-// kUfLdsEdges edges their live-edge arrays too; larger ones use the workspace.
+// Instances with at most kUfLdsNodes nodes keep par, moe and the node keys in LDS, and with
+// at most kUfLdsEdges edges their live-edge arrays too; larger ones use the workspace.
 template <bool DUAL>
 __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int n) {
     __shared__ int32_t s_par[kUfLdsNodes];
     __shared__ int32_t s_moe[kUfLdsNodes];
     __shared__ int32_t s_live[kUfLdsEdges], s_a[kUfLdsEdges], s_b[kUfLdsEdges];
+    __shared__ uint64_t s_key[kUfLdsNodes];
     __shared__ int s_wsum[kUfThreads / 64];
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
@@ -1231,9 +1249,9 @@ __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int
     }
     int32_t *gpar = arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0), *gmoe = arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0);
     int32_t *glive = arr<int32_t>(ws, I.o_live), *ga = arr<int32_t>(ws, I.o_ra), *gb = arr<int32_t>(ws, I.o_rb);
-    if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_wsum);
-    else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_wsum);
-    else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, s_wsum);
+    if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
+    else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_key, s_wsum);
+    else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, s_key, s_wsum);
 }
 
 // ====================================================================== output ====
