@@ -1845,7 +1845,11 @@ int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64
     if (trace && fc::trace_after(fc::K_ZERO, st) != PH_OK) return PH_EHIP;
     if (trace) fc::trace_before(fc::K_SCATTER);
     hipEvent_t s0 = prof ? fc::prof_mark(st) : nullptr;
-    hipLaunchKernelGGL(fc::k_scatter, dim3(64, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
+    // pairs are a small share of the voxels for any field that is not noise: one 256-thread
+    // block per 64Ki voxels of the mean instance (1..64 per instance); the loop strides over the rest
+    int64_t sb = (total_voxels / n + 65535) / 65536;
+    sb = sb < 1 ? 1 : (sb > 64 ? 64 : sb);
+    hipLaunchKernelGGL(fc::k_scatter, dim3((unsigned)sb, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
                        d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
     const bool ok = hipGetLastError() == hipSuccess;
     if (prof) fc::prof_push(fc::K_SCATTER, s0, ok ? fc::prof_mark(st) : nullptr);
