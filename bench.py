@@ -118,10 +118,11 @@ def algorithmic_bytes(name, wc, npairs, shapes):
                                             + int(wc[sel, 2].sum()) + int(wc[sel, 3].sum()))
     if name == "k_sort":
         return 16 * (ke + kf + m0)
-    if name in ("k_resolve_edges", "k_uf(h0)"):
-        return 16 * ke
-    if name in ("k_resolve_facets", "k_uf(top)"):
-        return 16 * facets
+    f3 = int(wc[is3, 1].sum())                          # facets of the volumes (walked beside H0)
+    if name in ("k_resolve", "k_unionfind"):
+        return 16 * (ke + f3)
+    if name in ("k_resolve(2d top)", "k_unionfind(2d top)"):
+        return 16 * (facets - f3)
     if name == "k_output":
         return 8 * (m0 + facets) + 32 * npairs
     if name == "k_zero":
@@ -137,9 +138,9 @@ def algorithmic_bytes(name, wc, npairs, shapes):
 # and write exactly COPY_BYTES.  --traffic-from reads the two counter CSVs, scales each counter
 # by what it reads for that kernel and writes bytes per launch per kernel for --traffic-json.
 COPY_BYTES = 1 << 30
-KERNEL_KEYS = ["k_classify2d", "k_classify3d", "k_sort", "k_resolve_edges", "k_resolve_facets", "k_uf<false>",
-               "k_uf<true>", "k_output", "k_plan", "k_zero", "k_scatter"]
-PROFILE_NAMES = {"k_uf<false>": "k_uf(h0)", "k_uf<true>": "k_uf(top)"}
+KERNEL_KEYS = ["k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind", "k_output", "k_plan",
+               "k_zero", "k_scatter"]
+PROFILE_NAMES = {}
 
 
 def profile_steps(steps):

@@ -9,7 +9,7 @@
 //   sort      : KEEP edges (and 3D KEEP squares) sorted by their refined-order keys
 //   resolve   : endpoints / cofacets of the sorted cells mapped to union-find nodes
 //   uf        : H0 union-find with the elder rule over the KEEP edges (Sec. 4.1 step 3,
-//               Sec. 4.2 step 2), by parallel rounds of safe merges (see k_uf)
+//               Sec. 4.2 step 2), by parallel rounds of safe merges (see uf_body)
 //   resolve   : cofacets of the facets left for the top dimension (2D: the edges H0 did not
 //               use, the cross-pruning of Sec. 3.2 / Sec. 4.1 step 4)
 //   uf (dual) : union-find on the dual graph with the cell at infinity, facets in decreasing
@@ -993,9 +993,9 @@ __device__ __forceinline__ void chase2(const int32_t *__restrict__ p, int64_t x0
     if (a1) { set_err(cnt, PH_EINTERNAL); r1 = -1; }
 }
 
-// H0: the two endpoints of every sorted KEEP edge, as H0 nodes (local minima).
-__global__ __launch_bounds__(256) void k_resolve_edges(uint8_t *__restrict__ ws, int n) {
-    const int i = blockIdx.y;
+// H0: the two endpoints of every sorted KEEP edge of instance i, as H0 nodes (local minima).
+// The blocks of one instance are blockIdx.x of gridDim.x.
+__device__ __forceinline__ void resolve_edges(uint8_t *__restrict__ ws, int n, int i) {
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (failed(cnt)) return;
@@ -1018,10 +1018,9 @@ __global__ __launch_bounds__(256) void k_resolve_edges(uint8_t *__restrict__ ws,
     }
 }
 
-// Top dimension: the two cofacets of every facet walked by the dual union-find, as dual
-// nodes (0 = the cell at infinity).  2D walks the KEEP edges that H0 did not use.
-__global__ __launch_bounds__(256) void k_resolve_facets(uint8_t *__restrict__ ws, int n) {
-    const int i = blockIdx.y;
+// Top dimension: the two cofacets of every facet of instance i walked by the dual union-find,
+// as dual nodes (0 = the cell at infinity).  2D walks the KEEP edges that H0 did not use.
+__device__ __forceinline__ void resolve_facets(uint8_t *__restrict__ ws, int n, int i) {
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (failed(cnt)) return;
@@ -1065,6 +1064,17 @@ __global__ __launch_bounds__(256) void k_resolve_facets(uint8_t *__restrict__ ws
         fa[r] = a;
         fb[r] = b;
     }
+}
+
+// Resolve passes, blockIdx.y = instance.  Stage 0: blockIdx.z = 0 the KEEP edges of every
+// instance, z = 1 (with the top dimension) the facets of the volumes, whose dual does not wait
+// for H0.  Stage 1: the facets of the images, which need the edges H0 used.
+__global__ __launch_bounds__(256) void k_resolve(uint8_t *__restrict__ ws, int n, int stage, int htop) {
+    const int i = blockIdx.y;
+    const bool vol = ((const Inst *)ws)[i].ndim == 3;
+    if (stage == 0 && blockIdx.z == 0) resolve_edges(ws, n, i);
+    else if (stage == 0 && htop && vol) resolve_facets(ws, n, i);
+    else if (stage == 1 && !vol) resolve_facets(ws, n, i);
 }
 
 // ================================================================== union-find ====
@@ -1230,13 +1240,12 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
 
 // Instances with at most kUfLdsNodes nodes keep par, moe and the node keys in LDS, and with
 // at most kUfLdsEdges edges their live-edge arrays too; larger ones use the workspace.
+// The H0 and dual union-finds of one volume run side by side: the dual keeps its live edges
+// in the free second live array and its roots in the sort scratch (8 max(L, N) bytes).
 template <bool DUAL>
-__global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int n) {
-    __shared__ int32_t s_par[kUfLdsNodes];
-    __shared__ int32_t s_moe[kUfLdsNodes];
-    __shared__ int32_t s_live[kUfLdsEdges], s_a[kUfLdsEdges], s_b[kUfLdsEdges];
-    __shared__ uint64_t s_key[kUfLdsNodes];
-    __shared__ int s_wsum[kUfThreads / 64];
+__device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_par, int32_t *s_moe,
+                                       int32_t *s_live, int32_t *s_a, int32_t *s_b, uint64_t *s_key,
+                                       int *s_wsum) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1248,10 +1257,27 @@ __global__ __launch_bounds__(kUfThreads) void k_uf(uint8_t *__restrict__ ws, int
         return;
     }
     int32_t *gpar = arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0), *gmoe = arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0);
-    int32_t *glive = arr<int32_t>(ws, I.o_live), *ga = arr<int32_t>(ws, I.o_ra), *gb = arr<int32_t>(ws, I.o_rb);
+    const int64_t L = I.E > I.F ? I.E : I.F;
+    int32_t *glive = arr<int32_t>(ws, DUAL ? I.o_live2 : I.o_live);
+    int32_t *ga = DUAL ? arr<int32_t>(ws, I.o_scratch) : arr<int32_t>(ws, I.o_ra);
+    int32_t *gb = DUAL ? arr<int32_t>(ws, I.o_scratch) + L : arr<int32_t>(ws, I.o_rb);
     if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
     else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_key, s_wsum);
     else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, s_key, s_wsum);
+}
+
+// Union-find passes, blockIdx.x = instance.  Stage 0: blockIdx.y = 0 H0 of every instance,
+// y = 1 (with the top dimension) the dual of the volumes; stage 1: the dual of the images.
+__global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ ws, int n, int stage, int htop) {
+    __shared__ int32_t s_par[kUfLdsNodes];
+    __shared__ int32_t s_moe[kUfLdsNodes];
+    __shared__ int32_t s_live[kUfLdsEdges], s_a[kUfLdsEdges], s_b[kUfLdsEdges];
+    __shared__ uint64_t s_key[kUfLdsNodes];
+    __shared__ int s_wsum[kUfThreads / 64];
+    const bool vol = ((const Inst *)ws)[blockIdx.x].ndim == 3;
+    if (stage == 0 && blockIdx.y == 0) uf_run<false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
+    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol))
+        uf_run<true>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
 }
 
 // ====================================================================== output ====
@@ -1447,10 +1473,8 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4>, 256},
         {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16>, 256},
         {"k_sort_lists", (const void *)k_sort_lists, kSortThreads},
-        {"k_resolve_edges", (const void *)k_resolve_edges, 256},
-        {"k_resolve_facets", (const void *)k_resolve_facets, 256},
-        {"k_uf<0>", (const void *)k_uf<false>, kUfThreads},
-        {"k_uf<1>", (const void *)k_uf<true>, kUfThreads},
+        {"k_resolve", (const void *)k_resolve, 256},
+        {"k_unionfind", (const void *)k_unionfind, kUfThreads},
         {"k_output", (const void *)k_output, kUfThreads},
         {"k_zero", (const void *)k_zero, 256},
         {"k_scatter", (const void *)k_scatter, 256},
@@ -1609,12 +1633,12 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // Optional per-launch timing with HIP events on the launch stream (not for use while the
 // stream is being captured into a graph).
 enum KernelId {
-    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE_EDGES,
-    K_UF_H0, K_RESOLVE_FACETS, K_UF_TOP, K_OUTPUT, K_ZERO, K_SCATTER, K_COUNT
+    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_OUTPUT,
+    K_ZERO, K_SCATTER, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
-    "k_plan", "k_classify2d", "k_classify3d", "k_sort",
-    "k_resolve_edges", "k_uf(h0)", "k_resolve_facets", "k_uf(top)", "k_output", "k_zero", "k_scatter"};
+    "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_output", "k_zero", "k_scatter"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -1674,8 +1698,11 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
         return PH_EINVAL;
-    for (int i = 0; i < n; ++i)
+    bool any2 = false, any3 = false;
+    for (int i = 0; i < n; ++i) {
         if (!valid_shape(h_shapes[i])) return PH_EINVAL;
+        (h_shapes[i].ndim == 3 ? any3 : any2) = true;
+    }
     if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
     int rc = device_luts();
     if (rc != PH_OK) return rc;
@@ -1723,11 +1750,14 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
     if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
     FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n));
-    FC_LAUNCH(K_RESOLVE_EDGES, hipLaunchKernelGGL(k_resolve_edges, dim3(rblocks, n), dim3(256), 0, st, ws, n));
-    FC_LAUNCH(K_UF_H0, hipLaunchKernelGGL(k_uf<false>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
-    if (flags & PH_HTOP) {
-        FC_LAUNCH(K_RESOLVE_FACETS, hipLaunchKernelGGL(k_resolve_facets, dim3(rblocks, n), dim3(256), 0, st, ws, n));
-        FC_LAUNCH(K_UF_TOP, hipLaunchKernelGGL(k_uf<true>, dim3(n), dim3(kUfThreads), 0, st, ws, n));
+    // volumes: the dual (resolve, union-find) beside H0; images: the dual after H0
+    const int htop = (flags & PH_HTOP) ? 1 : 0;
+    const unsigned side = htop && any3 ? 2 : 1;
+    FC_LAUNCH(K_RESOLVE, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n, side), dim3(256), 0, st, ws, n, 0, htop));
+    FC_LAUNCH(K_UF, hipLaunchKernelGGL(k_unionfind, dim3(n, side), dim3(kUfThreads), 0, st, ws, n, 0, htop));
+    if (htop && any2) {
+        FC_LAUNCH(K_RESOLVE_2D, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n), dim3(256), 0, st, ws, n, 1, htop));
+        FC_LAUNCH(K_UF_2D, hipLaunchKernelGGL(k_unionfind, dim3(n), dim3(kUfThreads), 0, st, ws, n, 1, htop));
     }
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
                                  d_status));
