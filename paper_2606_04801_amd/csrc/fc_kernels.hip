@@ -245,6 +245,26 @@ __device__ __forceinline__ int quad_slot(uint32_t q) {
     }
 }
 
+// 2 raw + (a < b), or with LE 2 raw + (a <= b), unsigned: the compare sets VCC and an add with
+// carry shifts it in (two vector instructions; compiled code takes a compare, a select and a
+// merge).  The nop gives the two wait states between a vector write of VCC and a vector read
+// of it.  The CPU emulation build of the kernels computes the same in C.
+template <bool LE>
+__device__ __forceinline__ uint32_t shift_in_less(uint32_t raw, uint32_t a, uint32_t b) {
+#if defined(__AMDGCN__)
+    uint32_t r;
+    if (LE)
+        asm("v_cmp_le_u32_e32 vcc, %1, %2\n\ts_nop 1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+            : "=v"(r) : "v"(a), "v"(b), "v"(raw) : "vcc");
+    else
+        asm("v_cmp_lt_u32_e32 vcc, %1, %2\n\ts_nop 1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+            : "=v"(r) : "v"(a), "v"(b), "v"(raw) : "vcc");
+    return r;
+#else
+    return raw + raw + (uint32_t)(LE ? a <= b : a < b);
+#endif
+}
+
 // v clamped into [0, hi]
 __device__ __forceinline__ int clamp0(int v, int hi) {
     const int a = v > 0 ? v : 0;
@@ -682,7 +702,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
                 const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
                 const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
                 const uint32_t kn = nb[((1 + dz) * KH + 1 + dy) * KW + 1 + dx];
-                raw = raw + raw + (uint32_t)(before ? kn <= kv : kn < kv);
+                raw = before ? shift_in_less<true>(raw, kn, kv) : shift_in_less<false>(raw, kn, kv);
             }
             // level 1 holds the canonical configuration for every raw square set; the cube
             // bits are compressed through its possible-cube mask one nibble at a time
