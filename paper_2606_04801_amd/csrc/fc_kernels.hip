@@ -681,6 +681,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
     constexpr uint64_t kValid = 1ull << 63;         // above every field of a 3D entry
     uint64_t ev[NIT];
     uint64_t packed = 0;              // minima | KEEP edges << 16 | KEEP squares << 32 | ROOT cubes << 48
+    bool bad = false;                 // a table index out of range (a corrupted table)
     // the 3x3x3 neighbourhood of vertex threadIdx.x + 256 it starts at skey[nb0 + it * kLayers * KH * KW]
     static_assert(256 % (TH * TW) == 0, "a block covers whole tile layers");
     constexpr int kLayers = 256 / (TH * TW);
@@ -691,36 +692,38 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
         const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
         const uint32_t *nb = skey + nb0 + it * kLayers * KH * KW;
-        uint64_t e = 0;
-        if (gz < D && gy < H && gx < W) {
-            const uint32_t kv = nb[(KH + 1) * KW + 1];
-            // bit code - 1 of raw: the neighbour at kOff[code] comes before v (ties by position);
-            // shifted in from the top code down
-            uint32_t raw = 0;
+        // branch-free, so the vertices of the thread form one scheduling region: a vertex
+        // outside the image (partial tiles) is computed on its clamped halo keys and dropped
+        const bool in = gz < D && gy < H && gx < W;
+        const uint32_t kv = nb[(KH + 1) * KW + 1];
+        // bit code - 1 of raw: the neighbour at kOff[code] comes before v (ties by position);
+        // shifted in from the top code down
+        uint32_t raw = 0;
 #pragma unroll
-            for (int code = 26; code >= 1; --code) {    // outside neighbours hold kOutside
-                const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
-                const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
-                const uint32_t kn = nb[((1 + dz) * KH + 1 + dy) * KW + 1 + dx];
-                raw = before ? shift_in_less<true>(raw, kn, kv) : shift_in_less<false>(raw, kn, kv);
-            }
-            // level 1 holds the canonical configuration for every raw square set; the cube
-            // bits are compressed through its possible-cube mask one nibble at a time
-            const uint32_t l1 = lut.l1[raw & (uint32_t)(kL1Size - 1)];
-            const uint32_t cb = raw >> 18;
-            const uint32_t lo = s_pext[((l1 & 15u) << 4) | (cb & 15u)];
-            const uint32_t hi = s_pext[(l1 & 0xF0u) | (cb >> 4)];
-            const uint32_t idx2 = (l1 >> 8) + lo + (hi << __popc(l1 & 15u));
-            e = kNoDirect;
-            if (idx2 < (uint32_t)kL3Configs) e = lut.l2[idx2];
-            else set_err(cnt, PH_EINTERNAL);
-            e |= kValid;
-            packed += (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((uint32_t)(e >> kL3Keep) & 63u) << 16) |
-                      ((uint64_t)__popc((uint32_t)(e >> kL3KeepSq) & 4095u) << 32) |
-                      ((uint64_t)__popc((uint32_t)(e >> kL3Root) & 255u) << 48);
+        for (int code = 26; code >= 1; --code) {        // outside neighbours hold kOutside
+            const int dz = kOff[code][0], dy = kOff[code][1], dx = kOff[code][2];
+            const bool before = dz < 0 || (dz == 0 && (dy < 0 || (dy == 0 && dx < 0)));
+            const uint32_t kn = nb[((1 + dz) * KH + 1 + dy) * KW + 1 + dx];
+            raw = before ? shift_in_less<true>(raw, kn, kv) : shift_in_less<false>(raw, kn, kv);
         }
+        // level 1 holds the canonical configuration for every raw square set; the cube bits
+        // are compressed through its possible-cube mask one nibble at a time
+        const uint32_t l1 = lut.l1[raw & (uint32_t)(kL1Size - 1)];
+        const uint32_t cb = raw >> 18;
+        const uint32_t lo = s_pext[((l1 & 15u) << 4) | (cb & 15u)];
+        const uint32_t hi = s_pext[(l1 & 0xF0u) | (cb >> 4)];
+        const uint32_t idx2 = (l1 >> 8) + lo + (hi << __popc(l1 & 15u));
+        const bool ok = idx2 < (uint32_t)kL3Configs;
+        bad |= in && !ok;
+        uint64_t e = lut.l2[ok ? idx2 : 0u];
+        e = in ? ((ok ? e : (uint64_t)kNoDirect) | kValid) : 0;
+        packed += in ? (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((uint32_t)(e >> kL3Keep) & 63u) << 16) |
+                           ((uint64_t)__popc((uint32_t)(e >> kL3KeepSq) & 4095u) << 32) |
+                           ((uint64_t)__popc((uint32_t)(e >> kL3Root) & 255u) << 48)
+                     : 0;
         ev[it] = e;
     }
+    if (bad) set_err(cnt, PH_EINTERNAL);
     const int lists[4] = {CNT_M0, CNT_E, CNT_F, CNT_MT};
     const uint64_t pre = block_alloc<4>(cnt, lists, packed, s_scan, s_base);
     int id0 = s_base[0] + (int)(pre & 0xFFFFu);
