@@ -464,19 +464,19 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
         const int l = threadIdx.x + it * 256;
         const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
         const uint32_t *nb = skey + nb0 + it * kRows * KW;
-        uint32_t e = 0;
-        if (gy < H && gx < W) {
-            const uint32_t kv = nb[KW + 1];
-            uint32_t mask = 0;
+        // branch-free (see the 3D kernel): a pixel outside the image is computed and dropped
+        const bool in = gy < H && gx < W;
+        const uint32_t kv = nb[KW + 1];
+        uint32_t mask = 0;                              // bit b: neighbour b comes before v
 #pragma unroll
-            for (int b = 0; b < 8; ++b) {               // outside neighbours hold kOutside
-                uint32_t kn = nb[(1 + NDY[b]) * KW + 1 + NDX[b]];
-                if (kn < kv || (kn == kv && NBEFORE[b])) mask |= 1u << b;
-            }
-            e = lut.l2d[mask] | kValid;
-            packed += (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((e >> kL2Keep) & 15u) << 16) |
-                      ((uint64_t)__popc((e >> kL2Root) & 15u) << 32);
+        for (int b = 7; b >= 0; --b) {                  // outside neighbours hold kOutside
+            const uint32_t kn = nb[(1 + NDY[b]) * KW + 1 + NDX[b]];
+            mask = NBEFORE[b] ? shift_in_less<true>(mask, kn, kv) : shift_in_less<false>(mask, kn, kv);
         }
+        const uint32_t e = in ? lut.l2d[mask] | kValid : 0u;
+        packed += in ? (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((e >> kL2Keep) & 15u) << 16) |
+                           ((uint64_t)__popc((e >> kL2Root) & 15u) << 32)
+                     : 0;
         ev[it] = e;
     }
     const int lists[3] = {CNT_M0, CNT_E, CNT_MT};
