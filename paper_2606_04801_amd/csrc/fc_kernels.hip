@@ -896,6 +896,53 @@ __device__ void bitonic_lds(uint64_t *s, int P) {
     }
 }
 
+__device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
+    const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m, 64);
+    const uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(x >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of s[0, P) ascending (P a power of two, 2 <= P <= 4 * blockDim.x; s holds
+// 4 * blockDim.x keys, padding included) by the whole block.  Thread t holds keys 4t .. 4t + 3
+// in registers.  A compare-exchange whose partner is in the same thread is done in registers,
+// in the same wave by lane shuffles, and only one in another wave goes through LDS: those
+// stages alternate between s and s2, with one barrier each.  On return x holds the thread's
+// four keys of the sorted sequence.  All threads of the block must call it.
+__device__ void bitonic_regs(uint64_t *s, uint64_t *s2, int P, uint64_t (&x)[4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) x[e] = s[4 * t + e];
+    bool flip = false;
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            uint64_t y[4];
+            if (j >= 256) {                          // partner in another wave
+                uint64_t *b = flip ? s2 : s;
+                flip = !flip;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) b[4 * t + e] = x[e];
+                lds_barrier();
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[e] = b[(4 * t + e) ^ j];
+            } else if (j >= 4) {                     // another lane of the wave
+#pragma unroll
+                for (int e = 0; e < 4; ++e) y[e] = shfl_xor64(x[e], j >> 2);
+            } else if (j == 2) {
+                y[0] = x[2]; y[1] = x[3]; y[2] = x[0]; y[3] = x[1];
+            } else {
+                y[0] = x[1]; y[1] = x[0]; y[2] = x[3]; y[3] = x[2];
+            }
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int i = 4 * t + e;
+                const bool keep_min = ((i & j) == 0) == ((i & k) == 0);
+                const bool lt = x[e] < y[e];
+                x[e] = keep_min == lt ? x[e] : y[e];
+            }
+        }
+    }
+}
+
 // Sort of one list of instance I (WHICH: 0 KEEP edges, 1 KEEP squares, 2 node keys), m keys,
 // by the whole block.  The list is a template argument, so each instantiation is straight-line
 // code: with the list chosen by a run-time argument, the gfx950 build of an earlier sort kernel
@@ -903,20 +950,24 @@ __device__ void bitonic_lds(uint64_t *s, int P) {
 // address, and loaded the count from near address 0.  The caller loads every count first.
 template <int WHICH>
 __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &I, int32_t *cnt, int m,
-                                          uint64_t *s) {
+                                          uint64_t *s, uint64_t *s2) {
     uint64_t *src = arr<uint64_t>(ws, WHICH == 0 ? I.o_keyE : (WHICH == 1 ? I.o_keyF : I.o_n0key));
     uint64_t *dst = WHICH == 2 ? arr<uint64_t>(ws, I.o_n0sorted) : src;
     const int64_t cap = WHICH == 0 ? I.E : (WHICH == 1 ? I.F : I.N);
     if (m > cap) { if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL); return; }
     if (m <= 0) return;
     if (m <= kSortCap) {
+        static_assert(kSortCap == 4 * kSortThreads, "four keys per thread");
         int P = 2;
         while (P < m) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += blockDim.x) s[t] = t < m ? src[t] : ~0ull;
+        for (int t = threadIdx.x; t < kSortCap; t += blockDim.x) s[t] = t < m ? src[t] : ~0ull;
         __syncthreads();
-        bitonic_lds(s, P);
-        for (int t = threadIdx.x; t < m; t += blockDim.x) dst[t] = s[t];
-        __syncthreads();                         // s is free for the caller's next sort
+        uint64_t x[4];
+        bitonic_regs(s, s2, P, x);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * (int)threadIdx.x + e < m) dst[4 * threadIdx.x + e] = x[e];
+        __syncthreads();                         // s, s2 are free for the caller's next sort
         return;
     }
     // long list: chunks in LDS, then merge passes dst <-> scratch
@@ -964,6 +1015,7 @@ __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &
 // sorts all three in turn and the other two leave.
 __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict__ ws, int n) {
     __shared__ uint64_t s[kSortCap];
+    __shared__ uint64_t s2[kSortCap];
     const int i = blockIdx.x, w = blockIdx.y;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -971,14 +1023,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
     const int mE = cnt[CNT_E], mF = cnt[CNT_F], mN = cnt[CNT_M0];
     const bool serial = mE > kSortCap || mF > kSortCap || mN > kSortCap;
     if (w == 0) {
-        sort_list<0>(ws, I, cnt, mE, s);
+        sort_list<0>(ws, I, cnt, mE, s, s2);
         if (serial) {
-            sort_list<1>(ws, I, cnt, mF, s);
-            sort_list<2>(ws, I, cnt, mN, s);
+            sort_list<1>(ws, I, cnt, mF, s, s2);
+            sort_list<2>(ws, I, cnt, mN, s, s2);
         }
     } else if (!serial) {
-        if (w == 1) sort_list<1>(ws, I, cnt, mF, s);
-        else sort_list<2>(ws, I, cnt, mN, s);
+        if (w == 1) sort_list<1>(ws, I, cnt, mF, s, s2);
+        else sort_list<2>(ws, I, cnt, mN, s, s2);
     }
 }
 

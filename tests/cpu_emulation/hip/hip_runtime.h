@@ -279,6 +279,7 @@ EMU_FN int __shfl_up(int v, int d, int = 64) {
     return (int)emu_read_lane(v, l - d < 0 ? l : l - d);
 }
 EMU_FN int __shfl(int v, int src, int = 64) { return (int)emu_read_lane(v, src & 63); }
+EMU_FN int __shfl_xor(int v, int m, int = 64) { return (int)emu_read_lane(v, (__lane_id() ^ m) & 63); }
 EMU_FN unsigned long long __ballot(int pred) {
     EmuBlock *b = emu_block;
     EmuBarrier &w = b->wave_bar[emu_wave()];
