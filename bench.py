@@ -405,6 +405,35 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
         tj = json.load(open(args.traffic_json))
         if tj.get("_library_sha256") == library_sha256():
             traffic = tj.get(name)
+    # the same instances quantised to 256 levels and read as uint8 (PH_IN_U8), checked bit for
+    # bit against the float32 path on the same values, then timed like the batched form
+    print("bench: batched forward + backward, uint8 input (graph replay)", file=sys.stderr, flush=True)
+    q8 = [torch.from_numpy(np.round(a * 255.0).astype(np.uint8)) for a in imgs]
+    sz = fc.Batch(shapes, device=dev)
+    sz.set_images([q.float() for q in q8])
+    batched_step(sz)
+    sync()
+    ref8 = sz.results()
+    gref8 = sz.grad.cpu().numpy().copy()
+    caps8 = sz.counts.cpu().numpy().tolist()
+    del sz
+    b8 = []
+    for _ in range(2):
+        b = fc.Batch(shapes, device=dev, capacities=caps8, dtype=torch.uint8)
+        b.set_images(q8)
+        b8.append(b)
+    batched_step(b8[0])
+    sync()
+    for i, r in enumerate(b8[0].results()):
+        if not same_bits(r, ref8[i]):
+            raise SystemExit("bench: uint8 and float32 inputs give different diagrams on instance %d" % i)
+    if not np.array_equal(b8[0].grad.cpu().numpy(), gref8):
+        raise SystemExit("bench: uint8 and float32 inputs give different gradients")
+    g_8 = [capture(lambda b=b: batched_step(b)) for b in b8]
+    t_8 = timed(lambda k: g_8[k % 2]())
+    for b in b8:
+        b.check()
+
     nvox = sum(int(np.prod(s)) for s in shapes)
     sb = step_bytes(prof.keys(), wc, npairs, shapes)
     fb = sb - algorithmic_bytes("k_zero", wc, npairs, shapes) - algorithmic_bytes("k_scatter", wc, npairs, shapes)
@@ -416,6 +445,8 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
             "batched_fwd_bwd": {"value": round(nvox / t_b / 1e6, 3), "ms": round(t_b * 1e3, 4), "hbm_frac": frac(sb, t_b)},
             "batched_fwd": {"value": round(nvox / t_f / 1e6, 3), "ms": round(t_f * 1e3, 4), "hbm_frac": frac(fb, t_f)},
             "per_image_fwd_bwd": {"value": round(nvox / t_p / 1e6, 3), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p)},
+            "batched_fwd_bwd_u8": {"value": round(nvox / t_8 / 1e6, 3), "ms": round(t_8 * 1e3, 4),
+                                   "input": "the same instances quantised to 256 levels, uint8"},
         },
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},

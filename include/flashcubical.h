@@ -61,8 +61,12 @@ enum {
     PH_EINTERNAL = -6
 };
 
-/* flags: which dimensions to report (H0 is always computed; 2D needs it for the top). */
-enum { PH_H0 = 1, PH_HTOP = 2 };
+/* flags: which dimensions to report (H0 is always computed; 2D needs it for the top), and the
+ * element type of the input (float32 unless one of PH_IN_U8, PH_IN_U16 is set; setting both
+ * is PH_EINVAL).  An integer input gives bitwise the results of the same values as float32
+ * (every 8- and 16-bit integer is exactly a float32); it reads 1 or 2 bytes per voxel and
+ * always uses the default tiles. */
+enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8 };
 
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
@@ -98,26 +102,27 @@ int64_t ph_capacity_bound(ph_shape shape);
 size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags);
 
 /* Persistence diagram of one image or volume (Sec. 4.1 / Sec. 4.2 steps 1-3).
- *   d_img     : device, row-major float32 pixels of `shape`.
+ *   d_img     : device, row-major pixels of `shape`, of the element type the flags name.
  *   out       : device SoA arrays with room for `capacity` pairs.
  *   d_count   : device int64, receives the number of pairs (even beyond capacity).
  *   d_status  : device int32, receives PH_OK or a kernel-detected error.
  *   d_ws      : device workspace of ws_bytes >= ph_workspace_bytes(&shape, 1, flags).
  * Returns PH_OK when the work was enqueued. */
-int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
+int ph_diagram(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
                int64_t capacity, int64_t *d_count, int32_t *d_status, void *d_ws,
                size_t ws_bytes, void *stream);
 
 /* Diagrams of n instances (1 <= n <= 65535) of uneven sizes and mixed 2D/3D in one set of launches:
  * persistent kernels walk a per-instance table built on the device from d_shapes.
- *   d_imgs     : all pixels concatenated; instance i starts at element d_img_off[i].
+ *   d_imgs     : all pixels concatenated (element type as the flags name); instance i
+ *                starts at element d_img_off[i].
  *   d_shapes   : device copy of h_shapes (n entries); h_shapes sizes the launch grids.
  *   out        : shared SoA output; instance i writes from element d_out_off[i] and has
  *                capacity d_out_off[i+1] - d_out_off[i] (d_out_off has n+1 entries).
  *   d_counts, d_status : n entries each.
  *   tuning     : NULL = default/autotuned tiles.
  * The pairs of each instance are bitwise those of a single ph_diagram call on it. */
-int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off,
+int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off,
                      const ph_shape *d_shapes, const ph_shape *h_shapes, uint32_t flags,
                      ph_pairs out, const int64_t *d_out_off, int64_t *d_counts,
                      int32_t *d_status, const ph_tuning *tuning, void *d_ws, size_t ws_bytes,
@@ -130,7 +135,7 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off,
  * later ph_diagram_batch calls with tuning == NULL in that class use it.  Arguments as for
  * ph_diagram_batch; the outputs hold the last run's results.  Waits for the stream (not for
  * use during graph capture).  Tile choices never change results, only speed. */
-int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
                 ph_tuning *best, void *stream);

@@ -25,6 +25,7 @@ LIB_PATH = os.path.join(_HERE, "libflashcubical.so")
 
 PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 PH_H0, PH_HTOP = 1, 2
+PH_IN_U8, PH_IN_U16 = 4, 8          # input element type (float32 when neither is set)
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
                 -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
 
@@ -256,13 +257,16 @@ _default_ws = Workspace()
 
 def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, ws: Workspace | None = None,
                stream=None) -> Diagram:
-    """Persistence diagram of one float32 image (H, W) or volume (D, H, W) on the GPU."""
+    """Persistence diagram of one image (H, W) or volume (D, H, W) on the GPU: float32, or
+    uint8 / uint16 (read as such, results those of the same values as float32)."""
     torch = _torch()
     # a host tensor would hand the kernels a host pointer; without a GPU the library itself
     # reports that it cannot run, so the check only matters when one is present
     on_device = img.is_cuda or not torch.cuda.is_available()
-    if not (on_device and img.dtype == torch.float32 and img.dim() in (2, 3)):
-        raise PHError(PH_EINVAL, "ph_diagram expects a 2D/3D float32 CUDA tensor")
+    kinds = _input_flags()
+    if not (on_device and img.dtype in kinds and img.dim() in (2, 3)):
+        raise PHError(PH_EINVAL, "ph_diagram expects a 2D/3D float32, uint8 or uint16 CUDA tensor")
+    flags = (int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[img.dtype]
     img = img.contiguous()
     shp = make_shape(img.shape)
     cap = capacity_bound(img.shape) if capacity is None else int(capacity)
@@ -278,6 +282,11 @@ def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, w
     return Diagram(bufs, count, status, img.shape)
 
 
+def _input_flags():
+    torch = _torch()
+    return {torch.float32: 0, torch.uint8: PH_IN_U8, torch.uint16: PH_IN_U16}
+
+
 def ph_backward(bufs: PairBuffers, counts, out_off, img_off, grad_birth, grad_death, grad_img, stream=None):
     """Scatter dL/dbirth, dL/ddeath into grad_img (overwritten) -- C ABI ph_backward."""
     n = int(counts.numel())
@@ -290,16 +299,24 @@ def ph_backward(bufs: PairBuffers, counts, out_off, img_off, grad_birth, grad_de
 class Batch:
     """Buffers and launches for a fixed list of instance shapes (2D and 3D may be mixed).
 
-    Inputs live in one packed float32 buffer (`images`), outputs in one SoA buffer with a
+    Inputs live in one packed buffer (`images`) of the batch's element type (float32, uint8
+    or uint16), outputs in one SoA buffer with a
     per-instance capacity of pixels + top cells, so nothing depends on the host between
     launches and the forward + backward pair can be captured in a HIP graph.
     """
 
-    def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda", capacities=None):
+    def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda", capacities=None,
+                 dtype=None):
         """capacities: pairs stored per instance (default: the bound pixels + top cells, which
         never overflows); a smaller one, e.g. the counts of an earlier call on the same
-        inputs, keeps the pair buffers small."""
+        inputs, keeps the pair buffers small.  dtype: element type of the inputs (float32,
+        uint8 or uint16; integer inputs use the default tiles)."""
         torch = _torch()
+        self.dtype = torch.float32 if dtype is None else dtype
+        kinds = _input_flags()
+        if self.dtype not in kinds:
+            raise PHError(PH_EINVAL, "Batch dtype must be float32, uint8 or uint16")
+        flags = (int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[self.dtype]
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
         self.n = len(self.shapes)
         self.flags = flags
@@ -319,7 +336,7 @@ class Batch:
         self.d_shapes = torch.from_numpy(d).to(self.device)
         self.img_off = torch.from_numpy(self.img_off_h[:-1].copy()).to(self.device)
         self.out_off = torch.from_numpy(self.out_off_h).to(self.device)
-        self.images = torch.zeros(self.total_voxels, dtype=torch.float32, device=self.device)
+        self.images = torch.zeros(self.total_voxels, dtype=self.dtype, device=self.device)
         self.grad = torch.zeros(self.total_voxels, dtype=torch.float32, device=self.device)
         self.pairs = PairBuffers(int(self.out_off_h[-1]), self.device)
         self.counts = torch.zeros(self.n, dtype=torch.int64, device=self.device)
@@ -331,7 +348,7 @@ class Batch:
     def set_images(self, imgs):
         torch = _torch()
         for i, a in enumerate(imgs):
-            t = torch.as_tensor(a, dtype=torch.float32).reshape(-1)
+            t = torch.as_tensor(a).to(self.dtype).reshape(-1)
             self.images[self.img_off_h[i]:self.img_off_h[i + 1]].copy_(t, non_blocking=False)
 
     def image(self, i):

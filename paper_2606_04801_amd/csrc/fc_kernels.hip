@@ -369,8 +369,8 @@ __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[
 }
 
 // ================================================================ classify 2D ====
-template <int TW, int TH>
-__global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ imgs,
+template <int TW, int TH, typename T>
+__global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, PW = TW + 1, NP = (TH + 1) * (TW + 1);
@@ -397,7 +397,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
     const int y0 = ty * TH, x0 = tx * TW;
-    const float *img = imgs + I.img_off;
+    const T *img = imgs + I.img_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
     uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
             const int l = threadIdx.x + 256 * k;
             const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
             const int cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy), cx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
-            f[k] = img[(int64_t)cy * W + cx];
+            f[k] = (float)img[(int64_t)cy * W + cx];
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
@@ -581,8 +581,8 @@ __global__ __launch_bounds__(256) void k_classify2d(const float *__restrict__ im
 // ================================================================ classify 3D ====
 // 256 threads, at least seven workgroups (28 waves) per compute unit: the register budget
 // (72) costs a few spilled registers, cheaper than losing a wave per SIMD
-template <int TW, int TH, int TD>
-__global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__ imgs,
+template <int TW, int TH, int TD, typename T>
+__global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
@@ -616,7 +616,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
     const int ty = rem / I.tx, tx = rem - ty * I.tx;
     const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
-    const float *img = imgs + I.img_off;
+    const T *img = imgs + I.img_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
     uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
@@ -645,7 +645,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const float *__restrict__
         for (int k = 0; k < NL; ++k) {
             const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
             const int cz = clamp0(gz, D - 1), cy = clamp0(gy, H - 1);
-            f[k] = img[(uint32_t)(cz * (int)HW + cy * W + cx)];
+            f[k] = (float)img[(uint32_t)(cz * (int)HW + cy * W + cx)];
             if (inx && (unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H) inside |= 1u << k;
             yy += kGroups % KH;
             zz += kGroups / KH;
@@ -1363,7 +1363,7 @@ __device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code
     return (Z * (2 * (int64_t)I.H - 1) + Y) * (2 * (int64_t)I.W - 1) + X;
 }
 
-__global__ __launch_bounds__(kUfThreads) void k_output(const float *__restrict__ imgs,
+__global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ imgs,
                                                       uint8_t *__restrict__ ws, int n, uint32_t flags,
                                                       ph_pairs out, int64_t *__restrict__ d_counts,
                                                       int32_t *__restrict__ d_status) {
@@ -1371,7 +1371,13 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const float *__restrict__
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    const float *img = imgs + I.img_off;
+    // pixel value as float32, from an input of the element type the flags name
+    auto img = [&](int64_t p) -> float {
+        const int64_t q = I.img_off + p;
+        if (flags & PH_IN_U8) return (float)((const uint8_t *)imgs)[q];
+        if (flags & PH_IN_U16) return (float)((const uint16_t *)imgs)[q];
+        return ((const float *)imgs)[q];
+    };
     const int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     const int32_t *death0 = arr<int32_t>(ws, I.o_death0);
     const int32_t *killer = arr<int32_t>(ws, I.o_killer);
@@ -1398,8 +1404,8 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const float *__restrict__
         if (pos >= cap) return;
         const int64_t j = o + pos;
         out.dim[j] = (int8_t)dim;
-        out.birth[j] = img[bpix];
-        out.death[j] = dpix >= 0 ? img[dpix] : __int_as_float(0x7f800000);
+        out.birth[j] = img(bpix);
+        out.death[j] = dpix >= 0 ? img(dpix) : __int_as_float(0x7f800000);
         out.birth_cell[j] = bc;
         out.death_cell[j] = dc;
         out.birth_vertex[j] = bpix;
@@ -1541,12 +1547,16 @@ bool hip_ok(hipError_t e, const char *what) {
 int check_kernels(int dev, char *report, size_t len) {
     const KInfo ks[] = {
         {"k_plan", (const void *)k_plan, kPlanThreads},
-        {"k_classify2d<64,16>", (const void *)k_classify2d<64, 16>, 256},
-        {"k_classify2d<32,32>", (const void *)k_classify2d<32, 32>, 256},
-        {"k_classify2d<128,8>", (const void *)k_classify2d<128, 8>, 256},
-        {"k_classify3d<16,8,8>", (const void *)k_classify3d<16, 8, 8>, 256},
-        {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4>, 256},
-        {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16>, 256},
+        {"k_classify2d<64,16>", (const void *)k_classify2d<64, 16, float>, 256},
+        {"k_classify2d<32,32>", (const void *)k_classify2d<32, 32, float>, 256},
+        {"k_classify2d<128,8>", (const void *)k_classify2d<128, 8, float>, 256},
+        {"k_classify2d<64,16,u8>", (const void *)k_classify2d<64, 16, uint8_t>, 256},
+        {"k_classify2d<64,16,u16>", (const void *)k_classify2d<64, 16, uint16_t>, 256},
+        {"k_classify3d<16,8,8>", (const void *)k_classify3d<16, 8, 8, float>, 256},
+        {"k_classify3d<32,8,4>", (const void *)k_classify3d<32, 8, 4, float>, 256},
+        {"k_classify3d<8,8,16>", (const void *)k_classify3d<8, 8, 16, float>, 256},
+        {"k_classify3d<16,8,8,u8>", (const void *)k_classify3d<16, 8, 8, uint8_t>, 256},
+        {"k_classify3d<16,8,8,u16>", (const void *)k_classify3d<16, 8, 8, uint16_t>, 256},
         {"k_sort_lists", (const void *)k_sort_lists, kSortThreads},
         {"k_resolve", (const void *)k_resolve, 256},
         {"k_unionfind", (const void *)k_unionfind, kUfThreads},
@@ -1657,13 +1667,13 @@ int64_t max_list(const ph_shape *h, int n) {
     return m;
 }
 
-template <int A, int B>
-void launch2d(int64_t tiles, const float *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify2d<A, B>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n, lut);
+template <int A, int B, typename T = float>
+void launch2d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify2d<A, B, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
 }
-template <int A, int B, int C>
-void launch3d(int64_t tiles, const float *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify3d<A, B, C>), dim3((unsigned)tiles), dim3(256), 0, st, imgs, ws, n, lut);
+template <int A, int B, int C, typename T = float>
+void launch3d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
+    hipLaunchKernelGGL((k_classify3d<A, B, C, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
 }
 
 Luts current_luts() {
@@ -1765,7 +1775,7 @@ int trace_after(int kid, hipStream_t st) {
     return e == hipSuccess ? PH_OK : PH_EHIP;
 }
 
-int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
         const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
         const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
         const ph_tuning *tuning, void *d_ws, size_t ws_bytes, hipStream_t st) {
@@ -1779,6 +1789,9 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
         (h_shapes[i].ndim == 3 ? any3 : any2) = true;
     }
     if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
+    if ((flags & PH_IN_U8) && (flags & PH_IN_U16)) return PH_EINVAL;
+    const int elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
+    if (elem != 0) tuning = nullptr;               // integer inputs use the default tiles
     int rc = device_luts();
     if (rc != PH_OK) return rc;
     const Tiles tl = tiles_of(tuning);
@@ -1809,12 +1822,16 @@ int run(int n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
     const Luts lut = current_luts();
     if (t2 > 0) {
-        if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, d_imgs, ws, n, lut, st)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint16_t>(t2, d_imgs, ws, n, lut, st)));
+        else if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
         else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, d_imgs, ws, n, lut, st));
         else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, d_imgs, ws, n, lut, st));
     }
     if (t3 > 0) {
-        if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, d_imgs, ws, n, lut, st)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, d_imgs, ws, n, lut, st)));
+        else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
         else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
         else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
     }
@@ -1868,14 +1885,14 @@ size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
     return (size_t)best;
 }
 
-int ph_diagram(const float *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
+int ph_diagram(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
                int64_t *d_count, int32_t *d_status, void *d_ws, size_t ws_bytes, void *stream) {
     if (capacity < 0) return PH_EINVAL;
     return fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
                    d_status, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
-int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                      const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                      int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
                      size_t ws_bytes, void *stream) {
@@ -1887,7 +1904,7 @@ int ph_diagram_batch(int32_t n, const float *d_imgs, const int64_t *d_img_off, c
                    d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
-int ph_autotune(int32_t n, const float *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
                 ph_tuning *best, void *stream) {

@@ -426,6 +426,10 @@ VALU1 = {   # D = f(S0)
     "v_not_b32": lambda a: ~vec(a),
     "v_bfrev_b32": lambda a: _brev32(vec(a)),
     "v_cvt_f32_u32": lambda a: bits(vec(a).astype(np.float64).astype(F32)),
+    "v_cvt_f32_ubyte0": lambda a: bits((vec(a) & U32(0xFF)).astype(F32)),
+    "v_cvt_f32_ubyte1": lambda a: bits(((vec(a) >> U32(8)) & U32(0xFF)).astype(F32)),
+    "v_cvt_f32_ubyte2": lambda a: bits(((vec(a) >> U32(16)) & U32(0xFF)).astype(F32)),
+    "v_cvt_f32_ubyte3": lambda a: bits((vec(a) >> U32(24)).astype(F32)),
     "v_cvt_f32_i32": lambda a: bits(s32(a).astype(np.float64).astype(F32)),
     "v_cvt_u32_f32": _cvt_u32_f32,
     "v_rcp_iflag_f32": _rcp,
@@ -1066,6 +1070,14 @@ def _compile_sdwa(op, O, mods, nxt):
             dst(w, mask_of(c(val(_sdwa_sel(a(w), s0, x0)), val(_sdwa_sel(b(w), s1, x1))) & w.exec()))
             return nxt
         return f
+    if op in VALU1 and len(O) == 2:
+        # one source with an operand select, written whole (dst_sel DWORD only)
+        f1 = VALU1[op]
+        a1, s01, x01 = r32(O[1]), mods.get("src0_sel", "DWORD"), O[1].sext
+        if mods.get("dst_sel", "DWORD") != "DWORD":
+            raise Unsupported("sdwa dst_sel for " + op)
+        w1 = wv(O[0])
+        return lambda w: (w1(w, vec(f1(_sdwa_sel(a1(w), s01, x01)))), nxt)[1]
     fn = VALU2.get(op)
     if fn is None:
         raise Unsupported("sdwa op " + op)

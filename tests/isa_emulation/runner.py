@@ -47,6 +47,15 @@ PAIR_FIELDS = [("dim", np.int8), ("birth", np.float32), ("death", np.float32), (
                ("death_cell", np.int64), ("birth_vertex", np.int32), ("death_vertex", np.int32)]
 
 
+IN_FLAGS = {np.dtype(np.float32): 0, np.dtype(np.uint8): 4, np.dtype(np.uint16): 8}   # PH_IN_U8, PH_IN_U16
+
+
+def as_input(a):
+    """the array in its input element type: uint8 and uint16 stay, anything else is float32"""
+    a = np.ascontiguousarray(a)
+    return a if a.dtype in (np.uint8, np.uint16) else a.astype(np.float32)
+
+
 def make_shape(shape):
     ext = list(shape) + [0] * (3 - len(shape))
     return ph_shape(len(shape), (ctypes.c_int32 * 3)(*ext))
@@ -151,7 +160,8 @@ class IsaRunner:
     # -------------------------------------------------------------- entry points --
     def diagram(self, img: np.ndarray, capacity: int | None = None):
         """(pairs, status, count) of ph_diagram on one image or volume"""
-        img = self.dev(np.ascontiguousarray(img, dtype=np.float32))
+        img = self.dev(as_input(img))
+        flags = 3 | IN_FLAGS[img.dtype]
         shp = make_shape(img.shape)
         cap = int(self.host.ph_capacity_bound(shp)) if capacity is None else capacity
         bufs, pr = self._pairs(cap)
@@ -159,7 +169,7 @@ class IsaRunner:
         status = self.dev(np.full(1, -77, np.int32))
         nb = int(self.host.ph_workspace_bytes(ctypes.byref(shp), 1, 3))
         ws = self.dev(np.frombuffer(np.random.default_rng(5).bytes(nb), np.uint8).copy())
-        rc = self.host.ph_diagram(img.ctypes.data, shp, 3, pr, cap, count.ctypes.data, status.ctypes.data,
+        rc = self.host.ph_diagram(img.ctypes.data, shp, flags, pr, cap, count.ctypes.data, status.ctypes.data,
                                   ws.ctypes.data, nb, None)
         self._check(rc, "ph_diagram")
         n = int(count[0])
@@ -170,7 +180,9 @@ class IsaRunner:
     def batch(self, imgs, tuning=None, backward=False):
         """per-instance (pairs, status) of ph_diagram_batch, and the gradient of the loss sum
         over finite pairs of (death - birth)^2 from ph_backward when asked"""
-        imgs = [np.ascontiguousarray(a, dtype=np.float32) for a in imgs]
+        imgs = [as_input(a) for a in imgs]
+        assert len({a.dtype for a in imgs}) == 1, "one element type per batch"
+        flags = 3 | IN_FLAGS[imgs[0].dtype]
         n = len(imgs)
         shapes = (ph_shape * n)(*[make_shape(a.shape) for a in imgs])
         sizes = [a.size for a in imgs]
@@ -187,7 +199,7 @@ class IsaRunner:
         nb = int(self.host.ph_workspace_bytes(shapes, n, 3))
         ws = self.dev(np.frombuffer(np.random.default_rng(6).bytes(nb), np.uint8).copy())
         tp = ctypes.byref(ph_tuning(*tuning)) if tuning is not None else None
-        rc = self.host.ph_diagram_batch(n, flat.ctypes.data, d_img_off.ctypes.data, d_shapes.ctypes.data, shapes, 3, pr,
+        rc = self.host.ph_diagram_batch(n, flat.ctypes.data, d_img_off.ctypes.data, d_shapes.ctypes.data, shapes, flags, pr,
                                         d_out_off.ctypes.data, counts.ctypes.data, status.ctypes.data, tp,
                                         ws.ctypes.data, nb, None)
         self._check(rc, "ph_diagram_batch")

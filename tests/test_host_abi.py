@@ -135,3 +135,16 @@ def test_library_loaded_before_torch_still_shares_its_runtime():
             "print(len(fc._hip_runtimes()))" % ROOT)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0 and r.stdout.strip().splitlines()[-1] in ("0", "1"), r.stdout + r.stderr[-2000:]
+
+
+def test_both_integer_input_flags_rejected():
+    """PH_IN_U8 with PH_IN_U16 names no element type: refused on the host, before any device
+    call (the pointers are never dereferenced)."""
+    L = fc.lib()
+    one = ctypes.c_void_p(1)
+    pr = fc.ph_pairs(one, one, one, one, one, one, one)
+    flags = fc.PH_H0 | fc.PH_HTOP | fc.PH_IN_U8 | fc.PH_IN_U16
+    assert L.ph_diagram(one, fc.make_shape((4, 4)), flags, pr, 16, one, one, one, 1 << 20, None) == fc.PH_EINVAL
+    sh = (fc.ph_shape * 1)(fc.make_shape((4, 4)))
+    assert L.ph_diagram_batch(1, one, one, one, sh, flags, pr, one, one, one, None, one, 1 << 20,
+                              None) == fc.PH_EINVAL

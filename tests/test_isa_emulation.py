@@ -126,3 +126,26 @@ def test_interpreter_covers_every_instruction(isa):
         except (Unsupported, IndexError, ValueError, KeyError) as e:
             missing.setdefault(isa.prog.text[pc].split()[0], "%s: %s" % (type(e).__name__, e))
     assert not missing, missing
+
+
+def test_integer_inputs(isa):
+    """uint8 and uint16 inputs (PH_IN_U8, PH_IN_U16) give the oracle's pairs of the same
+    values as float32; the coarse 7-level copies are dense in ties."""
+    for shape, sigma in (((48, 40), 2.0), ((12, 10, 14), 1.5)):
+        g = S.grf(shape, sigma, 77)
+        for dt, levels in ((np.uint8, 255), (np.uint16, 65535), (np.uint8, 7)):
+            q = np.round(g * levels).astype(dt)
+            got, st, _ = isa.diagram(q)
+            assert st == 0 and diff_pairs(got, oracle.diagram(q.astype(np.float32))) is None, (shape, dt, levels)
+    imgs = [np.round(S.grf((20, 21), 2.0, 5) * 9).astype(np.uint16),
+            np.round(S.grf((6, 7, 8), 1.2, 6) * 9).astype(np.uint16)]
+    res, grad = isa.batch(imgs, backward=True)
+    off = 0
+    for img, (got, st) in zip(imgs, res):
+        ref = oracle.diagram(img.astype(np.float32))
+        assert st == 0 and diff_pairs(got, ref) is None, img.shape
+        f = ref["death_cell"] >= 0
+        d = np.where(f, ref["death"] - ref["birth"], 0).astype(np.float32)
+        g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
+        np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
+        off += img.size
