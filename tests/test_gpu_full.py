@@ -66,6 +66,17 @@ def test_single_full_size(cfg):
     check_digest(cfg, idx, img, gpu(img))
 
 
+@full_size
+def test_c2u8_through_the_uint8_input_path():
+    """Config 2's 256-level copy read as uint8 (PH_IN_U8) gives the stored digest of the same
+    values as float32."""
+    (_, idx, kind, args), = items("c2u8")
+    img = make(kind, args)
+    q = img.astype(np.uint8)
+    assert np.array_equal(q.astype(np.float32), img)            # the copy holds integers 0..255
+    check_digest("c2u8", idx, img, gpu(q))
+
+
 def run_batch(imgs, tuning=None, autotune=False):
     bt = fc.Batch([a.shape for a in imgs], tuning=tuning, device=DEV)
     bt.set_images([torch.from_numpy(a) for a in imgs])
