@@ -28,7 +28,9 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    out_tmp = LIB + ".tmp%d" % os.getpid()
+    # a fixed command line: clang names the library's device-code symbols with a hash of it, so
+    # the same sources give the same library bytes (profiles/ figures are tied to that digest)
+    out_tmp = LIB + ".tmp"
     cmd = [hipcc(), "--offload-arch=%s" % ARCH, "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC, "-Wall", "-Wno-unused-function",
