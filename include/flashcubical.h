@@ -134,7 +134,9 @@ int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off,
  * (which dimensions it holds and the binary order of magnitude of its mean instance size):
  * later ph_diagram_batch calls with tuning == NULL in that class use it.  Arguments as for
  * ph_diagram_batch; the outputs hold the last run's results.  Waits for the stream (not for
- * use during graph capture).  Tile choices never change results, only speed. */
+ * use during graph capture).  Tile choices never change results, only speed.  With an integer
+ * input (PH_IN_U8, PH_IN_U16) it runs the batch once on the default tiles, writes those to
+ * *best and records nothing. */
 int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,

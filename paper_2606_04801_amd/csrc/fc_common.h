@@ -182,7 +182,7 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_ufT = take(4 * (T + 1));
     I.o_moeT = take(4 * (T + 1));
     I.o_live = take(4 * L);
-    I.o_live2 = take(4 * L);
+    I.o_live2 = take(4 * L);          // the dual's live edges (it runs beside H0 in volumes)
     I.o_ra = take(4 * L);
     I.o_rb = take(4 * L);
     I.o_scratch = take(8 * SCR);

@@ -1909,6 +1909,14 @@ int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const p
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
                 ph_tuning *best, void *stream) {
     if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1 || reps < 1 || !best) return PH_EINVAL;
+    ph_shape dummy0{2, {1, 1, 1}};
+    if (flags & (PH_IN_U8 | PH_IN_U16)) {
+        // integer inputs always take the default tiles: nothing to time, nothing recorded for
+        // the size class (float32 batches of the class keep their own choice)
+        *best = ph_tuning{0, 0};
+        return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy0, flags, out, d_out_off, 0, d_counts,
+                       d_status, best, d_ws, ws_bytes, (hipStream_t)stream);
+    }
     const fc::SizeClass cls = fc::size_class(h_shapes, n);
     const int n2 = std::get<0>(cls) ? 3 : 1, n3 = std::get<1>(cls) ? 3 : 1;
     hipStream_t st = (hipStream_t)stream;

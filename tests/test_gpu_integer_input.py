@@ -59,3 +59,16 @@ def test_integer_batch_with_backward(dt, levels):
     assert np.array_equal(gf, gi)
     for k in (2, 3):                                    # the small ones against the oracle too
         assert diff_pairs(ri[k], oracle.diagram(qs[k].astype(np.float32))) is None, shapes[k]
+
+
+def test_autotune_with_integer_input_keeps_defaults():
+    """An integer batch always runs the default tiles: ph_autotune returns them, the results
+    are the oracle's, and nothing is recorded for the size class."""
+    shapes = [(64, 80), (12, 10, 14)]
+    qs = [np.round(S.grf(s, 2.0, 300 + k) * 255).astype(np.uint8) for k, s in enumerate(shapes)]
+    bt = fc.Batch(shapes, device=DEV, dtype=torch.uint8)
+    bt.set_images([torch.from_numpy(q) for q in qs])
+    assert bt.ph_autotune(reps=1) == (0, 0)
+    torch.cuda.synchronize()
+    for q, got in zip(qs, bt.results()):
+        assert diff_pairs(got, oracle.diagram(q.astype(np.float32))) is None, q.shape
