@@ -19,7 +19,8 @@ def extract(so_path: str, arch: str = "gfx950") -> str:
     """Path of the unbundled gfx950 code object of a HIP shared library (in a temp dir)."""
     d = tempfile.mkdtemp(prefix="fc_co_")
     fb, co = os.path.join(d, "fatbin"), os.path.join(d, arch + ".co")
-    _run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section=.hip_fatbin=" + fb, so_path])
+    # an explicit output: without one llvm-objcopy rewrites its input in place
+    _run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section=.hip_fatbin=" + fb, so_path, os.path.join(d, "copy.so")])
     _run([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o", "--input=" + fb,
           "--targets=hipv4-amdgcn-amd-amdhsa--" + arch, "--output=" + co])
     return co

@@ -28,8 +28,9 @@ FORBIDDEN = [
 def code_object():
     d = tempfile.mkdtemp()
     fb, co = os.path.join(d, "fatbin"), os.path.join(d, "gfx950.co")
-    subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section=.hip_fatbin=" + fb, fc.LIB_PATH],
-                   check=True, capture_output=True)
+    # an explicit output: without one llvm-objcopy rewrites the library in place
+    subprocess.run([os.path.join(LLVM, "llvm-objcopy"), "--dump-section=.hip_fatbin=" + fb, fc.LIB_PATH,
+                    os.path.join(d, "copy.so")], check=True, capture_output=True)
     subprocess.run([os.path.join(LLVM, "clang-offload-bundler"), "--unbundle", "--type=o", "--input=" + fb,
                     "--targets=hipv4-amdgcn-amd-amdhsa--gfx950", "--output=" + co], check=True, capture_output=True)
     yield co
