@@ -1,4 +1,4 @@
-"""CPU oracle for V-filtration cubical persistence over F2 -- TEST INFRASTRUCTURE ONLY.
+"""CPU oracle for V- and T-filtration cubical persistence over F2 -- TEST INFRASTRUCTURE ONLY.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py``
 may import this package.  The GPU library never links, loads or calls it, and it shares no
@@ -11,6 +11,11 @@ code with that library.
     then dimension, then doubled-grid cell index);
   * standard F2 boundary-matrix reduction (paper Sec. 2.1), zero-persistence pairs omitted
     (paper Sec. 2.3).
+
+``diagram(..., filtration="T")`` takes the pixels as the top cells instead (paper Sec. 2.2):
+a cell's value is the minimum over the top cells containing it, the first-order tie-break is
+the top cell through which it enters (the pixel order's minimum of those), and pairs come
+sorted by (dim, death key), essential classes last.
 
 ``gradient`` is the reference backward: scatter of dL/dbirth and dL/ddeath to the pixel that
 attains each critical cell's value, accumulated in FP32 in output order.
@@ -79,6 +84,8 @@ def _load():
                                    ctypes.POINTER(ctypes.POINTER(_Pair)),
                                    ctypes.POINTER(ctypes.c_int64)]
         lib.or_diagram.restype = ctypes.c_int
+        lib.or_diagram_t.argtypes = lib.or_diagram.argtypes
+        lib.or_diagram_t.restype = ctypes.c_int
         lib.or_free.argtypes = [ctypes.c_void_p]
         lib.or_gradient.argtypes = [ctypes.POINTER(_Pair), ctypes.c_int64, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
@@ -92,8 +99,10 @@ def default_dims(ndim: int) -> tuple:
     return (0, ndim - 1)
 
 
-def diagram(img, dims=None, method: int = SPLIT, keep_zero: bool = False) -> np.ndarray:
-    """Persistence pairs of ``img`` (2D or 3D float32), sorted by (dim, birth key).
+def diagram(img, dims=None, method: int = SPLIT, keep_zero: bool = False,
+            filtration: str = "V") -> np.ndarray:
+    """Persistence pairs of ``img`` (2D or 3D float32) under the V- or T-filtration; V pairs
+    sorted by (dim, birth key), T pairs by (dim, death key) with essential classes last.
 
     Returns a structured array with fields of ``PAIR_DTYPE``.  ``dims`` lists the homology
     dimensions wanted (default: H0 and H_top).  ``keep_zero`` keeps zero-persistence pairs
@@ -107,11 +116,14 @@ def diagram(img, dims=None, method: int = SPLIT, keep_zero: bool = False) -> np.
     mask = 0
     for d in dims:
         mask |= 1 << int(d)
+    if filtration not in ("V", "T"):
+        raise OracleError("filtration must be 'V' or 'T'")
     lib = _load()
+    fn = lib.or_diagram if filtration == "V" else lib.or_diagram_t
     ext = (ctypes.c_int64 * a.ndim)(*a.shape)
     out = ctypes.POINTER(_Pair)()
     cnt = ctypes.c_int64(0)
-    rc = lib.or_diagram(a.ctypes.data, a.ndim, ext, mask, int(method), int(bool(keep_zero)),
+    rc = fn(a.ctypes.data, a.ndim, ext, mask, int(method), int(bool(keep_zero)),
                         ctypes.byref(out), ctypes.byref(cnt))
     if rc != 0:
         raise OracleError(_ERRORS.get(rc, "error %d" % rc))

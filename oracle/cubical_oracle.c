@@ -1,5 +1,5 @@
 /*
- * cubical_oracle.c -- plain CPU reference for V-filtration cubical persistence over F2.
+ * cubical_oracle.c -- plain CPU reference for V- and T-filtration cubical persistence over F2.
  *
  * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may load this file or the
  * library built from it; only the tests, the smoke check and the CPU-baseline leg of
@@ -28,6 +28,18 @@
  *              middle dimensions use their boundary block.  In this route the only
  *              essential class reported is the one of H0 (the grid is contractible).
  *
+ * T-filtration (or_diagram_t; paper Sec. 2.2, its dual construction): the pixels are the
+ * top cells of a complex on (H+1)x(W+1) [(D+1)x(H+1)x(W+1)] vertices.  A cell's value is
+ * the minimum over the top cells that contain it; the first-order tie-break is the top cell
+ * through which the cell enters, i.e. the minimum of those top cells under the pixel order
+ * (value, then row-major pixel index): the pseudo lower star the paper's Sec. 3 names for
+ * this case.  The rest of the order (dimension, then doubled-grid cell index) and the
+ * reduction are those of the V case.  birth_vertex / death_vertex name the pixel whose
+ * value the cell takes.  Output order: by dimension, then by the death cell's position in
+ * the refined order, essential classes last.  Pixel (i,j[,k]) is the top cell at doubled
+ * coordinates (2i+1, 2j+1[, 2k+1]); the doubled grid has extents 2e+1 (1 on the leading
+ * axis of an image).
+ *
  * Cell indexing: a 2D image of extents (H,W) is treated as a (1,H,W) volume.  Cell
  * coordinates live on the doubled grid (2H-1, 2W-1) [(2D-1, 2H-1, 2W-1) in 3D]; a
  * coordinate is odd where the cell has a non-degenerate factor.  cellidx is the
@@ -43,8 +55,9 @@
 
 typedef struct {
     int ndim;          /* 2 or 3: dimension of the complex the caller asks for */
+    int tmode;         /* 0: V-filtration (pixels are vertices), 1: T (pixels are top cells) */
     int64_t e[3];      /* pixel extents, slowest first, padded to 3 with leading 1 */
-    int64_t d[3];      /* doubled extents 2e-1 */
+    int64_t d[3];      /* doubled extents: 2e-1 (V), 2e+1 (T; 1 on the leading axis in 2D) */
     int64_t nvox;
     int64_t ncell;
     const float *img;
@@ -112,6 +125,36 @@ static int64_t cell_lsv(const grid_t *g, const int64_t co[3]) {
     return best;
 }
 
+/* T-filtration: the top cell through which the cell enters -- the minimum, under the pixel
+ * order, of the top cells containing it.  An odd coordinate is fixed; an even coordinate c
+ * on an axis of the complex takes the neighbours c-1 and c+1 that lie inside the grid. */
+static int64_t cell_entry_top(const grid_t *g, const int64_t co[3]) {
+    int64_t best = -1, bestr = -1;
+    const int k0 = 3 - g->ndim;                        /* first axis of the complex */
+    for (int m = 0; m < 8; ++m) {
+        int64_t t[3];
+        int ok = 1;
+        for (int k = 0; k < 3; ++k) {
+            int bit = (m >> k) & 1;
+            if (k < k0) { t[k] = 0; if (bit) ok = 0; continue; }
+            if (co[k] & 1) { t[k] = co[k]; if (bit) ok = 0; }
+            else t[k] = co[k] + (bit ? 1 : -1);
+            if (t[k] < 0 || t[k] >= g->d[k]) ok = 0;
+        }
+        if (!ok) continue;
+        int64_t q[3];
+        for (int k = 0; k < 3; ++k) q[k] = k < k0 ? 0 : (t[k] - 1) / 2;
+        int64_t p = (q[0] * g->e[1] + q[1]) * g->e[2] + q[2];
+        if (bestr < 0 || g->vrank[p] < bestr) { bestr = g->vrank[p]; best = p; }
+    }
+    return best;
+}
+
+/* The pixel whose value the cell takes and whose rank orders it first. */
+static int64_t cell_pixel(const grid_t *g, const int64_t co[3]) {
+    return g->tmode ? cell_entry_top(g, co) : cell_lsv(g, co);
+}
+
 /* Key of the fully refined order: (rank of lower-star vertex, dim, cellidx). */
 typedef struct { int64_t r; int64_t dim; int64_t c; } ckey_t;
 
@@ -127,7 +170,7 @@ static ckey_t key_of(const grid_t *g, int64_t c) {
     int64_t co[3];
     cell_coords(g, c, co);
     ckey_t k;
-    k.r = g->vrank[cell_lsv(g, co)];
+    k.r = g->vrank[cell_pixel(g, co)];
     k.dim = cell_dim(co);
     k.c = c;
     return k;
@@ -231,13 +274,13 @@ static int emit(const grid_t *g, plist_t *L, uint32_t dims_mask, int keep_zero,
     memset(&x, 0, sizeof x);
     x.dim = dim;
     x.birth_cell = b;
-    x.birth_vertex = cell_lsv(g, co);
+    x.birth_vertex = cell_pixel(g, co);
     x.birth = g->img[x.birth_vertex];
     if (d >= 0) {
         int64_t cd[3];
         cell_coords(g, d, cd);
         x.death_cell = d;
-        x.death_vertex = cell_lsv(g, cd);
+        x.death_vertex = cell_pixel(g, cd);
         x.death = g->img[x.death_vertex];
         if (!keep_zero && x.birth == x.death) return OR_OK;   /* zero persistence */
     } else {
@@ -412,16 +455,27 @@ static int cmp_pair(const void *a, const void *b) {
     return cmp_ckey(&kx, &ky);
 }
 
+/* T-filtration order: dimension, then the death cell's key, essential classes last. */
+static int cmp_pair_t(const void *a, const void *b) {
+    const or_pair *x = (const or_pair *)a, *y = (const or_pair *)b;
+    if (x->dim != y->dim) return x->dim < y->dim ? -1 : 1;
+    if ((x->death_cell < 0) != (y->death_cell < 0)) return x->death_cell < 0 ? 1 : -1;
+    if (x->death_cell < 0) return 0;
+    ckey_t kx = key_of(g_sort_grid, x->death_cell), ky = key_of(g_sort_grid, y->death_cell);
+    return cmp_ckey(&kx, &ky);
+}
+
 /* ------------------------------------------------------------------ entry ---- */
 
-int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
-               int32_t method, int32_t keep_zero, or_pair **out, int64_t *count) {
+static int diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
+                   int32_t method, int32_t keep_zero, int tmode, or_pair **out, int64_t *count) {
     *out = NULL;
     *count = 0;
     if (!img || !ext || (ndim != 2 && ndim != 3)) return OR_EINVAL;
     grid_t g;
     memset(&g, 0, sizeof g);
     g.ndim = ndim;
+    g.tmode = tmode;
     g.e[0] = 1;
     for (int k = 0; k < ndim; ++k) {
         if (ext[k] < 1) return OR_EINVAL;
@@ -429,7 +483,8 @@ int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims
     }
     if (ndim == 2) g.e[0] = 1;
     g.nvox = g.e[0] * g.e[1] * g.e[2];
-    for (int k = 0; k < 3; ++k) g.d[k] = 2 * g.e[k] - 1;
+    for (int k = 0; k < 3; ++k) g.d[k] = tmode ? 2 * g.e[k] + 1 : 2 * g.e[k] - 1;
+    if (tmode && ndim == 2) g.d[0] = 1;
     g.ncell = g.d[0] * g.d[1] * g.d[2];
     g.img = img;
     for (int64_t i = 0; i < g.nvox; ++i)
@@ -451,7 +506,7 @@ int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims
     }
     if (rc == OR_OK && L.n > 1) {
         g_sort_grid = &g;
-        qsort(L.p, (size_t)L.n, sizeof(or_pair), cmp_pair);
+        qsort(L.p, (size_t)L.n, sizeof(or_pair), tmode ? cmp_pair_t : cmp_pair);
         g_sort_grid = NULL;
     }
     free(g.vrank);
@@ -459,6 +514,16 @@ int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims
     *out = L.p;
     *count = L.n;
     return OR_OK;
+}
+
+int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
+               int32_t method, int32_t keep_zero, or_pair **out, int64_t *count) {
+    return diagram(img, ndim, ext, dims_mask, method, keep_zero, 0, out, count);
+}
+
+int or_diagram_t(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
+                 int32_t method, int32_t keep_zero, or_pair **out, int64_t *count) {
+    return diagram(img, ndim, ext, dims_mask, method, keep_zero, 1, out, count);
 }
 
 void or_free(void *p) { free(p); }

@@ -1,4 +1,4 @@
-/* cubical_oracle.h -- TEST INFRASTRUCTURE ONLY: plain CPU reference for V-filtration
+/* cubical_oracle.h -- TEST INFRASTRUCTURE ONLY: plain CPU reference for V- and T-filtration
  * cubical persistence over F2.  Not part of, and never linked into, the GPU library. */
 #ifndef CUBICAL_ORACLE_H
 #define CUBICAL_ORACLE_H
@@ -21,6 +21,11 @@ typedef struct {
  * On success *out holds *count pairs sorted by (dim, birth key); free with or_free. */
 int or_diagram(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
                int32_t method, int32_t keep_zero, or_pair **out, int64_t *count);
+/* The same for the T-filtration (pixels are the top cells); pairs sorted by (dim, death
+ * key), essential classes last; birth_vertex / death_vertex name the pixel whose value the
+ * cell takes. */
+int or_diagram_t(const float *img, int32_t ndim, const int64_t *ext, uint32_t dims_mask,
+                 int32_t method, int32_t keep_zero, or_pair **out, int64_t *count);
 void or_free(void *p);
 int or_gradient(const or_pair *pairs, int64_t n, const float *grad_birth,
                 const float *grad_death, float *grad_img, int64_t nvox);
