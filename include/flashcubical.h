@@ -65,8 +65,27 @@ enum {
  * element type of the input (float32 unless one of PH_IN_U8, PH_IN_U16 is set; setting both
  * is PH_EINVAL).  An integer input gives bitwise the results of the same values as float32
  * (every 8- and 16-bit integer is exactly a float32); it reads 1 or 2 bytes per voxel and
- * always uses the default tiles. */
-enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8 };
+ * always uses the default tiles.
+ *
+ * PH_TFILT selects the T-filtration (paper Sec. 2.2, its dual construction; the extension
+ * the paper's Sec. 7 names): the pixels are the top cells of a complex on (n+1) vertices per
+ * axis, and a cell enters with the first top cell that contains it (value = minimum over the
+ * top cells containing it; ties go to the smaller pixel index, then lower dimension, then
+ * smaller doubled-grid index).  By Alexander duality this complex is the dual cell complex of
+ * the V complex of the negated, point-reflected image framed by one ring of -inf pixels:
+ * the library computes that V diagram with the same kernels and maps every pair back (the
+ * dual of a T pair (s, t) of dimension k is the V pair (t*, s*) of dimension d-1-k).  Under
+ * PH_TFILT:
+ *   - PH_H0 / PH_HTOP name the T dimensions; both V dimensions are always computed;
+ *   - cells are indices on the T doubled grid, extents 2n+1 per axis (1 on the leading axis
+ *     of an image); pixel (i, j[, k]) is the top cell (2i+1, 2j+1[, 2k+1]); birth_vertex /
+ *     death_vertex name the pixel whose value the cell takes;
+ *   - pairs come by dimension, then by the death cell's position in the filtration order,
+ *     the essential class last;
+ *   - a +inf pixel is reported as PH_ENAN (it would tie the frame);
+ *   - ph_capacity_bound and ph_workspace_bytes of the same flags account for the frame: pass
+ *     the shape with every extent grown by 2 to ph_capacity_bound. */
+enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16 };
 
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
@@ -98,7 +117,8 @@ typedef struct {
 int64_t ph_capacity_bound(ph_shape shape);
 
 /* Workspace bytes needed by a batch of n instances with the given host shapes (also valid
- * for n = 1 and ph_diagram).  Returns 0 for invalid shapes. */
+ * for n = 1 and ph_diagram) under the given flags (PH_TFILT adds the framed dual images).
+ * Returns 0 for invalid shapes. */
 size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags);
 
 /* Persistence diagram of one image or volume (Sec. 4.1 / Sec. 4.2 steps 1-3).
@@ -135,8 +155,8 @@ int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off,
  * later ph_diagram_batch calls with tuning == NULL in that class use it.  Arguments as for
  * ph_diagram_batch; the outputs hold the last run's results.  Waits for the stream (not for
  * use during graph capture).  Tile choices never change results, only speed.  With an integer
- * input (PH_IN_U8, PH_IN_U16) it runs the batch once on the default tiles, writes those to
- * *best and records nothing. */
+ * input (PH_IN_U8, PH_IN_U16) or PH_TFILT it runs the batch once on the default tiles, writes
+ * those to *best and records nothing (a T batch with tuning == NULL takes the defaults). */
 int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,

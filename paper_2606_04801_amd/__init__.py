@@ -26,6 +26,7 @@ LIB_PATH = os.path.join(_HERE, "libflashcubical.so")
 PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 PH_H0, PH_HTOP = 1, 2
 PH_IN_U8, PH_IN_U16 = 4, 8          # input element type (float32 when neither is set)
+PH_TFILT = 16                       # T-filtration: pixels are the top cells (default: V)
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
                 -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
 
@@ -133,8 +134,18 @@ def make_shape(shape) -> ph_shape:
     return ph_shape(len(shape), (ctypes.c_int32 * 3)(*ext))
 
 
-def capacity_bound(shape) -> int:
+def capacity_bound(shape, filtration: str = "V") -> int:
+    """Pairs one instance can hold at most; under the T-filtration the bound of the framed
+    dual image (every extent + 2)."""
+    if filtration == "T":
+        shape = tuple(int(e) + 2 for e in shape)
     return int(lib().ph_capacity_bound(make_shape(shape)))
+
+
+def _filtration_flags(flags: int, filtration: str) -> int:
+    if filtration not in ("V", "T"):
+        raise PHError(PH_EINVAL, "filtration must be 'V' or 'T'")
+    return (int(flags) & ~PH_TFILT) | (PH_TFILT if filtration == "T" else 0)
 
 
 def workspace_bytes(shapes, flags=PH_H0 | PH_HTOP) -> int:
@@ -256,9 +267,10 @@ _default_ws = Workspace()
 
 
 def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, ws: Workspace | None = None,
-               stream=None) -> Diagram:
+               stream=None, filtration: str = "V") -> Diagram:
     """Persistence diagram of one image (H, W) or volume (D, H, W) on the GPU: float32, or
-    uint8 / uint16 (read as such, results those of the same values as float32)."""
+    uint8 / uint16 (read as such, results those of the same values as float32), under the
+    V-filtration (pixels are vertices) or the T-filtration (pixels are top cells)."""
     torch = _torch()
     # a host tensor would hand the kernels a host pointer; without a GPU the library itself
     # reports that it cannot run, so the check only matters when one is present
@@ -266,10 +278,10 @@ def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, w
     kinds = _input_flags()
     if not (on_device and img.dtype in kinds and img.dim() in (2, 3)):
         raise PHError(PH_EINVAL, "ph_diagram expects a 2D/3D float32, uint8 or uint16 CUDA tensor")
-    flags = (int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[img.dtype]
+    flags = _filtration_flags((int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[img.dtype], filtration)
     img = img.contiguous()
     shp = make_shape(img.shape)
-    cap = capacity_bound(img.shape) if capacity is None else int(capacity)
+    cap = capacity_bound(img.shape, filtration) if capacity is None else int(capacity)
     bufs = PairBuffers(cap, img.device)
     count = torch.zeros(1, dtype=torch.int64, device=img.device)
     status = torch.zeros(1, dtype=torch.int32, device=img.device)
@@ -306,23 +318,25 @@ class Batch:
     """
 
     def __init__(self, shapes, flags: int = PH_H0 | PH_HTOP, tuning=None, device="cuda", capacities=None,
-                 dtype=None):
+                 dtype=None, filtration: str = "V"):
         """capacities: pairs stored per instance (default: the bound pixels + top cells, which
         never overflows); a smaller one, e.g. the counts of an earlier call on the same
         inputs, keeps the pair buffers small.  dtype: element type of the inputs (float32,
-        uint8 or uint16; integer inputs use the default tiles)."""
+        uint8 or uint16; integer inputs use the default tiles).  filtration: "V" (pixels are
+        vertices) or "T" (pixels are top cells)."""
         torch = _torch()
         self.dtype = torch.float32 if dtype is None else dtype
         kinds = _input_flags()
         if self.dtype not in kinds:
             raise PHError(PH_EINVAL, "Batch dtype must be float32, uint8 or uint16")
-        flags = (int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[self.dtype]
+        flags = _filtration_flags((int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[self.dtype], filtration)
+        self.filtration = filtration
         self.shapes = [tuple(int(x) for x in s) for s in shapes]
         self.n = len(self.shapes)
         self.flags = flags
         self.device = torch.device(device)
         sizes = [int(np.prod(s)) for s in self.shapes]
-        caps = [capacity_bound(s) for s in self.shapes] if capacities is None else [max(int(c), 1) for c in capacities]
+        caps = [capacity_bound(s, filtration) for s in self.shapes] if capacities is None else [max(int(c), 1) for c in capacities]
         if len(caps) != self.n:
             raise PHError(PH_EINVAL, "capacities")
         self.img_off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -417,8 +431,8 @@ def _autograd():
         and dL/ddeath to the pixels attaining each critical cell's value (ph_backward)."""
 
         @staticmethod
-        def forward(ctx, img):
-            d = ph_diagram(img.detach())
+        def forward(ctx, img, filtration="V"):
+            d = ph_diagram(img.detach(), filtration=filtration)
             n = d.check()
             b = d.bufs
             ctx.save_for_backward(b.birth_vertex[:n].clone(), b.death_vertex[:n].clone())
@@ -440,7 +454,7 @@ def _autograd():
             out_off = torch.tensor([0, max(n, 1)], dtype=torch.int64, device=dev)
             img_off = torch.zeros(1, dtype=torch.int64, device=dev)
             ph_backward(ctx.bufs, counts, out_off, img_off, gb, gd, gimg)
-            return gimg
+            return gimg, None
 
     return PHDiagramFn
 

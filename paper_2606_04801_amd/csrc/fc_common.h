@@ -128,12 +128,14 @@ struct Inst {
     int32_t ndim, D, H, W;
     int64_t N, T, E, F, FAC;
     int64_t img_off, out_off, out_cap;
+    int64_t src_off;           // offset of the caller's image (img_off differs under the T-filtration)
     int64_t tile_base;         // first tile of this instance in its (2D or 3D) classify grid
-    int32_t tx, ty, tz, pad;   // tiles along x, y, z
+    int32_t tx, ty, tz;        // tiles along x, y, z
+    int32_t tfilt;             // 1: T-filtration, the grid is the framed dual image (extents + 2)
     // byte offsets of the per-instance arrays inside the workspace
     int64_t o_par0, o_parT, o_keyE, o_ea, o_eb, o_neg0, o_keyF, o_fa, o_fb, o_killer;
     int64_t o_n0key, o_n0sorted, o_nTkey, o_uf0, o_moe0, o_death0, o_ufT, o_moeT;
-    int64_t o_live, o_live2, o_ra, o_rb, o_scratch;
+    int64_t o_live, o_live2, o_ra, o_rb, o_scratch, o_gimg;
     int64_t end;
 };
 
@@ -186,6 +188,7 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_ra = take(4 * L);
     I.o_rb = take(4 * L);
     I.o_scratch = take(8 * SCR);
+    I.o_gimg = I.tfilt ? take(4 * N) : 0;   // T-filtration: the framed dual image (float32)
     I.end = at;
     return at;
 }

@@ -21,6 +21,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -78,7 +79,13 @@ FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
         I.tx = (I.W + tl.tw3 - 1) / tl.tw3; I.ty = (I.H + tl.th3 - 1) / tl.th3;
         I.tz = (I.D + tl.td3 - 1) / tl.td3;
     }
-    I.pad = 0;
+    I.tfilt = 0;
+}
+
+// T-filtration: the framed dual image has one more pixel on each side of every axis
+FC_HD ph_shape framed(ph_shape s) {
+    for (int k = 0; k < s.ndim; ++k) s.ext[k] += 2;
+    return s;
 }
 
 // One thread per instance, in chunks of the block: each instance's table entry, with its
@@ -91,7 +98,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
                        const int64_t *__restrict__ d_img_off, const int64_t *__restrict__ d_out_off,
                        int64_t single_cap, Tiles tl, uint8_t *__restrict__ ws,
                        int64_t *__restrict__ d_counts, int32_t *__restrict__ d_status,
-                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes) {
+                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes, int tfilt) {
     __shared__ int64_t s_scan[2][3][kPlanThreads];   // bytes, 2D tiles, 3D tiles (double buffer)
     __shared__ int64_t s_run[3];
     if (blockIdx.x != 0) return;
@@ -111,8 +118,14 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
             ph_shape s = d_shapes ? d_shapes[i] : single;
             ok = (s.ndim == 2 || s.ndim == 3) && s.ext[0] >= 1 && s.ext[1] >= 1 && (s.ndim == 2 || s.ext[2] >= 1);
             if (!ok) s = ph_shape{2, {1, 1, 1}};
+            if (tfilt) s = framed(s);
             fill_inst(I, s, tl);
-            if (I.N >= (1ll << kPixBits)) { ok = false; s = ph_shape{2, {1, 1, 1}}; fill_inst(I, s, tl); }
+            if (I.N >= (1ll << kPixBits)) {
+                ok = false;
+                s = ph_shape{2, {1, 1, 1}};
+                fill_inst(I, tfilt ? framed(s) : s, tl);
+            }
+            I.tfilt = tfilt;
             v[0] = layout(I, 0);
             if (I.ndim == 2) v[1] = (int64_t)I.tx * I.ty;
             else v[2] = (int64_t)I.tx * I.ty * I.tz;
@@ -129,13 +142,15 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
         }
         if (i < n) {
             const int64_t at = s_run[0] + s_scan[b][0][t] - v[0];
-            I.img_off = d_img_off ? d_img_off[i] : 0;
+            I.src_off = d_img_off ? d_img_off[i] : 0;
+            I.img_off = I.src_off;
             I.out_off = d_out_off ? d_out_off[i] : 0;
             I.out_cap = d_out_off ? d_out_off[i + 1] - d_out_off[i] : single_cap;
             tb2[i] = s_run[1] + s_scan[b][1][t] - v[1];
             tb3[i] = s_run[2] + s_scan[b][2][t] - v[2];
             I.tile_base = I.ndim == 2 ? tb2[i] : tb3[i];
             layout(I, at);
+            if (tfilt) I.img_off = I.o_gimg / 4;      // float32 elements from the workspace base
             tab[i] = I;
             for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
             cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
@@ -1355,6 +1370,36 @@ __global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ 
         uf_run<true>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
 }
 
+// ============================================================== T-filtration ====
+// The framed dual image of one instance per blockIdx.y: framed pixel (z, y, x) holds minus
+// the caller's pixel at the point reflection of (z-1, y-1, x-1) (an image has no frame along
+// z), the frame holds -inf.  Its V complex is the dual cell complex of the caller's T complex
+// with the frame added; the reflection makes the V tie-break (larger index enters later) the
+// T one read backwards.  A +inf pixel would tie the frame: it becomes NaN, which the
+// classify pass reports as PH_ENAN.
+template <typename T>
+__global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t *__restrict__ ws, int n) {
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (!I.tfilt || failed(cnt)) return;
+    float *g = (float *)ws + I.img_off;
+    const bool vol = I.ndim == 3;
+    const int D = I.D, H = I.H, W = I.W, HW = H * W;   // framed extents (D = 1 for an image)
+    const int sD = vol ? D - 2 : 1, sH = H - 2, sW = W - 2;
+    const int N = (int)I.N;                            // < 2^27
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < N; p += gridDim.x * 256) {
+        const int z = p / HW, r = p - z * HW, y = r / W, x = r - y * W;
+        float v = __int_as_float(0xff800000);          // -inf
+        if ((!vol || (z >= 1 && z <= D - 2)) && y >= 1 && y <= H - 2 && x >= 1 && x <= W - 2) {
+            const int q = ((vol ? sD - z : 0) * sH + (sH - y)) * sW + (sW - x);
+            const float f = (float)src[I.src_off + q];
+            v = f == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -f;
+        }
+        g[p] = v;
+    }
+}
+
 // ====================================================================== output ====
 __device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code) {
     const int64_t HW = (int64_t)I.H * I.W;
@@ -1371,9 +1416,9 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    // pixel value as float32, from an input of the element type the flags name
+    // pixel value as float32, from the caller's input of the element type the flags name
     auto img = [&](int64_t p) -> float {
-        const int64_t q = I.img_off + p;
+        const int64_t q = I.src_off + p;
         if (flags & PH_IN_U8) return (float)((const uint8_t *)imgs)[q];
         if (flags & PH_IN_U16) return (float)((const uint16_t *)imgs)[q];
         return ((const float *)imgs)[q];
@@ -1400,20 +1445,46 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
         return key_pix(k) < (uint64_t)I.N && c >= lo && c <= hi;
     };
 
-    auto put = [&](int64_t pos, int dim, uint32_t bv, int64_t bc, int32_t bpix, int64_t dc, int32_t dpix) {
+    // T-filtration: the V pairs are those of the framed dual image (extents D, H, W; the
+    // caller's are sD, sH, sW).  Its pixel p is the caller's pixel at the point reflection
+    // (-1 on the frame); its doubled-grid coordinate X on an axis is the T coordinate 2s+1-X.
+    const bool tf = (flags & PH_TFILT) != 0;
+    const bool vol = I.ndim == 3;
+    const int64_t sD = vol ? I.D - 2 : 1, sH = I.H - 2, sW = I.W - 2;
+    auto src_px = [&](int64_t v) -> int32_t {
+        const int64_t HW = (int64_t)I.H * I.W;
+        const int64_t z = v / HW, rem = v - z * HW, y = rem / I.W, x = rem - y * I.W;
+        if ((vol && (z < 1 || z > I.D - 2)) || y < 1 || y > I.H - 2 || x < 1 || x > I.W - 2) return -1;
+        return (int32_t)((((vol ? sD - z : 0) * sH) + (sH - y)) * sW + (sW - x));
+    };
+    auto t_cell = [&](int64_t v, int code) -> int64_t {
+        const int64_t HW = (int64_t)I.H * I.W;
+        const int64_t z = v / HW, rem = v - z * HW, y = rem / I.W, x = rem - y * I.W;
+        const int64_t Z = vol ? 2 * sD + 1 - (2 * z + off_of(code, 0)) : 0;
+        const int64_t Y = 2 * sH + 1 - (2 * y + off_of(code, 1)), X = 2 * sW + 1 - (2 * x + off_of(code, 2));
+        if (Z < 0 || Z > 2 * sD || Y < 0 || Y > 2 * sH || X < 0 || X > 2 * sW) return -1;
+        return (Z * (2 * sH + 1) + Y) * (2 * sW + 1) + X;
+    };
+
+    auto put = [&](int64_t pos, int dim, float bv, float dv, int64_t bc, int32_t bpix, int64_t dc, int32_t dpix) {
         if (pos >= cap) return;
         const int64_t j = o + pos;
         out.dim[j] = (int8_t)dim;
-        out.birth[j] = img(bpix);
-        out.death[j] = dpix >= 0 ? img(dpix) : __int_as_float(0x7f800000);
+        out.birth[j] = bv;
+        out.death[j] = dv;
         out.birth_cell[j] = bc;
         out.death_cell[j] = dc;
         out.birth_vertex[j] = bpix;
         out.death_vertex[j] = dpix;
-        (void)bv;
     };
+    const float kInf = __int_as_float(0x7f800000);
+    // A section's k-th pair (in the order of its list) goes to start + k, or, with rev >= 0
+    // pairs in the section, to start + rev - 1 - k.  With write false the section only counts.
+    auto place = [](int64_t start, int64_t rev, int64_t k) { return rev >= 0 ? start + rev - 1 - k : start + k; };
 
-    if (flags & PH_H0) {
+    // H0 pairs of the V complex, by birth key (under the T-filtration: its top pairs)
+    auto sec_h0 = [&](bool write, int64_t start, int64_t rev) -> int64_t {
+        int64_t Q = 0;
         for (int base = 0; base < M0; base += blockDim.x) {
             const int j = base + threadIdx.x;
             int flag = 0;
@@ -1426,25 +1497,35 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
                 if (pv >= 0 || id >= M0) { set_err(cnt, PH_EINTERNAL); }
                 else {
                     d = death0[id];
-                    if (d < 0) flag = 1;                          // essential
+                    if (d < 0) flag = !tf;                    // essential (the frame's, under T)
                     else if (d >= mE || !key_ok(ek = keyE[d], 1, 6)) set_err(cnt, PH_EINTERNAL);
                     else flag = key_ord(ek) != key_ord(nk);
                 }
             }
             int tot;
             const int pos = block_flag_scan(flag, s_wsum, &tot);
-            if (flag) {
+            if (flag && write) {
                 const int32_t bp = (int32_t)key_pix(nk);
-                if (d < 0) put(P + pos, 0, 0, cell_index(I, bp, 0), bp, -1, -1);
-                else {
+                const int64_t at = place(start, rev, Q + pos);
+                if (d < 0) put(at, 0, img(bp), kInf, cell_index(I, bp, 0), bp, -1, -1);
+                else if (!tf) {
                     const int32_t dp = (int32_t)key_pix(ek);
-                    put(P + pos, 0, 0, cell_index(I, bp, 0), bp, cell_index(I, dp, key_code(ek)), dp);
+                    put(at, 0, img(bp), img(dp), cell_index(I, bp, 0), bp, cell_index(I, dp, key_code(ek)), dp);
+                } else {
+                    const int32_t dp = (int32_t)key_pix(ek), sb = src_px(dp), sd = src_px(bp);
+                    const int64_t cb = t_cell(dp, key_code(ek)), cd = t_cell(bp, 0);
+                    if (sb < 0 || sd < 0 || cb < 0 || cd < 0) set_err(cnt, PH_EINTERNAL);
+                    else put(at, I.ndim - 1, img(sb), img(sd), cb, sb, cd, sd);
                 }
             }
-            P += tot;
+            Q += tot;
         }
-    }
-    if (flags & PH_HTOP) {
+        return Q;
+    };
+    // top-dimension pairs of the V complex, by birth key (under the T-filtration: its H0
+    // pairs; the one born on the frame is the essential class)
+    auto sec_top = [&](bool write, int64_t start, int64_t rev) -> int64_t {
+        int64_t Q = 0;
         for (int base = 0; base < mf; base += blockDim.x) {
             const int r = base + threadIdx.x;
             int flag = 0;
@@ -1462,13 +1543,39 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
             }
             int tot;
             const int pos = block_flag_scan(flag, s_wsum, &tot);
-            if (flag) {
+            if (flag && write) {
                 const int32_t bp = (int32_t)key_pix(fk), dp = (int32_t)key_pix(tk);
-                put(P + pos, I.ndim - 1, 0, cell_index(I, bp, key_code(fk)), bp,
-                    cell_index(I, dp, key_code(tk)), dp);
+                const int64_t at = place(start, rev, Q + pos);
+                if (!tf) {
+                    put(at, I.ndim - 1, img(bp), img(dp), cell_index(I, bp, key_code(fk)), bp,
+                        cell_index(I, dp, key_code(tk)), dp);
+                } else {
+                    const int32_t sb = src_px(dp), sd = src_px(bp);
+                    const int64_t cb = t_cell(dp, key_code(tk));
+                    if (sb < 0 || cb < 0) set_err(cnt, PH_EINTERNAL);
+                    else if (sd < 0) put(at, 0, img(sb), kInf, cb, sb, -1, -1);
+                    else {
+                        const int64_t cd = t_cell(bp, key_code(fk));
+                        if (cd < 0) set_err(cnt, PH_EINTERNAL);
+                        else put(at, 0, img(sb), img(sd), cb, sb, cd, sd);
+                    }
+                }
             }
-            P += tot;
+            Q += tot;
         }
+        return Q;
+    };
+
+    if (!tf) {
+        if (flags & PH_H0) P += sec_h0(true, P, -1);
+        if (flags & PH_HTOP) P += sec_top(true, P, -1);
+    } else {
+        // T order: by dimension, then by death key, so each section is written backwards
+        const int64_t c0 = (flags & PH_H0) ? sec_top(false, 0, -1) : 0;
+        const int64_t ct = (flags & PH_HTOP) ? sec_h0(false, 0, -1) : 0;
+        if (flags & PH_H0) sec_top(true, 0, c0);
+        if (flags & PH_HTOP) sec_h0(true, c0, ct);
+        P = c0 + ct;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1563,6 +1670,9 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_output", (const void *)k_output, kUfThreads},
         {"k_zero", (const void *)k_zero, 256},
         {"k_scatter", (const void *)k_scatter, 256},
+        {"k_tpad", (const void *)k_tpad<float>, 256},
+        {"k_tpad<u8>", (const void *)k_tpad<uint8_t>, 256},
+        {"k_tpad<u16>", (const void *)k_tpad<uint16_t>, 256},
     };
     int maxsh = 0, maxthr = 0;
     if (!hip_ok(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute") ||
@@ -1632,13 +1742,14 @@ Tiles tiles_of(const ph_tuning *t) {
 }
 
 // total workspace bytes and classify grid sizes for a list of host shapes
-int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3) {
+int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3, bool tfilt) {
     int64_t at = header_bytes(n);
     *t2 = 0;
     *t3 = 0;
     for (int i = 0; i < n; ++i) {
         Inst I;
-        fill_inst(I, h[i], tl);
+        fill_inst(I, tfilt ? framed(h[i]) : h[i], tl);
+        I.tfilt = tfilt;
         if (I.ndim == 2) *t2 += (int64_t)I.tx * I.ty;
         else *t3 += (int64_t)I.tx * I.ty * I.tz;
         at = layout(I, at);
@@ -1719,11 +1830,11 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // stream is being captured into a graph).
 enum KernelId {
     K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_OUTPUT,
-    K_ZERO, K_SCATTER, K_COUNT
+    K_ZERO, K_SCATTER, K_TPAD, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
-    "k_resolve(2d top)", "k_unionfind(2d top)", "k_output", "k_zero", "k_scatter"};
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_output", "k_zero", "k_scatter", "k_tpad"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -1783,20 +1894,30 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
         return PH_EINVAL;
+    // under the T-filtration the kernels below run on the framed dual images, which sit in
+    // the workspace as float32 (extents + 2); only k_tpad and k_output read the caller's input
+    const bool tf = (flags & PH_TFILT) != 0;
+    std::vector<ph_shape> framed_shapes;
+    if (tf) {
+        framed_shapes.resize(n);
+        for (int i = 0; i < n; ++i) framed_shapes[i] = framed(h_shapes[i]);
+    }
+    const ph_shape *hs = tf ? framed_shapes.data() : h_shapes;
     bool any2 = false, any3 = false;
     for (int i = 0; i < n; ++i) {
-        if (!valid_shape(h_shapes[i])) return PH_EINVAL;
+        if (!valid_shape(h_shapes[i]) || !valid_shape(hs[i])) return PH_EINVAL;
         (h_shapes[i].ndim == 3 ? any3 : any2) = true;
     }
     if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
     if ((flags & PH_IN_U8) && (flags & PH_IN_U16)) return PH_EINVAL;
-    const int elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
+    const int in_elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
+    const int elem = tf ? 0 : in_elem;             // element type the classify passes read
     if (elem != 0) tuning = nullptr;               // integer inputs use the default tiles
     int rc = device_luts();
     if (rc != PH_OK) return rc;
     const Tiles tl = tiles_of(tuning);
     int64_t t2, t3;
-    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3);
+    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3, tf);   // frames them itself
     if ((int64_t)ws_bytes < need) return PH_ENOMEM;
     if (t2 >= (1ll << 31) || t3 >= (1ll << 31)) return PH_EINVAL;
     uint8_t *ws = (uint8_t *)d_ws;
@@ -1819,31 +1940,39 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         if (trace && trace_after(KID, st) != PH_OK) return PH_EHIP;           \
     } while (0)
     FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, n, d_shapes, single, d_img_off, d_out_off,
-                                 single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes));
+                                 single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes, tf ? 1 : 0));
+    const int64_t ml = max_list(hs, n), mv = max_voxels(hs, n);
+    const void *cimgs = d_imgs;                    // what the classify passes read
+    if (tf) {
+        const unsigned pb = (unsigned)std::min<int64_t>(std::max<int64_t>((mv + 2047) / 2048, 1), 4096);
+        if (in_elem == 1) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint8_t>, dim3(pb, n), dim3(256), 0, st, (const uint8_t *)d_imgs, ws, n));
+        else if (in_elem == 2) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint16_t>, dim3(pb, n), dim3(256), 0, st, (const uint16_t *)d_imgs, ws, n));
+        else FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<float>, dim3(pb, n), dim3(256), 0, st, (const float *)d_imgs, ws, n));
+        cimgs = ws;
+    }
     const Luts lut = current_luts();
     if (t2 > 0) {
-        if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, d_imgs, ws, n, lut, st)));
-        else if (elem == 2) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint16_t>(t2, d_imgs, ws, n, lut, st)));
-        else if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, d_imgs, ws, n, lut, st));
-        else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, d_imgs, ws, n, lut, st));
-        else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, d_imgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, cimgs, ws, n, lut, st)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint16_t>(t2, cimgs, ws, n, lut, st)));
+        else if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, cimgs, ws, n, lut, st));
+        else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, cimgs, ws, n, lut, st));
+        else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, cimgs, ws, n, lut, st));
     }
     if (t3 > 0) {
-        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, d_imgs, ws, n, lut, st)));
-        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, d_imgs, ws, n, lut, st)));
-        else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, d_imgs, ws, n, lut, st));
-        else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, d_imgs, ws, n, lut, st));
-        else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, d_imgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, cimgs, ws, n, lut, st)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, cimgs, ws, n, lut, st)));
+        else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, cimgs, ws, n, lut, st));
+        else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, cimgs, ws, n, lut, st));
+        else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, cimgs, ws, n, lut, st));
     }
     // resolve grid: the lists are a small share of the voxels for any field that is not noise,
     // so 256 threads per 64Ki voxels of the largest instance; the loops stride over the rest
-    const int64_t ml = max_list(h_shapes, n), mv = max_voxels(h_shapes, n);
     int64_t rb = (mv + 65535) / 65536;
     if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
     FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n));
     // volumes: the dual (resolve, union-find) beside H0; images: the dual after H0
-    const int htop = (flags & PH_HTOP) ? 1 : 0;
+    const int htop = (tf || (flags & PH_HTOP)) ? 1 : 0;   // T's H0 is the V top
     const unsigned side = htop && any3 ? 2 : 1;
     FC_LAUNCH(K_RESOLVE, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n, side), dim3(256), 0, st, ws, n, 0, htop));
     FC_LAUNCH(K_UF, hipLaunchKernelGGL(k_unionfind, dim3(n, side), dim3(kUfThreads), 0, st, ws, n, 0, htop));
@@ -1871,15 +2000,15 @@ int64_t ph_capacity_bound(ph_shape s) {
 }
 
 size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
-    (void)flags;
+    const bool tf = (flags & PH_TFILT) != 0;
     if (!h_shapes || n < 1) return 0;
     for (int i = 0; i < n; ++i)
-        if (!fc::valid_shape(h_shapes[i])) return 0;
+        if (!fc::valid_shape(h_shapes[i]) || (tf && !fc::valid_shape(fc::framed(h_shapes[i])))) return 0;
     int64_t t2, t3, best = 0;
     for (int a = 0; a < 3; ++a)                      // large enough for every tile choice
         for (int b = 0; b < 3; ++b) {
             ph_tuning t{a, b};
-            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3);
+            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3, tf);
             if (need > best) best = need;
         }
     return (size_t)best;
@@ -1899,7 +2028,8 @@ int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off, co
     if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1) return PH_EINVAL;
     ph_shape dummy{2, {1, 1, 1}};
     ph_tuning tuned;
-    if (!tuning && fc::tuned_for(h_shapes, n, &tuned)) tuning = &tuned;
+    // the recorded choices are those of V batches of the size class: a T batch takes the defaults
+    if (!tuning && !(flags & PH_TFILT) && fc::tuned_for(h_shapes, n, &tuned)) tuning = &tuned;
     return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
                    d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream);
 }
@@ -1910,9 +2040,9 @@ int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const p
                 ph_tuning *best, void *stream) {
     if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1 || reps < 1 || !best) return PH_EINVAL;
     ph_shape dummy0{2, {1, 1, 1}};
-    if (flags & (PH_IN_U8 | PH_IN_U16)) {
-        // integer inputs always take the default tiles: nothing to time, nothing recorded for
-        // the size class (float32 batches of the class keep their own choice)
+    if (flags & (PH_IN_U8 | PH_IN_U16 | PH_TFILT)) {
+        // integer inputs and T batches take the default tiles: nothing to time, nothing
+        // recorded for the size class (float32 V batches of the class keep their own choice)
         *best = ph_tuning{0, 0};
         return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy0, flags, out, d_out_off, 0, d_counts,
                        d_status, best, d_ws, ws_bytes, (hipStream_t)stream);

@@ -482,8 +482,15 @@ def _brev32(x):
     return r
 
 
+# float compares: lt..lg are ordered (false when either side is NaN), the n-forms are their
+# negations (true when either side is NaN); ne is the integer compare
 CMP = {"lt": np.less, "le": np.less_equal, "gt": np.greater, "ge": np.greater_equal,
-       "eq": np.equal, "ne": np.not_equal, "lg": np.not_equal}
+       "eq": np.equal, "ne": np.not_equal,
+       "lg": lambda x, y: np.less(x, y) | np.greater(x, y),
+       "neq": lambda x, y: ~np.equal(x, y), "nlt": lambda x, y: ~np.less(x, y),
+       "nle": lambda x, y: ~np.less_equal(x, y), "ngt": lambda x, y: ~np.greater(x, y),
+       "nge": lambda x, y: ~np.greater_equal(x, y),
+       "nlg": lambda x, y: ~(np.less(x, y) | np.greater(x, y))}
 
 
 def _perm_b32(a, b, c):
@@ -656,11 +663,12 @@ def _compile_salu(op, O, mods, nxt):
                 w.scc = 1 if c(a(w), b(w)) else 0
                 return nxt
         return f
-    if op == "s_bitcmp1_b32":
+    if op in ("s_bitcmp1_b32", "s_bitcmp0_b32"):
         a, b = rs(O[0]), rs(O[1])
+        want = 1 if op == "s_bitcmp1_b32" else 0
 
         def f(w):
-            w.scc = (a(w) >> (b(w) & 31)) & 1
+            w.scc = 1 if ((a(w) >> (b(w) & 31)) & 1) == want else 0
             return nxt
         return f
     d = ws(O[0])

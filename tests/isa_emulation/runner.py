@@ -158,16 +158,18 @@ class IsaRunner:
         return out
 
     # -------------------------------------------------------------- entry points --
-    def diagram(self, img: np.ndarray, capacity: int | None = None):
-        """(pairs, status, count) of ph_diagram on one image or volume"""
+    def diagram(self, img: np.ndarray, capacity: int | None = None, tfilt: bool = False):
+        """(pairs, status, count) of ph_diagram on one image or volume (T-filtration with
+        tfilt, flag 16)"""
         img = self.dev(as_input(img))
-        flags = 3 | IN_FLAGS[img.dtype]
+        flags = 3 | IN_FLAGS[img.dtype] | (16 if tfilt else 0)
         shp = make_shape(img.shape)
-        cap = int(self.host.ph_capacity_bound(shp)) if capacity is None else capacity
+        bound = make_shape(tuple(e + 2 for e in img.shape)) if tfilt else shp
+        cap = int(self.host.ph_capacity_bound(bound)) if capacity is None else capacity
         bufs, pr = self._pairs(cap)
         count = self.dev(np.full(1, -7, np.int64))
         status = self.dev(np.full(1, -77, np.int32))
-        nb = int(self.host.ph_workspace_bytes(ctypes.byref(shp), 1, 3))
+        nb = int(self.host.ph_workspace_bytes(ctypes.byref(shp), 1, flags))
         ws = self.dev(np.frombuffer(np.random.default_rng(5).bytes(nb), np.uint8).copy())
         rc = self.host.ph_diagram(img.ctypes.data, shp, flags, pr, cap, count.ctypes.data, status.ctypes.data,
                                   ws.ctypes.data, nb, None)

@@ -263,7 +263,8 @@ def test_gpu_suites_against_host_library():
     env = dict(os.environ, FC_TEST_HOST_LIBRARY=so)
     env.pop("FC_EMULATE_FULL", None)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-m", "gpu", "-p", "no:cacheprovider",
-                        os.path.join(tests, "test_gpu_parity.py"), os.path.join(tests, "test_gpu_full.py")],
+                        os.path.join(tests, "test_gpu_parity.py"), os.path.join(tests, "test_gpu_full.py"),
+                        os.path.join(tests, "test_gpu_tfilt.py")],
                        capture_output=True, text=True, timeout=1200, env=env, cwd=os.path.dirname(tests))
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     assert " passed" in r.stdout and " failed" not in r.stdout

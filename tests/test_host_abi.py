@@ -148,3 +148,15 @@ def test_both_integer_input_flags_rejected():
     sh = (fc.ph_shape * 1)(fc.make_shape((4, 4)))
     assert L.ph_diagram_batch(1, one, one, one, sh, flags, pr, one, one, one, None, one, 1 << 20,
                               None) == fc.PH_EINVAL
+
+
+def test_t_filtration_sizes():
+    """Under PH_TFILT the workspace holds the framed dual images (extents + 2) and their lists,
+    and the capacity bound is that of the framed shape."""
+    sh = [(64, 64), (16, 16, 16)]
+    v = fc.workspace_bytes(sh)
+    t = fc.workspace_bytes(sh, fc.PH_H0 | fc.PH_HTOP | fc.PH_TFILT)
+    assert t > v + 4 * (66 * 66 + 18 ** 3)
+    assert fc.capacity_bound((3, 3), "T") == fc.capacity_bound((5, 5))
+    big = (1 << 13, (1 << 14) - 2)                     # fits, its frame does not
+    assert fc.workspace_bytes([big], fc.PH_H0 | fc.PH_HTOP | fc.PH_TFILT) == 0

@@ -149,3 +149,14 @@ def test_integer_inputs(isa):
         g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
         np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
         off += img.size
+
+
+def test_t_filtration(isa):
+    """PH_TFILT: the framed dual image (k_tpad) through the V kernels and back (k_output) gives
+    the oracle's T-filtration pairs, for float32 and uint8 inputs."""
+    for shape, sigma in (((30, 26), 2.0), ((9, 8, 11), 1.5)):
+        g = S.grf(shape, sigma, 81)
+        for img in (g, np.round(g * 7).astype(np.uint8)):
+            got, st, _ = isa.diagram(img, tfilt=True)
+            ref = oracle.diagram(np.asarray(img, np.float32), filtration="T")
+            assert st == 0 and diff_pairs(got, ref) is None, (shape, img.dtype)
