@@ -434,6 +434,29 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
     for b in b8:
         b.check()
 
+    # the same instances under the T-filtration (pixels as top cells, PH_TFILT): sized by a
+    # first call, then timed like the batched form (parity of this path is the T test suite's)
+    print("bench: batched forward + backward, T-filtration (graph replay)", file=sys.stderr, flush=True)
+    src = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)) for a in imgs]
+    sz = fc.Batch(shapes, device=dev, filtration="T")
+    sz.set_images(src)
+    batched_step(sz)
+    sync()
+    sz.check()
+    caps_t = sz.counts.cpu().numpy().tolist()
+    del sz
+    b_t = []
+    for _ in range(2):
+        b = fc.Batch(shapes, device=dev, capacities=caps_t, filtration="T")
+        b.set_images(src)
+        b_t.append(b)
+    g_t = [capture(lambda b=b: batched_step(b)) for b in b_t]
+    t_t = timed(lambda k: g_t[k % 2]())
+    for b in b_t:
+        b.check()
+        if not np.array_equal(b.counts.cpu().numpy(), np.asarray(caps_t)):
+            raise SystemExit("bench: T-filtration pair counts changed between calls")
+
     nvox = sum(int(np.prod(s)) for s in shapes)
     sb = step_bytes(prof.keys(), wc, npairs, shapes)
     fb = sb - algorithmic_bytes("k_zero", wc, npairs, shapes) - algorithmic_bytes("k_scatter", wc, npairs, shapes)
@@ -447,6 +470,8 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
             "per_image_fwd_bwd": {"value": round(nvox / t_p / 1e6, 3), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p)},
             "batched_fwd_bwd_u8": {"value": round(nvox / t_8 / 1e6, 3), "ms": round(t_8 * 1e3, 4),
                                    "input": "the same instances quantised to 256 levels, uint8"},
+            "batched_fwd_bwd_tfilt": {"value": round(nvox / t_t / 1e6, 3), "ms": round(t_t * 1e3, 4),
+                                      "input": "the same instances under the T-filtration"},
         },
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},

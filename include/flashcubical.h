@@ -68,7 +68,7 @@ enum {
  * always uses the default tiles.
  *
  * PH_TFILT selects the T-filtration (paper Sec. 2.2, its dual construction; the extension
- * the paper's Sec. 7 names): the pixels are the top cells of a complex on (n+1) vertices per
+ * the paper's Sec. 6 names): the pixels are the top cells of a complex on (n+1) vertices per
  * axis, and a cell enters with the first top cell that contains it (value = minimum over the
  * top cells containing it; ties go to the smaller pixel index, then lower dimension, then
  * smaller doubled-grid index).  By Alexander duality this complex is the dual cell complex of

@@ -32,7 +32,7 @@
  * top cells of a complex on (H+1)x(W+1) [(D+1)x(H+1)x(W+1)] vertices.  A cell's value is
  * the minimum over the top cells that contain it; the first-order tie-break is the top cell
  * through which the cell enters, i.e. the minimum of those top cells under the pixel order
- * (value, then row-major pixel index): the pseudo lower star the paper's Sec. 3 names for
+ * (value, then row-major pixel index): the pseudo lower star the paper's Sec. 3.3 names for
  * this case.  The rest of the order (dimension, then doubled-grid cell index) and the
  * reduction are those of the V case.  birth_vertex / death_vertex name the pixel whose
  * value the cell takes.  Output order: by dimension, then by the death cell's position in

@@ -225,7 +225,8 @@ def test_bench_flow_against_host_library():
     assert r.returncode == 0, r.stderr[-4000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
-    assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd", "per_image_fwd_bwd", "batched_fwd_bwd_u8"}
+    assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd", "per_image_fwd_bwd", "batched_fwd_bwd_u8",
+                                  "batched_fwd_bwd_tfilt"}
     assert line["cpu_baseline"]["kind"] == "oracle" and line["work"]["pairs"] > 0
 
 
