@@ -1377,6 +1377,7 @@ __global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ 
 // with the frame added; the reflection makes the V tie-break (larger index enters later) the
 // T one read backwards.  A +inf pixel would tie the frame: it becomes NaN, which the
 // classify pass reports as PH_ENAN.
+constexpr int kTpadRows = 16;                       // framed rows per wave step in k_tpad
 template <typename T>
 __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t *__restrict__ ws, int n) {
     const int i = blockIdx.y;
@@ -1385,18 +1386,38 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
     if (!I.tfilt || failed(cnt)) return;
     float *g = (float *)ws + I.img_off;
     const bool vol = I.ndim == 3;
-    const int D = I.D, H = I.H, W = I.W, HW = H * W;   // framed extents (D = 1 for an image)
+    const int D = I.D, H = I.H, W = I.W;               // framed extents (D = 1 for an image)
     const int sD = vol ? D - 2 : 1, sH = H - 2, sW = W - 2;
-    const int N = (int)I.N;                            // < 2^27
-    for (int p = blockIdx.x * 256 + threadIdx.x; p < N; p += gridDim.x * 256) {
-        const int z = p / HW, r = p - z * HW, y = r / W, x = r - y * W;
-        float v = __int_as_float(0xff800000);          // -inf
-        if ((!vol || (z >= 1 && z <= D - 2)) && y >= 1 && y <= H - 2 && x >= 1 && x <= W - 2) {
-            const int q = ((vol ? sD - z : 0) * sH + (sH - y)) * sW + (sW - x);
-            const float f = (float)src[I.src_off + q];
-            v = f == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -f;
+    const int lane = threadIdx.x & 63, rows = D * H;
+    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), waves = gridDim.x * 4;
+    // each wave takes kTpadRows framed rows at a time, lanes along x, so that that many loads
+    // are in flight per wave; a row's coordinates are found once per row
+    for (int r0 = wave * kTpadRows; r0 < rows; r0 += waves * kTpadRows) {
+        int64_t qrow[kTpadRows];
+        bool inner[kTpadRows];
+#pragma unroll
+        for (int k = 0; k < kTpadRows; ++k) {
+            const int r = r0 + k, z = r / H, y = r - z * H;
+            inner[k] = r < rows && (!vol || (z >= 1 && z <= D - 2)) && y >= 1 && y <= H - 2;
+            qrow[k] = I.src_off + ((int64_t)(vol ? sD - z : 0) * sH + (sH - y)) * sW + sW;
         }
-        g[p] = v;
+        for (int x = lane; x < W; x += 64) {
+            const bool col = x >= 1 && x <= W - 2;
+            // loads without branches (a frame pixel reads the instance's first pixel and drops
+            // it), so that all of them are issued before the first wait
+            float f[kTpadRows];
+#pragma unroll
+            for (int k = 0; k < kTpadRows; ++k)
+                f[k] = (float)src[inner[k] && col ? qrow[k] - x : I.src_off];   // source column sW - x
+            float v[kTpadRows];
+#pragma unroll
+            for (int k = 0; k < kTpadRows; ++k)
+                v[k] = !(inner[k] && col) ? __int_as_float(0xff800000)           // -inf
+                       : f[k] == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -f[k];
+#pragma unroll
+            for (int k = 0; k < kTpadRows; ++k)
+                if (r0 + k < rows) g[(int64_t)(r0 + k) * W + x] = v[k];
+        }
     }
 }
 
@@ -1944,7 +1965,14 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     const int64_t ml = max_list(hs, n), mv = max_voxels(hs, n);
     const void *cimgs = d_imgs;                    // what the classify passes read
     if (tf) {
-        const unsigned pb = (unsigned)std::min<int64_t>(std::max<int64_t>((mv + 2047) / 2048, 1), 4096);
+        // about 2048 blocks over the batch, at most one per 4 * kTpadRows rows (four waves)
+        // of the instance with the most framed rows
+        int64_t mrows = 1;
+        for (int i = 0; i < n; ++i) {
+            const ph_shape &f = framed_shapes[i];
+            mrows = std::max<int64_t>(mrows, f.ndim == 3 ? (int64_t)f.ext[0] * f.ext[1] : f.ext[0]);
+        }
+        const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((2048 + n - 1) / n, (mrows + 4 * kTpadRows - 1) / (4 * kTpadRows)));
         if (in_elem == 1) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint8_t>, dim3(pb, n), dim3(256), 0, st, (const uint8_t *)d_imgs, ws, n));
         else if (in_elem == 2) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint16_t>, dim3(pb, n), dim3(256), 0, st, (const uint16_t *)d_imgs, ws, n));
         else FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<float>, dim3(pb, n), dim3(256), 0, st, (const float *)d_imgs, ws, n));
