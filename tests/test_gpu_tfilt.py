@@ -177,3 +177,51 @@ def test_autograd_function_under_t():
     dd = np.where(f, p["death"] - p["birth"], 0).astype(np.float32)
     ref = oracle.gradient(p, -2 * dd, 2 * dd, x0.shape)
     np.testing.assert_allclose(x.grad.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+
+
+def test_graph_replay_t():
+    """A T forward + backward captured in a HIP graph replays to the eager results (the frame
+    is written by a kernel, nothing by a memset)."""
+    if HOST_MODE:
+        pytest.skip("graph capture needs the GPU")
+    imgs = mixed_batch()
+    bt = fc.Batch([a.shape for a in imgs], device=DEV, filtration="T")
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+
+    def step():
+        bt.ph_diagram_batch()
+        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+        bt.ph_backward((-2.0 * diff).contiguous(), (2.0 * diff).contiguous())
+
+    step()
+    sync()
+    ref, g_ref = bt.results(), bt.grad.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        step()
+    for rep in range(3):
+        bt.pairs.birth.fill_(float("nan"))
+        bt.grad.fill_(123.0)
+        bt.ws.fill_(0x5A)
+        sync()
+        graph.replay()
+        sync()
+        for a, b in zip(bt.results(), ref):
+            assert diff_pairs(a, b) is None, "replay %d" % rep
+        assert torch.equal(bt.grad, g_ref), "replay %d" % rep
+
+
+@pytest.mark.skipif(HOST_MODE, reason="full size against the host build takes minutes")
+def test_full_size_bench_instances_t():
+    """One 96^3 volume (sigma 3) and one 512^2 image (sigma 6) of the bench workload, batched
+    under T with the bench's default launch configuration, against the T oracle."""
+    imgs = [S.grf((96, 96, 96), 3.0, 2000), S.grf((512, 512), 6.0, 3000)]
+    bt = fc.Batch([a.shape for a in imgs], device=DEV, filtration="T")
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+    bt.ph_diagram_batch()
+    sync()
+    bt.check()
+    for img, r in zip(imgs, bt.results()):
+        print("oracle T", img.shape, flush=True)
+        assert diff_pairs(r, oracle.diagram(img, filtration="T")) is None, img.shape
