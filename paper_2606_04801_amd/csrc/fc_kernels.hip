@@ -1390,8 +1390,8 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
     const int sD = vol ? D - 2 : 1, sH = H - 2, sW = W - 2;
     const int lane = threadIdx.x & 63, rows = D * H;
     const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), waves = gridDim.x * 4;
-    // each wave takes kTpadRows framed rows at a time, lanes along x, so that that many loads
-    // are in flight per wave; a row's coordinates are found once per row
+    // each wave takes kTpadRows framed rows at a time, so that that many loads are in flight
+    // per wave; a row's coordinates are found once per row
     for (int r0 = wave * kTpadRows; r0 < rows; r0 += waves * kTpadRows) {
         int64_t qrow[kTpadRows];
         bool inner[kTpadRows];
@@ -1399,24 +1399,32 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
         for (int k = 0; k < kTpadRows; ++k) {
             const int r = r0 + k, z = r / H, y = r - z * H;
             inner[k] = r < rows && (!vol || (z >= 1 && z <= D - 2)) && y >= 1 && y <= H - 2;
-            qrow[k] = I.src_off + ((int64_t)(vol ? sD - z : 0) * sH + (sH - y)) * sW + sW;
+            qrow[k] = I.src_off + ((int64_t)(vol ? sD - z : 0) * sH + (sH - y)) * sW;   // source row start
         }
-        for (int x = lane; x < W; x += 64) {
-            const bool col = x >= 1 && x <= W - 2;
-            // loads without branches (a frame pixel reads the instance's first pixel and drops
-            // it), so that all of them are issued before the first wait
+        // source columns c0 .. c0+63, loaded in ascending order by lanes 0..63; framed column
+        // sW - c holds source column c, so lane l stores framed column sW - c0 - 63 + l with the
+        // value lane 63 - l loaded, and the stores ascend too
+        for (int c0 = 0; c0 < sW; c0 += 64) {
+            const int c = c0 + lane;
             float f[kTpadRows];
 #pragma unroll
             for (int k = 0; k < kTpadRows; ++k)
-                f[k] = (float)src[inner[k] && col ? qrow[k] - x : I.src_off];   // source column sW - x
-            float v[kTpadRows];
+                f[k] = (float)src[inner[k] && c < sW ? qrow[k] + c : I.src_off];
+            const int cs = c0 + 63 - lane;             // the source column this lane stores
+            const int x = sW - cs;                     // its framed column, >= 1 when cs < sW
+#pragma unroll
+            for (int k = 0; k < kTpadRows; ++k) {
+                const float fk = __int_as_float(__shfl((int)__float_as_uint(f[k]), 63 - lane, 64));
+                const float v = !inner[k] ? __int_as_float(0xff800000)                 // -inf
+                                : fk == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -fk;
+                if (r0 + k < rows && cs < sW) g[(int64_t)(r0 + k) * W + x] = v;
+            }
+        }
+        // the frame's first and last column of every row
+        if (lane < 2) {
 #pragma unroll
             for (int k = 0; k < kTpadRows; ++k)
-                v[k] = !(inner[k] && col) ? __int_as_float(0xff800000)           // -inf
-                       : f[k] == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -f[k];
-#pragma unroll
-            for (int k = 0; k < kTpadRows; ++k)
-                if (r0 + k < rows) g[(int64_t)(r0 + k) * W + x] = v[k];
+                if (r0 + k < rows) g[(int64_t)(r0 + k) * W + (lane ? W - 1 : 0)] = __int_as_float(0xff800000);
         }
     }
 }

@@ -1262,6 +1262,19 @@ def _compile_ds(op, O, mods, nxt):
     kind = op[3:]
     off = _offset(mods)
 
+    if kind == "bpermute_b32":
+        # lane l of the result takes data from lane ((addr[l] + offset) / 4) mod 64; a source
+        # lane outside exec gives 0; no LDS memory is touched
+        di, va, vd = O[0].idx, r32(O[1]), r32(O[2])
+
+        def f(w):
+            e = w.exec()
+            lane = ((vec(va(w)).astype(np.int64) + off) >> 2) & 63
+            data = np.where(e, vec(vd(w)), U32(0)).astype(U32)
+            w.v[di] = np.where(e, data[lane], w.v[di])
+            return nxt
+        return f
+
     def lds(w, addrs, n, what):
         lim = w.wg.lds_size
         bad = (addrs < 0) | (addrs + n > lim)
