@@ -102,7 +102,8 @@ def cpu_baseline(workers: int):
 
 
 def algorithmic_bytes(name, wc, npairs, shapes):
-    """Bytes one launch of `name` must move over the whole batch (model stated in the design doc).
+    """Bytes one launch of `name` must move over the whole batch: the unavoidable reads and
+    writes of its inputs and outputs (pixels, forest arrays, list keys, pairs), no re-reads.
 
     wc: per-instance work counters (KEEP edges, KEEP squares, H0 nodes, dual nodes, ...)."""
     is3 = np.array([len(s) == 3 for s in shapes])
