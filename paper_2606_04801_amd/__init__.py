@@ -11,6 +11,7 @@ Entry points (same names as the C ABI):
   Batch.ph_autotune               tile choice timed on the batch, kept for its size class
   Batch.ph_backward / ph_backward gradient scatter to the critical pixels
   PHDiagramFn                     torch.autograd.Function around ph_diagram / ph_backward
+  BatchDiagramFn                  torch.autograd.Function around ph_diagram_batch / ph_backward
   Batch.work_counters, profile / profile_read, device_report: inspection
 """
 from __future__ import annotations
@@ -428,7 +429,11 @@ def _autograd():
 
     class PHDiagramFn(torch.autograd.Function):
         """(birth, death, dim) of the pairs of one image/volume; backward scatters dL/dbirth
-        and dL/ddeath to the pixels attaining each critical cell's value (ph_backward)."""
+        and dL/ddeath to the pixels attaining each critical cell's value (ph_backward).
+
+        Upstream gradients pass through unchanged, non-finite ones included: only the death
+        of the essential class (+inf, no death pixel) has nothing to receive its gradient,
+        which ph_backward skips."""
 
         @staticmethod
         def forward(ctx, img, filtration="V"):
@@ -447,8 +452,6 @@ def _autograd():
             n = ctx.n
             gb = g_birth.contiguous() if g_birth is not None else torch.zeros(n, device=dev)
             gd = g_death.contiguous() if g_death is not None else torch.zeros(n, device=dev)
-            gb = torch.nan_to_num(gb, nan=0.0, posinf=0.0, neginf=0.0)
-            gd = torch.nan_to_num(gd, nan=0.0, posinf=0.0, neginf=0.0)
             gimg = torch.empty(ctx.shape, dtype=torch.float32, device=dev)
             counts = torch.tensor([n], dtype=torch.int64, device=dev)
             out_off = torch.tensor([0, max(n, 1)], dtype=torch.int64, device=dev)
@@ -456,16 +459,59 @@ def _autograd():
             ph_backward(ctx.bufs, counts, out_off, img_off, gb, gd, gimg)
             return gimg, None
 
-    return PHDiagramFn
+    class BatchDiagramFn(torch.autograd.Function):
+        """Diagrams of every instance of a Batch in one ph_diagram_batch call, with the
+        packed pixels as the differentiable input.
+
+        forward(images, batch) -> (birth, death): float32 over every pair slot of the batch
+        (batch.pairs.cap entries, instance i from batch.out_off_h[i]); slots past an
+        instance's count hold no pair: batch.valid_mask() marks the stored ones, and
+        batch.pairs.death_cell >= 0 the finite ones.  `images` is the batch's packed float32
+        input; when it is not batch.images itself it is copied there first.  backward
+        scatters dL/dbirth and dL/ddeath to the critical pixels (ph_backward) into a new
+        gradient tensor, from the pair vertices and counts this forward saved, so a later
+        forward on the same batch does not change it.  Captured in a HIP graph together
+        with the loss and its backward, a replay recomputes everything in place."""
+
+        @staticmethod
+        def forward(ctx, images, batch):
+            if batch.dtype != torch.float32 or images.dtype != torch.float32 or images.numel() != batch.total_voxels:
+                raise PHError(PH_EINVAL, "BatchDiagramFn: float32 images of the batch's total size")
+            if images.data_ptr() != batch.images.data_ptr():
+                batch.images.copy_(images.detach().reshape(-1))
+            batch.ph_diagram_batch()
+            ctx.batch = batch
+            ctx.save_for_backward(batch.pairs.birth_vertex.clone(), batch.pairs.death_vertex.clone(),
+                                  batch.counts.clone())
+            ctx.img_shape = images.shape
+            return batch.pairs.birth.clone(), batch.pairs.death.clone()
+
+        @staticmethod
+        def backward(ctx, g_birth, g_death):
+            b = ctx.batch
+            bv, dv, counts = ctx.saved_tensors
+            cap = bv.numel()
+            dev = bv.device
+            gb = g_birth.contiguous() if g_birth is not None else torch.zeros(cap, device=dev)
+            gd = g_death.contiguous() if g_death is not None else torch.zeros(cap, device=dev)
+            pairs = ph_pairs(None, None, None, None, None, bv.data_ptr(), dv.data_ptr())
+            gimg = torch.empty(b.total_voxels, dtype=torch.float32, device=dev)
+            rc = lib().ph_backward(b.n, pairs, _ptr(b.out_off), _ptr(counts), _ptr(gb), _ptr(gd), _ptr(gimg),
+                                   _ptr(b.img_off), b.total_voxels, _stream_ptr(None))
+            if rc != PH_OK:
+                raise PHError(rc, "ph_backward")
+            return gimg.view(ctx.img_shape), None
+
+    return PHDiagramFn, BatchDiagramFn
 
 
 _fn_cache = []
 
 
 def __getattr__(name):
-    # the autograd class is made on first use so that importing this module needs no torch
-    if name == "PHDiagramFn":
+    # the autograd classes are made on first use so that importing this module needs no torch
+    if name in ("PHDiagramFn", "BatchDiagramFn"):
         if not _fn_cache:
-            _fn_cache.append(_autograd())
-        return _fn_cache[0]
+            _fn_cache.extend(_autograd())
+        return _fn_cache[0] if name == "PHDiagramFn" else _fn_cache[1]
     raise AttributeError(name)

@@ -2,6 +2,9 @@
 
     python tests/golden/make_digests.py [--jobs 6] [--only c1,c2,...]
 
+Configs c1..c5 are under the V-filtration; c5t is c5's 128 instances under the T-filtration
+(pixels as top cells), whose pairs come in the T output order (dim, death key).
+
 Calls only the CPU oracle (oracle/) and the seeded generators (synthetic.py).  For every
 instance it stores the digest of its input pixels (so a change of generator is caught), the
 number of H0 and top-dimension pairs, and a SHA-256 over the pairs in output order, packed
@@ -56,7 +59,13 @@ def instances():
         out.append(("c5", i, "grf", ((96, 96, 96), 3.0, 2000 + i)))
     for i in range(64):
         out.append(("c5", 64 + i, "grf", ((512, 512), 6.0, 3000 + i)))
+    out += [("c5t",) + it[1:] for it in out if it[0] == "c5"]
     return out
+
+
+def filtration_of(cfg) -> str:
+    """"T" for the T-filtration configs (name ending in t), else "V"."""
+    return "T" if cfg.endswith("t") else "V"
 
 
 def make(kind, args):
@@ -75,7 +84,7 @@ def job(item):
     cfg, idx, kind, args = item
     img = make(kind, args)
     t0 = time.perf_counter()
-    p = oracle.diagram(img)
+    p = oracle.diagram(img, filtration=filtration_of(cfg))
     dt = time.perf_counter() - t0
     top = img.ndim - 1
     return cfg, idx, {"shape": list(img.shape), "input_sha256": input_digest(img),
@@ -92,7 +101,7 @@ def main():
     if a.only:
         keep = set(a.only.split(","))
         items = [it for it in items if it[0] in keep]
-    items.sort(key=lambda it: 0 if it[0] == "c3" else 1)       # the longest job first
+    items.sort(key=lambda it: 0 if it[0] == "c3" else (1 if len(it[3][0]) == 3 else 2))   # longest first
     path = os.path.join(HERE, "digests.json")
     doc = json.load(open(path)) if os.path.exists(path) else {}
     doc["_about"] = ("oracle diagrams of the full-size workloads (H0 + top dimension), written by "

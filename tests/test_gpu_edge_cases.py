@@ -1,0 +1,105 @@
+"""Edge cases on the GPU, each compared field by field with the oracle through the C ABI:
+the union-find's sequential finish (a staircase row whose H0 merges each wait for the one
+before, so the parallel rounds run out: the work counters must show edges finished
+sequentially), long strips along every axis, an all-ties checkerboard, a constant image,
+a 64x64 permutation, a thin volume with few levels, and IEEE special values; the same cases
+batched together, and under the T-filtration."""
+import numpy as np
+import pytest
+
+import oracle
+import synthetic as S
+from gpu_util import diff_pairs, device_for_tests
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2606_04801_amd as fc  # noqa: E402
+
+DEV, HOST_MODE = device_for_tests(fc, torch)
+if DEV is None:
+    pytest.skip("no GPU", allow_module_level=True)
+
+
+def staircase(n):
+    """1 x (2n+1) row: minima decreasing to the right, saddles increasing to the right."""
+    a = np.zeros(2 * n + 1, np.float32)
+    a[0::2] = np.linspace(0.5, 0.1, n + 1).astype(np.float32)
+    a[1::2] = np.linspace(1.0, 2.0, n).astype(np.float32)
+    return a.reshape(1, -1)
+
+
+def specials():
+    s = np.array([[np.inf, -np.inf, -0.0, 0.0, 1e-45, -1e-45, 3.4e38, -3.4e38]] * 5, np.float32)
+    s[2:] = s[2:, ::-1]
+    return s
+
+
+CASES = {
+    "staircase": lambda: staircase(150),
+    "staircase_mirror": lambda: staircase(150)[:, ::-1].copy(),
+    "staircase_column": lambda: staircase(150).T.copy(),
+    "staircase_volume_x": lambda: staircase(150).reshape(1, 1, -1),
+    "staircase_volume_z": lambda: staircase(150).reshape(-1, 1, 1).copy(),
+    "zeros": lambda: np.zeros((17, 23), np.float32),
+    "checkerboard": lambda: (np.indices((33, 47)).sum(axis=0) % 2).astype(np.float32),
+    "checkerboard_3d": lambda: (np.indices((9, 11, 10)).sum(axis=0) % 2).astype(np.float32),
+    "strip_1x5000": lambda: S.levels((1, 5000), 7, 1),
+    "strip_5000x1": lambda: S.levels((5000, 1), 7, 2),
+    "strip_1x1x3000": lambda: S.levels((1, 1, 3000), 5, 3),
+    "strip_3000x1x1": lambda: S.levels((3000, 1, 1), 5, 4),
+    "strip_1x3000x1": lambda: S.levels((1, 3000, 1), 5, 6),
+    "thin_2x2x700": lambda: S.levels((2, 2, 700), 3, 5),
+    "specials": specials,
+    "permutation_64": lambda: np.random.default_rng(5).permutation(64 * 64).reshape(64, 64).astype(np.float32),
+}
+SEQUENTIAL = {"staircase", "staircase_mirror", "staircase_column", "staircase_volume_x", "staircase_volume_z"}
+
+
+def single(img, filtration="V"):
+    print("case", img.shape, filtration, flush=True)
+    return fc.ph_diagram(torch.from_numpy(np.ascontiguousarray(img)).to(DEV), filtration=filtration).numpy()
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_edge_case_single(name):
+    img = CASES[name]()
+    assert diff_pairs(single(img), oracle.diagram(img)) is None, name
+
+
+@pytest.mark.parametrize("name", sorted(SEQUENTIAL))
+def test_sequential_finish_runs(name):
+    """The staircases leave live edges after the parallel rounds: the work counters show
+    edges finished by the sequential pass, and the result is still the oracle's."""
+    img = CASES[name]()
+    bt = fc.Batch([img.shape], device=DEV)
+    bt.set_images([torch.from_numpy(img)])
+    bt.ph_diagram_batch()
+    (got,) = bt.results()
+    assert diff_pairs(got, oracle.diagram(img)) is None
+    wc = bt.work_counters()
+    assert wc[0, 4] == 48 and wc[0, 6] > 0, wc[0]          # rounds at the limit, edges finished in order
+
+
+def test_edge_cases_batched():
+    """Every case in one batch: each instance bitwise the oracle's."""
+    imgs = [CASES[k]() for k in sorted(CASES)]
+    bt = fc.Batch([a.shape for a in imgs], device=DEV)
+    bt.set_images([torch.from_numpy(np.ascontiguousarray(a)) for a in imgs])
+    print("batch of", len(imgs), flush=True)
+    bt.ph_diagram_batch()
+    for name, a, got in zip(sorted(CASES), imgs, bt.results()):
+        assert diff_pairs(got, oracle.diagram(a)) is None, name
+    assert bt.work_counters()[:, 6].sum() > 0
+
+
+@pytest.mark.parametrize("name", sorted(k for k in CASES if k != "specials"))
+def test_edge_case_t_filtration(name):
+    img = CASES[name]()
+    assert diff_pairs(single(img, "T"), oracle.diagram(img, filtration="T")) is None, name
+
+
+def test_specials_t_filtration_without_plus_inf():
+    img = specials()
+    img[np.isposinf(img)] = 3.0e38
+    assert diff_pairs(single(img, "T"), oracle.diagram(img, filtration="T")) is None

@@ -213,15 +213,27 @@ def test_graph_replay_t():
 
 
 @pytest.mark.skipif(HOST_MODE, reason="full size against the host build takes minutes")
-def test_full_size_bench_instances_t():
-    """One 96^3 volume (sigma 3) and one 512^2 image (sigma 6) of the bench workload, batched
-    under T with the bench's default launch configuration, against the T oracle."""
-    imgs = [S.grf((96, 96, 96), 3.0, 2000), S.grf((512, 512), 6.0, 3000)]
+def test_full_size_bench_batch_t_against_digests():
+    """All 128 instances of the bench workload (64 volumes 96^3 sigma 3, 64 images 512^2
+    sigma 6) in one T batch with the bench's launch configuration, each against the digest of
+    the T oracle's diagram (tests/golden/make_digests.py, config c5t)."""
+    import json
+    import os
+    from golden.make_digests import instances, make, pair_digest, input_digest
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "digests.json")
+    dig = json.load(open(path)).get("c5t")
+    if not dig:
+        pytest.skip("no c5t digests")
+    its = [it for it in instances() if it[0] == "c5t"]
+    imgs = [make(kind, args) for _, _, kind, args in its]
     bt = fc.Batch([a.shape for a in imgs], device=DEV, filtration="T")
     bt.set_images([torch.from_numpy(a) for a in imgs])
+    print("T batch of", len(imgs), flush=True)
     bt.ph_diagram_batch()
     sync()
-    bt.check()
-    for img, r in zip(imgs, bt.results()):
-        print("oracle T", img.shape, flush=True)
-        assert diff_pairs(r, oracle.diagram(img, filtration="T")) is None, img.shape
+    for (c, idx, _, _), img, r in zip(its, imgs, bt.results()):
+        rec = dig[str(idx)]
+        assert rec["input_sha256"] == input_digest(img), "input generator changed"
+        top = img.ndim - 1
+        assert (int((r["dim"] == 0).sum()), int((r["dim"] == top).sum())) == (rec["h0"], rec["htop"]), idx
+        assert pair_digest(r) == rec["pairs_sha256"], idx

@@ -235,3 +235,28 @@ def test_signed_zero_and_infinities():
     assert _ref.multiset_of(pr) == _ref.persistent_betti_multiset(img)
     ess = pr[pr["death_cell"] < 0]
     assert len(ess) == 1 and ess["birth_vertex"][0] == 4     # -inf pixel is the minimum
+
+
+def test_output_order_is_refined_birth_order_under_ties():
+    """Pairs come by (dim, position of the birth cell in the refined order of Sec. 2.3), the
+    order _ref.Complex builds on its own (lexsort of lower-star vertex rank, dimension, cell
+    index).  Inputs with few levels make that order differ from the birth cell index, the
+    birth value alone, or the death key, so a sort on any of those fails here."""
+    witnessed = 0
+    for k in range(40):
+        nd = 2 + (k % 2)
+        rng = np.random.default_rng(8100 + k)
+        shape = tuple(int(x) for x in rng.integers(3, 9 if nd == 2 else 5, size=nd))
+        img = S.levels(shape, int(rng.choice([2, 3, 4])), 8200 + k)
+        cx = _ref.Complex(img)
+        dims = (0, 1, 2) if nd == 3 else (0, 1)
+        pr = oracle.diagram(img, dims=dims, method=oracle.FULL)
+        key = [(int(p["dim"]), int(cx.pos[int(p["birth_cell"])])) for p in pr]
+        assert key == sorted(key) and len(set(key)) == len(key), (shape, k)
+        # each dimension's pairs are in strictly increasing refined position of the birth
+        for d in dims:
+            sel = pr[pr["dim"] == d]
+            if len(sel) > 1:
+                cells = sel["birth_cell"].tolist()
+                witnessed += cells != sorted(cells)
+    assert witnessed >= 5, "the inputs never separate the refined order from the cell index"

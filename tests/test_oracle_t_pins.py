@@ -188,3 +188,51 @@ def test_full_and_split_reductions_agree():
         a = T(img, method=oracle.FULL)
         a = a[(a["dim"] == 0) | (a["dim"] == nd - 1)]
         assert same(a, T(img, method=oracle.SPLIT)) is None
+
+
+def t_death_key(img, cell):
+    """Refined T key of a cell of the T doubled grid (extents 2n+1, an image seen as one
+    layer): (value, pixel index of the entry top cell, dimension, cell index), the entry top
+    cell being the (value, index)-smallest pixel whose closed cell contains it."""
+    a = img.reshape((1,) * (3 - img.ndim) + img.shape)
+    n = a.shape
+    d = [1 if img.ndim == 2 and k == 0 else 2 * n[k] + 1 for k in range(3)]
+    z, rem = divmod(int(cell), d[1] * d[2])
+    y, x = divmod(rem, d[2])
+    co = (z, y, x)
+    choices = []
+    for k in range(3):
+        c = co[k]
+        if img.ndim == 2 and k == 0:
+            choices.append([0])
+        elif c % 2:
+            choices.append([(c - 1) // 2])
+        else:
+            choices.append([p for p in (c // 2 - 1, c // 2) if 0 <= p < n[k]])
+    best = min((float(a[i, j, l]) + 0.0, (i * n[1] + j) * n[2] + l)
+               for i in choices[0] for j in choices[1] for l in choices[2])
+    dim = sum(1 for k in range(3 - img.ndim, 3) if co[k] % 2 == 1)
+    return best + (dim, int(cell))
+
+
+def test_t_output_order_is_death_key_essential_last():
+    """T pairs come by (dim, refined T key of the death cell), the essential class last in
+    H0; the key is recomputed here from the T definition (Sec. 2.2) and reading T1.  Tied
+    inputs make the death key order differ from the death cell index and from the birth
+    order, so a sort on either fails."""
+    witnessed = 0
+    for k in range(60):
+        nd = 2 + (k % 2)
+        rng = np.random.default_rng(8300 + k)
+        shape = tuple(int(x) for x in rng.integers(4, 10 if nd == 2 else 6, size=nd))
+        img = S.levels(shape, int(rng.choice([2, 3, 4])), 8400 + k)
+        pr = T(img)
+        key = [(int(p["dim"]), 1, ()) if p["death_cell"] < 0 else
+               (int(p["dim"]), 0, t_death_key(img, p["death_cell"])) for p in pr]
+        assert key == sorted(key) and len(set(key)) == len(key), (shape, k)
+        assert int((pr["death_cell"] < 0).sum()) == 1 and pr["death_cell"][(pr["dim"] == 0).sum() - 1] == -1
+        for d in (0, nd - 1):
+            sel = pr[(pr["dim"] == d) & (pr["death_cell"] >= 0)]
+            if len(sel) > 1:
+                witnessed += sel["death_cell"].tolist() != sorted(sel["death_cell"].tolist())
+    assert witnessed >= 5, "the inputs never separate the death key order from the cell index"
