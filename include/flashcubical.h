@@ -26,7 +26,8 @@
  *   - Memory: every pointer named d_* is device memory owned by the caller; h_* is host
  *     memory.  The library allocates nothing per call.  It owns only its lookup tables,
  *     built on the host and copied once per device on first use into device buffers it
- *     keeps until the process ends (about 1.2 MB per device).
+ *     keeps until the process ends (about 1.2 MB per device), and the workspace array of
+ *     ph_diagram_noalloc (PH_NOALLOC_SCRATCH_MIB per device, part of its code object).
  *   - Streams: all work is enqueued on `stream`.  ph_diagram, ph_diagram_batch and
  *     ph_backward never synchronise with the host, so a sequence of them can be captured in a
  *     HIP graph; results are valid once the stream has reached them.  ph_autotune and the
@@ -132,6 +133,22 @@ int ph_diagram(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
                int64_t capacity, int64_t *d_count, int32_t *d_status, void *d_ws,
                size_t ws_bytes, void *stream);
 
+/* ph_diagram for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Arguments and results as for
+ * ph_diagram, without a workspace argument: the workspace is a library-owned device array of
+ * PH_NOALLOC_SCRATCH_MIB MiB per device, set up (its device address taken, the tables
+ * uploaded) by ph_init_device, which must have run on the current device first; the array
+ * lives until the process ends.  The call itself allocates nothing (no hipMalloc, hipFree,
+ * host heap), writes no memset, and never waits for the stream.
+ * Errors: PH_EINVAL if ph_init_device has not run on the current device, PH_ENOMEM (with a
+ * message on stderr) if ph_workspace_bytes(&shape, 1, flags) exceeds the array; otherwise as
+ * ph_diagram.  Every call on one device shares that device's array and leaves its contents
+ * behind (the kernels clear what must start at zero): calls that overlap in time on one
+ * device, on any streams, race and must not be made. */
+#define PH_NOALLOC_SCRATCH_MIB 64
+int ph_diagram_noalloc(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out,
+                       int64_t capacity, int64_t *d_count, int32_t *d_status, void *stream);
+
 /* Diagrams of n instances (1 <= n <= 65535) of uneven sizes and mixed 2D/3D in one set of launches:
  * persistent kernels walk a per-instance table built on the device from d_shapes.
  *   d_imgs     : all pixels concatenated (element type as the flags name); instance i
@@ -206,7 +223,8 @@ int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry);
 int32_t ph_lut_config_count(int32_t ndim);
 
 /* Upload the lookup tables to the current device now (they are otherwise uploaded on first
- * use) and verify the device copy; PH_OK, PH_EHIP or PH_EINTERNAL. */
+ * use), verify the device copy, and take the device address of the workspace array of
+ * ph_diagram_noalloc; PH_OK, PH_EHIP or PH_EINTERNAL. */
 int ph_init_device(void);
 
 /* Text report (into buf, len bytes) of the current device's per-block LDS and thread limits

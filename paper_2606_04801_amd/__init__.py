@@ -7,6 +7,7 @@ fallback.
 
 Entry points (same names as the C ABI):
   ph_diagram(img)                 one image or volume -> Diagram (device tensors)
+  ph_diagram_noalloc              the same into caller-owned outputs, library-owned workspace
   Batch(shapes).ph_diagram_batch  many instances of uneven sizes in one set of launches
   Batch.ph_autotune               tile choice timed on the batch, kept for its size class
   Batch.ph_backward / ph_backward gradient scatter to the critical pixels
@@ -101,6 +102,8 @@ def lib():
         L.ph_workspace_bytes.restype = ctypes.c_size_t
         L.ph_diagram.argtypes = [vp, ph_shape, u32, ph_pairs, i64, vp, vp, vp, ctypes.c_size_t, vp]
         L.ph_diagram.restype = ctypes.c_int
+        L.ph_diagram_noalloc.argtypes = [vp, ph_shape, u32, ph_pairs, i64, vp, vp, vp]
+        L.ph_diagram_noalloc.restype = ctypes.c_int
         L.ph_diagram_batch.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp,
                                        ctypes.POINTER(ph_tuning), vp, ctypes.c_size_t, vp]
         L.ph_diagram_batch.restype = ctypes.c_int
@@ -293,6 +296,21 @@ def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, w
     if rc != PH_OK:
         raise PHError(rc, "ph_diagram")
     return Diagram(bufs, count, status, img.shape)
+
+
+def ph_diagram_noalloc(img, bufs: PairBuffers, count, status, flags: int = PH_H0 | PH_HTOP,
+                       capacity: int | None = None, stream=None, filtration: str = "V") -> int:
+    """C ABI ph_diagram_noalloc: the diagram of one image or volume into caller-owned outputs
+    (bufs, count, status: device tensors), with the library's own per-device workspace
+    (ph_init_device must have run on the device); the call allocates nothing.  Returns the
+    C status (PH_OK once the work is enqueued); the kernels' status lands in `status`."""
+    kinds = _input_flags()
+    if img.dtype not in kinds or img.dim() not in (2, 3) or not img.is_contiguous():
+        raise PHError(PH_EINVAL, "ph_diagram_noalloc expects a contiguous 2D/3D float32, uint8 or uint16 tensor")
+    flags = _filtration_flags((int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[img.dtype], filtration)
+    cap = bufs.cap if capacity is None else int(capacity)
+    return int(lib().ph_diagram_noalloc(_ptr(img), make_shape(img.shape), flags, bufs.c(), cap, _ptr(count),
+                                        _ptr(status), _stream_ptr(stream)))
 
 
 def _input_flags():

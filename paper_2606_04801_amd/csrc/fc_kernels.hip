@@ -1926,12 +1926,18 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     // under the T-filtration the kernels below run on the framed dual images, which sit in
     // the workspace as float32 (extents + 2); only k_tpad and k_output read the caller's input
     const bool tf = (flags & PH_TFILT) != 0;
-    std::vector<ph_shape> framed_shapes;
-    if (tf) {
-        framed_shapes.resize(n);
-        for (int i = 0; i < n; ++i) framed_shapes[i] = framed(h_shapes[i]);
+    // (a single instance keeps its framed shape on the stack: the no-allocation entry point
+    // allocates nothing, on the host either)
+    ph_shape framed_one;
+    std::vector<ph_shape> framed_many;
+    ph_shape *framed_shapes = &framed_one;
+    if (tf && n > 1) {
+        framed_many.resize(n);
+        framed_shapes = framed_many.data();
     }
-    const ph_shape *hs = tf ? framed_shapes.data() : h_shapes;
+    if (tf)
+        for (int i = 0; i < n; ++i) framed_shapes[i] = framed(h_shapes[i]);
+    const ph_shape *hs = tf ? framed_shapes : h_shapes;
     bool any2 = false, any3 = false;
     for (int i = 0; i < n; ++i) {
         if (!valid_shape(h_shapes[i]) || !valid_shape(hs[i])) return PH_EINVAL;
@@ -2021,8 +2027,19 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     return PH_OK;
 }
 
+// Device address of the no-allocation workspace on each device (see `scratch` below), taken
+// by ph_init_device; null until then.
+void *g_scratch_dev[64] = {nullptr};
+
 }  // namespace
 }  // namespace fc
+
+// Workspace of ph_diagram_noalloc: one array per device, in the library's code object, held
+// until the process ends.  In host code `scratch` names a host-side stand-in, not device
+// memory: only the address hipGetSymbolAddress returns for the current device is ever passed
+// to a kernel (fc::g_scratch_dev).
+constexpr size_t kScratchBytes = (size_t)PH_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 // ====================================================================== C ABI ====
 
@@ -2055,6 +2072,25 @@ int ph_diagram(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out, 
     if (capacity < 0) return PH_EINVAL;
     return fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
                    d_status, nullptr, d_ws, ws_bytes, (hipStream_t)stream);
+}
+
+int ph_diagram_noalloc(const void *d_img, ph_shape shape, uint32_t flags, ph_pairs out, int64_t capacity,
+                       int64_t *d_count, int32_t *d_status, void *stream) {
+    if (capacity < 0) return PH_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return PH_EHIP;
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(fc::g_dev_mu);
+        ws = fc::g_scratch_dev[dev];             // set with the tables by ph_init_device
+    }
+    if (!ws) return PH_EINVAL;
+    const int rc = fc::run(1, d_img, nullptr, nullptr, &shape, shape, flags, out, nullptr, capacity, d_count,
+                           d_status, nullptr, ws, kScratchBytes, (hipStream_t)stream);
+    if (rc == PH_ENOMEM)
+        fprintf(stderr, "flashcubical: ph_diagram_noalloc: the instance needs more than the %d MiB of the "
+                        "library's workspace (ph_workspace_bytes gives its need)\n", PH_NOALLOC_SCRATCH_MIB);
+    return rc;
 }
 
 int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
@@ -2250,6 +2286,17 @@ int ph_device_report(char *buf, size_t len) {
 int ph_init_device(void) {
     int rc = fc::device_luts();
     if (rc != PH_OK) return rc;
+    {
+        int dev = 0;
+        if (!fc::hip_ok(hipGetDevice(&dev), "hipGetDevice") || dev < 0 || dev >= 64) return PH_EHIP;
+        std::lock_guard<std::mutex> lk(fc::g_dev_mu);
+        if (!fc::g_scratch_dev[dev]) {
+            void *p = nullptr;
+            if (!fc::hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress (scratch)") || !p)
+                return PH_EHIP;
+            fc::g_scratch_dev[dev] = p;
+        }
+    }
     std::vector<uint32_t> l2d(256), l1(fc::kL1Size);
     std::vector<uint64_t> l2(fc::kL3Configs);
     const fc::Luts t = fc::current_luts();
