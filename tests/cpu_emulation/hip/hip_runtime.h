@@ -68,6 +68,7 @@ inline void emu_check_access(const void *, size_t, int) {}
 #define __global__
 #endif
 #define __device__
+#define __align__(n) __attribute__((aligned(n)))
 #define __host__
 #define __constant__
 #define __forceinline__ inline
@@ -397,6 +398,25 @@ inline hipError_t hipFree(void *p) {
     return hipSuccess;
 }
 inline hipError_t hipMemcpy(void *d, const void *s, size_t n, hipMemcpyKind) { memcpy(d, s, n); return hipSuccess; }
+// A file-scope __device__ array is an ordinary host array here.  Its address is registered as
+// device memory (once) the first time the library asks for it, like a hipMalloc allocation.
+#define HIP_SYMBOL(x) ((const void *)&(x)), sizeof(x)
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym, size_t n) {
+    static std::vector<const void *> seen;
+    bool fresh = true;
+    for (const void *q : seen) fresh &= q != sym;
+    if (fresh) {
+        seen.push_back(sym);
+#ifdef EMU_TRACE
+        emu_dev_register(sym, n);
+#endif
+#ifdef EMU_ISA
+        if (emu_isa_alloc) emu_isa_alloc((void *)sym, n, 0);
+#endif
+    }
+    *p = (void *)sym;
+    return hipSuccess;
+}
 typedef struct EmuEvent { double t; } *hipEvent_t;
 inline double emu_now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
