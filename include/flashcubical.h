@@ -11,8 +11,8 @@
  *   - lookup-table classification and pruning of each vertex's lower star (Sec. 3.2, 3.3),
  *     union-find for H0 and union-find on the dual graph with a cell at infinity for the top
  *     dimension (Sec. 3.1, Appendix A), as assembled in Sec. 4.1 (2D) and Sec. 4.2 steps 1-3
- *     (3D).  H1 of a volume (Sec. 4.2 steps 4-5) is not computed by this library; a volume
- *     with an extent of 1 is still a volume (empty H2, no H1): pass it as an image for H1.
+ *     (3D), and with PH_H1 the middle dimension of a volume (Sec. 4.2 steps 4-5).  A volume
+ *     with an extent of 1 is still a volume (empty H2; its H1 needs PH_H1).
  *
  * Conventions shared by every entry point:
  *   - Pixel layout: row-major, last axis fastest.  2D extents are (H, W), 3D (D, H, W); every
@@ -85,8 +85,22 @@ enum {
  *     the essential class last;
  *   - a +inf pixel is reported as PH_ENAN (it would tie the frame);
  *   - ph_capacity_bound and ph_workspace_bytes of the same flags account for the frame: pass
- *     the shape with every extent grown by 2 to ph_capacity_bound. */
-enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16 };
+ *     the shape with every extent grown by 2 to ph_capacity_bound (ph_capacity_bound_flags
+ *     does it itself).
+ *
+ * PH_H1 adds H1 of every volume of the call (Sec. 4.2 steps 4-5; images ignore it, their H1
+ * is the top dimension).  The cells left unpaired by the lookup table, the H0 union-find and
+ * the dual union-find form a reduced problem: rows are the KEEP edges H0 left positive,
+ * columns the KEEP squares the dual union-find left unpaired.  Each column is first expressed
+ * in those rows by adding the reduced columns the table knows for every pair inside one lower
+ * star (legal column operations: each added column precedes the column), then the columns are
+ * reduced over F2 in square order.  The H1 pairs of non-zero persistence are reported between
+ * H0 and H2, in the same order and with the same fields as the other dimensions (under
+ * PH_TFILT: the T-filtration's H1, by duality, by death key).  Internal limits (a column's
+ * running sum beyond 1024 live edges, its boundary in critical cells beyond 64 edges, the
+ * columns' pool beyond 4 entries per KEEP-square slot) are reported as PH_EINTERNAL.  Volumes
+ * run the 3D classify pass on the default tiles under PH_H1. */
+enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16, PH_H1 = 32 };
 
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
@@ -116,6 +130,11 @@ typedef struct {
 /* Upper bound of the pairs of one instance: pixels + top cells (H0 pairs <= pixels, top
  * pairs <= top cells).  A capacity of this size can never overflow. */
 int64_t ph_capacity_bound(ph_shape shape);
+
+/* The same bound for a call with the given flags: under PH_TFILT that of the framed dual image
+ * (every extent + 2), and under PH_H1 a volume's H1 pairs are added (at most its squares
+ * minus its cubes).  0 for an invalid shape. */
+int64_t ph_capacity_bound_flags(ph_shape shape, uint32_t flags);
 
 /* Workspace bytes needed by a batch of n instances with the given host shapes (also valid
  * for n = 1 and ph_diagram) under the given flags (PH_TFILT adds the framed dual images).
@@ -247,10 +266,13 @@ int ph_profile(int32_t enable);
 int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count);
 
 /* Work counters of the last call that used workspace d_ws for n instances (the same n), for
- * sizing and diagnostics: 8 int32 per instance written to h_out (host), in order KEEP edges,
+ * sizing and diagnostics: 12 int32 per instance written to h_out (host), in order KEEP edges,
  * KEEP squares (3D), H0 nodes (local minima), dual nodes (ROOT top cells + the cell at
- * infinity), H0 union-find rounds, dual union-find rounds, edges finished sequentially, and
- * the instance's error word.  Copies synchronously; PH_OK, PH_EINVAL or PH_EHIP. */
+ * infinity), H0 union-find rounds, dual union-find rounds, edges finished sequentially, the
+ * instance's error word, and under PH_H1: H1 columns, columns reduced one by one (their
+ * lowest row occurs in an earlier column), the most rounds one column's expression in
+ * critical cells took, and the pool entries used.  Copies synchronously; PH_OK, PH_EINVAL or
+ * PH_EHIP. */
 int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out);
 
 /* Library version string. */

@@ -29,6 +29,7 @@ PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -
 PH_H0, PH_HTOP = 1, 2
 PH_IN_U8, PH_IN_U16 = 4, 8          # input element type (float32 when neither is set)
 PH_TFILT = 16                       # T-filtration: pixels are the top cells (default: V)
+PH_H1 = 32                          # volumes: H1 as well (images: H1 is the top dimension)
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
                 -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
 
@@ -98,6 +99,8 @@ def lib():
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         L.ph_capacity_bound.argtypes = [ph_shape]
         L.ph_capacity_bound.restype = i64
+        L.ph_capacity_bound_flags.argtypes = [ph_shape, u32]
+        L.ph_capacity_bound_flags.restype = i64
         L.ph_workspace_bytes.argtypes = [ctypes.POINTER(ph_shape), i32, u32]
         L.ph_workspace_bytes.restype = ctypes.c_size_t
         L.ph_diagram.argtypes = [vp, ph_shape, u32, ph_pairs, i64, vp, vp, vp, ctypes.c_size_t, vp]
@@ -138,12 +141,11 @@ def make_shape(shape) -> ph_shape:
     return ph_shape(len(shape), (ctypes.c_int32 * 3)(*ext))
 
 
-def capacity_bound(shape, filtration: str = "V") -> int:
-    """Pairs one instance can hold at most; under the T-filtration the bound of the framed
-    dual image (every extent + 2)."""
-    if filtration == "T":
-        shape = tuple(int(e) + 2 for e in shape)
-    return int(lib().ph_capacity_bound(make_shape(shape)))
+def capacity_bound(shape, filtration: str = "V", flags: int = PH_H0 | PH_HTOP) -> int:
+    """Pairs one instance can hold at most (C ABI ph_capacity_bound_flags): under the
+    T-filtration the bound of the framed dual image (every extent + 2); with PH_H1 a volume's
+    H1 pairs are added."""
+    return int(lib().ph_capacity_bound_flags(make_shape(shape), _filtration_flags(flags, filtration)))
 
 
 def _filtration_flags(flags: int, filtration: str) -> int:
@@ -285,7 +287,7 @@ def ph_diagram(img, flags: int = PH_H0 | PH_HTOP, capacity: int | None = None, w
     flags = _filtration_flags((int(flags) & ~(PH_IN_U8 | PH_IN_U16)) | kinds[img.dtype], filtration)
     img = img.contiguous()
     shp = make_shape(img.shape)
-    cap = capacity_bound(img.shape, filtration) if capacity is None else int(capacity)
+    cap = capacity_bound(img.shape, filtration, flags) if capacity is None else int(capacity)
     bufs = PairBuffers(cap, img.device)
     count = torch.zeros(1, dtype=torch.int64, device=img.device)
     status = torch.zeros(1, dtype=torch.int32, device=img.device)
@@ -355,7 +357,7 @@ class Batch:
         self.flags = flags
         self.device = torch.device(device)
         sizes = [int(np.prod(s)) for s in self.shapes]
-        caps = [capacity_bound(s, filtration) for s in self.shapes] if capacities is None else [max(int(c), 1) for c in capacities]
+        caps = [capacity_bound(s, filtration, flags) for s in self.shapes] if capacities is None else [max(int(c), 1) for c in capacities]
         if len(caps) != self.n:
             raise PHError(PH_EINVAL, "capacities")
         self.img_off_h = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
@@ -413,14 +415,15 @@ class Batch:
                     stream)
 
     def work_counters(self):
-        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 8) array:
+        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 12) array:
         KEEP edges, KEEP squares, H0 nodes, dual nodes, H0 rounds, dual rounds, sequential
-        edges, error word.  Synchronises."""
-        out = (ctypes.c_int32 * (8 * self.n))()
+        edges, error word, and for 3D H1: columns, columns reduced one by one, most rounds of
+        one column, pool entries.  Synchronises."""
+        out = (ctypes.c_int32 * (12 * self.n))()
         rc = lib().ph_work_counters(_ptr(self.ws), self.n, out)
         if rc != PH_OK:
             raise PHError(rc, "ph_work_counters")
-        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 8).copy()
+        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 12).copy()
 
     def valid_mask(self):
         """Device bool mask over the packed pair slots holding a stored pair (no sync)."""

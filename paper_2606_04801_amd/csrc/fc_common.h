@@ -132,10 +132,16 @@ struct Inst {
     int64_t tile_base;         // first tile of this instance in its (2D or 3D) classify grid
     int32_t tx, ty, tz;        // tiles along x, y, z
     int32_t tfilt;             // 1: T-filtration, the grid is the framed dual image (extents + 2)
+    int32_t h1;                // 1: a volume whose H1 is computed too (Sec. 4.2 steps 4-5)
     // byte offsets of the per-instance arrays inside the workspace
     int64_t o_par0, o_parT, o_keyE, o_ea, o_eb, o_neg0, o_keyF, o_fa, o_fb, o_killer;
     int64_t o_n0key, o_n0sorted, o_nTkey, o_uf0, o_moe0, o_death0, o_ufT, o_moeT;
     int64_t o_live, o_live2, o_ra, o_rb, o_scratch, o_gimg;
+    // H1 of a volume: per-vertex configuration index and first sorted KEEP edge, per KEEP
+    // square its H1 column (start and length in the pool, -1 if paired in H2), per KEEP edge
+    // its pivot column and the first column holding it, and the pool of column entries
+    int64_t o_cfg3, o_kpos, o_h1b, o_h1n, o_piv, o_first, o_pool;
+    int64_t pool_cap;          // int32 entries of the pool
     int64_t end;
 };
 
@@ -144,8 +150,13 @@ struct Inst {
 // of one tile, and of the tiles of one instance, do not queue behind each other on one line.
 enum {
     CNT_E = 0, CNT_F = 32, CNT_M0 = 64, CNT_MT = 96,
-    CNT_ERR = 128, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ, CNT_WORDS = 160
+    CNT_ERR = 128, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ,
+    CNT_H1COLS, CNT_H1UNSAFE, CNT_H1ROUNDS, CNT_H1ENTRIES,
+    CNT_H1POOL = 160, CNT_WORDS = 192
 };
+// pool entries per KEEP-square slot of an H1 volume: room for the Morse boundaries of the
+// columns (a few entries each) and the reduced forms of the columns that need reduction
+constexpr int64_t kH1PoolPerSquare = 4;
 
 FC_HD int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
@@ -189,6 +200,15 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_rb = take(4 * L);
     I.o_scratch = take(8 * SCR);
     I.o_gimg = I.tfilt ? take(4 * N) : 0;   // T-filtration: the framed dual image (float32)
+    const bool h1 = I.h1 && I.ndim == 3;
+    I.pool_cap = h1 ? kH1PoolPerSquare * F : 0;
+    I.o_cfg3 = h1 ? take(2 * N) : 0;
+    I.o_kpos = h1 ? take(4 * N) : 0;
+    I.o_h1b = h1 ? take(4 * F) : 0;
+    I.o_h1n = h1 ? take(4 * F) : 0;
+    I.o_piv = h1 ? take(4 * E) : 0;
+    I.o_first = h1 ? take(4 * E) : 0;
+    I.o_pool = h1 ? take(4 * I.pool_cap) : 0;
     I.end = at;
     return at;
 }

@@ -33,7 +33,7 @@
 namespace fc {
 
 int build_lut2d(uint32_t *lut, char *err, int errlen);
-int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen);
+int build_lut3d(uint32_t *l1, uint64_t *l2, uint16_t *h1e, uint16_t *h1s, char *err, int errlen);
 
 // The lookup tables live in device buffers the library allocates once per device and passes
 // to the kernels as arguments; device code reads no variable of its own code object.
@@ -41,6 +41,8 @@ struct Luts {
     const uint32_t *l2d;   // 256 entries (2D)
     const uint32_t *l1;    // kL1Size entries (3D level 1)
     const uint64_t *l2;    // kL3Configs entries (3D level 2)
+    const uint16_t *h1e;   // 8 per 3D entry: an edge's partner combination (3D H1)
+    const uint16_t *h1s;   // 16 per 3D entry: a KEEP square's own combination (3D H1)
 };
 
 constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
@@ -80,6 +82,7 @@ FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
         I.tz = (I.D + tl.td3 - 1) / tl.td3;
     }
     I.tfilt = 0;
+    I.h1 = 0;
 }
 
 // T-filtration: the framed dual image has one more pixel on each side of every axis
@@ -98,7 +101,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
                        const int64_t *__restrict__ d_img_off, const int64_t *__restrict__ d_out_off,
                        int64_t single_cap, Tiles tl, uint8_t *__restrict__ ws,
                        int64_t *__restrict__ d_counts, int32_t *__restrict__ d_status,
-                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes, int tfilt) {
+                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes, int tfilt, int h1) {
     __shared__ int64_t s_scan[2][3][kPlanThreads];   // bytes, 2D tiles, 3D tiles (double buffer)
     __shared__ int64_t s_run[3];
     if (blockIdx.x != 0) return;
@@ -126,6 +129,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
                 fill_inst(I, tfilt ? framed(s) : s, tl);
             }
             I.tfilt = tfilt;
+            I.h1 = h1 && I.ndim == 3;
             v[0] = layout(I, 0);
             if (I.ndim == 2) v[1] = (int64_t)I.tx * I.ty;
             else v[2] = (int64_t)I.tx * I.ty * I.tz;
@@ -596,7 +600,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 // ================================================================ classify 3D ====
 // 256 threads, at least seven workgroups (28 waves) per compute unit: the register budget
 // (72) costs a few spilled registers, cheaper than losing a wave per SIMD
-template <int TW, int TH, int TD, typename T>
+template <int TW, int TH, int TD, typename T, bool H1 = false>
 __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
@@ -732,6 +736,8 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         bad |= in && !ok;
         uint64_t e = lut.l2[ok ? idx2 : 0u];
         e = in ? ((ok ? e : (uint64_t)kNoDirect) | kValid) : 0;
+        if (H1 && in)                                  // 3D H1 looks the configurations up again
+            arr<uint16_t>(ws, I.o_cfg3)[(uint32_t)gz * (uint32_t)HW + (uint32_t)(gy * W + gx)] = (uint16_t)(ok ? idx2 : 0u);
         packed += in ? (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((uint32_t)(e >> kL3Keep) & 63u) << 16) |
                            ((uint64_t)__popc((uint32_t)(e >> kL3KeepSq) & 4095u) << 32) |
                            ((uint64_t)__popc((uint32_t)(e >> kL3Root) & 255u) << 48)
@@ -1039,6 +1045,16 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
     const bool serial = mE > kSortCap || mF > kSortCap || mN > kSortCap;
     if (w == 0) {
         sort_list<0>(ws, I, cnt, mE, s, s2);
+        if (I.h1 && I.ndim == 3) {
+            // 3D H1: the sorted position of each vertex's first KEEP edge (a vertex's KEEP edges
+            // are adjacent in the sorted list, by code)
+            const uint64_t *kE = arr<uint64_t>(ws, I.o_keyE);
+            int32_t *kpos = arr<int32_t>(ws, I.o_kpos);
+            for (int t = threadIdx.x; t < mE; t += blockDim.x) {
+                const uint32_t wv = key_pix(kE[t]);
+                if ((t == 0 || key_pix(kE[t - 1]) != wv) && wv < I.N) kpos[wv] = t;
+            }
+        }
         if (serial) {
             sort_list<1>(ws, I, cnt, mF, s, s2);
             sort_list<2>(ws, I, cnt, mN, s, s2);
@@ -1429,6 +1445,386 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
     }
 }
 
+// ======================================================================= 3D H1 ====
+// H1 of a volume (Sec. 4.2 steps 4-5): the cells not already paired.  Rows are the positive
+// edges; columns the KEEP squares the dual union-find left unpaired (squares paired in H2 are
+// dropped, as are zero-persistence pairs inside one lower star).  Every edge paired inside its
+// lower star L(w) with a square tau has a reduced column known from the table: the sum of the
+// boundaries of the squares of L(w) that tau's relative reduction added (tau's combination),
+// whose last entry is that edge.  A column sigma in L(v) starts as the sum of the boundaries of
+// its own combination (the squares of L(v) its relative reduction added), which has no entry
+// in L(v).  From then on every locally paired entry lies in an earlier lower star, so its
+// partner precedes sigma: adding the partner's reduced column is a legal column operation in
+// any order.  Rounds add them for every locally paired entry at once (the largest one present
+// always disappears and nothing above it is added, so the rounds end); entries that can never
+// be a pivot (negative edges: paired with their vertex, or H0-negative KEEP edges) are
+// dropped.  What is left are KEEP edges that H0 left positive: the column's boundary in the
+// complex of critical cells.  A standard reduction of those small columns, in square order,
+// then gives exactly the pairs of the full boundary-matrix reduction.
+//
+// One single-wave workgroup per column at a time; the column is an F2 set of edge keys in an
+// open-addressing table in LDS (toggling a key is adding the edge).
+constexpr int kH1Slots = 2048;             // table slots per workgroup (16 KiB of keys)
+constexpr int kH1SlotBits = 11;
+constexpr int kH1Compact = 1536;           // compact the table when more slots are in use
+constexpr int kH1MaxLive = 1024;           // more live entries than this after compacting: error
+constexpr int kH1MaxBoundary = 64;         // entries of one column's boundary in critical cells
+constexpr int kH1MaxRounds = 1 << 16;
+constexpr uint64_t kH1Empty = ~0ull;
+// an edge key has code 1..6 in its low 3 bits; bits 3 and 4 carry the slot state
+constexpr uint64_t kH1Present = 1ull << 3, kH1Final = 1ull << 4, kH1Flags = kH1Present | kH1Final;
+
+__device__ __forceinline__ uint32_t h1_hash(uint64_t key) {
+    const uint32_t x = (uint32_t)(key >> kCodeBits) * 8u + (uint32_t)(key & 7u);   // pixel, code
+    return (x * 2654435761u) >> (32 - kH1SlotBits);
+}
+
+// Add edge `key` to the column (toggle its presence).  False when the table is full.
+__device__ __forceinline__ bool h1_toggle(uint64_t *tab, int *used, uint64_t key) {
+    uint32_t h = h1_hash(key);
+    for (int probe = 0; probe < kH1Slots; ++probe, h = (h + 1) & (kH1Slots - 1)) {
+        unsigned long long v = __hip_atomic_load((unsigned long long *)&tab[h], __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (v == kH1Empty) {
+            v = atomicCAS((unsigned long long *)&tab[h], (unsigned long long)kH1Empty,
+                          (unsigned long long)(key | kH1Present));
+            if (v == kH1Empty) {
+                atomicAdd(used, 1);
+                return true;
+            }
+        }
+        if ((v & ~kH1Flags) == key) {
+            atomicXor((unsigned long long *)&tab[h], (unsigned long long)kH1Present);
+            return true;
+        }
+    }
+    return false;
+}
+
+// order key of voxel p: ord32 of its value, then p (the vertex order of Sec. 2.3)
+template <typename T>
+__device__ __forceinline__ uint64_t vox_key(const T *img, uint32_t p) {
+    return ((uint64_t)ord32(__float_as_uint((float)img[p])) << 32) | p;
+}
+// key of the edge between voxels a and b = a + the unit offset of edge code code_ab, from
+// their order keys: its last vertex is the later one, the code is seen from there
+__device__ __forceinline__ uint64_t edge_key_of(uint64_t ka, uint64_t kb, uint32_t code_ab) {
+    const bool a_last = ka > kb;
+    const uint64_t k = a_last ? ka : kb;
+    return (k & 0xFFFFFFFF00000000ull) | ((k & 0xFFFFFFFFull) << kCodeBits) | (a_last ? code_ab : 7u - code_ab);
+}
+
+// Add the boundary of square slot q of L(w) (w's key bits kw5 = order << 32 | w << 5) to the
+// column: its two edges at w and the two opposite ones, whose last vertices are looked up.
+template <typename T>
+__device__ __forceinline__ bool h1_square(const T *img, uint64_t kw5, uint32_t w, int q, int W, int HW,
+                                          uint64_t *tab, int *used) {
+    const int c = 7 + q;
+    const int a1 = off_of(c, 0) ? 0 : 1;            // the two axes the square spans, slowest first
+    const int a2 = off_of(c, 2) ? 2 : 1;
+    const int s1 = off_of(c, a1), s2 = off_of(c, a2);
+    const int st1 = a1 == 0 ? HW : W, st2 = a2 == 2 ? 1 : W;
+    const uint32_t c1 = s1 < 0 ? 1 + a1 : 6 - a1, c2 = s2 < 0 ? 1 + a2 : 6 - a2;
+    const uint32_t pa = (uint32_t)((int)w + s1 * st1), pb = (uint32_t)((int)w + s2 * st2);
+    const uint32_t pab = (uint32_t)((int)pa + s2 * st2);
+    const uint64_t ka = vox_key(img, pa), kb = vox_key(img, pb), kab = vox_key(img, pab);
+    bool ok = h1_toggle(tab, used, kw5 | c1);
+    ok &= h1_toggle(tab, used, kw5 | c2);
+    ok &= h1_toggle(tab, used, edge_key_of(ka, kab, c2));
+    ok &= h1_toggle(tab, used, edge_key_of(kb, kab, c1));
+    return ok;
+}
+
+// Class of edge `key` (no state bits): 0 negative (paired with its vertex, or a KEEP edge H0
+// used), 1 a KEEP edge left positive by H0 (*rr: its sorted position), 2 paired in its lower
+// star (*comb: its partner's combination), -1 inconsistent data.
+__device__ __forceinline__ int h1_class(uint64_t key, const uint16_t *cfg3, const int32_t *kpos,
+                                        const int32_t *neg0, int64_t N, int mE, const Luts &lut,
+                                        uint32_t *comb, int *rr) {
+    const uint32_t w = key_pix(key), c = key_code(key);
+    if (w >= N || c < 1 || c > 6) return -1;
+    const uint32_t cfg = cfg3[w];
+    const int32_t kp = kpos[w];                      // meaningful only if w has KEEP edges
+    if (cfg >= (uint32_t)kL3Configs) return -1;
+    const uint64_t ent = lut.l2[cfg];
+    if ((uint32_t)(ent & 7u) == c - 1) return 0;
+    const uint32_t keep = (uint32_t)(ent >> kL3Keep) & 63u;
+    if ((keep >> (c - 1)) & 1u) {
+        const int r = kp + __popc(keep & ((1u << (c - 1)) - 1u));
+        if (kp < 0 || r >= mE) return -1;
+        *rr = r;
+        return neg0[r] ? 0 : 1;
+    }
+    *comb = lut.h1e[cfg * 8 + (c - 1)];
+    return *comb ? 2 : -1;
+}
+
+// Rebuild the table with its live entries only (present and not known negative); all lanes.
+__device__ __forceinline__ void h1_compact(uint64_t *tab, const uint32_t *negbits, int *used) {
+    constexpr int PER = kH1Slots / 64;
+    uint64_t keep[PER];
+    const int lane = threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int k = lane + 64 * j;
+        const uint64_t x = tab[k];
+        const bool neg = (negbits[k >> 5] >> (k & 31)) & 1u;
+        keep[j] = (x != kH1Empty && (x & kH1Present) && !((x & kH1Final) && neg)) ? x : kH1Empty;
+    }
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) tab[lane + 64 * j] = kH1Empty;
+    if (lane == 0) *used = 0;
+    lds_barrier();
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        if (keep[j] == kH1Empty) continue;
+        uint32_t h = h1_hash(keep[j] & ~kH1Flags);
+        for (int probe = 0; probe < kH1Slots; ++probe, h = (h + 1) & (kH1Slots - 1)) {
+            const unsigned long long v = atomicCAS((unsigned long long *)&tab[h], (unsigned long long)kH1Empty,
+                                                   (unsigned long long)keep[j]);
+            if (v == kH1Empty) break;
+        }
+        atomicAdd(used, 1);
+    }
+    lds_barrier();
+}
+
+// One workgroup of 64 threads per column at a time, blockIdx.y = instance: the column's
+// boundary in critical cells (sorted descending) goes to the pool, its start and length to
+// h1b, h1n (-1 for a square paired in H2).
+template <typename T>
+__global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uint8_t *__restrict__ ws, int n,
+                                                 Luts lut) {
+    __shared__ uint64_t tab[kH1Slots];
+    __shared__ uint32_t negbits[kH1Slots / 32];
+    __shared__ int s_used;
+    __shared__ int32_t s_bnd[kH1MaxBoundary];
+    __shared__ int s_nb;
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (I.ndim != 3 || !I.h1) return;
+    if (block_failed(cnt)) return;
+    const int lane = threadIdx.x;
+    const int mF = cnt[CNT_F], mE = cnt[CNT_E];
+    if (mF > I.F || mE > I.E) {
+        if (lane == 0) set_err(cnt, PH_EINTERNAL);
+        return;
+    }
+    const T *img = imgs + I.img_off;
+    const int W = I.W, HW = I.H * I.W;
+    const uint64_t *keyF = arr<uint64_t>(ws, I.o_keyF);
+    const int32_t *killer = arr<int32_t>(ws, I.o_killer);
+    const uint16_t *cfg3 = arr<uint16_t>(ws, I.o_cfg3);
+    const int32_t *kpos = arr<int32_t>(ws, I.o_kpos);
+    const int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
+    int32_t *h1b = arr<int32_t>(ws, I.o_h1b), *h1n = arr<int32_t>(ws, I.o_h1n);
+    int32_t *pool = arr<int32_t>(ws, I.o_pool);
+    int cols = 0, max_rounds = 0;
+    for (int r = blockIdx.x; r < mF; r += gridDim.x) {
+        if (killer[r] >= 0) {                        // paired in H2: not a column
+            if (lane == 0) h1n[r] = -1;
+            continue;
+        }
+        ++cols;
+        for (int k = lane; k < kH1Slots; k += 64) tab[k] = kH1Empty;
+        for (int k = lane; k < kH1Slots / 32; k += 64) negbits[k] = 0;
+        if (lane == 0) { s_used = 0; s_nb = 0; }
+        lds_barrier();
+        // the column's own combination: the sum of its boundaries leaves L(v)
+        const uint64_t ks = keyF[r];
+        const uint32_t v = key_pix(ks), cs = key_code(ks);
+        bool ok = cs >= 7 && cs <= 18 && v < I.N;
+        const uint32_t cfg = ok ? cfg3[v] : 0u;
+        ok = ok && cfg < (uint32_t)kL3Configs;
+        const uint32_t comb = ok ? lut.h1s[cfg * 16 + (cs - 7)] : 0u;
+        ok = ok && ((comb >> (cs - 7)) & 1u);
+        if (ok && lane < 12 && ((comb >> lane) & 1u)) ok = h1_square(img, ks & ~31ull, v, lane, W, HW, tab, &s_used);
+        lds_barrier();
+        bool bad = __ballot(!ok) != 0;
+        int round = 0;
+        for (; !bad && round < kH1MaxRounds; ++round) {
+            bool any = false;
+            for (int win = 0; win < kH1Slots && !bad; win += 64) {
+                if (s_used > kH1Compact) {           // uniform: read after a barrier
+                    h1_compact(tab, negbits, &s_used);
+                    if (s_used > kH1MaxLive) { bad = true; break; }
+                    for (int k = lane; k < kH1Slots / 32; k += 64) negbits[k] = 0;
+                    lds_barrier();
+                    win = -64;                       // the slots moved: scan again
+                    continue;
+                }
+                const int k = win + lane;
+                const uint64_t x = tab[k];
+                bool pruned = false, err = false;
+                uint32_t cm = 0;
+                const uint64_t key = x & ~kH1Flags;
+                if (x != kH1Empty && (x & kH1Present)) {
+                    if (x & kH1Final) {
+                        if ((negbits[k >> 5] >> (k & 31)) & 1u)          // a negative added again
+                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)kH1Present);
+                    } else {
+                        int rr = -1;
+                        const int cl = h1_class(key, cfg3, kpos, neg0, I.N, mE, lut, &cm, &rr);
+                        if (cl == 0) {
+                            atomicOr(&negbits[k >> 5], 1u << (k & 31));
+                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)(kH1Present | kH1Final));
+                        } else if (cl == 1) {
+                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)kH1Final);
+                        } else if (cl == 2) {
+                            pruned = true;
+                        } else {
+                            err = true;
+                        }
+                    }
+                }
+                lds_barrier();
+                if (pruned) {
+                    any = true;
+                    for (uint32_t m = cm; m; m &= m - 1)
+                        err |= !h1_square(img, key & ~31ull, key_pix(key), __builtin_ctz(m), W, HW, tab, &s_used);
+                }
+                lds_barrier();
+                bad |= __ballot(err) != 0;
+            }
+            if (__ballot(any) == 0) break;
+        }
+        if (!bad && round >= kH1MaxRounds) bad = true;
+        if (bad) {
+            if (lane == 0) set_err(cnt, PH_EINTERNAL);
+            return;
+        }
+        max_rounds = round > max_rounds ? round : max_rounds;
+        // the entries left are KEEP edges H0 left positive: their sorted positions
+        for (int win = 0; win < kH1Slots; win += 64) {
+            const int k = win + lane;
+            const uint64_t x = tab[k];
+            const bool neg = (negbits[k >> 5] >> (k & 31)) & 1u;
+            if (x != kH1Empty && (x & kH1Present) && (x & kH1Final) && !neg) {
+                uint32_t cm = 0;
+                int rr = -1;
+                const int cl = h1_class(x & ~kH1Flags, cfg3, kpos, neg0, I.N, mE, lut, &cm, &rr);
+                const int at = atomicAdd(&s_nb, 1);
+                if (cl == 1 && at < kH1MaxBoundary) s_bnd[at] = rr;
+                else atomicOr(&s_nb, 1 << 30);       // marks the column bad
+            }
+        }
+        lds_barrier();
+        const int nb = s_nb;
+        if (nb <= 0 || nb > kH1MaxBoundary) {        // a negative square has a non-empty boundary
+            if (lane == 0) set_err(cnt, PH_EINTERNAL);
+            return;
+        }
+        // sort the boundary descending (ascending bitonic over the 64 lanes, read backwards)
+        int x = lane < nb ? s_bnd[lane] : 0x7FFFFFFF;
+        for (int kk = 2; kk <= 64; kk <<= 1)
+            for (int j = kk >> 1; j > 0; j >>= 1) {
+                const int y = __shfl_xor(x, j, 64);
+                const bool keep_min = ((lane & j) == 0) == ((lane & kk) == 0);
+                x = keep_min ? (x < y ? x : y) : (x > y ? x : y);
+            }
+        int off = 0;
+        if (lane == 0) off = atomicAdd(&cnt[CNT_H1POOL], nb);
+        off = __shfl(off, 0, 64);
+        if ((int64_t)off + nb > I.pool_cap) {
+            if (lane == 0) set_err(cnt, PH_EINTERNAL);
+            return;
+        }
+        if (lane < nb) pool[off + nb - 1 - lane] = x;
+        if (lane == 0) { h1b[r] = off; h1n[r] = nb; }
+        lds_barrier();
+    }
+    if (lane == 0 && cols) {
+        atomicAdd(&cnt[CNT_H1COLS], cols);
+        atomicMax(&cnt[CNT_H1ROUNDS], max_rounds);
+    }
+}
+
+// Reduction of the H1 columns of one volume per workgroup, in square order.  A column whose
+// lowest row appears in no earlier column keeps that row: it is paired at once, in parallel.
+// The others are reduced one after the other by adding the reduced columns of earlier pivots;
+// their reduced forms go to the pool.  piv[row] = the column paired with that KEEP edge.
+__global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ ws, int n) {
+    __shared__ int s_wsum[kUfThreads / 64];
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (I.ndim != 3 || !I.h1) return;
+    if (block_failed(cnt)) return;
+    const int mF = cnt[CNT_F], mE = cnt[CNT_E];
+    int32_t *h1b = arr<int32_t>(ws, I.o_h1b), *h1n = arr<int32_t>(ws, I.o_h1n);
+    int32_t *piv = arr<int32_t>(ws, I.o_piv), *first = arr<int32_t>(ws, I.o_first);
+    int32_t *pool = arr<int32_t>(ws, I.o_pool);
+    for (int t = threadIdx.x; t < mE; t += blockDim.x) {
+        piv[t] = -1;
+        first[t] = 0x7FFFFFFF;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < mF; r += blockDim.x) {
+        const int b = h1b[r], m = h1n[r];
+        for (int k = 0; m > 0 && k < m; ++k) {
+            const int e = pool[b + k];
+            if (e < 0 || e >= mE) set_err(cnt, PH_EINTERNAL);
+            else atomicMin(&first[e], r);
+        }
+    }
+    __syncthreads();
+    // columns whose lowest row no earlier column holds; the others, in order, into `list`
+    int32_t *list = arr<int32_t>(ws, I.o_ea);         // unsafe columns (H0's endpoints are done; E >= F)
+    int L = 0;
+    for (int base = 0; base < mF; base += blockDim.x) {
+        const int r = base + threadIdx.x;
+        int flag = 0;
+        if (r < mF && h1n[r] > 0) {
+            const int low = pool[h1b[r]];
+            if (low >= 0 && low < mE && first[low] == r) piv[low] = r;
+            else flag = 1;
+        }
+        int tot;
+        const int pos = block_flag_scan(flag, s_wsum, &tot);
+        if (flag) list[L + pos] = r;
+        L += tot;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    cnt[CNT_H1UNSAFE] = L;
+    // two work buffers of up to mE entries in the sort scratch (2 max(E, F, N) int32, free now)
+    int32_t *A = arr<int32_t>(ws, I.o_scratch), *B = A + I.E;
+    for (int u = 0; u < L; ++u) {
+        const int r = list[u];
+        int na = h1n[r];
+        for (int k = 0; k < na; ++k) A[k] = pool[h1b[r] + k];
+        bool changed = false;
+        for (int it = 0; na > 0 && it < kMaxChase; ++it) {
+            const int low = A[0];
+            const int j = piv[low];
+            if (j < 0) break;
+            // A := A + column j over F2, both descending
+            const int *C = pool + h1b[j];
+            const int nc = h1n[j];
+            int a = 0, c = 0, nb = 0;
+            while (a < na || c < nc) {
+                if (c >= nc || (a < na && A[a] > C[c])) B[nb++] = A[a++];
+                else if (a >= na || C[c] > A[a]) B[nb++] = C[c++];
+                else { ++a; ++c; }
+            }
+            int32_t *t = A; A = B; B = t;
+            na = nb;
+            changed = true;
+        }
+        if (na <= 0) { set_err(cnt, PH_EINTERNAL); return; }
+        if (changed) {
+            const int off = atomicAdd(&cnt[CNT_H1POOL], na);
+            if ((int64_t)off + na > I.pool_cap) { set_err(cnt, PH_EINTERNAL); return; }
+            for (int k = 0; k < na; ++k) pool[off + k] = A[k];
+            h1b[r] = off;
+            h1n[r] = na;
+        }
+        piv[A[0]] = r;
+    }
+}
+
 // ====================================================================== output ====
 __device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code) {
     const int64_t HW = (int64_t)I.H * I.W;
@@ -1595,16 +1991,58 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
         return Q;
     };
 
+    // H1 pairs of a volume (KEEP edge r paired with column piv[r]), by birth key (under the
+    // T-filtration: its H1 pairs, the dual of each, by death key)
+    const bool h1 = I.h1 && vol;
+    const int32_t *piv = h1 ? arr<int32_t>(ws, I.o_piv) : nullptr;
+    auto sec_h1 = [&](bool write, int64_t start, int64_t rev) -> int64_t {
+        int64_t Q = 0;
+        for (int base = 0; base < mE; base += blockDim.x) {
+            const int r = base + threadIdx.x;
+            int flag = 0;
+            uint64_t ek = 0, sk = 0;
+            if (r < mE) {
+                const int j = piv[r];
+                if (j >= mf) set_err(cnt, PH_EINTERNAL);
+                else if (j >= 0) {
+                    ek = keyE[r];
+                    sk = fkey[j];
+                    if (!key_ok(ek, 1, 6) || !key_ok(sk, 7, 18)) set_err(cnt, PH_EINTERNAL);
+                    else flag = key_ord(ek) != key_ord(sk);
+                }
+            }
+            int tot;
+            const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (flag && write) {
+                const int32_t bp = (int32_t)key_pix(ek), dp = (int32_t)key_pix(sk);
+                const int64_t at = place(start, rev, Q + pos);
+                if (!tf) {
+                    put(at, 1, img(bp), img(dp), cell_index(I, bp, key_code(ek)), bp, cell_index(I, dp, key_code(sk)), dp);
+                } else {
+                    const int32_t sb = src_px(dp), sd = src_px(bp);
+                    const int64_t cb = t_cell(dp, key_code(sk)), cd = t_cell(bp, key_code(ek));
+                    if (sb < 0 || sd < 0 || cb < 0 || cd < 0) set_err(cnt, PH_EINTERNAL);
+                    else put(at, 1, img(sb), img(sd), cb, sb, cd, sd);
+                }
+            }
+            Q += tot;
+        }
+        return Q;
+    };
+
     if (!tf) {
         if (flags & PH_H0) P += sec_h0(true, P, -1);
+        if (h1) P += sec_h1(true, P, -1);
         if (flags & PH_HTOP) P += sec_top(true, P, -1);
     } else {
         // T order: by dimension, then by death key, so each section is written backwards
         const int64_t c0 = (flags & PH_H0) ? sec_top(false, 0, -1) : 0;
+        const int64_t c1 = h1 ? sec_h1(false, 0, -1) : 0;
         const int64_t ct = (flags & PH_HTOP) ? sec_h0(false, 0, -1) : 0;
         if (flags & PH_H0) sec_top(true, 0, c0);
-        if (flags & PH_HTOP) sec_h0(true, c0, ct);
-        P = c0 + ct;
+        if (h1) sec_h1(true, c0, c1);
+        if (flags & PH_HTOP) sec_h0(true, c0 + c1, ct);
+        P = c0 + c1 + ct;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1648,6 +2086,7 @@ int g_lut_status = PH_OK;
 uint32_t g_h_lut2d[256];
 std::vector<uint32_t> g_h_l1;
 std::vector<uint64_t> g_h_l2;
+std::vector<uint16_t> g_h_h1e, g_h_h1s;
 int g_cfg2d = 0, g_cfg3d = 0;
 std::mutex g_dev_mu;
 bool g_dev_ready[64] = {false};
@@ -1657,9 +2096,11 @@ void build_host_luts() {
     char err[256] = {0};
     g_h_l1.assign(kL1Size, 0);
     g_h_l2.assign(kL3Configs, 0);
+    g_h_h1e.assign((size_t)kL3Configs * 8, 0);
+    g_h_h1s.assign((size_t)kL3Configs * 16, 0);
     g_cfg2d = build_lut2d(g_h_lut2d, err, sizeof err);
     if (g_cfg2d != kL2Configs) { fprintf(stderr, "flashcubical: 2D table: %s\n", err); g_lut_status = PH_EINTERNAL; return; }
-    g_cfg3d = build_lut3d(g_h_l1.data(), g_h_l2.data(), err, sizeof err);
+    g_cfg3d = build_lut3d(g_h_l1.data(), g_h_l2.data(), g_h_h1e.data(), g_h_h1s.data(), err, sizeof err);
     if (g_cfg3d != kL3Configs) { fprintf(stderr, "flashcubical: 3D table: %s\n", err); g_lut_status = PH_EINTERNAL; return; }
 }
 
@@ -1699,6 +2140,13 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_output", (const void *)k_output, kUfThreads},
         {"k_zero", (const void *)k_zero, 256},
         {"k_scatter", (const void *)k_scatter, 256},
+        {"k_classify3d<16,8,8,h1>", (const void *)k_classify3d<16, 8, 8, float, true>, 256},
+        {"k_classify3d<16,8,8,u8,h1>", (const void *)k_classify3d<16, 8, 8, uint8_t, true>, 256},
+        {"k_classify3d<16,8,8,u16,h1>", (const void *)k_classify3d<16, 8, 8, uint16_t, true>, 256},
+        {"k_h1_morse", (const void *)k_h1_morse<float>, 64},
+        {"k_h1_morse<u8>", (const void *)k_h1_morse<uint8_t>, 64},
+        {"k_h1_morse<u16>", (const void *)k_h1_morse<uint16_t>, 64},
+        {"k_h1_reduce", (const void *)k_h1_reduce, kUfThreads},
         {"k_tpad", (const void *)k_tpad<float>, 256},
         {"k_tpad<u8>", (const void *)k_tpad<uint8_t>, 256},
         {"k_tpad<u16>", (const void *)k_tpad<uint16_t>, 256},
@@ -1733,17 +2181,22 @@ int device_luts() {
     if (!hip_ok(hipGetDevice(&dev), "hipGetDevice") || dev < 0 || dev >= 64) return PH_EHIP;
     std::lock_guard<std::mutex> lk(g_dev_mu);
     if (g_dev_ready[dev]) return PH_OK;
-    void *a = nullptr, *b = nullptr, *c = nullptr;
-    if (!hip_ok(hipMalloc(&a, sizeof g_h_lut2d), "hipMalloc (tables)")) return PH_EHIP;
-    if (!hip_ok(hipMalloc(&b, sizeof(uint32_t) * kL1Size), "hipMalloc (tables)")) { (void)hipFree(a); return PH_EHIP; }
-    if (!hip_ok(hipMalloc(&c, sizeof(uint64_t) * kL3Configs), "hipMalloc (tables)")) { (void)hipFree(a); (void)hipFree(b); return PH_EHIP; }
-    if (!hip_ok(hipMemcpy(a, g_h_lut2d, sizeof g_h_lut2d, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
-        !hip_ok(hipMemcpy(b, g_h_l1.data(), sizeof(uint32_t) * kL1Size, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
-        !hip_ok(hipMemcpy(c, g_h_l2.data(), sizeof(uint64_t) * kL3Configs, hipMemcpyHostToDevice), "hipMemcpy (tables)")) {
-        (void)hipFree(a); (void)hipFree(b); (void)hipFree(c);
+    // one device buffer holds every table, each part 256-byte aligned
+    const size_t n2d = sizeof g_h_lut2d, n1 = sizeof(uint32_t) * kL1Size, n2 = sizeof(uint64_t) * kL3Configs;
+    const size_t ne = sizeof(uint16_t) * g_h_h1e.size(), ns = sizeof(uint16_t) * g_h_h1s.size();
+    const size_t o1 = align256(n2d), o2 = o1 + align256(n1), oe = o2 + align256(n2), os = oe + align256(ne);
+    uint8_t *buf = nullptr;
+    if (!hip_ok(hipMalloc((void **)&buf, os + ns), "hipMalloc (tables)")) return PH_EHIP;
+    if (!hip_ok(hipMemcpy(buf, g_h_lut2d, n2d, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(buf + o1, g_h_l1.data(), n1, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(buf + o2, g_h_l2.data(), n2, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(buf + oe, g_h_h1e.data(), ne, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(buf + os, g_h_h1s.data(), ns, hipMemcpyHostToDevice), "hipMemcpy (tables)")) {
+        (void)hipFree(buf);
         return PH_EHIP;
     }
-    g_dev_lut[dev] = Luts{(const uint32_t *)a, (const uint32_t *)b, (const uint64_t *)c};
+    g_dev_lut[dev] = Luts{(const uint32_t *)buf, (const uint32_t *)(buf + o1), (const uint64_t *)(buf + o2),
+                          (const uint16_t *)(buf + oe), (const uint16_t *)(buf + os)};
     rc = check_kernels(dev, nullptr, 0);
     if (rc != PH_OK) return rc;
     g_dev_ready[dev] = true;
@@ -1771,7 +2224,7 @@ Tiles tiles_of(const ph_tuning *t) {
 }
 
 // total workspace bytes and classify grid sizes for a list of host shapes
-int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3, bool tfilt) {
+int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3, bool tfilt, bool h1) {
     int64_t at = header_bytes(n);
     *t2 = 0;
     *t3 = 0;
@@ -1779,6 +2232,7 @@ int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_
         Inst I;
         fill_inst(I, tfilt ? framed(h[i]) : h[i], tl);
         I.tfilt = tfilt;
+        I.h1 = h1 && I.ndim == 3;
         if (I.ndim == 2) *t2 += (int64_t)I.tx * I.ty;
         else *t3 += (int64_t)I.tx * I.ty * I.tz;
         at = layout(I, at);
@@ -1811,9 +2265,9 @@ template <int A, int B, typename T = float>
 void launch2d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
     hipLaunchKernelGGL((k_classify2d<A, B, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
 }
-template <int A, int B, int C, typename T = float>
+template <int A, int B, int C, typename T = float, bool H1 = false>
 void launch3d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify3d<A, B, C, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
+    hipLaunchKernelGGL((k_classify3d<A, B, C, T, H1>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
 }
 
 Luts current_luts() {
@@ -1858,12 +2312,13 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // Optional per-launch timing with HIP events on the launch stream (not for use while the
 // stream is being captured into a graph).
 enum KernelId {
-    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_OUTPUT,
-    K_ZERO, K_SCATTER, K_TPAD, K_COUNT
+    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1REDUCE,
+    K_OUTPUT, K_ZERO, K_SCATTER, K_TPAD, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
-    "k_resolve(2d top)", "k_unionfind(2d top)", "k_output", "k_zero", "k_scatter", "k_tpad"};
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
+    "k_tpad"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -1943,16 +2398,23 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         if (!valid_shape(h_shapes[i]) || !valid_shape(hs[i])) return PH_EINVAL;
         (h_shapes[i].ndim == 3 ? any3 : any2) = true;
     }
-    if (!(flags & (PH_H0 | PH_HTOP))) return PH_EINVAL;
+    if (!(flags & (PH_H0 | PH_HTOP | PH_H1))) return PH_EINVAL;
     if ((flags & PH_IN_U8) && (flags & PH_IN_U16)) return PH_EINVAL;
     const int in_elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
     const int elem = tf ? 0 : in_elem;             // element type the classify passes read
     if (elem != 0) tuning = nullptr;               // integer inputs use the default tiles
+    const bool h1 = (flags & PH_H1) != 0;
+    ph_tuning h1_tuning;
+    if (h1 && tuning && tuning->tile3d != 0) {     // 3D H1 plans and runs the default 3D tile
+        h1_tuning = *tuning;
+        h1_tuning.tile3d = 0;
+        tuning = &h1_tuning;
+    }
     int rc = device_luts();
     if (rc != PH_OK) return rc;
     const Tiles tl = tiles_of(tuning);
     int64_t t2, t3;
-    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3, tf);   // frames them itself
+    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3, tf, h1);   // frames them itself
     if ((int64_t)ws_bytes < need) return PH_ENOMEM;
     if (t2 >= (1ll << 31) || t3 >= (1ll << 31)) return PH_EINVAL;
     uint8_t *ws = (uint8_t *)d_ws;
@@ -1975,7 +2437,8 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         if (trace && trace_after(KID, st) != PH_OK) return PH_EHIP;           \
     } while (0)
     FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, n, d_shapes, single, d_img_off, d_out_off,
-                                 single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes, tf ? 1 : 0));
+                                 single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes, tf ? 1 : 0,
+                                 h1 ? 1 : 0));
     const int64_t ml = max_list(hs, n), mv = max_voxels(hs, n);
     const void *cimgs = d_imgs;                    // what the classify passes read
     if (tf) {
@@ -2000,7 +2463,11 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, cimgs, ws, n, lut, st));
         else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, cimgs, ws, n, lut, st));
     }
-    if (t3 > 0) {
+    if (t3 > 0 && h1) {                            // 3D H1 keeps every configuration: default tiles
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t, true>(t3, cimgs, ws, n, lut, st)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t, true>(t3, cimgs, ws, n, lut, st)));
+        else FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, float, true>(t3, cimgs, ws, n, lut, st)));
+    } else if (t3 > 0) {
         if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, cimgs, ws, n, lut, st)));
         else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, cimgs, ws, n, lut, st)));
         else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, cimgs, ws, n, lut, st));
@@ -2014,13 +2481,23 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
     FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n));
     // volumes: the dual (resolve, union-find) beside H0; images: the dual after H0
-    const int htop = (tf || (flags & PH_HTOP)) ? 1 : 0;   // T's H0 is the V top
+    // T's H0 is the V top; 3D H1 needs the squares the dual union-find pairs
+    const int htop = (tf || (flags & PH_HTOP) || (h1 && any3)) ? 1 : 0;
     const unsigned side = htop && any3 ? 2 : 1;
     FC_LAUNCH(K_RESOLVE, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n, side), dim3(256), 0, st, ws, n, 0, htop));
     FC_LAUNCH(K_UF, hipLaunchKernelGGL(k_unionfind, dim3(n, side), dim3(kUfThreads), 0, st, ws, n, 0, htop));
     if (htop && any2) {
         FC_LAUNCH(K_RESOLVE_2D, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n), dim3(256), 0, st, ws, n, 1, htop));
         FC_LAUNCH(K_UF_2D, hipLaunchKernelGGL(k_unionfind, dim3(n), dim3(kUfThreads), 0, st, ws, n, 1, htop));
+    }
+    if (h1 && any3) {
+        // one 64-thread workgroup per 4096 voxels of the largest volume (at most 1024 per
+        // instance), each taking columns in turn
+        const unsigned hb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (mv + 4095) / 4096));
+        if (elem == 1) FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<uint8_t>, dim3(hb, n), dim3(64), 0, st, (const uint8_t *)cimgs, ws, n, lut));
+        else if (elem == 2) FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<uint16_t>, dim3(hb, n), dim3(64), 0, st, (const uint16_t *)cimgs, ws, n, lut));
+        else FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<float>, dim3(hb, n), dim3(64), 0, st, (const float *)cimgs, ws, n, lut));
+        FC_LAUNCH(K_H1REDUCE, hipLaunchKernelGGL(k_h1_reduce, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
                                  d_status));
@@ -2052,6 +2529,16 @@ int64_t ph_capacity_bound(ph_shape s) {
     return I.N + I.T;
 }
 
+int64_t ph_capacity_bound_flags(ph_shape s, uint32_t flags) {
+    if (flags & PH_TFILT) s = fc::framed(s);
+    if (!fc::valid_shape(s)) return 0;
+    fc::Inst I;
+    fc::fill_inst(I, s, fc::Tiles{64, 16, 16, 8, 8});
+    const fc::Geom g = fc::geom(I.ndim, I.D, I.H, I.W);
+    // H1 pairs of a volume: at most its negative squares, S - C (= E - V + 1 by Euler)
+    return I.N + I.T + ((flags & PH_H1) && I.ndim == 3 ? g.S - g.C : 0);
+}
+
 size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
     const bool tf = (flags & PH_TFILT) != 0;
     if (!h_shapes || n < 1) return 0;
@@ -2061,7 +2548,7 @@ size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
     for (int a = 0; a < 3; ++a)                      // large enough for every tile choice
         for (int b = 0; b < 3; ++b) {
             ph_tuning t{a, b};
-            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3, tf);
+            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3, tf, (flags & PH_H1) != 0);
             if (need > best) best = need;
         }
     return (size_t)best;
@@ -2222,10 +2709,11 @@ int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out) {
     if (hipMemcpy(c.data(), (const uint8_t *)d_ws + fc::off_cnt(n), c.size() * sizeof(int32_t),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return PH_EHIP;
-    const int pick[8] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
-                         fc::CNT_SEQ, fc::CNT_ERR};
+    const int pick[12] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
+                          fc::CNT_SEQ, fc::CNT_ERR, fc::CNT_H1COLS, fc::CNT_H1UNSAFE, fc::CNT_H1ROUNDS,
+                          fc::CNT_H1POOL};
     for (int i = 0; i < n; ++i)
-        for (int k = 0; k < 8; ++k) h_out[i * 8 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
+        for (int k = 0; k < 12; ++k) h_out[i * 12 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
     return PH_OK;
 }
 
@@ -2299,12 +2787,17 @@ int ph_init_device(void) {
     }
     std::vector<uint32_t> l2d(256), l1(fc::kL1Size);
     std::vector<uint64_t> l2(fc::kL3Configs);
+    std::vector<uint16_t> he(fc::g_h_h1e.size()), hs(fc::g_h_h1s.size());
     const fc::Luts t = fc::current_luts();
     if (!fc::hip_ok(hipMemcpy(l2d.data(), t.l2d, 256 * sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
         !fc::hip_ok(hipMemcpy(l1.data(), t.l1, l1.size() * sizeof(uint32_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
-        !fc::hip_ok(hipMemcpy(l2.data(), t.l2, l2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)"))
+        !fc::hip_ok(hipMemcpy(l2.data(), t.l2, l2.size() * sizeof(uint64_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
+        !fc::hip_ok(hipMemcpy(he.data(), t.h1e, he.size() * sizeof(uint16_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)") ||
+        !fc::hip_ok(hipMemcpy(hs.data(), t.h1s, hs.size() * sizeof(uint16_t), hipMemcpyDeviceToHost), "hipMemcpy (read-back)"))
         return PH_EHIP;
-    if (memcmp(l2d.data(), fc::g_h_lut2d, 256 * sizeof(uint32_t)) || l1 != fc::g_h_l1 || l2 != fc::g_h_l2) return PH_EINTERNAL;
+    if (memcmp(l2d.data(), fc::g_h_lut2d, 256 * sizeof(uint32_t)) || l1 != fc::g_h_l1 || l2 != fc::g_h_l2 ||
+        he != fc::g_h_h1e || hs != fc::g_h_h1s)
+        return PH_EINTERNAL;
     return PH_OK;
 }
 

@@ -42,13 +42,16 @@ struct Local {
     int partner[27];   // paired cell code, -1 if critical / absent
     bool birth[27];    // true when the cell is the positive member of its pair
     int link[27];      // for top cells paired in L(v): code of the cofacet across (may be absent)
+    uint32_t comb[27]; // cells of L(v) (bit per code) whose boundaries sum to the reduced column
 };
 
 // Relative reduction of L(v); `present` has bit c for each cell code in L(v).
 bool reduce_local(uint32_t present, Local &L, char *err, int errlen) {
     uint32_t R[27] = {0};
     int pivot_of[27];
-    for (int c = 0; c < 27; ++c) { pivot_of[c] = -1; L.partner[c] = -1; L.birth[c] = false; L.link[c] = -1; }
+    for (int c = 0; c < 27; ++c) {
+        pivot_of[c] = -1; L.partner[c] = -1; L.birth[c] = false; L.link[c] = -1; L.comb[c] = 0;
+    }
     for (int c = 0; c < 27; ++c) {                 // code order = order inside L(v)
         if (!((present >> c) & 1u)) continue;
         uint32_t col = 0;
@@ -60,11 +63,14 @@ bool reduce_local(uint32_t present, Local &L, char *err, int errlen) {
             if (!((present >> fc_) & 1u)) { snprintf(err, errlen, "L(v) not closed"); return false; }
             col |= 1u << fc_;
         }
+        uint32_t comb = 1u << c;
         while (col) {
             int low = 31 - __builtin_clz(col);
             if (pivot_of[low] < 0) break;
             col ^= R[pivot_of[low]];
+            comb ^= L.comb[pivot_of[low]];
         }
+        L.comb[c] = comb;
         if (col) {
             int low = 31 - __builtin_clz(col);
             pivot_of[low] = c;
@@ -145,9 +151,34 @@ bool entry2d(uint32_t present, uint32_t *out, char *err, int errlen) {
     return true;
 }
 
-bool entry3d(uint32_t present, uint64_t *out, char *err, int errlen) {
+// H1 rows of a 3D configuration (Sec. 4.2 steps 4-5): per edge slot i of L(v) paired with a
+// square tau of L(v), the squares of L(v) (12-bit mask, bit s = code 7 + s) whose boundaries
+// sum to tau's reduced column, whose last entry is that edge; per square slot s that stays
+// critical, the squares whose boundaries sum to zero inside L(v) (s itself and the earlier
+// columns its reduction added).  0 where the slot has no such role.
+bool h1rows(const Local &L, uint32_t present, uint16_t *edge, uint16_t *square, char *err, int errlen) {
+    for (int i = 0; i < 8; ++i) edge[i] = 0;
+    for (int s = 0; s < 16; ++s) square[s] = 0;
+    for (int i = 0; i < 6; ++i) {
+        const int c = 1 + i, t = L.partner[c];
+        if (!((present >> c) & 1u) || t < 7) continue;        // absent, critical or paired with v
+        if (t > 18 || !L.birth[c]) { snprintf(err, errlen, "edge %d paired with cell %d", c, t); return false; }
+        edge[i] = (uint16_t)((L.comb[t] >> 7) & 0xFFFu);
+        if (L.comb[t] & ~(0xFFFu << 7)) { snprintf(err, errlen, "square combination leaves the squares"); return false; }
+    }
+    for (int s = 0; s < 12; ++s) {
+        const int c = 7 + s;
+        if (!((present >> c) & 1u) || L.partner[c] >= 0) continue;
+        square[s] = (uint16_t)((L.comb[c] >> 7) & 0xFFFu);
+        if (L.comb[c] & ~(0xFFFu << 7)) { snprintf(err, errlen, "square combination leaves the squares"); return false; }
+    }
+    return true;
+}
+
+bool entry3d(uint32_t present, uint64_t *out, uint16_t *h1e, uint16_t *h1s, char *err, int errlen) {
     Local L;
     if (!reduce_local(present, L, err, errlen) || !dual_links(present, false, L, err, errlen)) return false;
+    if (!h1rows(L, present, h1e, h1s, err, errlen)) return false;
     uint64_t e = kNoDirect;
     if (L.partner[0] >= 0) e = (uint64_t)(L.partner[0] - 1);
     for (int i = 0; i < 6; ++i) {
@@ -195,8 +226,10 @@ int build_lut2d(uint32_t *lut, char *err, int errlen) {
     return (int)seen.size();
 }
 
-// 3D: level 1 (2^18 words) and level 2 (kL3Configs entries).  Returns the config count or -1.
-int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen) {
+// 3D: level 1 (2^18 words) and level 2 (kL3Configs entries), and the H1 rows of every level-2
+// entry (h1e: 8 uint16 per entry, h1s: 16 uint16 per entry; see h1rows).  Returns the config
+// count or -1.
+int build_lut3d(uint32_t *l1, uint64_t *l2, uint16_t *h1e, uint16_t *h1s, char *err, int errlen) {
     memset(l1, 0, sizeof(uint32_t) * kL1Size);
     uint32_t next = 0;
     for (uint32_t face = 0; face < 64; ++face) {
@@ -219,7 +252,7 @@ int build_lut3d(uint32_t *l1, uint64_t *l2, char *err, int errlen) {
                 for (int s = 0; s < 12; ++s) if ((sq >> s) & 1u) present |= 1u << (7 + s);
                 for (int c = 0; c < 8; ++c) if ((cb >> c) & 1u) present |= 1u << (19 + c);
                 uint32_t slot = next + compress8(cb, poss);
-                if (!entry3d(present, &l2[slot], err, errlen)) return -1;
+                if (!entry3d(present, &l2[slot], h1e + 8 * (size_t)slot, h1s + 16 * (size_t)slot, err, errlen)) return -1;
             }
             next += n2;
         }

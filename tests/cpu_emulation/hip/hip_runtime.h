@@ -333,6 +333,24 @@ template <typename T> EMU_FN T atomicMin(T *p, T v) {
     }
     return old;
 }
+template <typename T> EMU_FN T atomicXor(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
+    emu_maybe_yield();
+    return __atomic_fetch_xor(p, v, __ATOMIC_SEQ_CST);
+}
+template <typename T> EMU_FN T atomicOr(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
+    emu_maybe_yield();
+    return __atomic_fetch_or(p, v, __ATOMIC_SEQ_CST);
+}
+template <typename T> EMU_FN T atomicMax(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
+    emu_maybe_yield();
+    T old = __atomic_load_n(p, __ATOMIC_SEQ_CST);
+    while (v > old && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_SEQ_CST, __ATOMIC_SEQ_CST)) {
+    }
+    return old;
+}
 template <typename T> EMU_FN T atomicCAS(T *p, T cmp, T v) {
     emu_check_access(p, sizeof(T), 1);
     emu_maybe_yield();

@@ -3,7 +3,8 @@
     python tests/golden/make_digests.py [--jobs 6] [--only c1,c2,...]
 
 Configs c1..c5 are under the V-filtration; c5t is c5's 128 instances under the T-filtration
-(pixels as top cells), whose pairs come in the T output order (dim, death key).
+(pixels as top cells), whose pairs come in the T output order (dim, death key); c5h1 is c5's
+first eight volumes with every dimension (H0, H1, H2).
 
 Calls only the CPU oracle (oracle/) and the seeded generators (synthetic.py).  For every
 instance it stores the digest of its input pixels (so a change of generator is caught), the
@@ -60,7 +61,14 @@ def instances():
     for i in range(64):
         out.append(("c5", 64 + i, "grf", ((512, 512), 6.0, 3000 + i)))
     out += [("c5t",) + it[1:] for it in out if it[0] == "c5"]
+    out += [("c5h1",) + it[1:] for it in out if it[0] == "c5" and it[1] < 8]
     return out
+
+
+def dims_of(cfg, ndim):
+    """The dimensions a config's digest covers: every one for the H1 configs (name ending in
+    h1), else H0 and the top dimension."""
+    return tuple(range(ndim)) if cfg.endswith("h1") else (0, ndim - 1)
 
 
 def filtration_of(cfg) -> str:
@@ -84,7 +92,7 @@ def job(item):
     cfg, idx, kind, args = item
     img = make(kind, args)
     t0 = time.perf_counter()
-    p = oracle.diagram(img, filtration=filtration_of(cfg))
+    p = oracle.diagram(img, dims=dims_of(cfg, img.ndim), filtration=filtration_of(cfg))
     dt = time.perf_counter() - t0
     top = img.ndim - 1
     return cfg, idx, {"shape": list(img.shape), "input_sha256": input_digest(img),
