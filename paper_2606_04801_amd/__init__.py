@@ -415,15 +415,16 @@ class Batch:
                     stream)
 
     def work_counters(self):
-        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 12) array:
+        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 14) array:
         KEEP edges, KEEP squares, H0 nodes, dual nodes, H0 rounds, dual rounds, sequential
-        edges, error word, and for 3D H1: columns, columns reduced one by one, most rounds of
-        one column, pool entries.  Synchronises."""
-        out = (ctypes.c_int32 * (12 * self.n))()
+        edges, error word, and for 3D H1: columns, columns reduced one by one, most steps of
+        one column, pool entries, columns that needed the large tables, reduction rounds
+        (column additions when it ran one column at a time).  Synchronises."""
+        out = (ctypes.c_int32 * (14 * self.n))()
         rc = lib().ph_work_counters(_ptr(self.ws), self.n, out)
         if rc != PH_OK:
             raise PHError(rc, "ph_work_counters")
-        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 12).copy()
+        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 14).copy()
 
     def valid_mask(self):
         """Device bool mask over the packed pair slots holding a stored pair (no sync)."""

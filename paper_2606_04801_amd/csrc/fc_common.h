@@ -140,7 +140,7 @@ struct Inst {
     // H1 of a volume: per-vertex configuration index and first sorted KEEP edge, per KEEP
     // square its H1 column (start and length in the pool, -1 if paired in H2), per KEEP edge
     // its pivot column and the first column holding it, and the pool of column entries
-    int64_t o_cfg3, o_kpos, o_h1b, o_h1n, o_piv, o_first, o_pool;
+    int64_t o_cfg3, o_kpos, o_h1b, o_h1n, o_piv, o_first, o_pool, o_retry;
     int64_t pool_cap;          // int32 entries of the pool
     int64_t end;
 };
@@ -151,7 +151,7 @@ struct Inst {
 enum {
     CNT_E = 0, CNT_F = 32, CNT_M0 = 64, CNT_MT = 96,
     CNT_ERR = 128, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ,
-    CNT_H1COLS, CNT_H1UNSAFE, CNT_H1ROUNDS, CNT_H1ENTRIES,
+    CNT_H1COLS, CNT_H1UNSAFE, CNT_H1ROUNDS, CNT_H1RETRY, CNT_H1ADDS,
     CNT_H1POOL = 160, CNT_WORDS = 192
 };
 // pool entries per KEEP-square slot of an H1 volume: room for the Morse boundaries of the
@@ -209,6 +209,7 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_piv = h1 ? take(4 * E) : 0;
     I.o_first = h1 ? take(4 * E) : 0;
     I.o_pool = h1 ? take(4 * I.pool_cap) : 0;
+    I.o_retry = h1 ? take(4 * F) : 0;       // columns too large for the first pass's tables
     I.end = at;
     return at;
 }

@@ -1464,42 +1464,120 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
 //
 // One single-wave workgroup per column at a time; the column is an F2 set of edge keys in an
 // open-addressing table in LDS (toggling a key is adding the edge).
-constexpr int kH1Slots = 2048;             // table slots per workgroup (16 KiB of keys)
-constexpr int kH1SlotBits = 11;
-constexpr int kH1Compact = 1536;           // compact the table when more slots are in use
-constexpr int kH1MaxLive = 1024;           // more live entries than this after compacting: error
+constexpr int kH1Slots = 1024;             // table slots (and queue entries) of the first pass
+constexpr int kH1BigSlots = 4096;          // the same for the columns the first pass could not hold
 constexpr int kH1MaxBoundary = 64;         // entries of one column's boundary in critical cells
-constexpr int kH1MaxRounds = 1 << 16;
-constexpr uint64_t kH1Empty = ~0ull;
-// an edge key has code 1..6 in its low 3 bits; bits 3 and 4 carry the slot state
-constexpr uint64_t kH1Present = 1ull << 3, kH1Final = 1ull << 4, kH1Flags = kH1Present | kH1Final;
+constexpr int kH1MaxChunks = 1 << 20;
+// A column holds edges by their id, pixel << 5 | code (the low 32 bits of the edge key: the
+// pixel is the edge's last vertex, the code 1..6 sits in the low 3 bits); bits 3 and 4 of a
+// table entry carry the slot state.  An id is below 2^32 - 1, so the empty slot cannot occur.
+constexpr uint32_t kH1Empty = ~0u;
+constexpr uint32_t kH1Present = 1u << 3, kH1Final = 1u << 4, kH1Flags = kH1Present | kH1Final;
 
-__device__ __forceinline__ uint32_t h1_hash(uint64_t key) {
-    const uint32_t x = (uint32_t)(key >> kCodeBits) * 8u + (uint32_t)(key & 7u);   // pixel, code
-    return (x * 2654435761u) >> (32 - kH1SlotBits);
+template <int SLOTS>
+__device__ __forceinline__ uint32_t h1_hash(uint32_t id) {
+    constexpr int BITS = SLOTS == 512 ? 9 : (SLOTS == 1024 ? 10 : (SLOTS == 2048 ? 11 : 12));
+    static_assert((1 << BITS) == SLOTS, "power-of-two table");
+    const uint32_t x = (id >> kCodeBits) * 8u + (id & 7u);   // pixel, code
+    return (x * 2654435761u) >> (32 - BITS);
 }
 
-// Add edge `key` to the column (toggle its presence).  False when the table is full.
-__device__ __forceinline__ bool h1_toggle(uint64_t *tab, int *used, uint64_t key) {
-    uint32_t h = h1_hash(key);
-    for (int probe = 0; probe < kH1Slots; ++probe, h = (h + 1) & (kH1Slots - 1)) {
-        unsigned long long v = __hip_atomic_load((unsigned long long *)&tab[h], __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (v == kH1Empty) {
-            v = atomicCAS((unsigned long long *)&tab[h], (unsigned long long)kH1Empty,
-                          (unsigned long long)(key | kH1Present));
+// The LDS state of one column: an open-addressing table of edge keys (a key's slot keeps its
+// state: present in the column, classified, known negative), and a FIFO of keys that turned
+// present while unclassified (each is looked at once it comes out).
+template <int SLOTS>
+struct H1Col {
+    uint32_t *tab;
+    uint32_t *alt;                 // second table the big tables compact into (unused below 2048)
+    uint32_t *queue;
+    uint32_t *neg;                 // bit per slot: the key there is a negative edge
+    int *used, *tail, *over;
+    int head;                      // queue position of the chunk being processed (uniform)
+
+    __device__ __forceinline__ bool is_neg(uint32_t h) const { return (neg[h >> 5] >> (h & 31)) & 1u; }
+    __device__ __forceinline__ void enqueue(uint32_t key) {
+        const int t = atomicAdd(tail, 1);
+        if (t - head >= SLOTS) atomicOr(over, 1);
+        else queue[t & (SLOTS - 1)] = key;
+    }
+    // add edge `key` to the column (toggle its presence); negative edges are left out for good
+    __device__ __forceinline__ void toggle(uint32_t key) {
+        uint32_t h = h1_hash<SLOTS>(key);
+        for (int probe = 0; probe < SLOTS; ++probe, h = (h + 1) & (SLOTS - 1)) {
+            uint32_t v = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (v == kH1Empty) {
-                atomicAdd(used, 1);
-                return true;
+                v = atomicCAS(&tab[h], kH1Empty, key | kH1Present);
+                if (v == kH1Empty) {
+                    atomicAdd(used, 1);
+                    enqueue(key);
+                    return;
+                }
+            }
+            if ((v & ~kH1Flags) == key) {
+                if ((v & kH1Final) && is_neg(h)) return;
+                const uint32_t old = atomicXor(&tab[h], kH1Present);
+                if (!(old & kH1Present) && !(old & kH1Final)) enqueue(key);
+                return;
             }
         }
-        if ((v & ~kH1Flags) == key) {
-            atomicXor((unsigned long long *)&tab[h], (unsigned long long)kH1Present);
-            return true;
-        }
+        atomicOr(over, 1);
     }
-    return false;
-}
+    // slot of `key`, or -1
+    __device__ __forceinline__ int find(uint32_t key) const {
+        uint32_t h = h1_hash<SLOTS>(key);
+        for (int probe = 0; probe < SLOTS; ++probe, h = (h + 1) & (SLOTS - 1)) {
+            const uint32_t v = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (v == kH1Empty) return -1;
+            if ((v & ~kH1Flags) == key) return (int)h;
+        }
+        return -1;
+    }
+    __device__ __forceinline__ void reinsert(uint32_t *t, uint32_t x) {
+        uint32_t h = h1_hash<SLOTS>(x & ~kH1Flags);
+        for (int probe = 0; probe < SLOTS; ++probe, h = (h + 1) & (SLOTS - 1))
+            if (atomicCAS(&t[h], kH1Empty, x) == kH1Empty) break;
+        atomicAdd(used, 1);
+    }
+    // rebuild the table with its live entries (present, not negative); all lanes call it
+    __device__ __forceinline__ void compact() {
+        const int lane = threadIdx.x;
+        if constexpr (SLOTS >= 2048) {              // through the second table
+            lds_barrier();                          // every lane has read *used
+            for (int k = lane; k < SLOTS; k += 64) alt[k] = kH1Empty;
+            if (lane == 0) *used = 0;
+            lds_barrier();
+            for (int k = lane; k < SLOTS; k += 64) {
+                const uint32_t x = tab[k];
+                if (x != kH1Empty && (x & kH1Present) && !((x & kH1Final) && is_neg(k))) reinsert(alt, x);
+            }
+            lds_barrier();
+            for (int k = lane; k < SLOTS / 32; k += 64) neg[k] = 0;
+            uint32_t *t = tab;
+            tab = alt;
+            alt = t;
+            lds_barrier();
+            return;
+        }
+        constexpr int PER = SLOTS / 64;
+        uint32_t keep[PER];
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int k = lane + 64 * j;
+            const uint32_t x = tab[k];
+            keep[j] = (x != kH1Empty && (x & kH1Present) && !((x & kH1Final) && is_neg(k))) ? x : kH1Empty;
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < PER; ++j) tab[lane + 64 * j] = kH1Empty;
+        for (int k = lane; k < SLOTS / 32; k += 64) neg[k] = 0;
+        if (lane == 0) *used = 0;
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < PER; ++j)
+            if (keep[j] != kH1Empty) reinsert(tab, keep[j]);
+        lds_barrier();
+    }
+};
 
 // order key of voxel p: ord32 of its value, then p (the vertex order of Sec. 2.3)
 template <typename T>
@@ -1514,11 +1592,12 @@ __device__ __forceinline__ uint64_t edge_key_of(uint64_t ka, uint64_t kb, uint32
     return (k & 0xFFFFFFFF00000000ull) | ((k & 0xFFFFFFFFull) << kCodeBits) | (a_last ? code_ab : 7u - code_ab);
 }
 
-// Add the boundary of square slot q of L(w) (w's key bits kw5 = order << 32 | w << 5) to the
-// column: its two edges at w and the two opposite ones, whose last vertices are looked up.
-template <typename T>
-__device__ __forceinline__ bool h1_square(const T *img, uint64_t kw5, uint32_t w, int q, int W, int HW,
-                                          uint64_t *tab, int *used) {
+// Add the boundary of square slot q of L(w) to the column, every occurrence of edge `skip` left
+// out: its two edges at w (w is their last vertex) and the two opposite ones, whose last
+// vertices are looked up.
+template <int SLOTS, typename T>
+__device__ __forceinline__ void h1_square(H1Col<SLOTS> &col, const T *img, uint32_t w, int q, int W, int HW,
+                                          uint32_t skip) {
     const int c = 7 + q;
     const int a1 = off_of(c, 0) ? 0 : 1;            // the two axes the square spans, slowest first
     const int a2 = off_of(c, 2) ? 2 : 1;
@@ -1528,25 +1607,26 @@ __device__ __forceinline__ bool h1_square(const T *img, uint64_t kw5, uint32_t w
     const uint32_t pa = (uint32_t)((int)w + s1 * st1), pb = (uint32_t)((int)w + s2 * st2);
     const uint32_t pab = (uint32_t)((int)pa + s2 * st2);
     const uint64_t ka = vox_key(img, pa), kb = vox_key(img, pb), kab = vox_key(img, pab);
-    bool ok = h1_toggle(tab, used, kw5 | c1);
-    ok &= h1_toggle(tab, used, kw5 | c2);
-    ok &= h1_toggle(tab, used, edge_key_of(ka, kab, c2));
-    ok &= h1_toggle(tab, used, edge_key_of(kb, kab, c1));
-    return ok;
+    const uint32_t w5 = w << kCodeBits;
+    const uint32_t e[4] = {w5 | c1, w5 | c2, (uint32_t)edge_key_of(ka, kab, c2), (uint32_t)edge_key_of(kb, kab, c1)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (e[k] != skip) col.toggle(e[k]);
 }
 
-// Class of edge `key` (no state bits): 0 negative (paired with its vertex, or a KEEP edge H0
-// used), 1 a KEEP edge left positive by H0 (*rr: its sorted position), 2 paired in its lower
-// star (*comb: its partner's combination), -1 inconsistent data.
-__device__ __forceinline__ int h1_class(uint64_t key, const uint16_t *cfg3, const int32_t *kpos,
+// Class of the edge with id `key` (no state bits): 0 negative (paired with its vertex, or a KEEP
+// edge H0 used), 1 a KEEP edge left positive by H0 (*rr: its sorted position), 2 paired in its
+// lower star (*comb: its partner's combination), -1 inconsistent data.
+__device__ __forceinline__ int h1_class(uint32_t key, const uint16_t *cfg3, const int32_t *kpos,
                                         const int32_t *neg0, int64_t N, int mE, const Luts &lut,
                                         uint32_t *comb, int *rr) {
-    const uint32_t w = key_pix(key), c = key_code(key);
+    const uint32_t w = key >> kCodeBits, c = key & 31u;
     if (w >= N || c < 1 || c > 6) return -1;
     const uint32_t cfg = cfg3[w];
     const int32_t kp = kpos[w];                      // meaningful only if w has KEEP edges
     if (cfg >= (uint32_t)kL3Configs) return -1;
     const uint64_t ent = lut.l2[cfg];
+    const uint32_t cm = lut.h1e[cfg * 8 + (c - 1)];
     if ((uint32_t)(ent & 7u) == c - 1) return 0;
     const uint32_t keep = (uint32_t)(ent >> kL3Keep) & 63u;
     if ((keep >> (c - 1)) & 1u) {
@@ -1555,52 +1635,24 @@ __device__ __forceinline__ int h1_class(uint64_t key, const uint16_t *cfg3, cons
         *rr = r;
         return neg0[r] ? 0 : 1;
     }
-    *comb = lut.h1e[cfg * 8 + (c - 1)];
-    return *comb ? 2 : -1;
+    *comb = cm;
+    return cm ? 2 : -1;
 }
 
-// Rebuild the table with its live entries only (present and not known negative); all lanes.
-__device__ __forceinline__ void h1_compact(uint64_t *tab, const uint32_t *negbits, int *used) {
-    constexpr int PER = kH1Slots / 64;
-    uint64_t keep[PER];
-    const int lane = threadIdx.x;
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        const int k = lane + 64 * j;
-        const uint64_t x = tab[k];
-        const bool neg = (negbits[k >> 5] >> (k & 31)) & 1u;
-        keep[j] = (x != kH1Empty && (x & kH1Present) && !((x & kH1Final) && neg)) ? x : kH1Empty;
-    }
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < PER; ++j) tab[lane + 64 * j] = kH1Empty;
-    if (lane == 0) *used = 0;
-    lds_barrier();
-#pragma unroll
-    for (int j = 0; j < PER; ++j) {
-        if (keep[j] == kH1Empty) continue;
-        uint32_t h = h1_hash(keep[j] & ~kH1Flags);
-        for (int probe = 0; probe < kH1Slots; ++probe, h = (h + 1) & (kH1Slots - 1)) {
-            const unsigned long long v = atomicCAS((unsigned long long *)&tab[h], (unsigned long long)kH1Empty,
-                                                   (unsigned long long)keep[j]);
-            if (v == kH1Empty) break;
-        }
-        atomicAdd(used, 1);
-    }
-    lds_barrier();
-}
-
-// One workgroup of 64 threads per column at a time, blockIdx.y = instance: the column's
-// boundary in critical cells (sorted descending) goes to the pool, its start and length to
-// h1b, h1n (-1 for a square paired in H2).
-template <typename T>
+// One workgroup of 64 threads per column at a time, blockIdx.y = instance.  Pass 0 takes every
+// KEEP square in turn (a square paired in H2 is no column: h1n = -1) with tables of kH1Slots;
+// a column whose live entries outgrow them is put on the instance's retry list, which pass 1
+// goes through with kH1BigSlots.  The column's boundary in critical cells (sorted descending)
+// goes to the pool, its start and length to h1b, h1n.
+template <typename T, int SLOTS>
 __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uint8_t *__restrict__ ws, int n,
-                                                 Luts lut) {
-    __shared__ uint64_t tab[kH1Slots];
-    __shared__ uint32_t negbits[kH1Slots / 32];
-    __shared__ int s_used;
+                                                 Luts lut, int pass) {
+    __shared__ uint32_t s_tab[SLOTS];
+    __shared__ uint32_t s_tab2[SLOTS >= 2048 ? SLOTS : 1];
+    __shared__ uint32_t s_queue[SLOTS];
+    __shared__ uint32_t s_neg[SLOTS / 32];
+    __shared__ int s_used, s_tail, s_over, s_nb;
     __shared__ int32_t s_bnd[kH1MaxBoundary];
-    __shared__ int s_nb;
     const int i = blockIdx.y;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1621,16 +1673,27 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
     const int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
     int32_t *h1b = arr<int32_t>(ws, I.o_h1b), *h1n = arr<int32_t>(ws, I.o_h1n);
     int32_t *pool = arr<int32_t>(ws, I.o_pool);
-    int cols = 0, max_rounds = 0;
-    for (int r = blockIdx.x; r < mF; r += gridDim.x) {
-        if (killer[r] >= 0) {                        // paired in H2: not a column
+    int32_t *retry = arr<int32_t>(ws, I.o_retry);
+    const int ncols = pass == 0 ? mF : cnt[CNT_H1RETRY];
+    H1Col<SLOTS> col{s_tab, s_tab2, s_queue, s_neg, &s_used, &s_tail, &s_over, 0};
+    int cols = 0, max_chunks = 0;
+    for (int k = blockIdx.x; k < ncols; k += gridDim.x) {
+        const int r = pass == 0 ? k : retry[k];
+        if (r < 0 || r >= mF) {
+            if (lane == 0) set_err(cnt, PH_EINTERNAL);
+            return;
+        }
+        if (pass == 0 && killer[r] >= 0) {           // paired in H2: not a column
             if (lane == 0) h1n[r] = -1;
             continue;
         }
-        ++cols;
-        for (int k = lane; k < kH1Slots; k += 64) tab[k] = kH1Empty;
-        for (int k = lane; k < kH1Slots / 32; k += 64) negbits[k] = 0;
-        if (lane == 0) { s_used = 0; s_nb = 0; }
+        lds_barrier();                               // the previous column's last reads are done
+        col.tab = s_tab;
+        col.alt = s_tab2;
+        for (int t = lane; t < SLOTS; t += 64) s_tab[t] = kH1Empty;
+        for (int t = lane; t < SLOTS / 32; t += 64) s_neg[t] = 0;
+        if (lane == 0) { s_used = 0; s_tail = 0; s_over = 0; s_nb = 0; }
+        col.head = 0;
         lds_barrier();
         // the column's own combination: the sum of its boundaries leaves L(v)
         const uint64_t ks = keyF[r];
@@ -1640,68 +1703,68 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
         ok = ok && cfg < (uint32_t)kL3Configs;
         const uint32_t comb = ok ? lut.h1s[cfg * 16 + (cs - 7)] : 0u;
         ok = ok && ((comb >> (cs - 7)) & 1u);
-        if (ok && lane < 12 && ((comb >> lane) & 1u)) ok = h1_square(img, ks & ~31ull, v, lane, W, HW, tab, &s_used);
+        if (ok && lane < 12 && ((comb >> lane) & 1u)) h1_square(col, img, v, lane, W, HW, kH1Empty);
         lds_barrier();
         bool bad = __ballot(!ok) != 0;
-        int round = 0;
-        for (; !bad && round < kH1MaxRounds; ++round) {
-            bool any = false;
-            for (int win = 0; win < kH1Slots && !bad; win += 64) {
-                if (s_used > kH1Compact) {           // uniform: read after a barrier
-                    h1_compact(tab, negbits, &s_used);
-                    if (s_used > kH1MaxLive) { bad = true; break; }
-                    for (int k = lane; k < kH1Slots / 32; k += 64) negbits[k] = 0;
-                    lds_barrier();
-                    win = -64;                       // the slots moved: scan again
-                    continue;
-                }
-                const int k = win + lane;
-                const uint64_t x = tab[k];
-                bool pruned = false, err = false;
-                uint32_t cm = 0;
-                const uint64_t key = x & ~kH1Flags;
-                if (x != kH1Empty && (x & kH1Present)) {
-                    if (x & kH1Final) {
-                        if ((negbits[k >> 5] >> (k & 31)) & 1u)          // a negative added again
-                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)kH1Present);
+        int chunk = 0;
+        for (; !bad && chunk < kH1MaxChunks; ++chunk) {
+            if (s_over) break;                       // uniform: read after a barrier
+            if (s_used > SLOTS * 3 / 4) {
+                col.compact();
+                if (s_used > SLOTS / 2) { if (lane == 0) s_over = 1; lds_barrier(); break; }
+            }
+            const int tail = s_tail;
+            if (col.head >= tail) break;             // every key that turned present was looked at
+            const uint32_t key = col.head + lane < tail ? s_queue[(col.head + lane) & (SLOTS - 1)] : kH1Empty;
+            lds_barrier();
+            bool err = false;
+            if (key != kH1Empty) {
+                const int h = col.find(key);
+                const uint32_t x = h >= 0 ? col.tab[h] : 0u;
+                if (h >= 0 && (x & kH1Present) && !(x & kH1Final)) {
+                    uint32_t cm = 0;
+                    int rr = -1;
+                    const int cl = h1_class(key, cfg3, kpos, neg0, I.N, mE, lut, &cm, &rr);
+                    if (cl == 0) {
+                        atomicOr(&s_neg[h >> 5], 1u << (h & 31));
+                        atomicOr(&col.tab[h], kH1Final);
+                        atomicAnd(&col.tab[h], ~kH1Present);
+                    } else if (cl == 1) {
+                        atomicOr(&col.tab[h], kH1Final);
+                    } else if (cl == 2) {
+                        // claim the entry, then add its partner's reduced column without it
+                        const uint32_t old = atomicAnd(&col.tab[h], ~kH1Present);
+                        if ((old & kH1Present) && !(old & kH1Final))
+                            for (uint32_t m = cm; m; m &= m - 1)
+                                h1_square(col, img, key >> kCodeBits, __builtin_ctz(m), W, HW, key);
                     } else {
-                        int rr = -1;
-                        const int cl = h1_class(key, cfg3, kpos, neg0, I.N, mE, lut, &cm, &rr);
-                        if (cl == 0) {
-                            atomicOr(&negbits[k >> 5], 1u << (k & 31));
-                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)(kH1Present | kH1Final));
-                        } else if (cl == 1) {
-                            atomicXor((unsigned long long *)&tab[k], (unsigned long long)kH1Final);
-                        } else if (cl == 2) {
-                            pruned = true;
-                        } else {
-                            err = true;
-                        }
+                        err = true;
                     }
                 }
-                lds_barrier();
-                if (pruned) {
-                    any = true;
-                    for (uint32_t m = cm; m; m &= m - 1)
-                        err |= !h1_square(img, key & ~31ull, key_pix(key), __builtin_ctz(m), W, HW, tab, &s_used);
-                }
-                lds_barrier();
-                bad |= __ballot(err) != 0;
             }
-            if (__ballot(any) == 0) break;
+            col.head = col.head + 64 < tail ? col.head + 64 : tail;
+            lds_barrier();
+            bad |= __ballot(err) != 0;
         }
-        if (!bad && round >= kH1MaxRounds) bad = true;
+        if (!bad && chunk >= kH1MaxChunks) bad = true;
+        if (!bad && s_over) {
+            if (pass == 0) {                         // too large for these tables: the second pass
+                if (lane == 0) retry[atomicAdd(&cnt[CNT_H1RETRY], 1)] = r;
+                continue;
+            }
+            bad = true;
+        }
         if (bad) {
             if (lane == 0) set_err(cnt, PH_EINTERNAL);
             return;
         }
-        max_rounds = round > max_rounds ? round : max_rounds;
+        ++cols;
+        max_chunks = chunk > max_chunks ? chunk : max_chunks;
         // the entries left are KEEP edges H0 left positive: their sorted positions
-        for (int win = 0; win < kH1Slots; win += 64) {
-            const int k = win + lane;
-            const uint64_t x = tab[k];
-            const bool neg = (negbits[k >> 5] >> (k & 31)) & 1u;
-            if (x != kH1Empty && (x & kH1Present) && (x & kH1Final) && !neg) {
+        for (int win = 0; win < SLOTS; win += 64) {
+            const int h = win + lane;
+            const uint32_t x = col.tab[h];
+            if (x != kH1Empty && (x & kH1Present) && (x & kH1Final) && !col.is_neg(h)) {
                 uint32_t cm = 0;
                 int rr = -1;
                 const int cl = h1_class(x & ~kH1Flags, cfg3, kpos, neg0, I.N, mE, lut, &cm, &rr);
@@ -1716,7 +1779,7 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
             if (lane == 0) set_err(cnt, PH_EINTERNAL);
             return;
         }
-        // sort the boundary descending (ascending bitonic over the 64 lanes, read backwards)
+        // sort the boundary descending (ascending bitonic over the 64 lanes, stored backwards)
         int x = lane < nb ? s_bnd[lane] : 0x7FFFFFFF;
         for (int kk = 2; kk <= 64; kk <<= 1)
             for (int j = kk >> 1; j > 0; j >>= 1) {
@@ -1737,16 +1800,34 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
     }
     if (lane == 0 && cols) {
         atomicAdd(&cnt[CNT_H1COLS], cols);
-        atomicMax(&cnt[CNT_H1ROUNDS], max_rounds);
+        atomicMax(&cnt[CNT_H1ROUNDS], max_chunks);
     }
 }
 
 // Reduction of the H1 columns of one volume per workgroup, in square order.  A column whose
-// lowest row appears in no earlier column keeps that row: it is paired at once, in parallel.
-// The others are reduced one after the other by adding the reduced columns of earlier pivots;
-// their reduced forms go to the pool.  piv[row] = the column paired with that KEEP edge.
+// lowest row appears in no earlier column keeps that row for good ("safe"): it is paired at
+// once, in parallel.  The other ("unsafe") columns are reduced together in rounds: each adds
+// the column of smallest index that has the same lowest row (its form at the start of the
+// round), so every addition takes an earlier column and every column's lowest row only goes
+// down; when no two columns share a lowest row the matrix is reduced, and the pairs are those
+// of the sequential reduction.  The rounds run in LDS when the instance fits (rows, columns,
+// entries), else one thread reduces the unsafe columns in order out of the workspace.
+// piv[row] = the column paired with that KEEP edge.
+constexpr int kRedRows = 4096;             // KEEP edges of an instance reduced in LDS
+constexpr int kRedPool = 6144;             // column entries of one LDS buffer
+constexpr int kRedList = 2048;             // unsafe columns held in LDS
+constexpr int kRedRounds = 1 << 16;
+
+__device__ __forceinline__ uint64_t red_ref(int r, int off, int len) {    // min by column index
+    return ((uint64_t)(uint32_t)r << 32) | ((uint64_t)(uint32_t)off << 16) | (uint32_t)len;
+}
+
 __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ ws, int n) {
     __shared__ int s_wsum[kUfThreads / 64];
+    __shared__ uint64_t s_claim[kRedRows];          // per row: smallest column (index, start, length) with it lowest
+    __shared__ int32_t s_buf[2][kRedPool];          // unsafe columns' entries, this round and the next
+    __shared__ int32_t s_ul[kRedList], s_off[kRedList], s_len[kRedList];
+    __shared__ int s_top, s_any, s_fail;
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1770,8 +1851,8 @@ __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ 
         }
     }
     __syncthreads();
-    // columns whose lowest row no earlier column holds; the others, in order, into `list`
-    int32_t *list = arr<int32_t>(ws, I.o_ea);         // unsafe columns (H0's endpoints are done; E >= F)
+    // safe columns are paired; the unsafe ones, in order, into the list
+    int32_t *list = arr<int32_t>(ws, I.o_ea);         // (H0's endpoints are done; E >= F)
     int L = 0;
     for (int base = 0; base < mF; base += blockDim.x) {
         const int r = base + threadIdx.x;
@@ -1786,11 +1867,108 @@ __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ 
         if (flag) list[L + pos] = r;
         L += tot;
     }
+    if (threadIdx.x == 0) cnt[CNT_H1UNSAFE] = L;
     __syncthreads();
+    // the unsafe columns' entries into LDS buffer 0 (a block-wide prefix sum of their lengths)
+    bool lds = mE <= kRedRows && L <= kRedList;
+    if (lds) {
+        int at = 0;
+        for (int base = 0; base < L; base += blockDim.x) {
+            const int u = base + threadIdx.x;
+            const int len = u < L ? h1n[list[u]] : 0;
+            // exclusive scan of len over the chunk
+            int x = len;
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(x, d, 64);
+                if (__lane_id() >= d) x += y;
+            }
+            if (__lane_id() == 63) s_wsum[threadIdx.x >> 6] = x;
+            __syncthreads();
+            int wbase = 0, tot = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                if (w < (int)(threadIdx.x >> 6)) wbase += s_wsum[w];
+                tot += s_wsum[w];
+            }
+            __syncthreads();
+            if (u < L) {
+                s_ul[u] = list[u];
+                s_off[u] = at + wbase + x - len;
+                s_len[u] = len;
+            }
+            at += tot;
+        }
+        __syncthreads();                             // the list, starts and lengths are written
+        lds = at <= kRedPool;
+        if (lds)
+            for (int u = 0; u < L; ++u) {            // every thread copies its share of each column
+                const int b = h1b[s_ul[u]];
+                for (int k = threadIdx.x; k < s_len[u]; k += blockDim.x) s_buf[0][s_off[u] + k] = pool[b + k];
+            }
+        __syncthreads();
+    }
+    if (lds) {
+        int cur = 0, round = 0;
+        for (; round < kRedRounds; ++round) {
+            // claims: for each unsafe column's lowest row, the smallest unsafe column with it
+            for (int u = threadIdx.x; u < L; u += blockDim.x) s_claim[s_buf[cur][s_off[u]]] = ~0ull;
+            if (threadIdx.x == 0) { s_top = 0; s_any = 0; s_fail = 0; }
+            __syncthreads();
+            for (int u = threadIdx.x; u < L; u += blockDim.x)
+                atomicMin((unsigned long long *)&s_claim[s_buf[cur][s_off[u]]],
+                          (unsigned long long)red_ref(s_ul[u], s_off[u], s_len[u]));
+            __syncthreads();
+            // each column adds the safe pivot of its lowest row if there is one, else the
+            // claimant when that is an earlier column; the result goes to the other buffer
+            for (int u = threadIdx.x; u < L; u += blockDim.x) {
+                const int32_t *A = s_buf[cur] + s_off[u];
+                const int na = s_len[u], low = A[0], r = s_ul[u];
+                const int sp = piv[low];             // a safe column with this lowest row
+                const uint64_t cl = s_claim[low];
+                const int cr = (int)(cl >> 32);
+                const int32_t *C = nullptr;
+                int nc = 0;
+                if (sp >= 0) { C = pool + h1b[sp]; nc = h1n[sp]; }
+                else if (cr < r) { C = s_buf[cur] + (int)((cl >> 16) & 0xFFFFu); nc = (int)(cl & 0xFFFFu); }
+                const int room = na + nc;
+                const int dst = atomicAdd(&s_top, room);
+                if (dst + room > kRedPool) { s_fail = 1; continue; }
+                int32_t *B = s_buf[cur ^ 1] + dst;
+                int a = 0, k = 0, nb = 0;
+                while (a < na || k < nc) {           // A + C over F2, both descending
+                    const int32_t ck = k < nc ? C[k] : -1;
+                    if (k >= nc || (a < na && A[a] > ck)) B[nb++] = A[a++];
+                    else if (a >= na || ck > A[a]) { B[nb++] = ck; ++k; }
+                    else { ++a; ++k; }
+                }
+                if (nb == 0) s_fail = 2;             // a negative square reduces to a non-zero column
+                if (nc) s_any = 1;
+                s_off[u] = dst;
+                s_len[u] = nb;
+            }
+            __syncthreads();
+            if (s_fail) break;
+            cur ^= 1;
+            if (!s_any) break;
+            __syncthreads();
+        }
+        if (s_fail == 2 || round >= kRedRounds) {
+            if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL);
+            return;
+        }
+        if (!s_fail) {
+            // reduced: the lowest rows are distinct
+            for (int u = threadIdx.x; u < L; u += blockDim.x) piv[s_buf[cur][s_off[u]]] = s_ul[u];
+            if (threadIdx.x == 0) cnt[CNT_H1ADDS] = round;
+            return;
+        }
+        // out of LDS room: the one-by-one pass below starts again from the columns in the
+        // workspace (the rounds wrote nothing there, and piv holds the safe pivots only)
+    }
     if (threadIdx.x != 0) return;
-    cnt[CNT_H1UNSAFE] = L;
-    // two work buffers of up to mE entries in the sort scratch (2 max(E, F, N) int32, free now)
+    // one thread, in order, out of the workspace: two work buffers of up to mE entries in the
+    // sort scratch (2 max(E, F, N) int32, free now)
     int32_t *A = arr<int32_t>(ws, I.o_scratch), *B = A + I.E;
+    int adds = 0;
     for (int u = 0; u < L; ++u) {
         const int r = list[u];
         int na = h1n[r];
@@ -1812,6 +1990,7 @@ __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ 
             int32_t *t = A; A = B; B = t;
             na = nb;
             changed = true;
+            ++adds;
         }
         if (na <= 0) { set_err(cnt, PH_EINTERNAL); return; }
         if (changed) {
@@ -1823,6 +2002,7 @@ __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ 
         }
         piv[A[0]] = r;
     }
+    cnt[CNT_H1ADDS] = adds;
 }
 
 // ====================================================================== output ====
@@ -2143,9 +2323,12 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_classify3d<16,8,8,h1>", (const void *)k_classify3d<16, 8, 8, float, true>, 256},
         {"k_classify3d<16,8,8,u8,h1>", (const void *)k_classify3d<16, 8, 8, uint8_t, true>, 256},
         {"k_classify3d<16,8,8,u16,h1>", (const void *)k_classify3d<16, 8, 8, uint16_t, true>, 256},
-        {"k_h1_morse", (const void *)k_h1_morse<float>, 64},
-        {"k_h1_morse<u8>", (const void *)k_h1_morse<uint8_t>, 64},
-        {"k_h1_morse<u16>", (const void *)k_h1_morse<uint16_t>, 64},
+        {"k_h1_morse", (const void *)k_h1_morse<float, kH1Slots>, 64},
+        {"k_h1_morse<u8>", (const void *)k_h1_morse<uint8_t, kH1Slots>, 64},
+        {"k_h1_morse<u16>", (const void *)k_h1_morse<uint16_t, kH1Slots>, 64},
+        {"k_h1_morse<big>", (const void *)k_h1_morse<float, kH1BigSlots>, 64},
+        {"k_h1_morse<u8,big>", (const void *)k_h1_morse<uint8_t, kH1BigSlots>, 64},
+        {"k_h1_morse<u16,big>", (const void *)k_h1_morse<uint16_t, kH1BigSlots>, 64},
         {"k_h1_reduce", (const void *)k_h1_reduce, kUfThreads},
         {"k_tpad", (const void *)k_tpad<float>, 256},
         {"k_tpad<u8>", (const void *)k_tpad<uint8_t>, 256},
@@ -2312,12 +2495,12 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // Optional per-launch timing with HIP events on the launch stream (not for use while the
 // stream is being captured into a graph).
 enum KernelId {
-    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1REDUCE,
+    K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1MORSE2, K_H1REDUCE,
     K_OUTPUT, K_ZERO, K_SCATTER, K_TPAD, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
-    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
     "k_tpad"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
@@ -2494,9 +2677,17 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         // one 64-thread workgroup per 4096 voxels of the largest volume (at most 1024 per
         // instance), each taking columns in turn
         const unsigned hb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (mv + 4095) / 4096));
-        if (elem == 1) FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<uint8_t>, dim3(hb, n), dim3(64), 0, st, (const uint8_t *)cimgs, ws, n, lut));
-        else if (elem == 2) FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<uint16_t>, dim3(hb, n), dim3(64), 0, st, (const uint16_t *)cimgs, ws, n, lut));
-        else FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL(k_h1_morse<float>, dim3(hb, n), dim3(64), 0, st, (const float *)cimgs, ws, n, lut));
+        // pass 1 (64 workgroups per instance) takes the columns pass 0 could not hold
+        if (elem == 1) {
+            FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL((k_h1_morse<uint8_t, kH1Slots>), dim3(hb, n), dim3(64), 0, st, (const uint8_t *)cimgs, ws, n, lut, 0));
+            FC_LAUNCH(K_H1MORSE2, hipLaunchKernelGGL((k_h1_morse<uint8_t, kH1BigSlots>), dim3(64, n), dim3(64), 0, st, (const uint8_t *)cimgs, ws, n, lut, 1));
+        } else if (elem == 2) {
+            FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL((k_h1_morse<uint16_t, kH1Slots>), dim3(hb, n), dim3(64), 0, st, (const uint16_t *)cimgs, ws, n, lut, 0));
+            FC_LAUNCH(K_H1MORSE2, hipLaunchKernelGGL((k_h1_morse<uint16_t, kH1BigSlots>), dim3(64, n), dim3(64), 0, st, (const uint16_t *)cimgs, ws, n, lut, 1));
+        } else {
+            FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL((k_h1_morse<float, kH1Slots>), dim3(hb, n), dim3(64), 0, st, (const float *)cimgs, ws, n, lut, 0));
+            FC_LAUNCH(K_H1MORSE2, hipLaunchKernelGGL((k_h1_morse<float, kH1BigSlots>), dim3(64, n), dim3(64), 0, st, (const float *)cimgs, ws, n, lut, 1));
+        }
         FC_LAUNCH(K_H1REDUCE, hipLaunchKernelGGL(k_h1_reduce, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
@@ -2709,11 +2900,11 @@ int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out) {
     if (hipMemcpy(c.data(), (const uint8_t *)d_ws + fc::off_cnt(n), c.size() * sizeof(int32_t),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return PH_EHIP;
-    const int pick[12] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
+    const int pick[14] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
                           fc::CNT_SEQ, fc::CNT_ERR, fc::CNT_H1COLS, fc::CNT_H1UNSAFE, fc::CNT_H1ROUNDS,
-                          fc::CNT_H1POOL};
+                          fc::CNT_H1POOL, fc::CNT_H1RETRY, fc::CNT_H1ADDS};
     for (int i = 0; i < n; ++i)
-        for (int k = 0; k < 12; ++k) h_out[i * 12 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
+        for (int k = 0; k < 14; ++k) h_out[i * 14 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
     return PH_OK;
 }
 

@@ -20,6 +20,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <array>
 #include <vector>
 
 #include "hip/hip_runtime.h"
@@ -79,14 +80,22 @@ void guard_workspace(const void *) {
         const fc::Inst &I = ((const fc::Inst *)g_ws)[i];
         const int64_t N = I.N, T = I.T, E = I.E, F = I.F, FAC = I.FAC;
         const int64_t L = (E > F ? E : F) > 0 ? (E > F ? E : F) : 1, SCR = L > N ? L : N;
-        const int64_t a[][2] = {{I.o_par0, 4 * N}, {I.o_parT, 4 * T}, {I.o_keyE, 8 * E}, {I.o_ea, 4 * E},
-                                {I.o_eb, 4 * E}, {I.o_neg0, 4 * E}, {I.o_keyF, 8 * F}, {I.o_fa, 4 * FAC},
-                                {I.o_fb, 4 * FAC}, {I.o_killer, 4 * FAC}, {I.o_n0key, 8 * N},
-                                {I.o_n0sorted, 8 * N}, {I.o_nTkey, 8 * (T + 1)}, {I.o_uf0, 4 * N},
-                                {I.o_moe0, 4 * N}, {I.o_death0, 4 * N}, {I.o_ufT, 4 * (T + 1)},
-                                {I.o_moeT, 4 * (T + 1)}, {I.o_live, 4 * L}, {I.o_live2, 4 * L},
-                                {I.o_ra, 4 * L}, {I.o_rb, 4 * L}, {I.o_scratch, 8 * SCR}};
-        const int na = (int)(sizeof a / sizeof a[0]);
+        std::vector<std::array<int64_t, 2>> a = {
+            {I.o_par0, 4 * N}, {I.o_parT, 4 * T}, {I.o_keyE, 8 * E}, {I.o_ea, 4 * E},
+            {I.o_eb, 4 * E}, {I.o_neg0, 4 * E}, {I.o_keyF, 8 * F}, {I.o_fa, 4 * FAC},
+            {I.o_fb, 4 * FAC}, {I.o_killer, 4 * FAC}, {I.o_n0key, 8 * N},
+            {I.o_n0sorted, 8 * N}, {I.o_nTkey, 8 * (T + 1)}, {I.o_uf0, 4 * N},
+            {I.o_moe0, 4 * N}, {I.o_death0, 4 * N}, {I.o_ufT, 4 * (T + 1)},
+            {I.o_moeT, 4 * (T + 1)}, {I.o_live, 4 * L}, {I.o_live2, 4 * L},
+            {I.o_ra, 4 * L}, {I.o_rb, 4 * L}, {I.o_scratch, 8 * SCR}};
+        if (I.tfilt) a.push_back({I.o_gimg, 4 * N});                 // the framed dual image
+        if (I.h1 && I.ndim == 3) {                                   // 3D H1
+            const int64_t h1arr[][2] = {{I.o_cfg3, 2 * N}, {I.o_kpos, 4 * N}, {I.o_h1b, 4 * F}, {I.o_h1n, 4 * F},
+                                        {I.o_piv, 4 * E}, {I.o_first, 4 * E}, {I.o_pool, 4 * I.pool_cap},
+                                        {I.o_retry, 4 * F}};
+            for (const auto &x : h1arr) a.push_back({x[0], x[1]});
+        }
+        const int na = (int)a.size();
         if (a[0][0] != expect) { fprintf(stderr, "driver: unexpected workspace layout\n"); abort(); }
         for (int k = 0; k < na; ++k) {
             const int64_t next = k + 1 < na ? a[k + 1][0] : I.end;
@@ -148,7 +157,7 @@ int main(int argc, char **argv) {
             if (k < s[0]) nv *= s[1 + k];
         }
         img_off[i + 1] = img_off[i] + nv;
-        out_off[i + 1] = out_off[i] + (hdr[6] >= 0 ? hdr[6] : ph_capacity_bound(shapes[i]));
+        out_off[i + 1] = out_off[i] + (hdr[6] >= 0 ? hdr[6] : ph_capacity_bound_flags(shapes[i], flags));
     }
     std::vector<float> img(img_off[n]);
     if (fread(img.data(), 4, img.size(), f) != img.size()) return 2;

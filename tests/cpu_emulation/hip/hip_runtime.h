@@ -338,6 +338,11 @@ template <typename T> EMU_FN T atomicXor(T *p, T v) {
     emu_maybe_yield();
     return __atomic_fetch_xor(p, v, __ATOMIC_SEQ_CST);
 }
+template <typename T> EMU_FN T atomicAnd(T *p, T v) {
+    emu_check_access(p, sizeof(T), 1);
+    emu_maybe_yield();
+    return __atomic_fetch_and(p, v, __ATOMIC_SEQ_CST);
+}
 template <typename T> EMU_FN T atomicOr(T *p, T v) {
     emu_check_access(p, sizeof(T), 1);
     emu_maybe_yield();

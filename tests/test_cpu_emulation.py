@@ -38,11 +38,11 @@ def driver():
     return emu_build.build("asan")
 
 
-def run(exe, imgs, mode=0, tuning=None, backward=False, capacity=-1, with_count=False):
+def run(exe, imgs, mode=0, tuning=None, backward=False, capacity=-1, with_count=False, flags=3):
     """(per-instance (pairs, status), gradient or None) from the emulated kernels.  With
     with_count, each instance gives (pairs, status, count) instead."""
     imgs = [np.ascontiguousarray(a, dtype=np.float32) for a in imgs]
-    hdr = struct.pack("<7i", len(imgs), 3, mode, *(tuning if tuning else (-1, -1)), int(backward), capacity)
+    hdr = struct.pack("<7i", len(imgs), flags, mode, *(tuning if tuning else (-1, -1)), int(backward), capacity)
     for a in imgs:
         ext = list(a.shape) + [1] * (3 - a.ndim)
         hdr += struct.pack("<4i", a.ndim, *ext)
@@ -297,3 +297,49 @@ def test_kernels_touch_device_memory_only(monkeypatch, lockstep):
     out, grad = run(exe, imgs, mode=1, tuning=(2, 1), backward=True)
     for img, (got, st) in zip(imgs, out):
         assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
+def h1_batch():
+    rng = np.random.default_rng(21)
+    imgs = [S.grf((14, 15, 13), 2.0, 7201), S.levels((6, 7, 5), 3, 7202), S.uniform((9, 10, 8), 7203),
+            S.grf((30, 28), 2.0, 7204), S.levels((1, 9, 8), 2, 7205)]
+    for k in range(4):
+        shape = tuple(int(x) for x in rng.integers(1, 7, size=3))
+        imgs.append(S.levels(shape, int(rng.choice([2, 3, 1 << 20])), 7210 + k))
+    return imgs
+
+
+def h1_ref(a):
+    return oracle.diagram(a, dims=(0, 1, 2) if a.ndim == 3 else (0, 1))
+
+
+@pytest.mark.parametrize("variant", ["asan", "poison"])
+def test_h1_batch(variant):
+    """3D H1 (PH_H1) in a mixed batch through the emulated kernels, under AddressSanitizer
+    and on a workspace filled with garbage, against the oracle's every dimension."""
+    exe = emu_build.build(variant)
+    imgs = h1_batch()
+    out, _ = run(exe, imgs, mode=1, flags=3 | 32)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, h1_ref(img)) is None, img.shape
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_h1_random_interleavings(monkeypatch, seed):
+    """The H1 column kernels (LDS table and queue shared by the 64 threads, claims by atomics)
+    with the threads resumed in random order and turns given up at every atomic."""
+    exe = emu_build.build("poison")
+    monkeypatch.setenv("EMU_SHUFFLE", str(seed))
+    imgs = h1_batch()
+    out, _ = run(exe, imgs, mode=1, flags=3 | 32)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, h1_ref(img)) is None, img.shape
+
+
+def test_h1_touches_device_memory_only():
+    """Every access of the H1 kernels lands in device memory, LDS or private memory."""
+    exe = emu_build.build("trace")
+    imgs = h1_batch()[:4]
+    out, _ = run(exe, imgs, mode=1, flags=3 | 32)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, h1_ref(img)) is None, img.shape

@@ -68,6 +68,8 @@ def test_fields(shape, sigma, seed):
 
 def test_noise_and_ties():
     check(S.uniform((16, 17, 15), 5), label="uniform")
+    # more KEEP edges than the reduction keeps in LDS: the workspace path
+    check(S.uniform((30, 31, 29), 25), label="uniform, reduction out of the workspace")
     check(S.levels((14, 13, 12), 3, 6), label="three levels")
     check(S.quantize_u8(S.grf((24, 26, 22), 3.0, 7)), label="quantised")
 
@@ -168,3 +170,26 @@ def test_tile_choices_under_h1(tuning):
     bt.ph_diagram_batch()
     for a, got in zip(imgs, bt.results()):
         assert diff_pairs(got, ref(a)) is None, a.shape
+
+
+def ring_valley(R, depth, seed):
+    """A valley along a horizontal circle of radius R: one long H1 class whose killing square
+    sweeps the whole disk, so that column's running sum holds hundreds of edges at once."""
+    n = 2 * R + 12
+    z, y, x = np.mgrid[0:depth, 0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2
+    f = (np.hypot(y - c, x - c) - R) ** 2 + 4 * (z - (depth - 1) / 2) ** 2
+    f += np.random.default_rng(seed).random(f.shape) * 1e-3
+    return (f / f.max()).astype(np.float32)
+
+
+def test_large_column_takes_the_second_pass():
+    """A column whose live edges outgrow the first pass's tables is finished by the second
+    pass (work counter 12 > 0), with the oracle's result."""
+    a = ring_valley(100, 6, 1)
+    bt = fc.Batch([a.shape], flags=ALL, device=DEV)
+    bt.set_images([torch.from_numpy(a)])
+    bt.ph_diagram_batch()
+    (got,) = bt.results()
+    assert bt.work_counters()[0, 12] > 0
+    assert diff_pairs(got, ref(a)) is None
