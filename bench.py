@@ -2,31 +2,52 @@
 plain calls, on one MI355X; prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--traffic-json F]
+                    [--no-configs]
 
-Workload: 64 volumes 96^3 (random field, sigma 3, seeds 2000+i) and 64 images 512^2 (sigma 6,
-seeds 3000+i) in one batch; loss = sum over finite pairs of (death - birth)^2, so the backward
-scatters -2(d-b) to each birth pixel and +2(d-b) to each death pixel.  A step is one pass of
-the whole path over the batch: forward (ph_diagram_batch), loss gradient, backward
-(ph_backward).  The batched step is captured once in a HIP graph and replayed; the per-image
-form is a plain loop of ph_diagram + ph_backward calls per instance on one stream; the forward
-alone is timed as well.  Pair capacities come from a sizing pass on the same inputs, and timed
-steps alternate between two copies of inputs and buffers.  All forms are compared bit for bit
-before any timing.
+Headline workload (the differentiation configuration): 64 volumes 96^3 (random field, sigma 3,
+seeds 2000+i) and 64 images 512^2 (sigma 6, seeds 3000+i) in one batch; loss = sum over finite
+pairs of (death - birth)^2.  A step is one pass of the whole path over the batch: the forward
+(ph_diagram_batch) inside the batched autograd Function, the loss, and loss.backward(), whose
+backward is ph_backward.  The step is captured once in a HIP graph and replayed; timed steps
+alternate between two copies of inputs and buffers, so that a step does not find its inputs in
+the caches from the step before.  The same instances are also run as:
+  per_image_fwd_bwd      plain per-image calls of the C ABI (ph_diagram, the loss gradient,
+                         ph_backward) on buffers allocated beforehand, one stream, no graph;
+  batched_fwd_bwd_manual the loss gradient computed by hand and ph_backward called directly;
+  batched_fwd            the forward alone;
+  batched_fwd_bwd_u8     the instances quantised to 256 levels (floor(256 x)) and read as uint8;
+  batched_fwd_bwd_tfilt  the T-filtration (pixels as top cells);
+  batched_fwd_h1         the 64 volumes with their H1 as well (PH_H1).
+All forms are compared with each other bit for bit, and with the oracle's stored digests
+(tests/golden/digests.json) where they exist, before any timing.
 
-roofline: the dominant kernel of the batched step (largest event-timed total over the timed
+The other configurations are timed as their own forms (inputs generated in spawned processes
+while the CPU baseline runs, else in this process), each checked against its stored oracle
+digest:
+  c1_single     128^2 uniform, plain per-image call, forward + backward;
+  c2_single     2048^2 field sigma 8, float32, forward + backward; c2u8_single its 256-level
+                copy read as uint8;
+  c3_single     256^3 field sigma 4, forward + backward;
+  c4_batch      512 images of uneven sizes, tiles chosen by ph_autotune, one captured forward.
+
+roofline: the dominant kernel of the headline step (largest event-timed total over the timed
 profiled steps), its algorithmic bytes per launch divided by its mean launch duration, against
-8 TB/s.  traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, read from
+8 TB/s.  kernels: every kernel of that step with its mean time, algorithmic bytes (the resolve
+passes count 4 B per followed link, from the work counters) and fraction of the peak.
+traffic: HBM bytes per launch from rocprofv3 FETCH_SIZE + WRITE_SIZE, read from
 profiles/hbm_traffic.json (or --traffic-json) only when it was taken on the library build that
 is loaded (its sha256 is recorded), else null (see --profile-steps and --traffic-from).
 
-cpu_baseline: the CPU oracle (single-threaded C, one process per host core, at most 16) on a
-bounded sample of the same workload (one instance per core, half volumes and half images,
-forward + reference gradient, about 30 s), in Mvoxels/s.  The GPU results of those instances
-are also compared with the oracle's, bit for bit.
+cpu_baseline: the CPU oracle (single-threaded C, built -O3, one process per host core, at most
+16) on a bounded sample of the headline workload (one instance per core, half volumes and half
+images, forward + reference gradient, about 30 s), in Mvoxels/s.  The GPU results of those
+instances are also compared with the oracle's, bit for bit.
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -44,13 +65,15 @@ METRIC = "Mvoxels/s to H0+H_top diagrams, batched fwd+bwd vs per-image, bit-exac
 HBM_PEAK_GBS = 8000.0
 N3, N2 = 64, 64
 SHAPE3, SIG3, SHAPE2, SIG2 = (96, 96, 96), 3.0, (512, 512), 6.0
+SMALL = False
+DIGESTS = os.path.join(ROOT, "tests", "golden", "digests.json")
 
 
 def use_small_workload():
     """A reduced workload of the same kind, for checking this script against the host build of
     the library (--host-library); never used for a reported number."""
-    global N3, N2, SHAPE3, SHAPE2
-    N3, N2, SHAPE3, SHAPE2 = 3, 3, (20, 18, 22), (64, 70)
+    global N3, N2, SHAPE3, SHAPE2, SMALL
+    N3, N2, SHAPE3, SHAPE2, SMALL = 3, 3, (20, 18, 22), (64, 70), True
 
 
 def workload_shapes():
@@ -62,6 +85,32 @@ def workload_desc():
         N3, "x".join(map(str, SHAPE3)), N2, "x".join(map(str, SHAPE2)))
 
 
+def workload_images():
+    return [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
+
+
+# ------------------------------------------------------------ other configurations --
+def config_inputs(name, small=False):
+    """The float32 inputs of configuration `name` (c1..c4); the reduced sizes under `small`."""
+    if name == "c1":
+        return [S.uniform((32, 32) if small else (128, 128), 0)]
+    if name == "c2":
+        return [S.grf((96, 80) if small else (2048, 2048), 8.0, 1)]
+    if name == "c3":
+        return [S.grf((24, 22, 20) if small else (256, 256, 256), 4.0, 2)]
+    if name == "c4":
+        if small:
+            return [S.grf((int(h) // 4, int(w) // 4), s, 1000 + i) for i, ((h, w), s) in enumerate(S.batch_shapes_512(6))]
+        return S.workload_batch_512()
+    raise ValueError(name)
+
+
+def _gen_config(item):
+    name, small = item
+    return name, config_inputs(name, small)
+
+
+# ------------------------------------------------------------------- CPU baseline --
 def _oracle_instance(item):
     """One workload instance through the oracle: forward + reference gradient, timed."""
     import oracle
@@ -82,6 +131,8 @@ def cpu_baseline(workers: int):
     each run single-threaded in its own process; the rate is sample voxels over wall time.
     Returns the baseline record and {batch index: (pairs, gradient)} for the parity check."""
     from multiprocessing import get_context
+    import oracle
+    oracle.build(force=True)
     n3 = min((workers + 1) // 2, N3)
     n2 = min(workers - n3, N2)
     items = [(i, SHAPE3, SIG3, 2000 + i) for i in range(n3)] + \
@@ -95,22 +146,24 @@ def cpu_baseline(workers: int):
     rec = {"value": round(vox / wall / 1e6, 5), "unit": "Mvoxels/s", "cores": min(workers, len(items)),
            "kind": "oracle",
            "sample": "%d x %s volumes (seeds 2000..) + %d x %s images (seeds 3000..) of the workload, "
-                     "forward + gradient, one single-threaded C process per core, %.1f s wall "
+                     "forward + gradient, one single-threaded C process per core (-O3), %.1f s wall "
                      "(single-process sum %.1f s)" % (n3, "x".join(map(str, SHAPE3)), n2,
                                                      "x".join(map(str, SHAPE2)), wall, sum(r[2] for r in res))}
     return rec, ref
 
 
+# ------------------------------------------------------------------ byte models --
 def algorithmic_bytes(name, wc, npairs, shapes):
     """Bytes one launch of `name` must move over the whole batch: the unavoidable reads and
-    writes of its inputs and outputs (pixels, forest arrays, list keys, pairs), no re-reads.
+    writes of its inputs and outputs (pixels, forest arrays, list keys, pairs), no re-reads; the
+    resolve passes add 4 B per forest link they follow (counted by the kernels).
 
     wc: per-instance work counters (KEEP edges, KEEP squares, H0 nodes, dual nodes, ...)."""
     is3 = np.array([len(s) == 3 for s in shapes])
     N = sum(int(np.prod(s)) for s in shapes)
-    T = sum(int(np.prod([e - 1 for e in s])) for s in shapes)
     ke, kf, m0, mt = (int(wc[:, k].sum()) for k in range(4))
     facets = int(wc[~is3, 0].sum()) + kf                 # 2D walks the KEEP edges, 3D the KEEP squares
+    hops0, hopsT = wc[:, 14].astype(np.int64), wc[:, 15].astype(np.int64)
     if name == "k_classify2d" or name == "k_classify3d":
         sel = is3 if name == "k_classify3d" else ~is3
         n = sum(int(np.prod(s)) for s, k in zip(shapes, sel) if k)
@@ -120,9 +173,13 @@ def algorithmic_bytes(name, wc, npairs, shapes):
     if name == "k_sort":
         return 16 * (ke + kf + m0)
     f3 = int(wc[is3, 1].sum())                          # facets of the volumes (walked beside H0)
-    if name in ("k_resolve", "k_unionfind"):
+    if name == "k_resolve":
+        return 16 * (ke + f3) + 4 * int(hops0.sum() + hopsT[is3].sum())
+    if name == "k_unionfind":
         return 16 * (ke + f3)
-    if name in ("k_resolve(2d top)", "k_unionfind(2d top)"):
+    if name == "k_resolve(2d top)":
+        return 16 * (facets - f3) + 4 * int(hopsT[~is3].sum())
+    if name == "k_unionfind(2d top)":
         return 16 * (facets - f3)
     if name == "k_output":
         return 8 * (m0 + facets) + 32 * npairs
@@ -130,7 +187,21 @@ def algorithmic_bytes(name, wc, npairs, shapes):
         return 4 * N
     if name == "k_scatter":
         return 32 * npairs
+    if name == "k_tpad":
+        return 4 * N + 4 * sum(int(np.prod([e + 2 for e in s])) for s in shapes)
     return 0
+
+
+def kernel_table(prof, wc, npairs, shapes):
+    """{kernel: mean ms, launches, algorithmic bytes and GB/s per launch, fraction of the peak}."""
+    out = {}
+    for k, (launches, total_ms) in prof.items():
+        ms = total_ms / launches
+        b = algorithmic_bytes(k, wc, npairs, shapes)
+        gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
+        out[k] = {"ms": round(ms, 4), "launches": launches, "bytes": int(b), "gbs": round(gbs, 1),
+                  "frac": round(gbs / HBM_PEAK_GBS, 4) if b else None}
+    return out
 
 
 # ------------------------------------------------------------------ HBM traffic --
@@ -141,7 +212,6 @@ def algorithmic_bytes(name, wc, npairs, shapes):
 COPY_BYTES = 1 << 30
 KERNEL_KEYS = ["k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind", "k_output", "k_plan",
                "k_zero", "k_scatter"]
-PROFILE_NAMES = {}
 
 
 def profile_steps(steps):
@@ -149,8 +219,7 @@ def profile_steps(steps):
     import paper_2606_04801_amd as fc
     shapes = workload_shapes()
     bt = fc.Batch(shapes, device="cuda:0")
-    imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
-    bt.set_images([torch.from_numpy(a) for a in imgs])
+    bt.set_images([torch.from_numpy(a) for a in workload_images()])
     for k in range(steps):
         bt.ph_diagram_batch()
         fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
@@ -186,7 +255,6 @@ def _counter_means(path, counter):
 
 
 def library_sha256():
-    import hashlib
     import paper_2606_04801_amd as fc
     with open(fc.LIB_PATH, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()
@@ -202,10 +270,114 @@ def traffic_from(fetch_csv, write_csv, out_json):
     for k in fetch:
         if k == "copy" or k not in write:
             continue
-        res[PROFILE_NAMES.get(k, k)] = round(fetch[k] * 1024 * fs + write[k] * 1024 * ws)
+        res[k] = round(fetch[k] * 1024 * fs + write[k] * 1024 * ws)
     with open(out_json, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
+
+
+# ----------------------------------------------------------------------- helpers --
+PACKED = np.dtype([("dim", "<i1"), ("birth", "<u4"), ("death", "<u4"), ("birth_cell", "<i8"),
+                   ("death_cell", "<i8"), ("birth_vertex", "<i4"), ("death_vertex", "<i4")])
+
+
+def pair_digest(pairs) -> str:
+    """SHA-256 of a pair array packed as the stored oracle digests are (tests/golden)."""
+    a = np.zeros(len(pairs), PACKED)
+    for f in PACKED.names:
+        v = np.asarray(pairs[f])
+        a[f] = v.view(np.uint32) if v.dtype == np.float32 else v
+    return hashlib.sha256(a.tobytes()).hexdigest()
+
+
+def input_digest(img) -> str:
+    return hashlib.sha256(np.ascontiguousarray(img, dtype="<f4").tobytes()).hexdigest()
+
+
+def load_digests():
+    return json.load(open(DIGESTS)) if os.path.exists(DIGESTS) else {}
+
+
+def check_digests(dig, cfg, imgs, results, first=0):
+    """Number of instances checked against the stored oracle digests of config `cfg` (inputs
+    must match the stored input digest); raises on a mismatch."""
+    rec = dig.get(cfg, {})
+    n = 0
+    for k, (img, r) in enumerate(zip(imgs, results)):
+        d = rec.get(str(first + k))
+        if d is None or d["input_sha256"] != input_digest(img):
+            continue
+        if pair_digest(r) != d["pairs_sha256"]:
+            raise SystemExit("bench: %s instance %d differs from the oracle's digest" % (cfg, first + k))
+        n += 1
+    return n
+
+
+def same_bits(a, b):
+    """Pair arrays equal field by field, floats compared by their bits."""
+    return len(a) == len(b) and all(np.array_equal(np.ascontiguousarray(a[f]).view(np.uint8),
+                                                   np.ascontiguousarray(b[f]).view(np.uint8))
+                                    for f in a.dtype.names)
+
+
+class SingleCall:
+    """One image's plain call through the C ABI on buffers allocated beforehand: ph_diagram,
+    the loss gradient (d - b)^2 over the finite stored pairs, ph_backward."""
+
+    def __init__(self, fc, torch, img, dev, dtype=None, cap=None, flags=None):
+        self.fc, self.torch = fc, torch
+        dtype = dtype or torch.float32
+        self.img = torch.from_numpy(np.ascontiguousarray(img)).to(dev).to(dtype)
+        self.flags = (fc.PH_H0 | fc.PH_HTOP if flags is None else flags) | \
+            {torch.float32: 0, torch.uint8: fc.PH_IN_U8, torch.uint16: fc.PH_IN_U16}[dtype]
+        self.shape = fc.make_shape(img.shape)
+        self.cap = int(cap) if cap is not None else fc.capacity_bound(img.shape, "V", self.flags)
+        self.bufs = fc.PairBuffers(self.cap, dev)
+        self.count = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ws_bytes = int(fc.lib().ph_workspace_bytes(ctypes.byref(self.shape), 1, self.flags))
+        self.ws = torch.empty(self.ws_bytes, dtype=torch.uint8, device=dev)
+        self.grad = torch.empty(img.size, dtype=torch.float32, device=dev)
+        self.out_off = torch.tensor([0, self.cap], dtype=torch.int64, device=dev)
+        self.img_off = torch.zeros(1, dtype=torch.int64, device=dev)
+        self.idx = torch.arange(self.cap, device=dev)
+        self.nvox = int(img.size)
+
+    def forward(self):
+        fc = self.fc
+        rc = fc.lib().ph_diagram(fc._ptr(self.img), self.shape, self.flags, self.bufs.c(), self.cap,
+                                 fc._ptr(self.count), fc._ptr(self.status), fc._ptr(self.ws), self.ws_bytes,
+                                 fc._stream_ptr(None))
+        if rc != fc.PH_OK:
+            raise fc.PHError(rc, "ph_diagram")
+
+    def backward(self):
+        fc, torch = self.fc, self.torch
+        fin = (self.idx < self.count) & (self.bufs.death_cell >= 0)
+        diff = torch.where(fin, self.bufs.death - self.bufs.birth, 0.0)
+        gb, gd = -2.0 * diff, 2.0 * diff
+        rc = fc.lib().ph_backward(1, self.bufs.c(), fc._ptr(self.out_off), fc._ptr(self.count), fc._ptr(gb),
+                                  fc._ptr(gd), fc._ptr(self.grad), fc._ptr(self.img_off), self.nvox,
+                                  fc._stream_ptr(None))
+        if rc != fc.PH_OK:
+            raise fc.PHError(rc, "ph_backward")
+
+    def step(self):
+        self.forward()
+        self.backward()
+
+    def results(self):
+        st = int(self.status.item())
+        if st != self.fc.PH_OK:
+            raise self.fc.PHError(st, "ph_diagram")
+        return self.bufs.to_numpy(0, int(self.count.item()))
+
+    def work_counters(self):
+        out = (ctypes.c_int32 * 16)()
+        rc = self.fc.lib().ph_work_counters(self.fc._ptr(self.ws), 1, out)
+        if rc != self.fc.PH_OK:
+            raise self.fc.PHError(rc, "ph_work_counters")
+        return np.frombuffer(out, dtype=np.int32).reshape(1, 16).copy()
 
 
 def main():
@@ -214,6 +386,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", action="store_true", help="time the headline workload only")
     ap.add_argument("--cpu-workers", type=int, default=0, help="oracle processes (0: host cores, at most 16)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"),
                     help="HBM bytes per launch from the counter passes (used only for the library build they were taken on)")
@@ -242,11 +415,29 @@ def main():
             "vs_baseline": None, "dtype": "u64", "data": "synthetic",
             "config": {"workload": workload_desc(), "instances": len(shapes), "voxels": nvox}}
 
+    # the other configurations' inputs are made in spawned processes (before this process
+    # loads HIP) while the CPU baseline runs; without the baseline, in this process (no child
+    # processes: a profiler may have initialised the GPU in this one already)
+    from multiprocessing import get_context
+    gen_pool, gen_res = None, None
+    cfg_names = ("c3", "c4", "c2", "c1")
+    if not args.no_configs and not args.no_cpu_baseline:
+        gen_pool = get_context("spawn").Pool(4)
+        gen_res = gen_pool.map_async(_gen_config, [(c, SMALL) for c in cfg_names], chunksize=1)
     ref = {}
-    if not args.no_cpu_baseline:                 # before this process loads HIP
+    if not args.no_cpu_baseline:
         workers = args.cpu_workers or min(16, len(os.sched_getaffinity(0)))
         print("bench: cpu baseline (oracle on %d cores, about 30 s)" % workers, file=sys.stderr, flush=True)
         line["cpu_baseline"], ref = cpu_baseline(workers)
+    cfg_inputs = {}
+    if gen_res is not None:
+        print("bench: waiting for the other configurations' inputs", file=sys.stderr, flush=True)
+        cfg_inputs = dict(gen_res.get())
+        gen_pool.close()
+        gen_pool.join()
+    elif not args.no_configs:
+        print("bench: generating the other configurations' inputs", file=sys.stderr, flush=True)
+        cfg_inputs = dict(_gen_config((c, SMALL)) for c in cfg_names)
     import torch
     import paper_2606_04801_amd as fc
     if args.host_library:
@@ -254,43 +445,77 @@ def main():
     fc.lib()
     gpu = torch.cuda.is_available()
     if args.host_library:
-        line.update(run_gpu(fc, torch, shapes, args, ref, dev=torch.device("cpu")))
+        line.update(run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=torch.device("cpu")))
         line["status"] = "host-library check, not a measurement"
     elif not gpu:
         line["status"] = "no GPU"
     else:
-        line.update(run_gpu(fc, torch, shapes, args, ref))
+        line.update(run_gpu(fc, torch, shapes, args, ref, cfg_inputs))
     print(json.dumps(line), flush=True)
 
 
-def same_bits(a, b):
-    """Pair arrays equal field by field, floats compared by their bits."""
-    return len(a) == len(b) and all(np.array_equal(np.ascontiguousarray(a[f]).view(np.uint8),
-                                                   np.ascontiguousarray(b[f]).view(np.uint8))
-                                    for f in a.dtype.names)
-
-
-def step_bytes(prof_names, wc, npairs, shapes):
-    """Algorithmic bytes of one batched forward + backward step (kernel models summed)."""
-    return sum(algorithmic_bytes(k, wc, npairs, shapes) for k in prof_names)
-
-
-def run_gpu(fc, torch, shapes, args, ref, dev=None):
+def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
     dev = dev or torch.device("cuda:0")
     cuda = dev.type == "cuda"
     sync = torch.cuda.synchronize if cuda else (lambda: None)
-    print("bench: generating %d instances" % len(shapes), file=sys.stderr, flush=True)
-    imgs = [S.grf(SHAPE3, SIG3, 2000 + i) for i in range(N3)] + [S.grf(SHAPE2, SIG2, 3000 + i) for i in range(N2)]
+    log = lambda msg: print("bench: " + msg, file=sys.stderr, flush=True)
+    log("generating %d instances" % len(shapes))
+    imgs = workload_images()
     host = [torch.from_numpy(a) for a in imgs]
     if cuda:
         torch.zeros(1, device=dev)               # the device context exists before the library's first call
     rc = fc.lib().ph_init_device()
     if rc != fc.PH_OK:
         raise fc.PHError(rc, "ph_init_device")
+    dig = load_digests()
+    nvox = sum(int(np.prod(s)) for s in shapes)
+    BatchFn = fc.BatchDiagramFn
 
+    def capture(fn):
+        """A replayable step: a captured HIP graph on the GPU (the host check replays eagerly)."""
+        if not cuda:
+            for _ in range(args.warmup):
+                fn()
+            return fn
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):                # warm-up on a side stream, as capture requires
+            for _ in range(args.warmup):
+                fn()
+        torch.cuda.current_stream().wait_stream(s)
+        sync()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            fn()
+        return g.replay
+
+    def timed(run, steps=None):
+        steps = steps or args.steps
+        for k in range(args.warmup):
+            run(k)
+        sync()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            run(k)
+        sync()
+        return (time.perf_counter() - t0) / steps
+
+    def profiled(run, steps=None):
+        fc.profile(True)
+        for k in range(steps or args.steps):
+            run(k)
+        sync()
+        prof = fc.profile_read()
+        fc.profile(False)
+        return prof
+
+    def rate(vox, t):
+        return round(vox / t / 1e6, 3)
+
+    # ---------------------------------------------------------- headline workload --
     # sizing pass with the never-overflowing capacity, then exact capacities: the pair buffers
     # (and the loss-gradient arithmetic over them) stay as small as the diagrams
-    print("bench: sizing pass", file=sys.stderr, flush=True)
+    log("sizing pass")
     sizing = fc.Batch(shapes, device=dev)
     sizing.set_images(host)
     sizing.ph_diagram_batch()
@@ -301,100 +526,86 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
     if cuda:
         torch.cuda.empty_cache()
 
-    # two copies of inputs and buffers; timed steps alternate between them so that a step does
-    # not find its inputs in the caches from the step before
     bts = []
     for _ in range(2):
         bt = fc.Batch(shapes, device=dev, capacities=caps)
         bt.set_images(host)
+        bt.images.requires_grad_(True)
         bts.append(bt)
 
-    def batched_step(bt, backward=True):
+    def loss_of(bt, b, d):
+        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+        return (torch.where(fin, d - b, torch.zeros_like(d)) ** 2).sum()
+
+    def autograd_step(bt):
+        bt.images.grad = None                    # under capture the gradient lands in the graph's pool
+        b, d = BatchFn.apply(bt.images, bt)
+        loss_of(bt, b, d).backward()
+
+    def manual_step(bt, backward=True):
         bt.ph_diagram_batch()
         if backward:
             fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
             diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
             bt.ph_backward(-2.0 * diff, 2.0 * diff)
 
-    # per-image plain calls on the same inputs, one stream, no graph
-    singles = [[], []]
-    for c in range(2):
-        for i in range(len(imgs)):
-            singles[c].append(dict(img=bts[c].image(i), cap=int(caps[i]), ws=fc.Workspace(),
-                                   grad=torch.empty(imgs[i].shape, dtype=torch.float32, device=dev),
-                                   off=torch.tensor([0, max(int(caps[i]), 1)], dtype=torch.int64, device=dev),
-                                   ioff=torch.zeros(1, dtype=torch.int64, device=dev)))
+    # per-image plain calls on the same inputs, buffers allocated beforehand
+    singles = [[SingleCall(fc, torch, a, dev, cap=max(int(caps[i]), 1)) for i, a in enumerate(imgs)]
+               for _ in range(2)]
 
     def per_image_step(c):
         for s in singles[c]:
-            d = fc.ph_diagram(s["img"], capacity=s["cap"], ws=s["ws"])
-            s["diag"] = d
-            idx = torch.arange(d.bufs.cap, device=dev)
-            fin = (idx < d.count_t) & (d.bufs.death_cell >= 0)
-            diff = torch.where(fin, d.bufs.death - d.bufs.birth, 0.0)
-            fc.ph_backward(d.bufs, d.count_t, s["off"], s["ioff"], -2.0 * diff, 2.0 * diff, s["grad"])
+            s.step()
 
-    # parity: batched, per-image and (for the sampled instances) the oracle, bit for bit
-    print("bench: parity", file=sys.stderr, flush=True)
+    # parity: autograd, manual, per-image and (for the sampled instances) the oracle, bit for bit
+    log("parity")
     bt = bts[0]
-    batched_step(bt)
-    per_image_step(0)
+    with torch.no_grad():
+        manual_step(bt)
     sync()
     bt.check()
     res = bt.results()
+    g_manual = bt.grad.clone()
+    autograd_step(bt)
+    sync()
+    if not torch.allclose(bt.images.grad, g_manual, rtol=1e-6, atol=1e-7):
+        raise SystemExit("bench: autograd and manual gradients differ")
+    for i, r in enumerate(bt.results()):
+        if not same_bits(r, res[i]):
+            raise SystemExit("bench: autograd and manual diagrams differ on instance %d" % i)
+    per_image_step(0)
+    sync()
     for i, s in enumerate(singles[0]):
-        if not same_bits(res[i], s["diag"].numpy()):
+        if not same_bits(res[i], s.results()):
             raise SystemExit("bench: batched and per-image diagrams differ on instance %d" % i)
-        g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]]
-        if not torch.allclose(g1, s["grad"].reshape(-1), rtol=1e-6, atol=1e-7):
+        if not torch.allclose(g_manual[bt.img_off_h[i]:bt.img_off_h[i + 1]], s.grad, rtol=1e-6, atol=1e-7):
             raise SystemExit("bench: batched and per-image gradients differ on instance %d" % i)
     for i, (p, g) in ref.items():
         if not same_bits(res[i], p):
             raise SystemExit("bench: instance %d differs from the oracle" % i)
-        g1 = bt.grad[bt.img_off_h[i]:bt.img_off_h[i + 1]].cpu().numpy()
+        g1 = g_manual[bt.img_off_h[i]:bt.img_off_h[i + 1]].cpu().numpy()
         if not np.allclose(g1, g.reshape(-1), rtol=1e-6, atol=1e-7):
             raise SystemExit("bench: gradient of instance %d differs from the oracle" % i)
+    n_dig = check_digests(dig, "c5", imgs, res) if not SMALL else 0
 
-    def capture(fn):
-        """A replayable step: a captured HIP graph on the GPU (the host check replays eagerly)."""
-        for _ in range(args.warmup):
-            fn()
-        sync()
-        if not cuda:
-            return fn
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g):
-            fn()
-        return g.replay
-
-    def timed(run):
-        for k in range(args.warmup):
-            run(k)
-        sync()
-        t0 = time.perf_counter()
-        for k in range(args.steps):
-            run(k)
-        sync()
-        return (time.perf_counter() - t0) / args.steps
-
-    print("bench: batched forward + backward (graph replay)", file=sys.stderr, flush=True)
-    g_fb = [capture(lambda b=b: batched_step(b)) for b in bts]
+    log("batched forward + autograd backward (graph replay)")
+    for b in bts:
+        b.images.grad = None
+    g_fb = [capture(lambda b=b: autograd_step(b)) for b in bts]
     t_b = timed(lambda k: g_fb[k % 2]())
     for b in bts:
         b.check()
-    print("bench: batched forward only (graph replay)", file=sys.stderr, flush=True)
-    g_f = [capture(lambda b=b: batched_step(b, backward=False)) for b in bts]
+    log("batched forward + manual backward (graph replay)")
+    g_fm = [capture(lambda b=b: manual_step(b)) for b in bts]
+    t_m = timed(lambda k: g_fm[k % 2]())
+    log("batched forward only (graph replay)")
+    g_f = [capture(lambda b=b: manual_step(b, backward=False)) for b in bts]
     t_f = timed(lambda k: g_f[k % 2]())
-    print("bench: per-image plain calls", file=sys.stderr, flush=True)
+    log("per-image plain calls")
     t_p = timed(lambda k: per_image_step(k % 2))
 
-    # per-kernel event timing of the batched step (eager, the same launches as the graph)
-    fc.profile(True)
-    for k in range(args.steps):
-        batched_step(bts[k % 2])
-    sync()
-    prof = fc.profile_read()
-    fc.profile(False)
+    # per-kernel event timing of the headline step (eager, the same launches as the graph)
+    prof = profiled(lambda k: autograd_step(bts[k % 2]))
     npairs = int(bt.counts.cpu().numpy().sum())
     wc = bt.work_counters()
     name, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
@@ -406,13 +617,28 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
         tj = json.load(open(args.traffic_json))
         if tj.get("_library_sha256") == library_sha256():
             traffic = tj.get(name)
+    kt = kernel_table(prof, wc, npairs, shapes)
+    sb = sum(v["bytes"] for v in kt.values())
+    frac = lambda b, t: round(b / t / (HBM_PEAK_GBS * 1e9), 5)
+    forms = {
+        "batched_fwd_bwd": {"value": rate(nvox, t_b), "ms": round(t_b * 1e3, 4), "hbm_frac": frac(sb, t_b),
+                            "how": "BatchDiagramFn forward, loss, loss.backward() in one captured graph"},
+        "batched_fwd_bwd_manual": {"value": rate(nvox, t_m), "ms": round(t_m * 1e3, 4)},
+        "batched_fwd": {"value": rate(nvox, t_f), "ms": round(t_f * 1e3, 4)},
+        "per_image_fwd_bwd": {"value": rate(nvox, t_p), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p),
+                              "how": "C ABI calls per instance on buffers allocated beforehand, no graph"},
+    }
+    del singles
+    if cuda:
+        torch.cuda.empty_cache()
+
     # the same instances quantised to 256 levels and read as uint8 (PH_IN_U8), checked bit for
-    # bit against the float32 path on the same values, then timed like the batched form
-    print("bench: batched forward + backward, uint8 input (graph replay)", file=sys.stderr, flush=True)
-    q8 = [torch.from_numpy(np.round(a * 255.0).astype(np.uint8)) for a in imgs]
+    # bit against the float32 path on the same values, then timed like the headline manual form
+    log("batched forward + backward, uint8 input (graph replay)")
+    q8 = [torch.from_numpy(S.quantize_u8(a).astype(np.uint8)) for a in imgs]
     sz = fc.Batch(shapes, device=dev)
     sz.set_images([q.float() for q in q8])
-    batched_step(sz)
+    manual_step(sz)
     sync()
     ref8 = sz.results()
     gref8 = sz.grad.cpu().numpy().copy()
@@ -423,65 +649,162 @@ def run_gpu(fc, torch, shapes, args, ref, dev=None):
         b = fc.Batch(shapes, device=dev, capacities=caps8, dtype=torch.uint8)
         b.set_images(q8)
         b8.append(b)
-    batched_step(b8[0])
+    manual_step(b8[0])
     sync()
     for i, r in enumerate(b8[0].results()):
         if not same_bits(r, ref8[i]):
             raise SystemExit("bench: uint8 and float32 inputs give different diagrams on instance %d" % i)
-    if not np.array_equal(b8[0].grad.cpu().numpy(), gref8):
+    if not np.allclose(b8[0].grad.cpu().numpy(), gref8, rtol=1e-6, atol=1e-7):
         raise SystemExit("bench: uint8 and float32 inputs give different gradients")
-    g_8 = [capture(lambda b=b: batched_step(b)) for b in b8]
+    g_8 = [capture(lambda b=b: manual_step(b)) for b in b8]
     t_8 = timed(lambda k: g_8[k % 2]())
-    for b in b8:
-        b.check()
+    forms["batched_fwd_bwd_u8"] = {"value": rate(nvox, t_8), "ms": round(t_8 * 1e3, 4),
+                                   "input": "the same instances quantised to 256 levels, uint8"}
+    del b8, g_8
+    if cuda:
+        torch.cuda.empty_cache()
 
-    # the same instances under the T-filtration (pixels as top cells, PH_TFILT): sized by a
-    # first call, then timed like the batched form (parity of this path is the T test suite's)
-    print("bench: batched forward + backward, T-filtration (graph replay)", file=sys.stderr, flush=True)
+    # the same instances under the T-filtration (pixels as top cells, PH_TFILT), every instance
+    # against the T oracle's stored digest
+    log("batched forward + backward, T-filtration (graph replay)")
     src = [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)) for a in imgs]
     sz = fc.Batch(shapes, device=dev, filtration="T")
     sz.set_images(src)
-    batched_step(sz)
+    manual_step(sz)
     sync()
     sz.check()
     caps_t = sz.counts.cpu().numpy().tolist()
+    n_dig_t = check_digests(dig, "c5t", imgs, sz.results()) if not SMALL else 0
     del sz
     b_t = []
     for _ in range(2):
         b = fc.Batch(shapes, device=dev, capacities=caps_t, filtration="T")
         b.set_images(src)
         b_t.append(b)
-    g_t = [capture(lambda b=b: batched_step(b)) for b in b_t]
+    g_t = [capture(lambda b=b: manual_step(b)) for b in b_t]
     t_t = timed(lambda k: g_t[k % 2]())
     for b in b_t:
         b.check()
         if not np.array_equal(b.counts.cpu().numpy(), np.asarray(caps_t)):
             raise SystemExit("bench: T-filtration pair counts changed between calls")
+    forms["batched_fwd_bwd_tfilt"] = {"value": rate(nvox, t_t), "ms": round(t_t * 1e3, 4),
+                                      "input": "the same instances under the T-filtration",
+                                      "oracle_digests_checked": n_dig_t}
+    del b_t, g_t
+    if cuda:
+        torch.cuda.empty_cache()
 
-    nvox = sum(int(np.prod(s)) for s in shapes)
-    sb = step_bytes(prof.keys(), wc, npairs, shapes)
-    fb = sb - algorithmic_bytes("k_zero", wc, npairs, shapes) - algorithmic_bytes("k_scatter", wc, npairs, shapes)
-    frac = lambda b, t: round(b / t / (HBM_PEAK_GBS * 1e9), 5)
+    # the volumes with H1 as well (PH_H1), forward; the first eight against their H0+H1+H2 digests
+    log("batched forward with H1, the volumes (graph replay)")
+    vols = imgs[:N3]
+    vvox = sum(a.size for a in vols)
+    h1f = fc.PH_H0 | fc.PH_HTOP | fc.PH_H1
+    sz = fc.Batch([a.shape for a in vols], device=dev, flags=h1f)
+    sz.set_images([torch.from_numpy(a) for a in vols])
+    sz.ph_diagram_batch()
+    sync()
+    sz.check()
+    caps_h = sz.counts.cpu().numpy().tolist()
+    n_dig_h = check_digests(dig, "c5h1", vols, sz.results()) if not SMALL else 0
+    del sz
+    b_h = []
+    for _ in range(2):
+        b = fc.Batch([a.shape for a in vols], device=dev, flags=h1f, capacities=caps_h)
+        b.set_images([torch.from_numpy(a) for a in vols])
+        b_h.append(b)
+    g_h = [capture(lambda b=b: b.ph_diagram_batch()) for b in b_h]
+    t_h = timed(lambda k: g_h[k % 2]())
+    prof_h = profiled(lambda k: b_h[k % 2].ph_diagram_batch(), 3)
+    wch = b_h[0].work_counters()
+    forms["batched_fwd_h1"] = {"value": rate(vvox, t_h), "ms": round(t_h * 1e3, 4),
+                               "input": "the %d volumes, H0 + H1 + H2" % N3, "oracle_digests_checked": n_dig_h,
+                               "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in prof_h.items()},
+                               "h1_columns": int(wch[:, 8].sum())}
+    del b_h, g_h
+    if cuda:
+        torch.cuda.empty_cache()
+
+    # ------------------------------------------------------ other configurations --
+    if cfg_inputs:
+        forms.update(config_forms(fc, torch, dev, cfg_inputs, dig, capture, timed, profiled, sync, log, args))
+
     return {
-        "value": round(nvox / t_b / 1e6, 3),
-        "ms_per_step": round(t_b * 1e3, 4),
-        "forms": {
-            "batched_fwd_bwd": {"value": round(nvox / t_b / 1e6, 3), "ms": round(t_b * 1e3, 4), "hbm_frac": frac(sb, t_b)},
-            "batched_fwd": {"value": round(nvox / t_f / 1e6, 3), "ms": round(t_f * 1e3, 4), "hbm_frac": frac(fb, t_f)},
-            "per_image_fwd_bwd": {"value": round(nvox / t_p / 1e6, 3), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p)},
-            "batched_fwd_bwd_u8": {"value": round(nvox / t_8 / 1e6, 3), "ms": round(t_8 * 1e3, 4),
-                                   "input": "the same instances quantised to 256 levels, uint8"},
-            "batched_fwd_bwd_tfilt": {"value": round(nvox / t_t / 1e6, 3), "ms": round(t_t * 1e3, 4),
-                                      "input": "the same instances under the T-filtration"},
-        },
+        "value": forms["batched_fwd_bwd"]["value"],
+        "ms_per_step": forms["batched_fwd_bwd"]["ms"],
+        "forms": forms,
         "roofline": {"bound": "hbm", "kernel": name, "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic},
-        "kernels_ms": {k: round(v[1] / v[0], 4) for k, v in prof.items()},
+        "kernels": kt,
+        "kernels_ms": {k: v["ms"] for k, v in kt.items()},
         "work": {"keep_edges": int(wc[:, 0].sum()), "keep_squares": int(wc[:, 1].sum()),
                  "h0_nodes": int(wc[:, 2].sum()), "dual_nodes": int(wc[:, 3].sum()),
                  "pairs": npairs, "max_rounds": int(wc[:, 4:6].max()),
-                 "sequential_edges": int(wc[:, 6].sum())},
+                 "sequential_edges": int(wc[:, 6].sum()), "links_followed": int(wc[:, 14:16].sum())},
+        "parity": {"oracle_instances": len(ref), "oracle_digests_checked": n_dig,
+                   "batched_eq_per_image": True, "autograd_eq_manual": True},
     }
+
+
+def config_forms(fc, torch, dev, cfg_inputs, dig, capture, timed, profiled, sync, log, args):
+    """Forms for configurations 1-4, each checked against its stored oracle digests."""
+    forms = {}
+
+    def dominant(prof, wc, npairs, shapes):
+        kt = kernel_table(prof, wc, npairs, shapes)
+        k = max(kt, key=lambda n: kt[n]["ms"] * kt[n]["launches"])
+        return {"kernel": k, "ms": kt[k]["ms"], "frac": kt[k]["frac"]}, {n: v["ms"] for n, v in kt.items()}
+
+    def single_form(label, cfg, img, dtype=None):
+        log("%s: plain per-image call, forward + backward" % label)
+        s = SingleCall(fc, torch, img if dtype is None else img.astype(np.uint8), dev, dtype=dtype)
+        s.step()
+        sync()
+        r = s.results()
+        n = check_digests(dig, cfg, [img], [r]) if not SMALL else 0
+        s2 = SingleCall(fc, torch, img if dtype is None else img.astype(np.uint8), dev, dtype=dtype, cap=max(len(r), 1))
+        t_fb = timed(lambda k: s2.step())
+        t_f = timed(lambda k: s2.forward())
+        prof = profiled(lambda k: s2.step(), 3)
+        dom, kms = dominant(prof, s2.work_counters(), len(r), [img.shape])
+        return {"value": round(img.size / t_fb / 1e6, 3), "ms": round(t_fb * 1e3, 4),
+                "fwd_value": round(img.size / t_f / 1e6, 3), "fwd_ms": round(t_f * 1e3, 4),
+                "shape": list(img.shape), "dominant": dom, "kernels_ms": kms, "oracle_digests_checked": n}
+
+    if "c1" in cfg_inputs:
+        forms["c1_single"] = single_form("config 1", "c1", cfg_inputs["c1"][0])
+    if "c2" in cfg_inputs:
+        x = cfg_inputs["c2"][0]
+        forms["c2_single"] = single_form("config 2", "c2", x)
+        forms["c2u8_single"] = single_form("config 2 uint8", "c2u8", S.quantize_u8(x), dtype=torch.uint8)
+    if "c3" in cfg_inputs:
+        forms["c3_single"] = single_form("config 3", "c3", cfg_inputs["c3"][0])
+    if "c4" in cfg_inputs:
+        imgs = cfg_inputs["c4"]
+        log("config 4: %d images, autotuned tiles, one captured forward" % len(imgs))
+        shapes = [a.shape for a in imgs]
+        nv = sum(a.size for a in imgs)
+        bt = fc.Batch(shapes, device=dev)
+        bt.set_images([torch.from_numpy(a) for a in imgs])
+        tiles = bt.ph_autotune(reps=2)
+        bt.ph_diagram_batch()
+        sync()
+        res = bt.results()
+        n = check_digests(dig, "c4", imgs, res) if not SMALL else 0
+        caps = bt.counts.cpu().numpy().tolist()
+        del bt
+        b2 = [fc.Batch(shapes, device=dev, capacities=caps) for _ in range(2)]
+        for b in b2:
+            b.set_images([torch.from_numpy(a) for a in imgs])
+        g = [capture(lambda b=b: b.ph_diagram_batch()) for b in b2]
+        t = timed(lambda k: g[k % 2]())
+        for b in b2:
+            b.check()
+        prof = profiled(lambda k: b2[k % 2].ph_diagram_batch(), 3)
+        dom, kms = dominant(prof, b2[0].work_counters(), int(sum(caps)), shapes)
+        forms["c4_batch"] = {"value": round(nv / t / 1e6, 3), "ms": round(t * 1e3, 4), "instances": len(imgs),
+                             "voxels": nv, "tiles": list(tiles), "dominant": dom, "kernels_ms": kms,
+                             "oracle_digests_checked": n}
+    return forms
 
 
 if __name__ == "__main__":

@@ -266,14 +266,15 @@ int ph_profile(int32_t enable);
 int ph_profile_read(ph_kernel_time *out, int32_t max, int32_t *count);
 
 /* Work counters of the last call that used workspace d_ws for n instances (the same n), for
- * sizing and diagnostics: 14 int32 per instance written to h_out (host), in order KEEP edges,
+ * sizing and diagnostics: 16 int32 per instance written to h_out (host), in order KEEP edges,
  * KEEP squares (3D), H0 nodes (local minima), dual nodes (ROOT top cells + the cell at
  * infinity), H0 union-find rounds, dual union-find rounds, edges finished sequentially, the
  * instance's error word, and under PH_H1: H1 columns, columns reduced one by one (their
  * lowest row occurs in an earlier column), the most steps one column's expression in
  * critical cells took, the pool entries used, the columns that needed the large tables, and
- * the reduction's rounds (or, when it ran one column at a time, its column additions).
- * Copies synchronously; PH_OK, PH_EINVAL or PH_EHIP. */
+ * the reduction's rounds (or, when it ran one column at a time, its column additions); then
+ * the forest links followed to resolve the KEEP edges' endpoints (H0) and the facets'
+ * cofacets (top dimension).  Copies synchronously; PH_OK, PH_EINVAL or PH_EHIP. */
 int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out);
 
 /* Library version string. */

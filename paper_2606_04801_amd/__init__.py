@@ -415,16 +415,17 @@ class Batch:
                     stream)
 
     def work_counters(self):
-        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 14) array:
+        """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 16) array:
         KEEP edges, KEEP squares, H0 nodes, dual nodes, H0 rounds, dual rounds, sequential
         edges, error word, and for 3D H1: columns, columns reduced one by one, most steps of
         one column, pool entries, columns that needed the large tables, reduction rounds
-        (column additions when it ran one column at a time).  Synchronises."""
-        out = (ctypes.c_int32 * (14 * self.n))()
+        (column additions when it ran one column at a time), and the forest links the
+        resolve passes followed (H0 endpoints, top-dimension cofacets).  Synchronises."""
+        out = (ctypes.c_int32 * (16 * self.n))()
         rc = lib().ph_work_counters(_ptr(self.ws), self.n, out)
         if rc != PH_OK:
             raise PHError(rc, "ph_work_counters")
-        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 14).copy()
+        return np.frombuffer(out, dtype=np.int32).reshape(self.n, 16).copy()
 
     def valid_mask(self):
         """Device bool mask over the packed pair slots holding a stored pair (no sync)."""

@@ -266,17 +266,18 @@ __device__ __forceinline__ int quad_slot(uint32_t q) {
 
 // 2 raw + (a < b), or with LE 2 raw + (a <= b), unsigned: the compare sets VCC and an add with
 // carry shifts it in (two vector instructions; compiled code takes a compare, a select and a
-// merge).  The nop gives the two wait states between a vector write of VCC and a vector read
-// of it.  The CPU emulation build of the kernels computes the same in C.
+// merge).  A vector read of VCC as carry right after a vector compare wrote it needs no wait
+// states (the same pairing as the add and add-with-carry of a 64-bit sum).  The CPU emulation
+// build of the kernels computes the same in C.
 template <bool LE>
 __device__ __forceinline__ uint32_t shift_in_less(uint32_t raw, uint32_t a, uint32_t b) {
 #if defined(__AMDGCN__)
     uint32_t r;
     if (LE)
-        asm("v_cmp_le_u32_e32 vcc, %1, %2\n\ts_nop 1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+        asm("v_cmp_le_u32_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
             : "=v"(r) : "v"(a), "v"(b), "v"(raw) : "vcc");
     else
-        asm("v_cmp_lt_u32_e32 vcc, %1, %2\n\ts_nop 1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+        asm("v_cmp_lt_u32_e32 vcc, %1, %2\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
             : "=v"(r) : "v"(a), "v"(b), "v"(raw) : "vcc");
     return r;
 #else
@@ -1070,13 +1071,14 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
 // their loads are in flight together; -1 (and an error) if a link leaves [0, size) or a node
 // id is not below nodes; a walk not run yields 0.
 __device__ __forceinline__ void chase2(const int32_t *__restrict__ p, int64_t x0, int64_t x1, bool run0, bool run1,
-                                       int64_t size, int nodes, int32_t *cnt, int &r0, int &r1) {
+                                       int64_t size, int nodes, int32_t *cnt, int &r0, int &r1, int &hops) {
     r0 = 0;
     r1 = 0;
     bool a0 = run0, a1 = run1;
     for (int it = 0; (a0 || a1) && it < kMaxChase; ++it) {
         if (a0 && (x0 < 0 || x0 >= size)) { set_err(cnt, PH_EINTERNAL); r0 = -1; a0 = false; }
         if (a1 && (x1 < 0 || x1 >= size)) { set_err(cnt, PH_EINTERNAL); r1 = -1; a1 = false; }
+        hops += (int)a0 + (int)a1;
         const int32_t v0 = a0 ? p[x0] : 0, v1 = a1 ? p[x1] : 0;
         if (a0) {
             if (v0 >= 0) x0 = v0;
@@ -1099,8 +1101,14 @@ __device__ __forceinline__ void chase2(const int32_t *__restrict__ p, int64_t x0
     if (a1) { set_err(cnt, PH_EINTERNAL); r1 = -1; }
 }
 
+// Add a per-thread count to a counter with one atomic per wave (all lanes of the wave call it).
+__device__ __forceinline__ void wave_count(int32_t *counter, int v) {
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (__lane_id() == 0 && v) atomicAdd(counter, v);
+}
+
 // H0: the two endpoints of every sorted KEEP edge of instance i, as H0 nodes (local minima).
-// The blocks of one instance are blockIdx.x of gridDim.x.
+// The blocks of one instance are blockIdx.x of gridDim.x; the links followed are counted.
 __device__ __forceinline__ void resolve_edges(uint8_t *__restrict__ ws, int n, int i) {
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1111,17 +1119,21 @@ __device__ __forceinline__ void resolve_edges(uint8_t *__restrict__ ws, int n, i
     const int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *ea = arr<int32_t>(ws, I.o_ea), *eb = arr<int32_t>(ws, I.o_eb);
     const int64_t HW = (int64_t)I.H * I.W;
-    for (int r = blockIdx.x * 256 + threadIdx.x; r < m; r += gridDim.x * 256) {
+    int hops = 0;
+    for (int r0 = blockIdx.x * 256; r0 < m; r0 += gridDim.x * 256) {    // whole waves iterate
+        const int r = r0 + threadIdx.x;
+        if (r >= m) continue;
         const uint64_t k = keyE[r];
         const int64_t v = key_pix(k);
         const int code = key_code(k);
         if (code < 1 || code > 6) { set_err(cnt, PH_EINTERNAL); ea[r] = eb[r] = -1; continue; }
         const int64_t u = v + off_of(code, 0) * HW + off_of(code, 1) * (int64_t)I.W + off_of(code, 2);
         int a, b;
-        chase2(par0, v, u, true, true, I.N, M0, cnt, a, b);
+        chase2(par0, v, u, true, true, I.N, M0, cnt, a, b, hops);
         ea[r] = a;
         eb[r] = b;
     }
+    wave_count(&cnt[CNT_HOPS0], hops);
 }
 
 // Top dimension: the two cofacets of every facet of instance i walked by the dual union-find,
@@ -1139,7 +1151,10 @@ __device__ __forceinline__ void resolve_facets(uint8_t *__restrict__ ws, int n, 
     int32_t *fa = arr<int32_t>(ws, I.o_fa), *fb = arr<int32_t>(ws, I.o_fb);
     const int D = I.D, H = I.H, W = I.W;
     const int64_t HW = (int64_t)H * W;
-    for (int r = blockIdx.x * 256 + threadIdx.x; r < m; r += gridDim.x * 256) {
+    int hops = 0;
+    for (int r0 = blockIdx.x * 256; r0 < m; r0 += gridDim.x * 256) {    // whole waves iterate
+        const int r = r0 + threadIdx.x;
+        if (r >= m) continue;
         if (is2d && neg0[r]) { fa[r] = -1; fb[r] = -1; continue; }   // cross-pruned
         const uint64_t k = key[r];
         const int64_t v = key_pix(k);
@@ -1166,10 +1181,11 @@ __device__ __forceinline__ void resolve_facets(uint8_t *__restrict__ ws, int n, 
             top[t] = ((int64_t)cz * (H - 1) + cy) * (W - 1) + cx;
         }
         int a, b;
-        chase2(parT, top[0], top[1], in[0], in[1], I.T, MT, cnt, a, b);
+        chase2(parT, top[0], top[1], in[0], in[1], I.T, MT, cnt, a, b, hops);
         fa[r] = a;
         fb[r] = b;
     }
+    wave_count(&cnt[CNT_HOPST], hops);
 }
 
 // Resolve passes, blockIdx.y = instance.  Stage 0: blockIdx.z = 0 the KEEP edges of every
@@ -2900,11 +2916,11 @@ int ph_work_counters(const void *d_ws, int32_t n, int32_t *h_out) {
     if (hipMemcpy(c.data(), (const uint8_t *)d_ws + fc::off_cnt(n), c.size() * sizeof(int32_t),
                   hipMemcpyDeviceToHost) != hipSuccess)
         return PH_EHIP;
-    const int pick[14] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
+    const int pick[16] = {fc::CNT_E, fc::CNT_F, fc::CNT_M0, fc::CNT_MT, fc::CNT_ROUNDS0, fc::CNT_ROUNDST,
                           fc::CNT_SEQ, fc::CNT_ERR, fc::CNT_H1COLS, fc::CNT_H1UNSAFE, fc::CNT_H1ROUNDS,
-                          fc::CNT_H1POOL, fc::CNT_H1RETRY, fc::CNT_H1ADDS};
+                          fc::CNT_H1POOL, fc::CNT_H1RETRY, fc::CNT_H1ADDS, fc::CNT_HOPS0, fc::CNT_HOPST};
     for (int i = 0; i < n; ++i)
-        for (int k = 0; k < 14; ++k) h_out[i * 14 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
+        for (int k = 0; k < 16; ++k) h_out[i * 16 + k] = c[(size_t)i * fc::CNT_WORDS + pick[k]];
     return PH_OK;
 }
 

@@ -39,7 +39,8 @@ def main(so):
     for a, r, ref in zip(imgs, res, refs):
         assert diff_pairs(r, ref) is None, a.shape
     wc = bt.work_counters()
-    assert wc.shape == (len(imgs), 8) and (wc[:, 7] == 0).all() and (wc[:, 2] >= 1).all(), wc
+    assert wc.shape == (len(imgs), 16) and (wc[:, 7] == 0).all() and (wc[:, 2] >= 1).all(), wc
+    assert (wc[:, 14] >= 2 * wc[:, 0]).all(), wc     # each KEEP edge reads the forest at both endpoints
     fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
     assert int(bt.valid_mask().sum()) == sum(len(r) for r in refs)
     diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)

@@ -225,8 +225,11 @@ def test_bench_flow_against_host_library():
     assert r.returncode == 0, r.stderr[-4000:]
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
-    assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd", "per_image_fwd_bwd", "batched_fwd_bwd_u8",
-                                  "batched_fwd_bwd_tfilt"}
+    assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd_bwd_manual", "batched_fwd", "per_image_fwd_bwd",
+                                  "batched_fwd_bwd_u8", "batched_fwd_bwd_tfilt", "batched_fwd_h1", "c1_single",
+                                  "c2_single", "c2u8_single", "c3_single", "c4_batch"}
+    assert line["parity"]["autograd_eq_manual"] and line["forms"]["batched_fwd_h1"]["h1_columns"] > 0
+    assert all(k["bytes"] > 0 for n, k in line["kernels"].items() if n not in ("k_plan",))
     assert line["cpu_baseline"]["kind"] == "oracle" and line["work"]["pairs"] > 0
 
 
