@@ -187,8 +187,6 @@ def algorithmic_bytes(name, wc, npairs, shapes):
         return 4 * N
     if name == "k_scatter":
         return 32 * npairs
-    if name == "k_tpad":
-        return 4 * N + 4 * sum(int(np.prod([e + 2 for e in s])) for s in shapes)
     return 0
 
 

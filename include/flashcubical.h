@@ -16,7 +16,8 @@
  *
  * Conventions shared by every entry point:
  *   - Pixel layout: row-major, last axis fastest.  2D extents are (H, W), 3D (D, H, W); every
- *     extent >= 1, and the voxel count of one instance must be below 2^27.
+ *     extent >= 1, and the voxel count of one instance is at most 2^27 (a 512^3 volume; under
+ *     PH_TFILT the framed extents, each + 2, count).
  *   - pixidx: row-major pixel index.  Cell index: row-major index on the doubled grid
  *     (2H-1, 2W-1) or (2D-1, 2H-1, 2W-1), a coordinate being odd where the cell spans that
  *     axis.
@@ -97,8 +98,9 @@ enum {
  * reduced over F2 in square order.  The H1 pairs of non-zero persistence are reported between
  * H0 and H2, in the same order and with the same fields as the other dimensions (under
  * PH_TFILT: the T-filtration's H1, by duality, by death key).  Internal limits (a column's
- * running sum beyond 1024 live edges, its boundary in critical cells beyond 64 edges, the
- * columns' pool beyond 4 entries per KEEP-square slot) are reported as PH_EINTERNAL.  Volumes
+ * running sum beyond 2048 live edges (columns beyond 512 take a second pass with larger
+ * tables), its boundary in critical cells beyond 64 edges, the columns' pool beyond 4 entries
+ * per KEEP-square slot) are reported as PH_EINTERNAL.  Volumes
  * run the 3D classify pass on the default tiles under PH_H1. */
 enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16, PH_H1 = 32 };
 
@@ -110,7 +112,7 @@ typedef struct {
 /* Structure-of-arrays output, device pointers, caller-owned.  Each array holds at least the
  * capacity of the call (sum of capacities for a batch). */
 typedef struct {
-    int8_t *dim;            /* homology dimension: 0 or ndim-1 */
+    int8_t *dim;            /* homology dimension: 0, ndim-1, or 1 for a volume under PH_H1 */
     float *birth;           /* value of the birth cell */
     float *death;           /* value of the death cell; +inf for the essential class */
     int64_t *birth_cell;    /* doubled-grid index of the birth cell */

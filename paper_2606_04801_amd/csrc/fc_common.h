@@ -31,7 +31,7 @@
 namespace fc {
 
 constexpr int kCodeBits = 5;
-constexpr int kPixBits = 27;                       // voxels per instance < 2^27
+constexpr int kPixBits = 27;                       // pixel index field: voxels per instance <= 2^27
 constexpr uint64_t kPixMask = (1ull << kPixBits) - 1;
 
 // offsets (dz, dy, dx) of the 27 local cells, in code order
@@ -127,16 +127,17 @@ FC_HD Geom geom(int ndim, int64_t D, int64_t H, int64_t W) {
 struct Inst {
     int32_t ndim, D, H, W;
     int64_t N, T, E, F, FAC;
-    int64_t img_off, out_off, out_cap;
-    int64_t src_off;           // offset of the caller's image (img_off differs under the T-filtration)
+    int64_t src_off;           // offset of the instance's pixels in the caller's input (elements)
+    int64_t out_off, out_cap;
     int64_t tile_base;         // first tile of this instance in its (2D or 3D) classify grid
     int32_t tx, ty, tz;        // tiles along x, y, z
-    int32_t tfilt;             // 1: T-filtration, the grid is the framed dual image (extents + 2)
+    int32_t tfilt;             // 1: T-filtration, the grid is the framed dual image (extents + 2),
+                               // read from the caller's pixels on the fly (see tf_value)
     int32_t h1;                // 1: a volume whose H1 is computed too (Sec. 4.2 steps 4-5)
     // byte offsets of the per-instance arrays inside the workspace
     int64_t o_par0, o_parT, o_keyE, o_ea, o_eb, o_neg0, o_keyF, o_fa, o_fb, o_killer;
     int64_t o_n0key, o_n0sorted, o_nTkey, o_uf0, o_moe0, o_death0, o_ufT, o_moeT;
-    int64_t o_live, o_live2, o_ra, o_rb, o_scratch, o_gimg;
+    int64_t o_live, o_live2, o_ra, o_rb, o_scratch;
     // H1 of a volume: per-vertex configuration index and first sorted KEEP edge, per KEEP
     // square its H1 column (start and length in the pool, -1 if paired in H2), per KEEP edge
     // its pivot column and the first column holding it, and the pool of column entries
@@ -199,7 +200,6 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_ra = take(4 * L);
     I.o_rb = take(4 * L);
     I.o_scratch = take(8 * SCR);
-    I.o_gimg = I.tfilt ? take(4 * N) : 0;   // T-filtration: the framed dual image (float32)
     const bool h1 = I.h1 && I.ndim == 3;
     I.pool_cap = h1 ? kH1PoolPerSquare * F : 0;
     I.o_cfg3 = h1 ? take(2 * N) : 0;

@@ -123,7 +123,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
             if (!ok) s = ph_shape{2, {1, 1, 1}};
             if (tfilt) s = framed(s);
             fill_inst(I, s, tl);
-            if (I.N >= (1ll << kPixBits)) {
+            if (I.N > (1ll << kPixBits)) {
                 ok = false;
                 s = ph_shape{2, {1, 1, 1}};
                 fill_inst(I, tfilt ? framed(s) : s, tl);
@@ -147,14 +147,12 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
         if (i < n) {
             const int64_t at = s_run[0] + s_scan[b][0][t] - v[0];
             I.src_off = d_img_off ? d_img_off[i] : 0;
-            I.img_off = I.src_off;
             I.out_off = d_out_off ? d_out_off[i] : 0;
             I.out_cap = d_out_off ? d_out_off[i + 1] - d_out_off[i] : single_cap;
             tb2[i] = s_run[1] + s_scan[b][1][t] - v[1];
             tb3[i] = s_run[2] + s_scan[b][2][t] - v[2];
             I.tile_base = I.ndim == 2 ? tb2[i] : tb3[i];
             layout(I, at);
-            if (tfilt) I.img_off = I.o_gimg / 4;      // float32 elements from the workspace base
             tab[i] = I;
             for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
             cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
@@ -290,6 +288,21 @@ __device__ __forceinline__ int clamp0(int v, int hi) {
     const int a = v > 0 ? v : 0;
     return a < hi ? a : hi;
 }
+
+// T-filtration (Sec. 2.2): the kernels run the V construction on the framed dual image of the
+// caller's pixels, whose pixel (z, y, x) holds minus the caller's pixel at the point reflection
+// (sD - z, sH - y, sW - x) of the inner box (s* = framed extent - 2; an image has no frame
+// along z) and -inf on the frame.  Its V complex is the dual cell complex of the caller's T
+// complex with the frame added; the reflection turns the V tie-break (a larger index enters
+// later) into the T one read backwards.  Nothing is stored: the classify passes and 3D H1 read
+// the caller's pixels through this map.  f is the caller's pixel, inner whether the framed
+// pixel lies inside the frame.  A +inf pixel would tie the frame: it becomes NaN, which the
+// classify pass reports as PH_ENAN.
+__device__ __forceinline__ float tf_value(float f, bool inner) {
+    return !inner ? __int_as_float(0xff800000)                                    // -inf
+                  : (f == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -f);
+}
+template <bool B> using tf_tag = std::integral_constant<bool, B>;
 __device__ __forceinline__ int32_t slot_get(const int32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
@@ -417,7 +430,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
     const int y0 = ty * TH, x0 = tx * TW;
-    const T *img = imgs + I.img_off;
+    const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
     uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
@@ -426,17 +439,23 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
-    {
-        // every halo load of the thread is issued before the first is used: the addresses
-        // are clamped into the image and outside pixels replaced afterwards
+    // every halo load of the thread is issued before the first is used: the addresses are
+    // clamped into the image and outside pixels replaced afterwards.  Under the T-filtration
+    // the image is the framed dual one, read through the reflection (tf_value).
+    auto halo = [&](auto tf) {
+        constexpr bool TF = decltype(tf)::value;
         constexpr int NS = (TH + 2) * KW, NL = (NS + 255) / 256;
         float f[NL];
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
             const int l = threadIdx.x + 256 * k;
             const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
-            const int cy = gy < 0 ? 0 : (gy >= H ? H - 1 : gy), cx = gx < 0 ? 0 : (gx >= W ? W - 1 : gx);
-            f[k] = (float)img[(int64_t)cy * W + cx];
+            if constexpr (TF) {
+                const int sH = H - 2, sW = W - 2;       // the caller's extents
+                f[k] = (float)img[(int64_t)clamp0(sH - gy, sH - 1) * sW + clamp0(sW - gx, sW - 1)];
+            } else {
+                f[k] = (float)img[(int64_t)clamp0(gy, H - 1) * W + clamp0(gx, W - 1)];
+            }
         }
 #pragma unroll
         for (int k = 0; k < NL; ++k) {
@@ -445,13 +464,17 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
             if (l >= NS) break;
             uint32_t key = kOutside;
             if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                nan |= (f[k] != f[k]);
-                const uint32_t o = ord32(__float_as_uint(f[k]));
+                float v = f[k];
+                if constexpr (TF) v = tf_value(v, gy >= 1 && gy <= H - 2 && gx >= 1 && gx <= W - 2);
+                nan |= (v != v);
+                const uint32_t o = ord32(__float_as_uint(v));
                 key = o < kOutside ? o : kOutside - 1u;
             }
             skey[l] = key;
         }
-    }
+    };
+    if (I.tfilt) halo(tf_tag<true>{});
+    else halo(tf_tag<false>{});
     // square slots start unset (padding final); after pass 2 the slots no vertex of the tile
     // wrote get their square's global index (see is_local).  s_row[r]: global index of the
     // first square of slot row r (x = x0 - 1) and whether the row lies in the image.
@@ -636,7 +659,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
     const int ty = rem / I.tx, tx = rem - ty * I.tx;
     const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
-    const T *img = imgs + I.img_off;
+    const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
     uint64_t *keyE = arr<uint64_t>(ws, I.o_keyE);
@@ -652,33 +675,50 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         // The halo box is KD * KH rows of KW keys.  A group of KW consecutive threads loads
         // one row, kGroups rows at a time, so a thread keeps its column and steps its row by a
         // constant.  Every load of the thread is issued before the first is used: addresses
-        // are clamped into the volume (offsets fit 32 bits: an instance has < 2^27 voxels)
-        // and outside voxels replaced afterwards.
+        // are clamped into the volume (offsets fit 32 bits: an instance has <= 2^27 voxels)
+        // and outside voxels replaced afterwards.  Under the T-filtration the volume is the
+        // framed dual one, read through the reflection (tf_value).
         constexpr int kGroups = 256 / KW, NR = KD * KH, NL = (NR + kGroups - 1) / kGroups;
         const int g = threadIdx.x / KW, c = threadIdx.x - g * KW;
-        const int gx = x0 - 1 + c, cx = clamp0(gx, W - 1);
+        const int gx = x0 - 1 + c;
         const bool inx = (unsigned)gx < (unsigned)W && g < kGroups;
-        float f[NL];
-        uint32_t inside = 0;                                // bit k: row g + k kGroups, in the volume
-        int zz = g / KH, yy = g - zz * KH;
+        auto halo = [&](auto tf) {
+            constexpr bool TF = decltype(tf)::value;
+            const int cx = TF ? clamp0(W - 2 - gx, W - 3) : clamp0(gx, W - 1);   // T: reflected
+            float f[NL];
+            uint32_t inside = 0;                            // bit k: row g + k kGroups, in the volume
+            uint32_t inner = 0;                             // T: and inside the frame
+            int zz = g / KH, yy = g - zz * KH;
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
-            const int cz = clamp0(gz, D - 1), cy = clamp0(gy, H - 1);
-            f[k] = (float)img[(uint32_t)(cz * (int)HW + cy * W + cx)];
-            if (inx && (unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H) inside |= 1u << k;
-            yy += kGroups % KH;
-            zz += kGroups / KH;
-            if (yy >= KH) { yy -= KH; ++zz; }
-        }
+            for (int k = 0; k < NL; ++k) {
+                const int gz = z0 - 1 + zz, gy = y0 - 1 + yy;
+                if constexpr (TF) {
+                    const int sD = D - 2, sH = H - 2, sW = W - 2;   // the caller's extents
+                    const int cz = clamp0(sD - gz, sD - 1), cy = clamp0(sH - gy, sH - 1);
+                    f[k] = (float)img[(uint32_t)((cz * sH + cy) * sW + cx)];
+                    if (gx >= 1 && gx <= W - 2 && gz >= 1 && gz <= D - 2 && gy >= 1 && gy <= H - 2) inner |= 1u << k;
+                } else {
+                    const int cz = clamp0(gz, D - 1), cy = clamp0(gy, H - 1);
+                    f[k] = (float)img[(uint32_t)(cz * (int)HW + cy * W + cx)];
+                }
+                if (inx && (unsigned)gz < (unsigned)D && (unsigned)gy < (unsigned)H) inside |= 1u << k;
+                yy += kGroups % KH;
+                zz += kGroups / KH;
+                if (yy >= KH) { yy -= KH; ++zz; }
+            }
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            if (g >= kGroups || g + k * kGroups >= NR) break;   // threads past the last group load only
-            const uint32_t o = ord32(__float_as_uint(f[k]));
-            const bool in = (inside >> k) & 1u;
-            nan |= in && f[k] != f[k];
-            skey[threadIdx.x + k * kGroups * KW] = in ? (o < kOutside ? o : kOutside - 1u) : kOutside;
-        }
+            for (int k = 0; k < NL; ++k) {
+                if (g >= kGroups || g + k * kGroups >= NR) break;   // threads past the last group load only
+                float v = f[k];
+                if constexpr (TF) v = tf_value(v, (inner >> k) & 1u);
+                const uint32_t o = ord32(__float_as_uint(v));
+                const bool in = (inside >> k) & 1u;
+                nan |= in && v != v;
+                skey[threadIdx.x + k * kGroups * KW] = in ? (o < kOutside ? o : kOutside - 1u) : kOutside;
+            }
+        };
+        if (I.tfilt) halo(tf_tag<true>{});
+        else halo(tf_tag<false>{});
     }
     // cube slots start unset (padding rows final); after pass 2 the slots no vertex of the
     // tile wrote get their cube's global index (see is_local).  s_row[r]: global index of the
@@ -1402,65 +1442,6 @@ __global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ 
         uf_run<true>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
 }
 
-// ============================================================== T-filtration ====
-// The framed dual image of one instance per blockIdx.y: framed pixel (z, y, x) holds minus
-// the caller's pixel at the point reflection of (z-1, y-1, x-1) (an image has no frame along
-// z), the frame holds -inf.  Its V complex is the dual cell complex of the caller's T complex
-// with the frame added; the reflection makes the V tie-break (larger index enters later) the
-// T one read backwards.  A +inf pixel would tie the frame: it becomes NaN, which the
-// classify pass reports as PH_ENAN.
-constexpr int kTpadRows = 16;                       // framed rows per wave step in k_tpad
-template <typename T>
-__global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t *__restrict__ ws, int n) {
-    const int i = blockIdx.y;
-    const Inst &I = ((const Inst *)ws)[i];
-    const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (!I.tfilt || failed(cnt)) return;
-    float *g = (float *)ws + I.img_off;
-    const bool vol = I.ndim == 3;
-    const int D = I.D, H = I.H, W = I.W;               // framed extents (D = 1 for an image)
-    const int sD = vol ? D - 2 : 1, sH = H - 2, sW = W - 2;
-    const int lane = threadIdx.x & 63, rows = D * H;
-    const int wave = blockIdx.x * 4 + (threadIdx.x >> 6), waves = gridDim.x * 4;
-    // each wave takes kTpadRows framed rows at a time, so that that many loads are in flight
-    // per wave; a row's coordinates are found once per row
-    for (int r0 = wave * kTpadRows; r0 < rows; r0 += waves * kTpadRows) {
-        int64_t qrow[kTpadRows];
-        bool inner[kTpadRows];
-#pragma unroll
-        for (int k = 0; k < kTpadRows; ++k) {
-            const int r = r0 + k, z = r / H, y = r - z * H;
-            inner[k] = r < rows && (!vol || (z >= 1 && z <= D - 2)) && y >= 1 && y <= H - 2;
-            qrow[k] = I.src_off + ((int64_t)(vol ? sD - z : 0) * sH + (sH - y)) * sW;   // source row start
-        }
-        // source columns c0 .. c0+63, loaded in ascending order by lanes 0..63; framed column
-        // sW - c holds source column c, so lane l stores framed column sW - c0 - 63 + l with the
-        // value lane 63 - l loaded, and the stores ascend too
-        for (int c0 = 0; c0 < sW; c0 += 64) {
-            const int c = c0 + lane;
-            float f[kTpadRows];
-#pragma unroll
-            for (int k = 0; k < kTpadRows; ++k)
-                f[k] = (float)src[inner[k] && c < sW ? qrow[k] + c : I.src_off];
-            const int cs = c0 + 63 - lane;             // the source column this lane stores
-            const int x = sW - cs;                     // its framed column, >= 1 when cs < sW
-#pragma unroll
-            for (int k = 0; k < kTpadRows; ++k) {
-                const float fk = __int_as_float(__shfl((int)__float_as_uint(f[k]), 63 - lane, 64));
-                const float v = !inner[k] ? __int_as_float(0xff800000)                 // -inf
-                                : fk == __int_as_float(0x7f800000) ? __int_as_float(0x7fc00000) : -fk;
-                if (r0 + k < rows && cs < sW) g[(int64_t)(r0 + k) * W + x] = v;
-            }
-        }
-        // the frame's first and last column of every row
-        if (lane < 2) {
-#pragma unroll
-            for (int k = 0; k < kTpadRows; ++k)
-                if (r0 + k < rows) g[(int64_t)(r0 + k) * W + (lane ? W - 1 : 0)] = __int_as_float(0xff800000);
-        }
-    }
-}
-
 // ======================================================================= 3D H1 ====
 // H1 of a volume (Sec. 4.2 steps 4-5): the cells not already paired.  Rows are the positive
 // edges; columns the KEEP squares the dual union-find left unpaired (squares paired in H2 are
@@ -1471,15 +1452,16 @@ __global__ __launch_bounds__(256) void k_tpad(const T *__restrict__ src, uint8_t
 // its own combination (the squares of L(v) its relative reduction added), which has no entry
 // in L(v).  From then on every locally paired entry lies in an earlier lower star, so its
 // partner precedes sigma: adding the partner's reduced column is a legal column operation in
-// any order.  Rounds add them for every locally paired entry at once (the largest one present
-// always disappears and nothing above it is added, so the rounds end); entries that can never
-// be a pivot (negative edges: paired with their vertex, or H0-negative KEEP edges) are
-// dropped.  What is left are KEEP edges that H0 left positive: the column's boundary in the
-// complex of critical cells.  A standard reduction of those small columns, in square order,
-// then gives exactly the pairs of the full boundary-matrix reduction.
+// any order.  Each entry that turns present is queued and classified once it comes out of the
+// queue; a locally paired one still present gets its partner's reduced column added (which
+// removes it and adds only entries below it, so the work ends); entries that can never be a
+// pivot (negative edges: paired with their vertex, or H0-negative KEEP edges) are dropped.
+// What is left are KEEP edges that H0 left positive: the column's boundary in the complex of
+// critical cells.  A standard reduction of those small columns, in square order, then gives
+// exactly the pairs of the full boundary-matrix reduction.
 //
-// One single-wave workgroup per column at a time; the column is an F2 set of edge keys in an
-// open-addressing table in LDS (toggling a key is adding the edge).
+// One single-wave workgroup per column at a time, 64 queued entries per step; the column is an
+// F2 set of edge keys in an open-addressing table in LDS (toggling a key is adding the edge).
 constexpr int kH1Slots = 1024;             // table slots (and queue entries) of the first pass
 constexpr int kH1BigSlots = 4096;          // the same for the columns the first pass could not hold
 constexpr int kH1MaxBoundary = 64;         // entries of one column's boundary in critical cells
@@ -1595,10 +1577,25 @@ struct H1Col {
     }
 };
 
+// The voxel values 3D H1 compares: the caller's, or under the T-filtration those of the framed
+// dual volume (extents D, H, W), read through the reflection (tf_value).
+template <typename T>
+struct VoxVals {
+    const T *img;
+    int tf, D, H, W;
+    __device__ __forceinline__ float at(uint32_t p) const {
+        if (!tf) return (float)img[p];
+        const int HW = H * W, z = (int)(p / (uint32_t)HW), rem = (int)p - z * HW, y = rem / W, x = rem - y * W;
+        const bool inner = z >= 1 && z <= D - 2 && y >= 1 && y <= H - 2 && x >= 1 && x <= W - 2;
+        const int sD = D - 2, sH = H - 2, sW = W - 2;
+        return tf_value(inner ? (float)img[(uint32_t)(((sD - z) * sH + (sH - y)) * sW + (sW - x))] : 0.0f, inner);
+    }
+};
+
 // order key of voxel p: ord32 of its value, then p (the vertex order of Sec. 2.3)
 template <typename T>
-__device__ __forceinline__ uint64_t vox_key(const T *img, uint32_t p) {
-    return ((uint64_t)ord32(__float_as_uint((float)img[p])) << 32) | p;
+__device__ __forceinline__ uint64_t vox_key(const VoxVals<T> &img, uint32_t p) {
+    return ((uint64_t)ord32(__float_as_uint(img.at(p))) << 32) | p;
 }
 // key of the edge between voxels a and b = a + the unit offset of edge code code_ab, from
 // their order keys: its last vertex is the later one, the code is seen from there
@@ -1612,7 +1609,7 @@ __device__ __forceinline__ uint64_t edge_key_of(uint64_t ka, uint64_t kb, uint32
 // out: its two edges at w (w is their last vertex) and the two opposite ones, whose last
 // vertices are looked up.
 template <int SLOTS, typename T>
-__device__ __forceinline__ void h1_square(H1Col<SLOTS> &col, const T *img, uint32_t w, int q, int W, int HW,
+__device__ __forceinline__ void h1_square(H1Col<SLOTS> &col, const VoxVals<T> &img, uint32_t w, int q, int W, int HW,
                                           uint32_t skip) {
     const int c = 7 + q;
     const int a1 = off_of(c, 0) ? 0 : 1;            // the two axes the square spans, slowest first
@@ -1680,7 +1677,7 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
         if (lane == 0) set_err(cnt, PH_EINTERNAL);
         return;
     }
-    const T *img = imgs + I.img_off;
+    const VoxVals<T> img{imgs + I.src_off, I.tfilt, I.D, I.H, I.W};
     const int W = I.W, HW = I.H * I.W;
     const uint64_t *keyF = arr<uint64_t>(ws, I.o_keyF);
     const int32_t *killer = arr<int32_t>(ws, I.o_killer);
@@ -2346,9 +2343,6 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_h1_morse<u8,big>", (const void *)k_h1_morse<uint8_t, kH1BigSlots>, 64},
         {"k_h1_morse<u16,big>", (const void *)k_h1_morse<uint16_t, kH1BigSlots>, 64},
         {"k_h1_reduce", (const void *)k_h1_reduce, kUfThreads},
-        {"k_tpad", (const void *)k_tpad<float>, 256},
-        {"k_tpad<u8>", (const void *)k_tpad<uint8_t>, 256},
-        {"k_tpad<u16>", (const void *)k_tpad<uint16_t>, 256},
     };
     int maxsh = 0, maxthr = 0;
     if (!hip_ok(hipDeviceGetAttribute(&maxsh, hipDeviceAttributeMaxSharedMemoryPerBlock, dev), "hipDeviceGetAttribute") ||
@@ -2407,9 +2401,10 @@ bool valid_shape(const ph_shape &s) {
     int64_t nv = 1;
     for (int k = 0; k < s.ndim; ++k) {
         if (s.ext[k] < 1) return false;
-        nv *= s.ext[k];
+        nv *= s.ext[k];                            // <= 2^27 * 2^31 before the check: no overflow
+        if (nv > (1ll << kPixBits)) return false;  // pixel indices must fit the key's 27 bits
     }
-    return nv < (1ll << kPixBits);
+    return true;
 }
 
 const int kTile2[3][2] = {{64, 16}, {32, 32}, {128, 8}};
@@ -2512,12 +2507,11 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // stream is being captured into a graph).
 enum KernelId {
     K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1MORSE2, K_H1REDUCE,
-    K_OUTPUT, K_ZERO, K_SCATTER, K_TPAD, K_COUNT
+    K_OUTPUT, K_ZERO, K_SCATTER, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
-    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
-    "k_tpad"};
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -2577,8 +2571,8 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
         return PH_EINVAL;
-    // under the T-filtration the kernels below run on the framed dual images, which sit in
-    // the workspace as float32 (extents + 2); only k_tpad and k_output read the caller's input
+    // under the T-filtration the kernels below run on the framed dual images (extents + 2),
+    // which they read from the caller's pixels through the reflection (tf_value)
     const bool tf = (flags & PH_TFILT) != 0;
     // (a single instance keeps its framed shape on the stack: the no-allocation entry point
     // allocates nothing, on the host either)
@@ -2599,8 +2593,7 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     }
     if (!(flags & (PH_H0 | PH_HTOP | PH_H1))) return PH_EINVAL;
     if ((flags & PH_IN_U8) && (flags & PH_IN_U16)) return PH_EINVAL;
-    const int in_elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
-    const int elem = tf ? 0 : in_elem;             // element type the classify passes read
+    const int elem = (flags & PH_IN_U8) ? 1 : ((flags & PH_IN_U16) ? 2 : 0);   // 0 float32, 1 u8, 2 u16
     if (elem != 0) tuning = nullptr;               // integer inputs use the default tiles
     const bool h1 = (flags & PH_H1) != 0;
     ph_tuning h1_tuning;
@@ -2640,20 +2633,6 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
                                  h1 ? 1 : 0));
     const int64_t ml = max_list(hs, n), mv = max_voxels(hs, n);
     const void *cimgs = d_imgs;                    // what the classify passes read
-    if (tf) {
-        // about 2048 blocks over the batch, at most one per 4 * kTpadRows rows (four waves)
-        // of the instance with the most framed rows
-        int64_t mrows = 1;
-        for (int i = 0; i < n; ++i) {
-            const ph_shape &f = framed_shapes[i];
-            mrows = std::max<int64_t>(mrows, f.ndim == 3 ? (int64_t)f.ext[0] * f.ext[1] : f.ext[0]);
-        }
-        const unsigned pb = (unsigned)std::max<int64_t>(1, std::min<int64_t>((2048 + n - 1) / n, (mrows + 4 * kTpadRows - 1) / (4 * kTpadRows)));
-        if (in_elem == 1) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint8_t>, dim3(pb, n), dim3(256), 0, st, (const uint8_t *)d_imgs, ws, n));
-        else if (in_elem == 2) FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<uint16_t>, dim3(pb, n), dim3(256), 0, st, (const uint16_t *)d_imgs, ws, n));
-        else FC_LAUNCH(K_TPAD, hipLaunchKernelGGL(k_tpad<float>, dim3(pb, n), dim3(256), 0, st, (const float *)d_imgs, ws, n));
-        cimgs = ws;
-    }
     const Luts lut = current_luts();
     if (t2 > 0) {
         if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, cimgs, ws, n, lut, st)));

@@ -12,6 +12,12 @@ F2 ranks of bit-packed Python integers, and implements textbook special cases.
   * ``kruskal_h0``: H0 by sequential Kruskal with the elder rule over all edges.
   * ``dual_union_find_top``: top-dimension pairs by union-find on the dual graph (top cells
     plus one cell at infinity, facets taken in reverse order; paper Sec. 3.1 / Appendix A).
+  * ``product_field`` / ``product_bars``: an image or volume f = max(g_0(i_0), g_1(i_1), ...)
+    of 1D sequences is a product filtration; by the Kuenneth formula over a field its
+    barcode is fixed by the factors' 1D H0 bars: H0 is every combination
+    [max of births, min of deaths) of non-zero length and no higher dimension has a bar
+    (each factor has only H0, and the torsion terms of the max-product are empty).  This
+    gives the value multiset at any size, e.g. for a 2^27-voxel volume.
 """
 from __future__ import annotations
 
@@ -270,4 +276,55 @@ def dual_union_find_top(img, ndim=None, keep_zero=False):
         parent[young] = old
         if keep_zero or cx.f[s] != cx.f[young]:
             out.append((int(s), int(young)))
+    return sorted(out)
+
+
+def bars_1d(g):
+    """H0 bars (birth, death) of a 1D sequence under the V-filtration (an edge enters at the
+    larger of its two values), by union-find with the elder rule; the essential bar last."""
+    g = [float(x) for x in g]
+    n = len(g)
+    parent = list(range(n))
+    born = {}
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    events = [(g[t], 0, t) for t in range(n)] + [(max(g[t], g[t + 1]), 1, t) for t in range(n - 1)]
+    out = []
+    for v, kind, t in sorted(events):
+        if kind == 0:
+            born[t] = (g[t], t)
+            continue
+        a, b = find(t), find(t + 1)
+        if born[a] < born[b]:
+            a, b = b, a                       # a: the younger root, which dies
+        out.append((born[a][0], v))
+        parent[a] = b
+    out.append((born[find(0)][0], float("inf")))
+    return out
+
+
+def product_field(gs):
+    """f[i_0, i_1, ...] = max_k g_k[i_k] as float32 (gs: 2 or 3 sequences, slowest axis first)."""
+    gs = [np.asarray(g, np.float32) for g in gs]
+    f = gs[0].reshape((-1,) + (1,) * (len(gs) - 1))
+    for k, g in enumerate(gs[1:], 1):
+        shape = [1] * len(gs)
+        shape[k] = -1
+        f = np.maximum(f, g.reshape(shape))
+    return np.ascontiguousarray(f, dtype=np.float32)
+
+
+def product_bars(gs):
+    """Sorted (dim, birth, death) multiset of product_field(gs), non-zero persistence only."""
+    out = []
+    for tr in itertools.product(*[bars_1d(g) for g in gs]):
+        b = max(x[0] for x in tr)
+        d = min(x[1] for x in tr)
+        if d > b:
+            out.append((0, b, d))
     return sorted(out)

@@ -88,7 +88,6 @@ void guard_workspace(const void *) {
             {I.o_moe0, 4 * N}, {I.o_death0, 4 * N}, {I.o_ufT, 4 * (T + 1)},
             {I.o_moeT, 4 * (T + 1)}, {I.o_live, 4 * L}, {I.o_live2, 4 * L},
             {I.o_ra, 4 * L}, {I.o_rb, 4 * L}, {I.o_scratch, 8 * SCR}};
-        if (I.tfilt) a.push_back({I.o_gimg, 4 * N});                 // the framed dual image
         if (I.h1 && I.ndim == 3) {                                   // 3D H1
             const int64_t h1arr[][2] = {{I.o_cfg3, 2 * N}, {I.o_kpos, 4 * N}, {I.o_h1b, 4 * F}, {I.o_h1n, 4 * F},
                                         {I.o_piv, 4 * E}, {I.o_first, 4 * E}, {I.o_pool, 4 * I.pool_cap},

@@ -30,6 +30,10 @@ SPECIAL = {"vcc_lo": (106, 1), "vcc_hi": (107, 1), "vcc": (106, 2), "exec_lo": (
 FLOAT_INLINE = {"0.5": 0x3F000000, "-0.5": 0xBF000000, "1.0": 0x3F800000, "-1.0": 0xBF800000,
                 "2.0": 0x40000000, "-2.0": 0xC0000000, "4.0": 0x40800000, "-4.0": 0xC0800000,
                 "0.15915494": 0x3E22F983}
+# Flat addresses in [SHARED_APERTURE, SHARED_APERTURE + 2^32) are LDS.  Code that forms such
+# pointers parses; an access through one is refused (Memory has no allocation there), since
+# flat access to LDS is not emulated.
+SHARED_APERTURE = 0x10000 << 32
 LANE = np.arange(LANES, dtype=np.int64)
 BIT = (np.uint64(1) << np.arange(LANES, dtype=np.uint64))
 
@@ -85,6 +89,8 @@ class Memory:
         if k >= 0:
             base, size, _ = self.regions[k]
             near = " (nearest allocation below: 0x%x, %d bytes, access at +%d)" % (base, size, lo - base)
+        if SHARED_APERTURE <= lo < SHARED_APERTURE + (1 << 32):
+            raise Fault("%s: flat access to LDS (0x%x) is not emulated" % (what, lo))
         raise Fault("%s outside device memory: [0x%x, 0x%x)%s" % (what, lo, hi, near))
 
     def _idx(self, addrs, nbytes, what):
@@ -158,6 +164,9 @@ class Opd:
             return
         if t == "off":
             self.kind = "off"
+            return
+        if t == "src_shared_base":             # base of the flat aperture that maps LDS
+            self.kind, self.val, self.lit = "imm", SHARED_APERTURE, True
             return
         if t in FLOAT_INLINE:
             self.kind, self.val = "imm", FLOAT_INLINE[t]
@@ -272,7 +281,7 @@ def rs64(o: Opd):
         i = o.idx
         return lambda w: w.s[i] | (w.s[i + 1] << 32)
     if o.kind == "imm":
-        c = (o.val & M32) if o.lit else (o.val & M64)
+        c = (o.val & M32) if o.lit and o.val != SHARED_APERTURE else (o.val & M64)
         return lambda w: c
     raise Unsupported("scalar source64 " + o.text)
 
@@ -818,13 +827,16 @@ def _compile_salu(op, O, mods, nxt):
             d(w, _scc_nz(w, r & M32))
             return nxt
         return f
-    if op == "s_min_i32":
+    if op in ("s_min_i32", "s_max_i32", "s_min_u32", "s_max_u32"):
+        signed, take_max = op.endswith("i32"), op.startswith("s_max")
+
         def f(w):
             x, y = ra(w), rb(w)
-            xs = x - (1 << 32) if x >= 1 << 31 else x
-            ys = y - (1 << 32) if y >= 1 << 31 else y
-            w.scc = 1 if xs < ys else 0
-            d(w, x if xs < ys else y)
+            xs = x - (1 << 32) if signed and x >= 1 << 31 else x
+            ys = y - (1 << 32) if signed and y >= 1 << 31 else y
+            first = xs > ys if take_max else xs < ys     # SCC: the first operand was taken
+            w.scc = 1 if first else 0
+            d(w, x if first else y)
             return nxt
         return f
     raise Unsupported(op)
@@ -1058,6 +1070,19 @@ def _sdwa_sel(x, sel, sext):
 
 
 def _compile_sdwa(op, O, mods, nxt):
+    if op == "v_cndmask_b32":
+        # lane-wise select of the two selected source fields by VCC, written whole
+        if mods.get("dst_sel", "DWORD") != "DWORD":
+            raise Unsupported("sdwa dst_sel for " + op)
+        d, a, b = wv(O[0]), r32(O[1]), r32(O[2])
+        s0, s1 = mods.get("src0_sel", "DWORD"), mods.get("src1_sel", "DWORD")
+        x0, x1 = O[1].sext, O[2].sext
+
+        def f(w):
+            m = bools_of(w.s[106] | (w.s[107] << 32))
+            d(w, np.where(m, _sdwa_sel(b(w), s1, x1), _sdwa_sel(a(w), s0, x0)))
+            return nxt
+        return f
     if op.startswith("v_cmp_"):
         # VOPC with operand selects: compare the selected fields, write the lane mask
         _, _, cmpop, ty = op.split("_")
@@ -1369,6 +1394,54 @@ def _compile_ds(op, O, mods, nxt):
             data = vec(da(w))
             srcok = e[idx]
             w.v[di] = np.where(e, np.where(srcok, data[idx], U32(0)), w.v[di])
+            return nxt
+        return f
+    if kind in ("add_rtn_u32", "and_rtn_b32", "or_rtn_b32", "xor_rtn_b32", "cmpst_rtn_b32"):
+        # the old word goes to vdst; cmpst stores data1 where the word equals data0
+        di, va, da = O[0].idx, r32(O[1]), r32(O[2])
+        db = r32(O[3]) if kind == "cmpst_rtn_b32" else None
+
+        def f(w):
+            e = w.exec()
+            lanes = np.nonzero(e)[0]
+            addrs = (vec(va(w)).astype(np.int64) + off) & M32
+            data = vec(da(w))
+            data1 = vec(db(w)) if db is not None else None
+            mem = lds(w, addrs[e], 4, op) if len(lanes) else None
+            out = w.v[di].copy()
+            for l in lanes:                        # lanes in order, one at a time
+                a = int(addrs[l])
+                old = int(mem[a:a + 4].view("<u4")[0])
+                x = int(data[l])
+                if kind == "add_rtn_u32":
+                    new = (old + x) & M32
+                elif kind == "and_rtn_b32":
+                    new = old & x
+                elif kind == "or_rtn_b32":
+                    new = old | x
+                elif kind == "xor_rtn_b32":
+                    new = old ^ x
+                else:
+                    new = int(data1[l]) if old == x else old
+                mem[a:a + 4] = np.array([new], "<u4").view(U8)
+                out[l] = old
+            w.v[di] = out
+            return nxt
+        return f
+    if kind == "min_u64":
+        va, da = r32(O[0]), O[1]
+        di = da.idx
+
+        def f(w):
+            e = w.exec()
+            lanes = np.nonzero(e)[0]
+            addrs = (vec(va(w)).astype(np.int64) + off) & M32
+            mem = lds(w, addrs[e], 8, op) if len(lanes) else None
+            for l in lanes:
+                a = int(addrs[l])
+                old = int(mem[a:a + 8].view("<u8")[0])
+                x = int(w.v[di][l]) | (int(w.v[di + 1][l]) << 32)
+                mem[a:a + 8] = np.array([min(old, x)], "<u8").view(U8)
             return nxt
         return f
     if kind in ("or_b32", "min_i32", "add_u32", "max_i32", "min_u32", "and_b32"):

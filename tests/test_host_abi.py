@@ -49,8 +49,12 @@ def test_invalid_shapes_rejected():
     for bad in [(0, 4), (4, 0), (0, 1, 1), (-1, 3)]:
         assert fc.capacity_bound(bad) == 0
         assert fc.workspace_bytes([bad]) == 0
-    big = (1 << 14, 1 << 13)                           # 2^27 pixels: above the per-instance limit
+    big = (1 << 14, (1 << 13) + 1)                     # above 2^27 pixels: the key's pixel field
     assert fc.capacity_bound(big) == 0
+    assert fc.capacity_bound((512, 512, 512)) == 512 ** 3 + 511 ** 3     # 2^27 voxels: accepted
+    assert fc.capacity_bound((512, 512, 512), "T") == 0                  # framed: 514^3
+    huge = (1 << 30, 1 << 30, 1 << 30)                 # extents whose product overflows 64 bits
+    assert fc.capacity_bound(huge) == 0 and fc.workspace_bytes([huge]) == 0
     with pytest.raises(fc.PHError):
         fc.make_shape((4,))
     assert L.ph_workspace_bytes(None, 1, 3) == 0

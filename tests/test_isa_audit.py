@@ -76,7 +76,12 @@ def test_kernel_descriptors(code_object):
 
 
 def test_no_device_globals(code_object):
+    """The only device variable is the no-allocation entry point's workspace (`scratch`, 64 MiB,
+    reached by its address from hipGetSymbolAddress); the kernels keep no other state."""
     out = subprocess.run([os.path.join(LLVM, "llvm-readelf"), "--dyn-syms", "-S", code_object], check=True,
                          capture_output=True, text=True).stdout
-    objs = [l.split()[-1] for l in out.splitlines() if " OBJECT " in l and ".kd" not in l]
-    assert all(o.startswith("__hip_cuid") for o in objs), objs
+    rows = [l.split() for l in out.splitlines() if " OBJECT " in l and ".kd" not in l]
+    objs = {r[-1]: int(r[2], 0) for r in rows}
+    others = [o for o in objs if not o.startswith("__hip_cuid")]
+    assert others == ["_ZL7scratch"], objs
+    assert objs["_ZL7scratch"] == 64 << 20

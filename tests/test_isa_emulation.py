@@ -152,8 +152,8 @@ def test_integer_inputs(isa):
 
 
 def test_t_filtration(isa):
-    """PH_TFILT: the framed dual image (k_tpad) through the V kernels and back (k_output) gives
-    the oracle's T-filtration pairs, for float32 and uint8 inputs."""
+    """PH_TFILT: the framed dual image (read through the reflection by the classify passes)
+    and back (k_output) gives the oracle's T-filtration pairs, for float32 and uint8 inputs."""
     for shape, sigma in (((30, 26), 2.0), ((9, 8, 11), 1.5)):
         g = S.grf(shape, sigma, 81)
         for img in (g, np.round(g * 7).astype(np.uint8)):

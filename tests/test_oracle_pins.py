@@ -174,6 +174,22 @@ def test_rank_replacement_keeps_indices():
             assert np.array_equal(a[f], b[f])
 
 
+def test_product_fields_follow_kuenneth():
+    """f = max(g_0, g_1[, g_2]) over the axes is a product filtration: its barcode is fixed by
+    the factors' 1D H0 bars (Kuenneth over F2): H0 = every combination [max birth, min death)
+    of non-zero length, no H1 (2D) and no H1, H2 (3D).  Random factors on few levels, so the
+    product is dense in ties; every dimension of the full reduction."""
+    rng = np.random.default_rng(11)
+    for trial in range(24):
+        nd = 2 if trial % 3 == 0 else 3
+        shape = tuple(int(x) for x in rng.integers(2, 11, nd))
+        gs = [rng.integers(0, 5, n).astype(np.float32) / 4 for n in shape]
+        img = _ref.product_field(gs)
+        pr = oracle.diagram(img, dims=range(nd), method=oracle.FULL)
+        got = sorted((int(d), float(b), float(e)) for d, b, e in zip(pr["dim"], pr["birth"], pr["death"]))
+        assert got == _ref.product_bars(gs), (shape, gs)
+
+
 def test_symmetries_keep_value_multiset():
     imgs = [S.levels((5, 4), 3, 11), S.uniform((6, 5), 12), S.levels((3, 3, 4), 3, 13),
             S.uniform((3, 4, 3), 14)]
