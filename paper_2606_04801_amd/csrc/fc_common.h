@@ -195,10 +195,12 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_death0 = take(4 * N);
     I.o_ufT = take(4 * (T + 1));
     I.o_moeT = take(4 * (T + 1));
-    I.o_live = take(4 * L);
-    I.o_live2 = take(4 * L);          // the dual's live edges (it runs beside H0 in volumes)
-    I.o_ra = take(4 * L);
-    I.o_rb = take(4 * L);
+    // live, live2 and ra, rb are two contiguous 8L-byte regions: each is also the merge scratch
+    // of one long sorted list (KEEP squares, node keys: at most L keys each)
+    I.o_live = take(8 * L);
+    I.o_live2 = I.o_live + 4 * L;     // the dual's live edges (it runs beside H0 in volumes)
+    I.o_ra = take(8 * L);
+    I.o_rb = I.o_ra + 4 * L;
     I.o_scratch = take(8 * SCR);
     const bool h1 = I.h1 && I.ndim == 3;
     I.pool_cap = h1 ? kH1PoolPerSquare * F : 0;

@@ -49,8 +49,10 @@ constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same t
 constexpr int32_t kUnset = 0x7FFFFFFF;     // LDS cube slot not yet written
 constexpr int kMaxChase = 1 << 22;         // bound of every pointer walk
 constexpr int kUfThreads = 1024;
-constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS (2 x 20 KiB)
+constexpr int kUfLdsNodes = 5120;          // union-find nodes kept in LDS with their keys (40 KiB + 40 KiB)
 constexpr int kUfLdsEdges = 4096;          // union-find live edges kept in LDS (3 x 16 KiB)
+constexpr int kUfLdsWords = 40880;         // the union-find's LDS (160 KiB less its other shared words), int32
+constexpr int kUfLdsNodesOnly = kUfLdsWords / 2;   // nodes whose par, moe alone fit in LDS
 constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
@@ -942,21 +944,10 @@ __device__ __forceinline__ int block_flag_scan(int flag, int *s_wsum, int *total
 // ======================================================================== sort ====
 // Sort one list per instance ascending.  which: 0 = KEEP edges (in place), 1 = KEEP squares
 // (in place), 2 = H0 node keys copied to a sorted array.  Lists that fit in LDS are sorted
-// there by a bitonic network; longer ones are sorted in LDS-sized chunks and merged in
-// global memory (each element placed by a binary search in the partner run).
-__device__ void bitonic_lds(uint64_t *s, int P) {
-    for (int k = 2; k <= P; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int t = threadIdx.x; t < (P >> 1); t += blockDim.x) {
-                const int a = ((t / j) * 2 * j) + (t % j), b = a + j;
-                const uint64_t x = s[a], y = s[b];
-                const bool up = (a & k) == 0;
-                if ((x > y) == up) { s[a] = y; s[b] = x; }
-            }
-            __syncthreads();
-        }
-    }
-}
+// there by a bitonic network; longer ones are sorted in LDS-sized runs by the same network
+// and the runs merged pairwise in global memory, a tile of outputs at a time through LDS
+// (merge path: each tile's share of the two runs is found by one binary search per tile).
+// Keys are unique (the pixel and code are part of them), so every order is total.
 
 __device__ __forceinline__ uint64_t shfl_xor64(uint64_t x, int m) {
     const uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)x, m, 64);
@@ -1032,39 +1023,81 @@ __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &
         __syncthreads();                         // s, s2 are free for the caller's next sort
         return;
     }
-    // long list: chunks in LDS, then merge passes dst <-> scratch
-    uint64_t *scr = arr<uint64_t>(ws, I.o_scratch);
+    // long list: LDS-sized runs, then merge passes between dst and the list's own scratch
+    uint64_t *scr = arr<uint64_t>(ws, WHICH == 0 ? I.o_scratch : (WHICH == 1 ? I.o_live : I.o_ra));
     for (int base = 0; base < m; base += kSortCap) {
         const int len = (m - base) < kSortCap ? (m - base) : kSortCap;
         int P = 2;
         while (P < len) P <<= 1;
-        for (int t = threadIdx.x; t < P; t += blockDim.x) s[t] = t < len ? src[base + t] : ~0ull;
+        for (int t = threadIdx.x; t < kSortCap; t += blockDim.x) s[t] = t < len ? src[base + t] : ~0ull;
         __syncthreads();
-        bitonic_lds(s, P);
-        for (int t = threadIdx.x; t < len; t += blockDim.x) dst[base + t] = s[t];
+        uint64_t x[4];
+        bitonic_regs(s, s2, P, x);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * (int)threadIdx.x + e < len) dst[base + 4 * threadIdx.x + e] = x[e];
         __syncthreads();
     }
-    uint64_t *a = dst, *b = scr;
+    const uint64_t *a = dst;
+    uint64_t *b = scr;
+    int *s_split = (int *)s2;                        // split points of a batch of tiles
     for (int64_t w = kSortCap; w < m; w <<= 1) {
-        for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
-            const int64_t run = t / w, start = (run & ~1ll) * w;
-            const uint64_t x = a[t];
-            int64_t lo, hi, rank;
-            if ((run & 1) == 0) {                  // element of the left run: count right < x
-                lo = start + w; hi = start + 2 * w < m ? start + 2 * w : m;
-                int64_t L = lo, R = hi;
-                while (L < R) { int64_t M = (L + R) >> 1; if (a[M] < x) L = M + 1; else R = M; }
-                rank = (t - start) + (L - lo);
-            } else {                               // element of the right run: count left < x
-                lo = start; hi = start + w;
-                int64_t L = lo, R = hi;
-                while (L < R) { int64_t M = (L + R) >> 1; if (a[M] < x) L = M + 1; else R = M; }
-                rank = (t - start - w) + (L - lo);
+        const int64_t ntiles = (m + kSortCap - 1) / kSortCap;
+        for (int64_t tb = 0; tb < ntiles; tb += kSortThreads) {
+            const int64_t nb = ntiles - tb < kSortThreads ? ntiles - tb : kSortThreads;
+            // tile k starts at output o = (tb + k) T of its pair [ps, ps + 2w): the number of
+            // left-run keys among the pair's first o - ps outputs (merge path); k = nb too, the
+            // batch's end (used only when the batch's last tile ends inside its pair)
+            for (int k = threadIdx.x; k <= nb; k += blockDim.x) {
+                const int64_t o = (tb + k) * kSortCap, ps = o / (2 * w) * (2 * w);
+                if (o >= m) { s_split[k] = 0; continue; }   // past the list: never read
+                const int64_t la = (m - ps) < w ? (m - ps) : w;
+                const int64_t lb = (m - ps - la) < w ? (m - ps - la) : w;
+                const int64_t d = o - ps;
+                int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a[ps + mid] < a[ps + w + d - 1 - mid]) lo = mid + 1;
+                    else hi = mid;
+                }
+                s_split[k] = (int)lo;
             }
-            b[start + rank] = x;
+            __syncthreads();
+            for (int64_t k = 0; k < nb; ++k) {
+                const int64_t o0 = (tb + k) * kSortCap, ps = o0 / (2 * w) * (2 * w);
+                const int64_t la = (m - ps) < w ? (m - ps) : w;
+                const int64_t lb = (m - ps - la) < w ? (m - ps - la) : w;
+                const int64_t pend = ps + la + lb;
+                const int64_t o1 = o0 + kSortCap < pend ? o0 + kSortCap : pend;
+                const int64_t i0 = s_split[k], j0 = o0 - ps - i0;
+                // the tile's end: the next tile's split inside the same pair, else the pair's end
+                const int64_t i1 = o1 == pend ? la : s_split[k + 1];
+                const int na = (int)(i1 - i0), nt = (int)(o1 - o0), nb2 = nt - na;
+                for (int t = threadIdx.x; t < nt; t += blockDim.x)
+                    s[t] = t < na ? a[ps + i0 + t] : a[ps + w + j0 + (t - na)];
+                __syncthreads();
+                // thread t writes outputs 4t .. 4t + 3 of the tile: its split in LDS, then a
+                // short sequential merge
+                const int d = 4 * (int)threadIdx.x;
+                if (d < nt) {
+                    int lo = d > nb2 ? d - nb2 : 0, hi = d < na ? d : na;
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s[mid] < s[na + d - 1 - mid]) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    int ia = lo, ib = d - lo;
+                    for (int e = 0; e < 4 && d + e < nt; ++e) {
+                        const bool take_a = ib >= nb2 || (ia < na && s[ia] < s[na + ib]);
+                        b[o0 + d + e] = take_a ? s[ia++] : s[na + ib++];
+                    }
+                }
+                __syncthreads();
+            }
         }
-        __syncthreads();
-        uint64_t *tmp = a; a = b; b = tmp;
+        const uint64_t *t = a;
+        a = b;
+        b = (uint64_t *)t;
     }
     if (a != dst)
         for (int64_t t = threadIdx.x; t < m; t += blockDim.x) dst[t] = a[t];
@@ -1072,9 +1105,9 @@ __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &
 }
 
 // The three sorts of every instance in one launch: block (i, w) sorts list w of instance i, so
-// the lists of all instances are sorted side by side.  A list longer than the LDS merges through
-// the instance's one scratch buffer; when any list of the instance is that long, block (i, 0)
-// sorts all three in turn and the other two leave.
+// the lists of all instances are sorted side by side.  A list longer than the LDS merges
+// through scratch of its own: the sort scratch (KEEP edges), the live-edge arrays (KEEP
+// squares) and the root arrays (node keys), which the union-find only uses afterwards.
 __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict__ ws, int n) {
     __shared__ uint64_t s[kSortCap];
     __shared__ uint64_t s2[kSortCap];
@@ -1083,7 +1116,6 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
     const int mE = cnt[CNT_E], mF = cnt[CNT_F], mN = cnt[CNT_M0];
-    const bool serial = mE > kSortCap || mF > kSortCap || mN > kSortCap;
     if (w == 0) {
         sort_list<0>(ws, I, cnt, mE, s, s2);
         if (I.h1 && I.ndim == 3) {
@@ -1096,13 +1128,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
                 if ((t == 0 || key_pix(kE[t - 1]) != wv) && wv < I.N) kpos[wv] = t;
             }
         }
-        if (serial) {
-            sort_list<1>(ws, I, cnt, mF, s, s2);
-            sort_list<2>(ws, I, cnt, mN, s, s2);
-        }
-    } else if (!serial) {
-        if (w == 1) sort_list<1>(ws, I, cnt, mF, s, s2);
-        else sort_list<2>(ws, I, cnt, mN, s, s2);
+    } else if (w == 1) {
+        sort_list<1>(ws, I, cnt, mF, s, s2);
+    } else {
+        sort_list<2>(ws, I, cnt, mN, s, s2);
     }
 }
 
@@ -1266,9 +1295,10 @@ __device__ __forceinline__ void st_node(int32_t *p, int32_t v) {
 
 // The round loop.  GN: the node arrays (par, moe) live in global memory, else in LDS; GL: the
 // live-edge arrays (walk position q, and the current roots A, B of the edge's two ends) live in
-// global memory, else in LDS.  A fired edge is marked by complementing its q; compaction keeps
-// the edges whose ends still lie in different components and moves them down in place.
-template <bool DUAL, bool GN, bool GL>
+// global memory, else in LDS; KG: the node keys are read from global memory, else copied to
+// LDS (s_key).  A fired edge is marked by complementing its q; compaction keeps the edges whose
+// ends still lie in different components and moves them down in place.
+template <bool DUAL, bool GN, bool GL, bool KG = GN>
 __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t *par, int32_t *moe,
                                         int32_t *live, int32_t *A, int32_t *B, uint64_t *s_key, int *s_wsum) {
     const int i = blockIdx.x;
@@ -1280,7 +1310,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     const int32_t *ea = arr<int32_t>(ws, DUAL ? I.o_fa : I.o_ea);
     const int32_t *eb = arr<int32_t>(ws, DUAL ? I.o_fb : I.o_eb);
     const uint64_t *gkey = arr<uint64_t>(ws, DUAL ? I.o_nTkey : I.o_n0key);
-    const uint64_t *nkey = GN ? gkey : s_key;       // node keys, copied to LDS with the nodes
+    const uint64_t *nkey = KG ? gkey : s_key;       // node keys, else copied to LDS with the nodes
     int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
     int32_t *death0 = arr<int32_t>(ws, I.o_death0);
     int32_t *killer = arr<int32_t>(ws, I.o_killer);
@@ -1314,7 +1344,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     for (int x = threadIdx.x; x < M; x += blockDim.x) {
         st_node<GN>(&par[x], x);
         st_node<GN>(&moe[x], kInf);
-        if (!GN) s_key[x] = gkey[x];
+        if (!KG) s_key[x] = gkey[x];
     }
     if (DUAL) { for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1; }
     else {
@@ -1401,13 +1431,13 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
 }
 
 // Instances with at most kUfLdsNodes nodes keep par, moe and the node keys in LDS, and with
-// at most kUfLdsEdges edges their live-edge arrays too; larger ones use the workspace.
-// The H0 and dual union-finds of one volume run side by side: the dual keeps its live edges
-// in the free second live array and its roots in the sort scratch (8 max(L, N) bytes).
+// at most kUfLdsEdges edges their live-edge arrays too; up to kUfLdsNodesOnly nodes keep par
+// and moe in the whole LDS (keys and live edges in the workspace); larger ones use the
+// workspace for everything.  The H0 and dual union-finds of one volume run side by side: the
+// dual keeps its live edges in the free second live array and its roots in the sort scratch
+// (8 max(L, N) bytes).  s_lds: kUfLdsWords int32 words, 8-byte aligned.
 template <bool DUAL>
-__device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_par, int32_t *s_moe,
-                                       int32_t *s_live, int32_t *s_a, int32_t *s_b, uint64_t *s_key,
-                                       int *s_wsum) {
+__device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_lds, int *s_wsum) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1423,23 +1453,28 @@ __device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t 
     int32_t *glive = arr<int32_t>(ws, DUAL ? I.o_live2 : I.o_live);
     int32_t *ga = DUAL ? arr<int32_t>(ws, I.o_scratch) : arr<int32_t>(ws, I.o_ra);
     int32_t *gb = DUAL ? arr<int32_t>(ws, I.o_scratch) + L : arr<int32_t>(ws, I.o_rb);
+    // LDS carve for the small case: par, moe (kUfLdsNodes each), live, A, B (kUfLdsEdges each),
+    // then the node keys (8-byte aligned: the offset is even)
+    int32_t *s_par = s_lds, *s_moe = s_lds + kUfLdsNodes, *s_live = s_lds + 2 * kUfLdsNodes;
+    int32_t *s_a = s_live + kUfLdsEdges, *s_b = s_a + kUfLdsEdges;
+    uint64_t *s_key = (uint64_t *)(s_b + kUfLdsEdges);
+    static_assert((2 * kUfLdsNodes + 3 * kUfLdsEdges) % 2 == 0, "node keys 8-byte aligned");
+    static_assert(2 * kUfLdsNodes + 3 * kUfLdsEdges + 2 * kUfLdsNodes <= kUfLdsWords, "LDS carve");
     if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
     else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_key, s_wsum);
-    else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, s_key, s_wsum);
+    else if (M <= kUfLdsNodesOnly)
+        uf_body<DUAL, false, true, true>(ws, n, s_lds, s_lds + kUfLdsNodesOnly, glive, ga, gb, nullptr, s_wsum);
+    else uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, nullptr, s_wsum);
 }
 
 // Union-find passes, blockIdx.x = instance.  Stage 0: blockIdx.y = 0 H0 of every instance,
 // y = 1 (with the top dimension) the dual of the volumes; stage 1: the dual of the images.
 __global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ ws, int n, int stage, int htop) {
-    __shared__ int32_t s_par[kUfLdsNodes];
-    __shared__ int32_t s_moe[kUfLdsNodes];
-    __shared__ int32_t s_live[kUfLdsEdges], s_a[kUfLdsEdges], s_b[kUfLdsEdges];
-    __shared__ uint64_t s_key[kUfLdsNodes];
+    __shared__ __align__(8) int32_t s_lds[kUfLdsWords];
     __shared__ int s_wsum[kUfThreads / 64];
     const bool vol = ((const Inst *)ws)[blockIdx.x].ndim == 3;
-    if (stage == 0 && blockIdx.y == 0) uf_run<false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
-    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol))
-        uf_run<true>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
+    if (stage == 0 && blockIdx.y == 0) uf_run<false>(ws, n, s_lds, s_wsum);
+    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol)) uf_run<true>(ws, n, s_lds, s_wsum);
 }
 
 // ======================================================================= 3D H1 ====
@@ -1731,6 +1766,7 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
             const uint32_t key = col.head + lane < tail ? s_queue[(col.head + lane) & (SLOTS - 1)] : kH1Empty;
             lds_barrier();
             bool err = false;
+            uint32_t tasks = 0;                          // squares of a claimed entry's partner
             if (key != kH1Empty) {
                 const int h = col.find(key);
                 const uint32_t x = h >= 0 ? col.tab[h] : 0u;
@@ -1745,14 +1781,39 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
                     } else if (cl == 1) {
                         atomicOr(&col.tab[h], kH1Final);
                     } else if (cl == 2) {
-                        // claim the entry, then add its partner's reduced column without it
+                        // claim the entry; its partner's reduced column (without it) is added
+                        // below, one square per lane
                         const uint32_t old = atomicAnd(&col.tab[h], ~kH1Present);
-                        if ((old & kH1Present) && !(old & kH1Final))
-                            for (uint32_t m = cm; m; m &= m - 1)
-                                h1_square(col, img, key >> kCodeBits, __builtin_ctz(m), W, HW, key);
+                        if ((old & kH1Present) && !(old & kH1Final)) tasks = cm;
                     } else {
                         err = true;
                     }
+                }
+            }
+            // the claimed entries' squares, spread over the lanes 64 at a time: square g of the
+            // wave's list belongs to the lane whose exclusive prefix is the largest one <= g
+            const int ntask = __popc(tasks);
+            int off = ntask;                             // inclusive prefix over the lanes
+            for (int d = 1; d < 64; d <<= 1) {
+                const int y = __shfl_up(off, d, 64);
+                if (lane >= d) off += y;
+            }
+            const int total = __shfl(off, 63, 64);
+            off -= ntask;
+            for (int r0 = 0; r0 < total; r0 += 64) {
+                const int g = r0 + lane;
+                int owner = 0;
+                for (int st = 32; st > 0; st >>= 1) {
+                    const int cand = owner + st < 64 ? owner + st : 63;
+                    const int co = __shfl(off, cand, 64);
+                    if (owner + st < 64 && co <= g) owner = cand;
+                }
+                uint32_t m = (uint32_t)__shfl((int)tasks, owner, 64);
+                const uint32_t okey = (uint32_t)__shfl((int)key, owner, 64);
+                const int kth = g - __shfl(off, owner, 64);
+                if (g < total) {
+                    for (int j = 0; j < kth; ++j) m &= m - 1;
+                    h1_square(col, img, okey >> kCodeBits, __builtin_ctz(m), W, HW, okey);
                 }
             }
             col.head = col.head + 64 < tail ? col.head + 64 : tail;

@@ -86,8 +86,8 @@ void guard_workspace(const void *) {
             {I.o_fb, 4 * FAC}, {I.o_killer, 4 * FAC}, {I.o_n0key, 8 * N},
             {I.o_n0sorted, 8 * N}, {I.o_nTkey, 8 * (T + 1)}, {I.o_uf0, 4 * N},
             {I.o_moe0, 4 * N}, {I.o_death0, 4 * N}, {I.o_ufT, 4 * (T + 1)},
-            {I.o_moeT, 4 * (T + 1)}, {I.o_live, 4 * L}, {I.o_live2, 4 * L},
-            {I.o_ra, 4 * L}, {I.o_rb, 4 * L}, {I.o_scratch, 8 * SCR}};
+            {I.o_moeT, 4 * (T + 1)}, {I.o_live, 8 * L}, {I.o_ra, 8 * L},
+            {I.o_scratch, 8 * SCR}};
         if (I.h1 && I.ndim == 3) {                                   // 3D H1
             const int64_t h1arr[][2] = {{I.o_cfg3, 2 * N}, {I.o_kpos, 4 * N}, {I.o_h1b, 4 * F}, {I.o_h1n, 4 * F},
                                         {I.o_piv, 4 * E}, {I.o_first, 4 * E}, {I.o_pool, 4 * I.pool_cap},

@@ -177,6 +177,38 @@ def test_edge_cases(driver):
         assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
 
 
+def test_long_lists_and_large_forests(driver):
+    """Lists past one LDS sort (4096 keys) through several merge passes with ragged runs, and
+    union-finds past the LDS node capacities: uniform noise keeps about a sixth of the edges.
+    200 x 230: ~15k KEEP edges (4 runs), ~9k H0 nodes (par, moe in LDS, keys and live edges in
+    the workspace); 350 x 360: ~40k edges (10 runs, 4 passes), ~26k nodes (all in the
+    workspace); a 26 x 27 x 25 volume: long KEEP-square and node lists side by side."""
+    for img in (S.uniform((200, 230), 21), S.uniform((350, 360), 22), S.uniform((34, 35, 33), 23)):
+        (got, st), = run(driver, [img])[0]
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
+@pytest.mark.parametrize("seed", [3, 4])
+def test_long_lists_random_interleavings(driver, monkeypatch, seed):
+    """The merge passes and the union-find with LDS nodes under random thread interleavings,
+    side by side in one batch."""
+    monkeypatch.setenv("EMU_SHUFFLE", str(seed))
+    imgs = [S.uniform((200, 230), 21), S.uniform((34, 35, 33), 23)]
+    out, _ = run(driver, imgs, mode=1)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
+def test_long_lists_touch_device_memory_only():
+    """Every access of the merge passes (each list with its own scratch) and of the large
+    union-finds lands in a device allocation or LDS (trace build)."""
+    exe = emu_build.build("trace")
+    imgs = [S.uniform((200, 230), 21), S.uniform((34, 35, 33), 23)]
+    out, _ = run(exe, imgs, mode=1)
+    for img, (got, st) in zip(imgs, out):
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
+
+
 def test_capacity_overflow_keeps_true_count(driver):
     img = S.uniform((40, 40), 9)
     ref = oracle.diagram(img)

@@ -3,7 +3,8 @@ the union-find's sequential finish (a staircase row whose H0 merges each wait fo
 before, so the parallel rounds run out: the work counters must show edges finished
 sequentially), long strips along every axis, an all-ties checkerboard, a constant image,
 a 64x64 permutation, a thin volume with few levels, and IEEE special values; the same cases
-batched together, and under the T-filtration."""
+batched together, and under the T-filtration.  Then noise large enough for the sorts' merge
+passes and for every layout of the union-find."""
 import numpy as np
 import pytest
 
@@ -103,3 +104,44 @@ def test_specials_t_filtration_without_plus_inf():
     img = specials()
     img[np.isposinf(img)] = 3.0e38
     assert diff_pairs(single(img, "T"), oracle.diagram(img, filtration="T")) is None
+
+
+# Lists past one LDS sort (4096 keys) and forests past the union-find's LDS capacities, from
+# uniform noise (about a sixth of the edges kept): (KEEP edges, H0 nodes) of each, and which
+# layout the union-find takes (par, moe and keys in LDS up to 5120 nodes; par and moe alone up
+# to 20440; else the workspace).
+LARGE = {
+    "noise_200x230": lambda: S.uniform((200, 230), 21),        # 14k edges, 9k nodes
+    "noise_350x360": lambda: S.uniform((350, 360), 22),        # 39k edges, 25k nodes
+    "noise_34x35x33": lambda: S.uniform((34, 35, 33), 23),     # 13k edges, 8k squares, 6k nodes
+    "noise_1024x1024": lambda: S.uniform((1024, 1024), 25),    # 330k edges: 81 runs, 7 passes
+    "noise_80x80x80": lambda: S.uniform((80, 80, 80), 26),     # long lists of all three kinds
+}
+
+
+@pytest.mark.parametrize("name", sorted(LARGE))
+def test_long_lists_and_large_forests(name):
+    img = LARGE[name]()
+    bt = fc.Batch([img.shape], device=DEV)
+    bt.set_images([torch.from_numpy(img)])
+    print("case", name, flush=True)
+    bt.ph_diagram_batch()
+    (got,) = bt.results()
+    assert diff_pairs(got, oracle.diagram(img)) is None, name
+    wc = bt.work_counters()
+    assert wc[0, 0] > 4096 and wc[0, 2] > 5120, wc[0]
+
+
+def test_long_lists_batched_and_t_filtration():
+    """The large cases side by side in one batch (each list with its own merge scratch), and
+    two of them under the T-filtration."""
+    imgs = [LARGE[k]() for k in ("noise_200x230", "noise_350x360", "noise_34x35x33")]
+    bt = fc.Batch([a.shape for a in imgs], device=DEV)
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+    print("batch of large cases", flush=True)
+    bt.ph_diagram_batch()
+    for a, got in zip(imgs, bt.results()):
+        assert diff_pairs(got, oracle.diagram(a)) is None, a.shape
+    for k in ("noise_350x360", "noise_34x35x33"):
+        img = LARGE[k]()
+        assert diff_pairs(single(img, "T"), oracle.diagram(img, filtration="T")) is None, k

@@ -65,6 +65,14 @@ def test_fields_and_edge_cases(isa):
         assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape
 
 
+def test_long_lists_and_lds_forest(isa):
+    """180 x 180 uniform noise: 10k KEEP edges sorted in three runs and two merge passes, and
+    6.5k H0 nodes, past the keyed LDS capacity, in the union-find's node-only LDS layout."""
+    img = S.uniform((180, 180), 24)
+    got, st, _ = isa.diagram(img)
+    assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None
+
+
 def test_status_words(isa):
     img = S.grf((20, 20), 2.0, 3)
     img[4, 5] = np.nan
