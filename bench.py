@@ -17,7 +17,9 @@ the caches from the step before.  The same instances are also run as:
   batched_fwd            the forward alone;
   batched_fwd_bwd_u8     the instances quantised to 256 levels (floor(256 x)) and read as uint8;
   batched_fwd_bwd_tfilt  the T-filtration (pixels as top cells);
-  batched_fwd_h1         the 64 volumes with their H1 as well (PH_H1).
+  batched_fwd_h1         the 64 volumes with their H1 as well (PH_H1);
+  batched_fwd_bwd_list_fraction  the lists sized to 1/256 of their worst case (a tenth of the
+                         workspace), bit for bit the same pairs and gradient.
 All forms are compared with each other bit for bit, and with the oracle's stored digests
 (tests/golden/digests.json) where they exist, before any timing.
 
@@ -627,6 +629,32 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
                               "how": "C ABI calls per instance on buffers allocated beforehand, no graph"},
     }
     del singles
+    if cuda:
+        torch.cuda.empty_cache()
+
+    # the same step with the lists sized to 1/256 of their worst case (PH_LIST_FRACTION(1)):
+    # a fraction of the workspace, bit for bit the same pairs and gradient
+    log("batched forward + backward, lists at 1/256 of the worst case (graph replay)")
+    lf = fc.PH_H0 | fc.PH_HTOP | fc.PH_LIST_FRACTION(1)
+    b_l = []
+    for _ in range(2):
+        b = fc.Batch(shapes, device=dev, capacities=caps, flags=lf)
+        b.set_images(host)
+        b_l.append(b)
+    manual_step(b_l[0])
+    sync()
+    for i, r in enumerate(b_l[0].results()):
+        if not same_bits(r, res[i]):
+            raise SystemExit("bench: list fraction changes the diagram of instance %d" % i)
+    if not torch.equal(b_l[0].grad, g_manual):
+        raise SystemExit("bench: list fraction changes the gradient")
+    g_l = [capture(lambda b=b: manual_step(b)) for b in b_l]
+    t_l = timed(lambda k: g_l[k % 2]())
+    forms["batched_fwd_bwd_list_fraction"] = {
+        "value": rate(nvox, t_l), "ms": round(t_l * 1e3, 4),
+        "workspace_gb": round(b_l[0].ws_bytes / 1e9, 3), "workspace_gb_worst_case": round(bts[0].ws_bytes / 1e9, 3),
+        "input": "the same instances, PH_LIST_FRACTION(1)"}
+    del b_l, g_l
     if cuda:
         torch.cuda.empty_cache()
 

@@ -37,8 +37,8 @@
  *     PH_ENOMEM for a too-small workspace, PH_EHIP for a failed HIP call).  Errors found
  *     by the kernels are written to the per-instance status word (PH_ENAN for a NaN pixel,
  *     PH_ECAPACITY when the pairs exceed the capacity: the true count is still written and
- *     the first `capacity` pairs in output order are stored, PH_EINTERNAL if a bounded
- *     loop ran out of iterations).
+ *     the first `capacity` pairs in output order are stored, PH_ELISTS when the lists outgrow
+ *     a PH_LIST_FRACTION, PH_EINTERNAL if a bounded loop ran out of iterations).
  *   - Calls that share a workspace must not overlap in time.
  *   - FLASHCUBICAL_TRACE=1 in the environment names every kernel launch on stderr and waits
  *     for it (a debugging aid: it synchronises, so it must not be set during graph capture).
@@ -60,7 +60,8 @@ enum {
     PH_ECAPACITY = -3,
     PH_ENOMEM = -4,
     PH_EHIP = -5,
-    PH_EINTERNAL = -6
+    PH_EINTERNAL = -6,
+    PH_ELISTS = -7
 };
 
 /* flags: which dimensions to report (H0 is always computed; 2D needs it for the top), and the
@@ -104,6 +105,20 @@ enum {
  * run the 3D classify pass on the default tiles under PH_H1. */
 enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16, PH_H1 = 32 };
 
+/* List fraction (flags bits 8-15; not in the paper, a sizing choice).  The workspace holds, per
+ * instance, the lists of cells that survive pruning (KEEP edges, KEEP squares, H0 nodes, dual
+ * nodes) and the sort, union-find and H1 arrays sized by them.  By default every list is sized
+ * for the worst case (every edge kept), which never overflows but costs about 160 B per pixel
+ * for images and 240 B per voxel for volumes.  PH_LIST_FRACTION(k), k = 1..255, sizes each list
+ * to k/256 of its worst case (at least 4096 entries, never more than the worst case); the
+ * per-pixel arrays (forest links) keep their size.  Smooth fields keep well under 1 % of their
+ * cells, so PH_LIST_FRACTION(1) fits them in a tenth of the workspace; noise keeps about a sixth
+ * of the edges.  Pass the same flags to ph_workspace_bytes and to the call.  An instance whose
+ * lists outgrow their capacities gets the status PH_ELISTS and no pairs; ph_work_counters
+ * still reports its true list sizes (KEEP edges, KEEP squares, H0 nodes, dual nodes), from which
+ * a sufficient fraction follows.  Results that fit are bitwise those of the worst-case sizing. */
+#define PH_LIST_FRACTION(k) ((uint32_t)((k) & 0xFF) << 8)
+
 typedef struct {
     int32_t ndim;       /* 2 or 3 */
     int32_t ext[3];     /* extents, slowest first; ext[2] unused when ndim == 2 */
@@ -139,7 +154,8 @@ int64_t ph_capacity_bound(ph_shape shape);
 int64_t ph_capacity_bound_flags(ph_shape shape, uint32_t flags);
 
 /* Workspace bytes needed by a batch of n instances with the given host shapes (also valid
- * for n = 1 and ph_diagram) under the given flags (PH_TFILT adds the framed dual images).
+ * for n = 1 and ph_diagram) under the given flags (PH_TFILT: the framed extents; PH_H1: the
+ * volumes' H1 arrays; PH_LIST_FRACTION(k): the lists at k/256 of their worst case).
  * Returns 0 for invalid shapes. */
 size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags);
 

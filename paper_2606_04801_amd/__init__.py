@@ -25,13 +25,22 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libflashcubical.so")
 
-PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
+PH_OK, PH_EINVAL, PH_ENAN, PH_ECAPACITY, PH_ENOMEM, PH_EHIP, PH_EINTERNAL, PH_ELISTS = 0, -1, -2, -3, -4, -5, -6, -7
 PH_H0, PH_HTOP = 1, 2
 PH_IN_U8, PH_IN_U16 = 4, 8          # input element type (float32 when neither is set)
 PH_TFILT = 16                       # T-filtration: pixels are the top cells (default: V)
 PH_H1 = 32                          # volumes: H1 as well (images: H1 is the top dimension)
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
-                -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded"}
+                -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded",
+                -7: "lists outgrew the list fraction"}
+
+
+def PH_LIST_FRACTION(k: int) -> int:
+    """flags bits sizing the per-instance lists to k/256 of their worst case (C ABI
+    PH_LIST_FRACTION): a smaller workspace; an instance whose lists outgrow it gets PH_ELISTS."""
+    if not 0 <= int(k) <= 255:
+        raise ValueError("list fraction k must be in 0..255")
+    return (int(k) & 0xFF) << 8
 
 PAIR_DTYPE = np.dtype([
     ("dim", np.int8), ("birth", np.float32), ("death", np.float32),
@@ -440,6 +449,13 @@ class Batch:
         bad = np.nonzero(st != PH_OK)[0]
         if len(bad):
             raise PHError(int(st[bad[0]]), "instance %d" % int(bad[0]))
+
+    def result(self, i):
+        """Pairs of instance i (raises if its own status is not PH_OK; the others are not looked at)."""
+        st = int(self.status[i].item())
+        if st != PH_OK:
+            raise PHError(st, "instance %d" % i)
+        return self.pairs.to_numpy(int(self.out_off_h[i]), int(self.counts[i].item()))
 
     def results(self):
         self.check()

@@ -134,6 +134,8 @@ struct Inst {
     int32_t tfilt;             // 1: T-filtration, the grid is the framed dual image (extents + 2),
                                // read from the caller's pixels on the fly (see tf_value)
     int32_t h1;                // 1: a volume whose H1 is computed too (Sec. 4.2 steps 4-5)
+    int32_t lists;             // list capacities in 1/256 of the worst case (0: the worst case)
+    int64_t M0cap, MTcap;      // capacities of the H0 and dual node lists (worst: N, T + 1)
     // byte offsets of the per-instance arrays inside the workspace
     int64_t o_par0, o_parT, o_keyE, o_ea, o_eb, o_neg0, o_keyF, o_fa, o_fb, o_killer;
     int64_t o_n0key, o_n0sorted, o_nTkey, o_uf0, o_moe0, o_death0, o_ufT, o_moeT;
@@ -161,6 +163,15 @@ constexpr int64_t kH1PoolPerSquare = 4;
 
 FC_HD int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
+// Capacity of a list whose worst case is `worst` entries, under a list fraction of k / 256
+// (k = 0: the worst case): at least kListFloor entries, never above the worst case.
+constexpr int64_t kListFloor = 4096;
+FC_HD int64_t list_cap(int64_t worst, int k) {
+    if (k <= 0 || worst <= kListFloor) return worst;
+    const int64_t c = (worst * k + 255) / 256;
+    return c < kListFloor ? kListFloor : (c > worst ? worst : c);
+}
+
 // Unused bytes left after every workspace array (0 in the library; the CPU emulation build of
 // the tests sets it so that a run past the end of an array lands in poisoned memory).
 #ifndef FC_ARRAY_GAP
@@ -169,9 +180,9 @@ FC_HD int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
 
 // Fill the array offsets of one instance starting at byte `at`; returns the end offset.
 FC_HD int64_t layout(Inst &I, int64_t at) {
-    const int64_t N = I.N, T = I.T, E = I.E, F = I.F, FAC = I.FAC;
+    const int64_t N = I.N, T = I.T, E = I.E, F = I.F, FAC = I.FAC, M0 = I.M0cap, MT = I.MTcap;
     const int64_t L = (E > F ? E : F) > 0 ? (E > F ? E : F) : 1;
-    int64_t SCR = L > N ? L : N;
+    int64_t SCR = L > M0 ? L : M0;
     auto take = [&](int64_t bytes) {
         int64_t o = at;
         at = align256(at + (bytes > 0 ? bytes : 1) + FC_ARRAY_GAP);
@@ -187,19 +198,19 @@ FC_HD int64_t layout(Inst &I, int64_t at) {
     I.o_fa = take(4 * FAC);
     I.o_fb = take(4 * FAC);
     I.o_killer = take(4 * FAC);
-    I.o_n0key = take(8 * N);
-    I.o_n0sorted = take(8 * N);
-    I.o_nTkey = take(8 * (T + 1));
-    I.o_uf0 = take(4 * N);
-    I.o_moe0 = take(4 * N);
-    I.o_death0 = take(4 * N);
-    I.o_ufT = take(4 * (T + 1));
-    I.o_moeT = take(4 * (T + 1));
-    // live, live2 and ra, rb are two contiguous 8L-byte regions: each is also the merge scratch
-    // of one long sorted list (KEEP squares, node keys: at most L keys each)
+    I.o_n0key = take(8 * M0);
+    I.o_n0sorted = take(8 * M0);
+    I.o_nTkey = take(8 * MT);
+    I.o_uf0 = take(4 * M0);
+    I.o_moe0 = take(4 * M0);
+    I.o_death0 = take(4 * M0);
+    I.o_ufT = take(4 * MT);
+    I.o_moeT = take(4 * MT);
+    // live, live2 and ra, rb are two contiguous regions: each is also the merge scratch of one
+    // long sorted list (KEEP squares: at most L keys; node keys: at most SCR)
     I.o_live = take(8 * L);
     I.o_live2 = I.o_live + 4 * L;     // the dual's live edges (it runs beside H0 in volumes)
-    I.o_ra = take(8 * L);
+    I.o_ra = take(8 * SCR);
     I.o_rb = I.o_ra + 4 * L;
     I.o_scratch = take(8 * SCR);
     const bool h1 = I.h1 && I.ndim == 3;

@@ -71,12 +71,20 @@ FC_HD int64_t header_bytes(int n) { return off_cnt(n) + align256((int64_t)n * CN
 
 struct Tiles { int tw2, th2, tw3, th3, td3; };
 
-FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
+// lists: the list fraction (k / 256 of the worst case, 0 for the worst case); I.E, I.F and
+// I.FAC are the capacities of the KEEP-edge, KEEP-square and facet lists from then on
+FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl, int lists = 0) {
     I.ndim = s.ndim;
     if (s.ndim == 2) { I.D = 1; I.H = s.ext[0]; I.W = s.ext[1]; }
     else { I.D = s.ext[0]; I.H = s.ext[1]; I.W = s.ext[2]; }
     Geom g = geom(I.ndim, I.D, I.H, I.W);
-    I.N = g.N; I.T = g.T; I.E = g.E; I.F = g.F; I.FAC = g.FAC;
+    I.N = g.N; I.T = g.T;
+    I.lists = lists;
+    I.E = list_cap(g.E, lists);
+    I.F = list_cap(g.F, lists);
+    I.FAC = I.ndim == 2 ? I.E : I.F;                 // the facets the dual walks: KEEP edges / squares
+    I.M0cap = list_cap(g.N, lists);
+    I.MTcap = list_cap(g.T + 1, lists);
     if (s.ndim == 2) {
         I.tx = (I.W + tl.tw2 - 1) / tl.tw2; I.ty = (I.H + tl.th2 - 1) / tl.th2; I.tz = 1;
     } else {
@@ -86,6 +94,9 @@ FC_HD void fill_inst(Inst &I, const ph_shape &s, const Tiles &tl) {
     I.tfilt = 0;
     I.h1 = 0;
 }
+
+// list fraction k of the flags (PH_LIST_FRACTION(k): capacities k / 256 of the worst case)
+inline int list_fraction(uint32_t flags) { return (int)((flags >> 8) & 0xFFu); }
 
 // T-filtration: the framed dual image has one more pixel on each side of every axis
 FC_HD ph_shape framed(ph_shape s) {
@@ -103,7 +114,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
                        const int64_t *__restrict__ d_img_off, const int64_t *__restrict__ d_out_off,
                        int64_t single_cap, Tiles tl, uint8_t *__restrict__ ws,
                        int64_t *__restrict__ d_counts, int32_t *__restrict__ d_status,
-                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes, int tfilt, int h1) {
+                       int64_t want_t2, int64_t want_t3, int64_t ws_bytes, int tfilt, int h1, int lists) {
     __shared__ int64_t s_scan[2][3][kPlanThreads];   // bytes, 2D tiles, 3D tiles (double buffer)
     __shared__ int64_t s_run[3];
     if (blockIdx.x != 0) return;
@@ -124,11 +135,11 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
             ok = (s.ndim == 2 || s.ndim == 3) && s.ext[0] >= 1 && s.ext[1] >= 1 && (s.ndim == 2 || s.ext[2] >= 1);
             if (!ok) s = ph_shape{2, {1, 1, 1}};
             if (tfilt) s = framed(s);
-            fill_inst(I, s, tl);
+            fill_inst(I, s, tl, lists);
             if (I.N > (1ll << kPixBits)) {
                 ok = false;
                 s = ph_shape{2, {1, 1, 1}};
-                fill_inst(I, tfilt ? framed(s) : s, tl);
+                fill_inst(I, tfilt ? framed(s) : s, tl, lists);
             }
             I.tfilt = tfilt;
             I.h1 = h1 && I.ndim == 3;
@@ -185,6 +196,13 @@ __device__ __forceinline__ bool failed(const int32_t *cnt) {
 __device__ __forceinline__ bool block_failed(const int32_t *cnt) {
     return __syncthreads_or(failed(cnt) ? 1 : 0) != 0;
 }
+// The classify passes go on after a list overflow (PH_ELISTS), writing nothing beyond the
+// capacities, so that the list counts they reserve are the instance's true sizes; any other
+// error stops them.
+__device__ __forceinline__ bool block_failed_classify(const int32_t *cnt) {
+    const int e = __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __syncthreads_or(e != 0 && e != PH_ELISTS ? 1 : 0) != 0;
+}
 
 // Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup w runs on XCD w % 8),
 // and each XCD has its own L2.  Tiles are renumbered so that every XCD gets one contiguous run
@@ -228,6 +246,11 @@ __device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + 
 
 __device__ __forceinline__ void set_err(int32_t *cnt, int code) {
     atomicCAS(&cnt[CNT_ERR], 0, code);
+}
+// A list outgrew its capacity: PH_ELISTS under a list fraction, else (the worst case cannot
+// overflow) an internal error
+__device__ __forceinline__ void list_overflow(const Inst &I, int32_t *cnt) {
+    set_err(cnt, I.lists ? PH_ELISTS : PH_EINTERNAL);
 }
 
 // Links inside a classify tile.  A slot holds a final value (a node, a link out of the tile,
@@ -427,7 +450,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed(cnt)) return;
+    if (block_failed_classify(cnt)) return;
     const int H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
@@ -547,7 +570,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
         // H0 forest: link to the other end of the DIRECT edge, or become a node
         if (direct == kNoDirect) {
             int id = id0++;
-            if (id >= I.N) { set_err(cnt, PH_EINTERNAL); id = 0; }
+            if (id >= I.M0cap) { list_overflow(I, cnt); id = 0; }
             sp0[l] = -(id + 1);
             n0key[id] = make_key(kv, pv, 0);
         } else {
@@ -563,7 +586,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
         // KEEP edges -> compact list
         for (uint32_t m = keep; m; m &= m - 1) {
             const int b = __builtin_ctz(m);
-            if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else set_err(cnt, PH_EINTERNAL);
+            if (kb < I.E) keyE[kb] = make_key(kv, pv, 2 + b); else list_overflow(I, cnt);
             ++kb;
         }
         // squares of L(v): ROOT -> dual node, the others -> dual link.  Square q = (y x bits)
@@ -575,7 +598,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
                                    ((gx >= 1 ? 0x5u : 0u) | (gx <= W - 2 ? 0xAu : 0u));
             for (uint32_t m = root & present; m; m &= m - 1) {
                 const int q = __builtin_ctz(m);
-                if (rb > I.T) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                if (rb >= I.MTcap) { list_overflow(I, cnt); rb = 0; }
                 spT[pos0 + quad_slot<PW>(q)] = -(rb + 1);
                 nTkey[rb] = make_key(kv, pv, 11 + q);
                 ++rb;
@@ -624,10 +647,11 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 }
 
 // ================================================================ classify 3D ====
-// 256 threads, at least seven workgroups (28 waves) per compute unit: the register budget
-// (72) costs a few spilled registers, cheaper than losing a wave per SIMD
+// 256 threads, eight workgroups (32 waves, eight per SIMD) per compute unit: the 64-register
+// budget spills a few registers, which costs less than the lost waves (seven per SIMD at 68
+// registers measured 1.5 % slower)
 template <int TW, int TH, int TD, typename T, bool H1 = false>
-__global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
+__global__ __launch_bounds__(256, 8) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
@@ -655,7 +679,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed(cnt)) return;
+    if (block_failed_classify(cnt)) return;
     const int D = I.D, H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
@@ -796,7 +820,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     int rb = s_base[3] + (int)((pre >> 48) & 0xFFFFu);
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
-    const int64_t capN = I.N, capE = I.E, capF = I.F, capT = I.T;
+    const int64_t capN = I.M0cap, capE = I.E, capF = I.F, capT = I.MTcap;
 #pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint64_t e = ev[it];
@@ -815,7 +839,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
 
         if (direct == kNoDirect) {
             int64_t id = id0++;
-            if (id >= capN) { set_err(cnt, PH_EINTERNAL); id = 0; }
+            if (id >= capN) { list_overflow(I, cnt); id = 0; }
             sp0[l] = -(int32_t)(id + 1);
             n0key[id] = make_key(kv, pv, 0);
         } else {
@@ -834,12 +858,12 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         }
         for (uint32_t m = keep; m; m &= m - 1) {
             const int b = __builtin_ctz(m);
-            if (kb < capE) keyE[kb] = make_key(kv, pv, 1 + b); else set_err(cnt, PH_EINTERNAL);
+            if (kb < capE) keyE[kb] = make_key(kv, pv, 1 + b); else list_overflow(I, cnt);
             ++kb;
         }
         for (uint32_t m = keepsq; m; m &= m - 1) {
             const int q = __builtin_ctz(m);
-            if (fb < capF) keyF[fb] = make_key(kv, pv, 7 + q); else set_err(cnt, PH_EINTERNAL);
+            if (fb < capF) keyF[fb] = make_key(kv, pv, 7 + q); else list_overflow(I, cnt);
             ++fb;
         }
         if (present) {
@@ -857,7 +881,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
             // roots are rare, so most waves skip the first)
             for (uint32_t m = root & present; m; m &= m - 1) {
                 const int b = __builtin_ctz(m);
-                if (rb > capT) { set_err(cnt, PH_EINTERNAL); rb = 0; }
+                if (rb >= capT) { list_overflow(I, cnt); rb = 0; }
                 spT[pos0 + oct_slot<PW, PH>(b)] = -(rb + 1);
                 nTkey[rb] = make_key(kv, pv, 19 + b);
                 ++rb;
@@ -1006,7 +1030,7 @@ __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &
                                           uint64_t *s, uint64_t *s2) {
     uint64_t *src = arr<uint64_t>(ws, WHICH == 0 ? I.o_keyE : (WHICH == 1 ? I.o_keyF : I.o_n0key));
     uint64_t *dst = WHICH == 2 ? arr<uint64_t>(ws, I.o_n0sorted) : src;
-    const int64_t cap = WHICH == 0 ? I.E : (WHICH == 1 ? I.F : I.N);
+    const int64_t cap = WHICH == 0 ? I.E : (WHICH == 1 ? I.F : I.M0cap);
     if (m > cap) { if (threadIdx.x == 0) set_err(cnt, PH_EINTERNAL); return; }
     if (m <= 0) return;
     if (m <= kSortCap) {
@@ -1213,7 +1237,7 @@ __device__ __forceinline__ void resolve_facets(uint8_t *__restrict__ ws, int n, 
     if (failed(cnt)) return;
     const bool is2d = I.ndim == 2;
     const int m = is2d ? cnt[CNT_E] : cnt[CNT_F], MT = cnt[CNT_MT];
-    if (m > (is2d ? I.E : I.F) || MT > I.T + 1) { set_err(cnt, PH_EINTERNAL); return; }
+    if (m > (is2d ? I.E : I.F) || MT > I.MTcap) { set_err(cnt, PH_EINTERNAL); return; }
     const uint64_t *key = arr<uint64_t>(ws, is2d ? I.o_keyE : I.o_keyF);
     const int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
     const int32_t *parT = arr<int32_t>(ws, I.o_parT);
@@ -1444,7 +1468,7 @@ __device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t 
     const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
     const int m = DUAL ? (I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
     if (block_failed(cnt)) return;
-    if (M < 1 || M > (DUAL ? I.T + 1 : I.N) || m > (DUAL && I.ndim == 3 ? I.F : I.E)) {
+    if (M < 1 || M > (DUAL ? I.MTcap : I.M0cap) || m > (DUAL && I.ndim == 3 ? I.F : I.E)) {
         if (threadIdx.x == 0) set_err((int32_t *)cnt, PH_EINTERNAL);
         return;
     }
@@ -2479,13 +2503,14 @@ Tiles tiles_of(const ph_tuning *t) {
 }
 
 // total workspace bytes and classify grid sizes for a list of host shapes
-int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3, bool tfilt, bool h1) {
+int64_t plan_host(const ph_shape *h, int n, const Tiles &tl, int64_t *t2, int64_t *t3, bool tfilt, bool h1,
+                  int lists) {
     int64_t at = header_bytes(n);
     *t2 = 0;
     *t3 = 0;
     for (int i = 0; i < n; ++i) {
         Inst I;
-        fill_inst(I, tfilt ? framed(h[i]) : h[i], tl);
+        fill_inst(I, tfilt ? framed(h[i]) : h[i], tl, lists);
         I.tfilt = tfilt;
         I.h1 = h1 && I.ndim == 3;
         if (I.ndim == 2) *t2 += (int64_t)I.tx * I.ty;
@@ -2667,7 +2692,8 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     if (rc != PH_OK) return rc;
     const Tiles tl = tiles_of(tuning);
     int64_t t2, t3;
-    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3, tf, h1);   // frames them itself
+    const int lists = list_fraction(flags);
+    const int64_t need = plan_host(h_shapes, n, tl, &t2, &t3, tf, h1, lists);   // frames them itself
     if ((int64_t)ws_bytes < need) return PH_ENOMEM;
     if (t2 >= (1ll << 31) || t3 >= (1ll << 31)) return PH_EINVAL;
     uint8_t *ws = (uint8_t *)d_ws;
@@ -2691,7 +2717,7 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     } while (0)
     FC_LAUNCH(K_PLAN, hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, n, d_shapes, single, d_img_off, d_out_off,
                                  single_cap, tl, ws, d_counts, d_status, t2, t3, (int64_t)ws_bytes, tf ? 1 : 0,
-                                 h1 ? 1 : 0));
+                                 h1 ? 1 : 0, lists));
     const int64_t ml = max_list(hs, n), mv = max_voxels(hs, n);
     const void *cimgs = d_imgs;                    // what the classify passes read
     const Luts lut = current_luts();
@@ -2795,7 +2821,8 @@ size_t ph_workspace_bytes(const ph_shape *h_shapes, int32_t n, uint32_t flags) {
     for (int a = 0; a < 3; ++a)                      // large enough for every tile choice
         for (int b = 0; b < 3; ++b) {
             ph_tuning t{a, b};
-            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3, tf, (flags & PH_H1) != 0);
+            int64_t need = fc::plan_host(h_shapes, n, fc::tiles_of(&t), &t2, &t3, tf, (flags & PH_H1) != 0,
+                                         fc::list_fraction(flags));
             if (need > best) best = need;
         }
     return (size_t)best;

@@ -258,6 +258,7 @@ def test_bench_flow_against_host_library():
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
     assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd_bwd_manual", "batched_fwd", "per_image_fwd_bwd",
+                                  "batched_fwd_bwd_list_fraction",
                                   "batched_fwd_bwd_u8", "batched_fwd_bwd_tfilt", "batched_fwd_h1", "c1_single",
                                   "c2_single", "c2u8_single", "c3_single", "c4_batch"}
     assert line["parity"]["autograd_eq_manual"] and line["forms"]["batched_fwd_h1"]["h1_columns"] > 0
@@ -300,7 +301,7 @@ def test_gpu_suites_against_host_library():
     env.pop("FC_EMULATE_FULL", None)
     r = subprocess.run([sys.executable, "-m", "pytest", "-q", "-m", "gpu", "-p", "no:cacheprovider",
                         os.path.join(tests, "test_gpu_parity.py"), os.path.join(tests, "test_gpu_full.py"),
-                        os.path.join(tests, "test_gpu_tfilt.py")],
+                        os.path.join(tests, "test_gpu_tfilt.py"), os.path.join(tests, "test_gpu_lists.py")],
                        capture_output=True, text=True, timeout=1200, env=env, cwd=os.path.dirname(tests))
     assert r.returncode == 0, r.stdout[-4000:] + r.stderr[-2000:]
     assert " passed" in r.stdout and " failed" not in r.stdout
