@@ -13,6 +13,7 @@ alternate between two copies of inputs and buffers, so that a step does not find
 the caches from the step before.  The same instances are also run as:
   per_image_fwd_bwd      plain per-image calls of the C ABI (ph_diagram, the loss gradient,
                          ph_backward) on buffers allocated beforehand, one stream, no graph;
+  per_image_fwd_bwd_graph  the same calls captured in one HIP graph (no host launch overhead);
   batched_fwd_bwd_manual the loss gradient computed by hand and ph_backward called directly;
   batched_fwd            the forward alone;
   batched_fwd_bwd_u8     the instances quantised to 256 levels (floor(256 x)) and read as uint8;
@@ -603,6 +604,11 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
     t_f = timed(lambda k: g_f[k % 2]())
     log("per-image plain calls")
     t_p = timed(lambda k: per_image_step(k % 2))
+    # the same per-image calls captured in one graph: what is left of the gap is the batching
+    # itself (one launch of each kernel over all instances), not host launch overhead
+    log("per-image calls in one graph")
+    g_p = [capture(lambda c=c: per_image_step(c)) for c in range(2)]
+    t_pg = timed(lambda k: g_p[k % 2]())
 
     # per-kernel event timing of the headline step (eager, the same launches as the graph)
     prof = profiled(lambda k: autograd_step(bts[k % 2]))
@@ -627,8 +633,10 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
         "batched_fwd": {"value": rate(nvox, t_f), "ms": round(t_f * 1e3, 4)},
         "per_image_fwd_bwd": {"value": rate(nvox, t_p), "ms": round(t_p * 1e3, 4), "hbm_frac": frac(sb, t_p),
                               "how": "C ABI calls per instance on buffers allocated beforehand, no graph"},
+        "per_image_fwd_bwd_graph": {"value": rate(nvox, t_pg), "ms": round(t_pg * 1e3, 4),
+                                    "how": "the same per-instance C ABI calls captured in one graph"},
     }
-    del singles
+    del singles, g_p
     if cuda:
         torch.cuda.empty_cache()
 

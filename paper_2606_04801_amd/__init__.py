@@ -437,12 +437,14 @@ class Batch:
         return np.frombuffer(out, dtype=np.int32).reshape(self.n, 16).copy()
 
     def valid_mask(self):
-        """Device bool mask over the packed pair slots holding a stored pair (no sync)."""
+        """Device bool mask over the packed pair slots holding a stored pair (no sync).  The
+        slot -> (instance, position) map is fixed by the capacities and made once."""
         torch = _torch()
-        idx = torch.arange(self.pairs.cap, device=self.device)
-        inst = torch.searchsorted(self.out_off[1:], idx, right=True)
-        inst = torch.clamp(inst, max=self.n - 1)
-        return (idx - self.out_off[inst]) < self.counts[inst]
+        if getattr(self, "_slot_inst", None) is None:
+            idx = torch.arange(self.pairs.cap, device=self.device)
+            inst = torch.clamp(torch.searchsorted(self.out_off[1:], idx, right=True), max=self.n - 1)
+            self._slot_inst, self._slot_pos = inst, idx - self.out_off[inst]
+        return self._slot_pos < self.counts[self._slot_inst]
 
     def check(self):
         st = self.status.cpu().numpy()

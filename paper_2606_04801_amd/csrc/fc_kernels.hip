@@ -647,11 +647,11 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 }
 
 // ================================================================ classify 3D ====
-// 256 threads, eight workgroups (32 waves, eight per SIMD) per compute unit: the 64-register
-// budget spills a few registers, which costs less than the lost waves (seven per SIMD at 68
-// registers measured 1.5 % slower)
+// 256 threads, seven workgroups (28 waves) per compute unit at 68 registers, without spills.
+// Eight (the 64-register budget) measured up to 1.5 % faster, but its spilled registers added
+// about 45 % to the kernel's HBM traffic (FETCH_SIZE + WRITE_SIZE)
 template <int TW, int TH, int TD, typename T, bool H1 = false>
-__global__ __launch_bounds__(256, 8) void k_classify3d(const T *__restrict__ imgs,
+__global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
@@ -2756,9 +2756,10 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         FC_LAUNCH(K_UF_2D, hipLaunchKernelGGL(k_unionfind, dim3(n), dim3(kUfThreads), 0, st, ws, n, 1, htop));
     }
     if (h1 && any3) {
-        // one 64-thread workgroup per 4096 voxels of the largest volume (at most 1024 per
-        // instance), each taking columns in turn
-        const unsigned hb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(1024, (mv + 4095) / 4096));
+        // one 64-thread workgroup per 512 voxels of the largest volume (at most 8192 per
+        // instance), each taking columns in turn: short-lived workgroups, so the hardware
+        // balances the columns' uneven costs (per 4096 voxels measured 13 % slower)
+        const unsigned hb = (unsigned)std::max<int64_t>(1, std::min<int64_t>(8192, (mv + 511) / 512));
         // pass 1 (64 workgroups per instance) takes the columns pass 0 could not hold
         if (elem == 1) {
             FC_LAUNCH(K_H1MORSE, hipLaunchKernelGGL((k_h1_morse<uint8_t, kH1Slots>), dim3(hb, n), dim3(64), 0, st, (const uint8_t *)cimgs, ws, n, lut, 0));

@@ -258,7 +258,7 @@ def test_bench_flow_against_host_library():
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert line["value"] > 0 and line["roofline"]["kernel"].startswith("k_")
     assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd_bwd_manual", "batched_fwd", "per_image_fwd_bwd",
-                                  "batched_fwd_bwd_list_fraction",
+                                  "batched_fwd_bwd_list_fraction", "per_image_fwd_bwd_graph",
                                   "batched_fwd_bwd_u8", "batched_fwd_bwd_tfilt", "batched_fwd_h1", "c1_single",
                                   "c2_single", "c2u8_single", "c3_single", "c4_batch"}
     assert line["parity"]["autograd_eq_manual"] and line["forms"]["batched_fwd_h1"]["h1_columns"] > 0
