@@ -215,17 +215,23 @@ KERNEL_KEYS = ["k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfi
                "k_zero", "k_scatter"]
 
 
-def profile_steps(steps):
+def profile_steps(steps, h1=False):
+    """K eager batched forward + backward steps (h1: K forwards of the volumes with PH_H1),
+    then the calibration copy."""
     import torch
     import paper_2606_04801_amd as fc
     shapes = workload_shapes()
-    bt = fc.Batch(shapes, device="cuda:0")
-    bt.set_images([torch.from_numpy(a) for a in workload_images()])
+    imgs = workload_images()
+    if h1:
+        shapes, imgs = shapes[:N3], imgs[:N3]
+    bt = fc.Batch(shapes, device="cuda:0", flags=fc.PH_H0 | fc.PH_HTOP | (fc.PH_H1 if h1 else 0))
+    bt.set_images([torch.from_numpy(a) for a in imgs])
     for k in range(steps):
         bt.ph_diagram_batch()
-        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
-        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
-        bt.ph_backward(-2.0 * diff, 2.0 * diff)
+        if not h1:
+            fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+            diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+            bt.ph_backward(-2.0 * diff, 2.0 * diff)
         torch.cuda.synchronize()
         print("bench: profile step %d done" % k, file=sys.stderr, flush=True)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
@@ -392,6 +398,7 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "hbm_traffic.json"),
                     help="HBM bytes per launch from the counter passes (used only for the library build they were taken on)")
     ap.add_argument("--profile-steps", type=int, default=0, help="only run K eager steps and a calibration copy")
+    ap.add_argument("--profile-h1", action="store_true", help="with --profile-steps: the volumes' forward with PH_H1")
     ap.add_argument("--traffic-from", nargs=3, metavar=("FETCH_CSV", "WRITE_CSV", "OUT_JSON"))
     ap.add_argument("--host-library", default=None,
                     help="check this script on the CPU against a host build of the C ABI (small workload)")
@@ -400,7 +407,7 @@ def main():
         traffic_from(*args.traffic_from)
         return
     if args.profile_steps:
-        profile_steps(args.profile_steps)
+        profile_steps(args.profile_steps, args.profile_h1)
         return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the batch would shard by instance "
