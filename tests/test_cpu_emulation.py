@@ -260,7 +260,8 @@ def test_bench_flow_against_host_library():
     assert set(line["forms"]) == {"batched_fwd_bwd", "batched_fwd_bwd_manual", "batched_fwd", "per_image_fwd_bwd",
                                   "batched_fwd_bwd_list_fraction", "per_image_fwd_bwd_graph",
                                   "batched_fwd_bwd_u8", "batched_fwd_bwd_tfilt", "batched_fwd_h1", "c1_single",
-                                  "c2_single", "c2u8_single", "c3_single", "c4_batch"}
+                                  "c2_single", "c2u8_single", "c3_single", "c4_batch",
+                                  "noise_20x20", "noise_40x44", "noise_10x11x12"}
     assert line["parity"]["autograd_eq_manual"] and line["forms"]["batched_fwd_h1"]["h1_columns"] > 0
     assert all(k["bytes"] > 0 for n, k in line["kernels"].items() if n not in ("k_plan",))
     assert line["cpu_baseline"]["kind"] == "oracle" and line["work"]["pairs"] > 0
