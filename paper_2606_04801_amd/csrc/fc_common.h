@@ -60,6 +60,9 @@ FC_HD uint32_t ord32(uint32_t u) {
     if (u == 0x80000000u) u = 0;                   // -0 ranks with +0
     return (u >> 31) ? ~u : (u | 0x80000000u);
 }
+// ord32 of the bits of a float that is not -0: a float plus +0.0 (which turns -0 into +0 and
+// leaves every other value, subnormals and NaNs included, as it was) qualifies
+FC_HD uint32_t ord32_no_neg0(uint32_t u) { return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u); }
 
 FC_HD uint64_t make_key(uint32_t ord, uint32_t pix, uint32_t code) {
     return ((uint64_t)ord << 32) | ((uint64_t)pix << kCodeBits) | code;

@@ -43,6 +43,7 @@ struct Luts {
     const uint64_t *l2;    // kL3Configs entries (3D level 2)
     const uint16_t *h1e;   // 8 per 3D entry: an edge's partner combination (3D H1)
     const uint16_t *h1s;   // 16 per 3D entry: a KEEP square's own combination (3D H1)
+    const uint8_t *pext;   // 256: [mask nibble << 4 | bits nibble] -> compress8(bits, mask)
 };
 
 constexpr int32_t kLocal = 0x40000000;     // LDS link to an entry of the same tile
@@ -196,13 +197,6 @@ __device__ __forceinline__ bool failed(const int32_t *cnt) {
 __device__ __forceinline__ bool block_failed(const int32_t *cnt) {
     return __syncthreads_or(failed(cnt) ? 1 : 0) != 0;
 }
-// The classify passes go on after a list overflow (PH_ELISTS), writing nothing beyond the
-// capacities, so that the list counts they reserve are the instance's true sizes; any other
-// error stops them.
-__device__ __forceinline__ bool block_failed_classify(const int32_t *cnt) {
-    const int e = __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return __syncthreads_or(e != 0 && e != PH_ELISTS ? 1 : 0) != 0;
-}
 
 // Workgroups are dealt to the 8 XCDs of the chip round-robin (workgroup w runs on XCD w % 8),
 // and each XCD has its own L2.  Tiles are renumbered so that every XCD gets one contiguous run
@@ -241,6 +235,19 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// The classify passes go on after a list overflow (PH_ELISTS), writing nothing beyond the
+// capacities, so that the list counts they reserve are the instance's true sizes; any other
+// error stops them.  One thread reads the word and the block takes its answer through LDS
+// (s_flag), so every thread decides alike.  Every thread must call it.
+__device__ __forceinline__ bool block_failed_classify(const int32_t *cnt, int *s_flag) {
+    if (threadIdx.x == 0) {
+        const int e = __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        *s_flag = e != 0 && e != PH_ELISTS;
+    }
+    lds_barrier();
+    return *s_flag != 0;
+}
+
 template <typename T>
 __device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + off); }
 
@@ -260,31 +267,39 @@ __device__ __forceinline__ void list_overflow(const Inst &I, int32_t *cnt) {
 // every local link by its target's value until none is left.
 __device__ __forceinline__ bool is_local(int32_t v) { return v >= kLocal; }
 
-// Offset of octant t = (z y x bits) of the eight cubes around a vertex from the slot of the
-// first (t = 0), in a slot box of rows PW and layers PW * PH.  When every offset fits a byte
-// the eight are picked with one byte permute.
+// Offset of octant t = (z y x bits), t < 8, of the eight cubes around a vertex from the slot
+// of the first (t = 0), in a slot box of rows PW and layers PW * PH.  When every offset fits a
+// byte the eight are picked with one byte permute; t itself is the selector: its upper bytes
+// are zero and pick byte 0 of the low word, the first octant's offset, which is zero.
 template <int PW, int PH>
 __device__ __forceinline__ int oct_slot(uint32_t t) {
     constexpr uint32_t L = PH * PW;
     if constexpr (L + PW + 1 < 256) {
         constexpr uint32_t lo = 0u | 1u << 8 | (uint32_t)PW << 16 | (uint32_t)(PW + 1) << 24;
         constexpr uint32_t hi = L | (L + 1) << 8 | (L + PW) << 16 | (L + PW + 1) << 24;
-        return (int)__builtin_amdgcn_perm(hi, lo, t | 0x0C0C0C00u);
+        return (int)__builtin_amdgcn_perm(hi, lo, t);
     } else {
         return (int)((t >> 2) * L + ((t >> 1) & 1u) * PW + (t & 1u));
     }
 }
 
-// Offset of square q = (y x bits) of the four squares around a vertex from the slot of the
-// first (q = 0), in rows of PW slots; picked with a byte permute when every offset fits a byte.
+// Offset of square q = (y x bits), q < 4, of the four squares around a vertex from the slot of
+// the first (q = 0), in rows of PW slots; picked with a byte permute (q as the selector, as in
+// oct_slot) when every offset fits a byte.
 template <int PW>
 __device__ __forceinline__ int quad_slot(uint32_t q) {
     if constexpr (PW + 1 < 256) {
-        return (int)__builtin_amdgcn_perm(0u, 0u | 1u << 8 | (uint32_t)PW << 16 | (uint32_t)(PW + 1) << 24,
-                                          q | 0x0C0C0C00u);
+        return (int)__builtin_amdgcn_perm(0u, 0u | 1u << 8 | (uint32_t)PW << 16 | (uint32_t)(PW + 1) << 24, q);
     } else {
         return (int)((q >> 1) * PW + (q & 1u));
     }
+}
+
+// link to slot s of the tile when bit t of inimg is set, else -1 (the cell at infinity):
+// kp = kLocal | pos0 with s = pos0 + off; a sign-extended bit field and one bit select
+__device__ __forceinline__ int32_t dual_link(uint32_t inimg, uint32_t t, int32_t kp, int off) {
+    const int32_t m = -(int32_t)((inimg >> t) & 1u);                 // 0 or -1
+    return ((kp + off) & m) | ~m;
 }
 
 // 2 raw + (a < b), or with LE 2 raw + (a <= b), unsigned: the compare sets VCC and an add with
@@ -360,24 +375,30 @@ template <int N0, int NT, int ST>
 __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (&v0)[N0], int32_t (&vT)[NT],
                                            int *s_any, int32_t *cnt) {
     const int tid = threadIdx.x;
+    bool any = true;                                // a thread whose slots are all final stays so
     for (int round = 0; round <= 256 * (N0 + NT); ++round) {
-        bool any = false;
+        if (any) {
+            any = false;
 #pragma unroll
-        for (int k = 0; k < N0; ++k) {
-            if (is_local(v0[k])) {
-                const uint32_t d = (uint32_t)(v0[k] - kLocal), t = d < 256u * N0 - 1u ? d : 256u * N0 - 1u;
-                v0[k] = slot_get(&sp0[t]);
-                slot_put(&sp0[tid + 256 * k], v0[k]);
-                any |= is_local(v0[k]);
+            for (int k = 0; k < N0; ++k) {
+                if (is_local(v0[k])) {
+                    // kLocal | s, s clamped to the last slot; times 4 it wraps to the offset 4 s
+                    const uint32_t u = (uint32_t)v0[k], hi = (uint32_t)kLocal + 256u * N0 - 1u;
+                    const uint32_t t = (u < hi ? u : hi) - (uint32_t)kLocal;
+                    v0[k] = slot_get(&sp0[t]);
+                    slot_put(&sp0[tid + 256 * k], v0[k]);
+                    any |= is_local(v0[k]);
+                }
             }
-        }
 #pragma unroll
-        for (int k = 0; k < NT; ++k) {
-            if (is_local(vT[k])) {
-                const uint32_t d = (uint32_t)(vT[k] - kLocal), t = d < ST * NT - 1u ? d : ST * NT - 1u;
-                vT[k] = slot_get(&spT[t]);
-                slot_put(&spT[tid + ST * k], vT[k]);
-                any |= is_local(vT[k]);
+            for (int k = 0; k < NT; ++k) {
+                if (is_local(vT[k])) {
+                    const uint32_t u = (uint32_t)vT[k], hi = (uint32_t)kLocal + ST * NT - 1u;
+                    const uint32_t t = (u < hi ? u : hi) - (uint32_t)kLocal;
+                    vT[k] = slot_get(&spT[t]);
+                    slot_put(&spT[tid + ST * k], vT[k]);
+                    any |= is_local(vT[k]);
+                }
             }
         }
         if (!block_any(any, s_any, round & 1)) return;
@@ -392,22 +413,27 @@ __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (
 // atomic per non-empty list instead of one per wave and pass.  Returns the thread's
 // exclusive prefix (packed the same way); the lists' first slots are left in s_base.  All
 // threads call it.
-__device__ __forceinline__ uint64_t shfl_up64(uint64_t x, int d) {
-    const uint32_t lo = (uint32_t)__shfl_up((int)(uint32_t)x, d, 64);
-    const uint32_t hi = (uint32_t)__shfl_up((int)(uint32_t)(x >> 32), d, 64);
-    return ((uint64_t)hi << 32) | lo;
+// Inclusive sum of x over the lanes of a wave up to each lane, with data-parallel-primitive
+// moves: sums inside each row of 16 lanes (row shifts by 1, 2, 4 and 8 lanes, a lane shifted in
+// from outside the row reading 0), then the totals carried up (lane 15 of row 0 and 2 added
+// to rows 1 and 3, lane 31 to rows 2 and 3).  All 64 lanes must be active.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
 }
 
 template <int NLIST>
 __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[NLIST], uint64_t packed,
                                                 uint64_t *s_scan, int32_t *s_base) {
     const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    uint64_t x = packed;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint64_t y = shfl_up64(x, off);
-        if (lane >= off) x += y;
-    }
+    // the 16-bit fields never carry: each block total stays below 2^16, so the two 32-bit
+    // halves are summed apart
+    const uint64_t x = (uint64_t)wave_incl_sum((uint32_t)(packed >> 32)) << 32 | wave_incl_sum((uint32_t)packed);
     if (lane == 63) s_scan[wid] = x;
     lds_barrier();
     if (threadIdx.x == 0) {
@@ -442,15 +468,15 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     __shared__ uint64_t s_scan[4];
     __shared__ int32_t s_base[4];
     __shared__ int s_any[8];
-
-
+    __shared__ int2 s_dir[4];
+    __shared__ int s_fail;
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed_classify(cnt)) return;
+    if (block_failed_classify(cnt, &s_fail)) return;
     const int H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
@@ -464,38 +490,51 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
-    // every halo load of the thread is issued before the first is used: the addresses are
-    // clamped into the image and outside pixels replaced afterwards.  Under the T-filtration
-    // the image is the framed dual one, read through the reflection (tf_value).
+    // The halo box is TH + 2 rows of KW keys.  Wave w loads rows w, w + 4, ... in whole
+    // 64-column chunks, so a row's y, its clamp and whether it lies in the image are the same
+    // for the wave; the KW % 64 columns left over are loaded one key per thread.  Every load of
+    // the thread is issued before the first is used: the addresses are clamped into the image
+    // and outside pixels replaced afterwards.  Clamped loads read a pixel of the instance: a
+    // NaN there is one of the instance's own.  Under the T-filtration the image is the framed
+    // dual one, read through the reflection (tf_value).
     auto halo = [&](auto tf) {
         constexpr bool TF = decltype(tf)::value;
-        constexpr int NS = (TH + 2) * KW, NL = (NS + 255) / 256;
-        float f[NL];
+        constexpr int NR = TH + 2, NFC = KW / 64, REM = KW - 64 * NFC;
+        constexpr int ITEMS = NR * NFC, PERW = (ITEMS + 3) / 4;     // (row, chunk) items
+        constexpr int NREM = NR * REM, NLR = (NREM + 255) / 256;   // left-over keys
+        const int sH = H - 2, sW = W - 2;                           // T: the caller's extents
+        const int lane = __lane_id(), w = threadIdx.x >> 6;
+        auto at = [&](int gy, int gx) -> uint32_t {                // clamped source offset
+            return TF ? (uint32_t)(clamp0(sH - gy, sH - 1) * sW + clamp0(sW - gx, sW - 1))
+                      : (uint32_t)(clamp0(gy, H - 1) * W + clamp0(gx, W - 1));
+        };
+        auto put = [&](int idx, float v, int gy, int gx) {
+            if constexpr (TF) v = tf_value(v, gy >= 1 && gy <= H - 2 && gx >= 1 && gx <= W - 2);
+            nan |= v != v;
+            const uint32_t o = ord32_no_neg0(__float_as_uint(v + 0.0f));
+            const bool in = (unsigned)gy < (unsigned)H && (unsigned)gx < (unsigned)W;
+            skey[idx] = in ? (o < kOutside ? o : kOutside - 1u) : kOutside;
+        };
+        float f[PERW > 0 ? PERW : 1], fr[NLR > 0 ? NLR : 1];
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int l = threadIdx.x + 256 * k;
-            const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
-            if constexpr (TF) {
-                const int sH = H - 2, sW = W - 2;       // the caller's extents
-                f[k] = (float)img[(int64_t)clamp0(sH - gy, sH - 1) * sW + clamp0(sW - gx, sW - 1)];
-            } else {
-                f[k] = (float)img[(int64_t)clamp0(gy, H - 1) * W + clamp0(gx, W - 1)];
-            }
+        for (int k = 0; k < PERW; ++k) {
+            const int j = w + 4 * k, r = j / (NFC > 0 ? NFC : 1), ch = j - r * NFC;
+            if (j < ITEMS) f[k] = (float)img[at(y0 - 1 + r, x0 - 1 + ch * 64 + lane)];
         }
 #pragma unroll
-        for (int k = 0; k < NL; ++k) {
-            const int l = threadIdx.x + 256 * k;
-            const int r = l / KW, c = l - r * KW, gy = y0 - 1 + r, gx = x0 - 1 + c;
-            if (l >= NS) break;
-            uint32_t key = kOutside;
-            if (gy >= 0 && gy < H && gx >= 0 && gx < W) {
-                float v = f[k];
-                if constexpr (TF) v = tf_value(v, gy >= 1 && gy <= H - 2 && gx >= 1 && gx <= W - 2);
-                nan |= (v != v);
-                const uint32_t o = ord32(__float_as_uint(v));
-                key = o < kOutside ? o : kOutside - 1u;
-            }
-            skey[l] = key;
+        for (int k = 0; k < NLR; ++k) {
+            const int q = threadIdx.x + 256 * k, r = q / (REM > 0 ? REM : 1), c = 64 * NFC + q - r * REM;
+            if (q < NREM) fr[k] = (float)img[at(y0 - 1 + r, x0 - 1 + c)];
+        }
+#pragma unroll
+        for (int k = 0; k < PERW; ++k) {
+            const int j = w + 4 * k, r = j / (NFC > 0 ? NFC : 1), ch = j - r * NFC;
+            if (j < ITEMS) put(r * KW + ch * 64 + lane, f[k], y0 - 1 + r, x0 - 1 + ch * 64 + lane);
+        }
+#pragma unroll
+        for (int k = 0; k < NLR; ++k) {
+            const int q = threadIdx.x + 256 * k, r = q / (REM > 0 ? REM : 1), c = 64 * NFC + q - r * REM;
+            if (q < NREM) put(r * KW + c, fr[k], y0 - 1 + r, x0 - 1 + c);
         }
     };
     if (I.tfilt) halo(tf_tag<true>{});
@@ -503,14 +542,19 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     // square slots start unset (padding final); after pass 2 the slots no vertex of the tile
     // wrote get their square's global index (see is_local).  s_row[r]: global index of the
     // first square of slot row r (x = x0 - 1) and whether the row lies in the image.
-    for (int p = threadIdx.x; p < 256 * NKT; p += 256) spT[p] = p < NP ? kUnset : 0;
+#pragma unroll
+    for (int k = 0; k < NKT; ++k) spT[threadIdx.x + 256 * k] = threadIdx.x + 256 * k < NP ? kUnset : 0;
     for (int r = threadIdx.x; r < NRT; r += 256) {
         const int sy = y0 - 1 + r;
         s_row[r] = make_int2(sy * (W - 1) + x0 - 1, r <= TH && (unsigned)sy < (unsigned)(H - 1));
     }
-    // every link slot starts final (0 is never followed); slots of vertices outside the
-    // image keep it, so the pointer jumping below never reads an uninitialised slot
-    for (int l = threadIdx.x; l < TH * TW; l += 256) sp0[l] = 0;
+    if (threadIdx.x < 4) {
+        // direct edge 2 + d (d = 0..3: up, left, right, down): the step to the neighbour's slot
+        // in the tile (low word) and to its pixel in the image (high word)
+        const int d = threadIdx.x;
+        s_dir[d] = d == 0 ? make_int2(-TW, -W) : d == 1 ? make_int2(-1, -1) : d == 2 ? make_int2(1, 1)
+                                                                                  : make_int2(TW, W);
+    }
     lds_barrier();
     if (nan) s_nan = 1;
 
@@ -522,7 +566,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     // pass 1: every vertex of the thread through the table; counts of the cells it keeps
     constexpr uint32_t kValid = 1u << 31;           // above every field of a 2D entry
     uint32_t ev[NIT];
-    uint64_t packed = 0;                            // minima | KEEP edges << 16 | ROOT squares << 32
+    uint32_t c_min = 0, c_edge = 0, c_root = 0;     // cells the thread keeps, by list
     // the 3x3 neighbourhood of vertex threadIdx.x + 256 it starts at skey[nb0 + it * kRows * KW]
     static_assert(256 % TW == 0, "a block covers whole tile rows");
     constexpr int kRows = 256 / TW;
@@ -542,24 +586,36 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
             mask = NBEFORE[b] ? shift_in_less<true>(mask, kn, kv) : shift_in_less<false>(mask, kn, kv);
         }
         const uint32_t e = in ? lut.l2d[mask] | kValid : 0u;
-        packed += in ? (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((e >> kL2Keep) & 15u) << 16) |
-                           ((uint64_t)__popc((e >> kL2Root) & 15u) << 32)
-                     : 0;
+        // (an entry outside the image is 0 and counts nothing)
+        c_min += (e & 7u) == kNoDirect ? 1u : 0u;
+        c_edge += __popc((e >> kL2Keep) & 15u);
+        c_root += __popc((e >> kL2Root) & 15u);
         ev[it] = e;
     }
     const int lists[3] = {CNT_M0, CNT_E, CNT_MT};
+    const uint64_t packed = c_min | c_edge << 16 | (uint64_t)c_root << 32;
     const uint64_t pre = block_alloc<3>(cnt, lists, packed, s_scan, s_base);
     int id0 = s_base[0] + (int)(pre & 0xFFFFu);
     int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
     int rb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
 
-    // pass 2: forest links, node keys and compact lists at the reserved slots
+    // pass 2: forest links, node keys and compact lists at the reserved slots.  Vertex
+    // threadIdx.x + 256 it lies at row r0 + it kRows, column c0 of the tile; bit d of out_x:
+    // the direct edge 2 + d leaves the tile sideways
+    const int r0 = threadIdx.x / TW, c0 = threadIdx.x % TW;
+    const uint32_t out_x = (c0 == 0 ? 2u : 0u) | (c0 == TW - 1 ? 4u : 0u);
+    static_assert(NIT >= 2, "the first and last rows of the tile fall to different iterations");
+    const uint32_t out_first = out_x | (r0 == 0 ? 1u : 0u);               // it = 0: r = r0
+    const uint32_t out_last = out_x | (r0 == kRows - 1 ? 8u : 0u);        // it = NIT - 1
 #pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint32_t e = ev[it];
-        if (!(e & kValid)) continue;
         const int l = threadIdx.x + it * 256;
-        const int r = l / TW, c = l - r * TW, gy = y0 + r, gx = x0 + c;
+        if (!(e & kValid)) {                       // outside the image: a final slot value
+            sp0[l] = 0;
+            continue;
+        }
+        const int r = r0 + it * kRows, c = c0, gy = y0 + r, gx = x0 + c;
         const uint32_t kv = skey[(r + 1) * KW + c + 1];
         const uint32_t pv = (uint32_t)(gy * W + gx);
         const uint32_t direct = e & 7u;
@@ -574,14 +630,11 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
             sp0[l] = -(id + 1);
             n0key[id] = make_key(kv, pv, 0);
         } else {
-            const int dy = direct == 0 ? -1 : (direct == 3 ? 1 : 0);
-            const int dx = direct == 1 ? -1 : (direct == 2 ? 1 : 0);
-            const int rr = r + dy, cc = c + dx;
-            if (rr >= 0 && rr < TH && cc >= 0 && cc < TW) {
-                sp0[l] = kLocal | (rr * TW + cc);
-            } else {
-                sp0[l] = (int32_t)((gy + dy) * W + gx + dx);
-            }
+            // a link to the neighbour across the direct edge: its slot, or its pixel when it
+            // lies outside the tile
+            const uint32_t out = it == 0 ? out_first : (it == NIT - 1 ? out_last : out_x);
+            const int2 dd = s_dir[direct];
+            sp0[l] = (out >> direct) & 1u ? (int32_t)pv + dd.y : kLocal | (l + dd.x);
         }
         // KEEP edges -> compact list
         for (uint32_t m = keep; m; m &= m - 1) {
@@ -606,8 +659,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
             for (uint32_t m = present & ~root; m; m &= m - 1) {
                 const int q = __builtin_ctz(m);
                 const uint32_t t = (e >> (kL2Link + 2 * q)) & 3u;
-                spT[pos0 + quad_slot<PW>(q)] = (inimg >> t) & 1u ? kLocal | (pos0 + quad_slot<PW>(t))
-                                                                 : -1;    // the cell at infinity
+                spT[pos0 + quad_slot<PW>(q)] = dual_link(inimg, t, kLocal | pos0, quad_slot<PW>(t));
             }
         }
     }
@@ -647,7 +699,7 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 }
 
 // ================================================================ classify 3D ====
-// 256 threads, seven workgroups (28 waves) per compute unit at 68 registers, without spills.
+// 256 threads, seven workgroups (28 waves) per compute unit at 72 registers, without spills.
 // Eight (the 64-register budget) measured up to 1.5 % faster, but its spilled registers added
 // about 45 % to the kernel's HBM traffic (FETCH_SIZE + WRITE_SIZE)
 template <int TW, int TH, int TD, typename T, bool H1 = false>
@@ -671,15 +723,15 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     __shared__ int s_any[8];
     __shared__ uint8_t s_pext[256];              // [mask nibble << 4 | bits nibble]: compress8 of the two
     __shared__ int2 s_row[NKT * GT];
-
-
+    __shared__ int2 s_dir[6];
+    __shared__ int s_fail;
 
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed_classify(cnt)) return;
+    if (block_failed_classify(cnt, &s_fail)) return;
     const int D = I.D, H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
@@ -697,7 +749,45 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
 
     if (threadIdx.x == 0) s_nan = 0;
     int nan = 0;
-    {
+    constexpr int KP = KH * KW;                    // keys in one layer of the halo box
+    if constexpr (KP <= 256 && 2 * KP > 256) {
+        // One thread per (y, x) of a halo layer, stepping through the KD layers: the layer's
+        // z, its clamp and whether it lies in the volume are the same for the whole block, so
+        // a key costs its load, its order bits and the inside select.  Clamped loads read a
+        // voxel of the instance: a NaN there is one of the instance's own.
+        const int yy = threadIdx.x / KW, c = threadIdx.x - yy * KW;
+        const int gx = x0 - 1 + c, gy = y0 - 1 + yy;
+        auto halo = [&](auto tf) {
+            constexpr bool TF = decltype(tf)::value;
+            const int sD = D - 2, sH = H - 2, sW = W - 2;   // T: the caller's extents
+            const uint32_t off = TF ? (uint32_t)(clamp0(sH - gy, sH - 1) * sW + clamp0(W - 2 - gx, W - 3))
+                                    : (uint32_t)(clamp0(gy, H - 1) * W + clamp0(gx, W - 1));
+            const bool inyx = (unsigned)gx < (unsigned)W && (unsigned)gy < (unsigned)H;
+            const bool inner_yx = gx >= 1 && gx <= W - 2 && gy >= 1 && gy <= H - 2;
+            float f[KD];
+#pragma unroll
+            for (int k = 0; k < KD; ++k) {
+                const int gz = z0 - 1 + k;
+                const uint32_t layer = TF ? (uint32_t)(clamp0(sD - gz, sD - 1) * sH * sW)
+                                          : (uint32_t)(clamp0(gz, D - 1) * (int)HW);
+                f[k] = (float)img[layer + off];
+            }
+#pragma unroll
+            for (int k = 0; k < KD; ++k) {
+                const int gz = z0 - 1 + k;
+                float v = f[k];
+                if constexpr (TF) v = tf_value(v, inner_yx && gz >= 1 && gz <= D - 2);
+                nan |= v != v;
+                const uint32_t o = ord32_no_neg0(__float_as_uint(v + 0.0f));
+                const bool in = inyx && (unsigned)gz < (unsigned)D;
+                skey[threadIdx.x + k * KP] = in ? (o < kOutside ? o : kOutside - 1u) : kOutside;
+            }
+        };
+        if (threadIdx.x < KP) {
+            if (I.tfilt) halo(tf_tag<true>{});
+            else halo(tf_tag<false>{});
+        }
+    } else {
         // The halo box is KD * KH rows of KW keys.  A group of KW consecutive threads loads
         // one row, kGroups rows at a time, so a thread keeps its column and steps its row by a
         // constant.  Every load of the thread is issued before the first is used: addresses
@@ -758,15 +848,22 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         s_row[r] = make_int2(cz * (int)TH1W1 + cy * (W - 1) + x0 - 1,
                              r < NRT && (unsigned)cz < (unsigned)(D - 1) && (unsigned)cy < (unsigned)(H - 1));
     }
-    for (int l = threadIdx.x; l < NV; l += 256) sp0[l] = 0;
-    s_pext[threadIdx.x] = (uint8_t)compress8(threadIdx.x & 15u, threadIdx.x >> 4);
+    s_pext[threadIdx.x] = lut.pext[threadIdx.x];
+    if (threadIdx.x < 6) {
+        // direct edge 1 + d (d = 0..5: -z, -y, -x, +x, +y, +z): the step to the neighbour's
+        // slot in the tile (low word) and to its voxel in the volume (high word)
+        const int d = threadIdx.x, sgn = d < 3 ? -1 : 1, axis = d < 3 ? d : 5 - d;
+        const int sdel = axis == 0 ? TH * TW : (axis == 1 ? TW : 1);
+        const int gdel = axis == 0 ? (int)HW : (axis == 1 ? W : 1);
+        s_dir[d] = make_int2(sgn * sdel, sgn * gdel);
+    }
     lds_barrier();
     if (nan) s_nan = 1;
 
     // pass 1: every vertex of the thread through the table; counts of the cells it keeps
     constexpr uint64_t kValid = 1ull << 63;         // above every field of a 3D entry
     uint64_t ev[NIT];
-    uint64_t packed = 0;              // minima | KEEP edges << 16 | KEEP squares << 32 | ROOT cubes << 48
+    uint32_t c_min = 0, c_edge = 0, c_sq = 0, c_root = 0;   // cells the thread keeps, by list
     bool bad = false;                 // a table index out of range (a corrupted table)
     // the 3x3x3 neighbourhood of vertex threadIdx.x + 256 it starts at skey[nb0 + it * kLayers * KH * KW]
     static_assert(256 % (TH * TW) == 0, "a block covers whole tile layers");
@@ -800,19 +897,21 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         const uint32_t hi = s_pext[(l1 & 0xF0u) | (cb >> 4)];
         const uint32_t idx2 = (l1 >> 8) + lo + (hi << __popc(l1 & 15u));
         const bool ok = idx2 < (uint32_t)kL3Configs;
-        bad |= in && !ok;
+        bad |= !ok;                                    // the entry read instead is refused below
         uint64_t e = lut.l2[ok ? idx2 : 0u];
-        e = in ? ((ok ? e : (uint64_t)kNoDirect) | kValid) : 0;
+        e = in ? e | kValid : 0;
         if (H1 && in)                                  // 3D H1 looks the configurations up again
             arr<uint16_t>(ws, I.o_cfg3)[(uint32_t)gz * (uint32_t)HW + (uint32_t)(gy * W + gx)] = (uint16_t)(ok ? idx2 : 0u);
-        packed += in ? (uint64_t)((e & 7u) == kNoDirect) | ((uint64_t)__popc((uint32_t)(e >> kL3Keep) & 63u) << 16) |
-                           ((uint64_t)__popc((uint32_t)(e >> kL3KeepSq) & 4095u) << 32) |
-                           ((uint64_t)__popc((uint32_t)(e >> kL3Root) & 255u) << 48)
-                     : 0;
+        // (an entry outside the volume is 0 and counts nothing)
+        c_min += (e & 7u) == kNoDirect ? 1u : 0u;
+        c_edge += __popc((uint32_t)(e >> kL3Keep) & 63u);
+        c_sq += __popc((uint32_t)(e >> kL3KeepSq) & 4095u);
+        c_root += __popc((uint32_t)(e >> kL3Root) & 255u);
         ev[it] = e;
     }
     if (bad) set_err(cnt, PH_EINTERNAL);
     const int lists[4] = {CNT_M0, CNT_E, CNT_F, CNT_MT};
+    const uint64_t packed = c_min | c_edge << 16 | (uint64_t)(c_sq | c_root << 16) << 32;
     const uint64_t pre = block_alloc<4>(cnt, lists, packed, s_scan, s_base);
     int id0 = s_base[0] + (int)(pre & 0xFFFFu);
     int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
@@ -821,12 +920,23 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
 
     // pass 2: forest links, node keys and compact lists at the reserved slots
     const int64_t capN = I.M0cap, capE = I.E, capF = I.F, capT = I.MTcap;
+    // vertex threadIdx.x + 256 it lies at (lz0 + it kLayers, ly0, lx0) of the tile; bit d of
+    // out_yx: the direct edge 1 + d along y or x leaves the tile
+    const int lz0 = threadIdx.x / (TH * TW), ly0 = (threadIdx.x / TW) % TH, lx0 = threadIdx.x % TW;
+    const uint32_t out_yx = (ly0 == 0 ? 2u : 0u) | (lx0 == 0 ? 4u : 0u) | (lx0 == TW - 1 ? 8u : 0u) |
+                            (ly0 == TH - 1 ? 16u : 0u);
+    static_assert(NIT >= 2, "the first and last layers of the tile fall to different iterations");
+    const uint32_t out_first = out_yx | (lz0 == 0 ? 1u : 0u);              // it = 0: lz = lz0
+    const uint32_t out_last = out_yx | (lz0 == kLayers - 1 ? 32u : 0u);    // it = NIT - 1
 #pragma unroll 1                                    // rolled: fewer live registers, more waves per SIMD
     for (int it = 0; it < NIT; ++it) {
         const uint64_t e = ev[it];
-        if (!(e & kValid)) continue;
         const int l = threadIdx.x + it * 256;
-        const int lz = l / (TH * TW), lrem = l - lz * TH * TW, ly = lrem / TW, lx = lrem - ly * TW;
+        if (!(e & kValid)) {                       // outside the volume: a final slot value
+            sp0[l] = 0;
+            continue;
+        }
+        const int lz = lz0 + it * kLayers, ly = ly0, lx = lx0;
         const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
         const uint32_t kv = skey[((lz + 1) * KH + ly + 1) * KW + lx + 1];
         const uint32_t pv = (uint32_t)gz * (uint32_t)HW + (uint32_t)(gy * W + gx);   // < 2^27
@@ -843,18 +953,11 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
             sp0[l] = -(int32_t)(id + 1);
             n0key[id] = make_key(kv, pv, 0);
         } else {
-            // edge code 1 + direct: -z, -y, -x, +x, +y, +z
-            const int axis = direct < 3 ? (int)direct : 5 - (int)direct;
-            const int sgn = direct < 3 ? -1 : 1;
-            const int lc = axis == 0 ? lz : (axis == 1 ? ly : lx);
-            const int lim = axis == 0 ? TD : (axis == 1 ? TH : TW);
-            const int sdel = axis == 0 ? TH * TW : (axis == 1 ? TW : 1);
-            const int gdel = axis == 0 ? (int)HW : (axis == 1 ? W : 1);
-            if ((unsigned)(lc + sgn) < (unsigned)lim) {
-                sp0[l] = kLocal | (l + sgn * sdel);
-            } else {
-                sp0[l] = (int32_t)pv + sgn * gdel;
-            }
+            // a link to the neighbour across the direct edge: its slot, or its voxel when it
+            // lies outside the tile
+            const uint32_t out = it == 0 ? out_first : (it == NIT - 1 ? out_last : out_yx);
+            const int2 dd = s_dir[direct];
+            sp0[l] = (out >> direct) & 1u ? (int32_t)pv + dd.y : kLocal | (l + dd.x);
         }
         for (uint32_t m = keep; m; m &= m - 1) {
             const int b = __builtin_ctz(m);
@@ -889,8 +992,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
             for (uint32_t m = present & ~root; m; m &= m - 1) {
                 const int b = __builtin_ctz(m);
                 const uint32_t t = (links >> (3 * b)) & 7u;
-                spT[pos0 + oct_slot<PW, PH>(b)] = (inimg >> t) & 1u ? kLocal | (pos0 + oct_slot<PW, PH>(t))
-                                                                     : -1;   // the cell at infinity
+                spT[pos0 + oct_slot<PW, PH>(b)] = dual_link(inimg, t, kLocal | pos0, oct_slot<PW, PH>(t));
             }
         }
     }
@@ -2463,18 +2565,22 @@ int device_luts() {
     const size_t n2d = sizeof g_h_lut2d, n1 = sizeof(uint32_t) * kL1Size, n2 = sizeof(uint64_t) * kL3Configs;
     const size_t ne = sizeof(uint16_t) * g_h_h1e.size(), ns = sizeof(uint16_t) * g_h_h1s.size();
     const size_t o1 = align256(n2d), o2 = o1 + align256(n1), oe = o2 + align256(n2), os = oe + align256(ne);
+    const size_t op = os + align256(ns);
+    uint8_t h_pext[256];
+    for (uint32_t k = 0; k < 256; ++k) h_pext[k] = (uint8_t)compress8(k & 15u, k >> 4);
     uint8_t *buf = nullptr;
-    if (!hip_ok(hipMalloc((void **)&buf, os + ns), "hipMalloc (tables)")) return PH_EHIP;
+    if (!hip_ok(hipMalloc((void **)&buf, op + sizeof h_pext), "hipMalloc (tables)")) return PH_EHIP;
     if (!hip_ok(hipMemcpy(buf, g_h_lut2d, n2d, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
         !hip_ok(hipMemcpy(buf + o1, g_h_l1.data(), n1, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
         !hip_ok(hipMemcpy(buf + o2, g_h_l2.data(), n2, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
         !hip_ok(hipMemcpy(buf + oe, g_h_h1e.data(), ne, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
-        !hip_ok(hipMemcpy(buf + os, g_h_h1s.data(), ns, hipMemcpyHostToDevice), "hipMemcpy (tables)")) {
+        !hip_ok(hipMemcpy(buf + os, g_h_h1s.data(), ns, hipMemcpyHostToDevice), "hipMemcpy (tables)") ||
+        !hip_ok(hipMemcpy(buf + op, h_pext, sizeof h_pext, hipMemcpyHostToDevice), "hipMemcpy (tables)")) {
         (void)hipFree(buf);
         return PH_EHIP;
     }
     g_dev_lut[dev] = Luts{(const uint32_t *)buf, (const uint32_t *)(buf + o1), (const uint64_t *)(buf + o2),
-                          (const uint16_t *)(buf + oe), (const uint16_t *)(buf + os)};
+                          (const uint16_t *)(buf + oe), (const uint16_t *)(buf + os), buf + op};
     rc = check_kernels(dev, nullptr, 0);
     if (rc != PH_OK) return rc;
     g_dev_ready[dev] = true;

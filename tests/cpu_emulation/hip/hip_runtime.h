@@ -280,6 +280,21 @@ EMU_FN int __shfl_up(int v, int d, int = 64) {
     return (int)emu_read_lane(v, l - d < 0 ? l : l - d);
 }
 EMU_FN int __shfl(int v, int src, int = 64) { return (int)emu_read_lane(v, src & 63); }
+// v_mov_b32_dpp with the controls the kernels use: row_shr:1..15 (0x111..0x11F), row_bcast:15
+// (0x142) and row_bcast:31 (0x143); a lane of a row or bank left out by the masks, or whose
+// source lies outside its row without bound_ctrl, keeps old
+EMU_FN int __builtin_amdgcn_update_dpp(int old, int src, int ctrl, int row_mask, int bank_mask, bool bound_ctrl) {
+    const int l = __lane_id(), row = l >> 4, p = l & 15;
+    int s = -1;
+    if (ctrl >= 0x111 && ctrl <= 0x11F) s = p >= ctrl - 0x110 ? l - (ctrl - 0x110) : -1;
+    else if (ctrl == 0x142) s = row >= 1 ? 16 * row - 1 : -1;
+    else if (ctrl == 0x143) s = row >= 2 ? 31 : -1;
+    else { fprintf(stderr, "emulation: update_dpp control 0x%x not emulated\n", ctrl); abort(); }
+    const int v = (int)emu_read_lane(src, s < 0 ? l : s);     // every lane takes part
+    if (!((row_mask >> row) & 1) || !((bank_mask >> (p >> 2)) & 1)) return old;
+    if (s < 0) return bound_ctrl ? 0 : old;
+    return v;
+}
 EMU_FN int __shfl_xor(int v, int m, int = 64) { return (int)emu_read_lane(v, (__lane_id() ^ m) & 63); }
 EMU_FN unsigned long long __ballot(int pred) {
     EmuBlock *b = emu_block;

@@ -424,6 +424,9 @@ VALU2 = {   # D = f(S0, S1)
     "v_mbcnt_lo_u32_b32": _mbcnt(True),
     "v_mbcnt_hi_u32_b32": _mbcnt(False),
     "v_mul_f32": lambda a, b: bits(f32(a) * f32(b)),
+    "v_add_f32": lambda a, b: bits(f32(a) + f32(b)),      # IEEE, subnormals kept (as the kernels' mode)
+    "v_sub_f32": lambda a, b: bits(f32(a) - f32(b)),
+    "v_subrev_f32": lambda a, b: bits(f32(b) - f32(a)),
     "v_add_u16": lambda a, b: ((vec(a) + vec(b)) & U32(0xFFFF)),
     "v_mul_lo_u16": lambda a, b: (((vec(a) & U32(0xFFFF)) * (vec(b) & U32(0xFFFF))) & U32(0xFFFF)),
     "v_sub_u16": lambda a, b: ((vec(a) - vec(b)) & U32(0xFFFF)),
@@ -1019,6 +1022,11 @@ def _dpp_src(ctrl):
     if ctrl == "row_half_mirror":
         q = LANE % 8
         return LANE - q + (7 - q)
+    if ctrl == "row_bcast:15":                 # lane 15 of the row below (rows 1..3)
+        r = LANE // 16
+        return np.where(r >= 1, 16 * r - 1, -1)
+    if ctrl == "row_bcast:31":                 # lane 31 (rows 2 and 3)
+        return np.where(LANE >= 32, 31, -1)
     if ctrl == "wave_shl:1":
         return np.where(LANE + 1 < 64, LANE + 1, -1)
     if ctrl == "wave_shr:1":
@@ -1032,8 +1040,9 @@ def _compile_dpp(op, O, mods, nxt):
     if len(ctrl) != 1:
         raise Unsupported("dpp controls %s" % mods)
     src = _dpp_src(ctrl[0])
-    if mods.get("row_mask", "0xf") != "0xf" or mods.get("bank_mask", "0xf") != "0xf":
-        raise Unsupported("dpp masks")
+    if mods.get("bank_mask", "0xf") != "0xf":
+        raise Unsupported("dpp bank mask")
+    row_on = ((int(mods.get("row_mask", "0xf"), 16) >> (LANE // 16)) & 1).astype(bool)   # rows written
     bound0 = mods.get("bound_ctrl") in ("1", True, "0")
     d = wv(O[0])
     a = r32(O[1])
@@ -1052,6 +1061,7 @@ def _compile_dpp(op, O, mods, nxt):
         if not bound0:
             keep = ~ok
             r = np.where(keep, w.v[di], r)
+        r = np.where(row_on, r, w.v[di])
         d(w, r)
         return nxt
     return f
