@@ -830,22 +830,28 @@ def config_forms(fc, torch, dev, cfg_inputs, dig, capture, timed, profiled, sync
         # the paper's uniform-noise workloads, forward only (the paper times the diagram), one
         # plain call each; the GPU tests hold noise of these kinds against the oracle (200x230,
         # 350x360, 1024^2, 34x35x33, 80^3)
+        # (PH_WIDE: noise holds about a sixth of its pixels as H0 nodes, so the union-finds of
+        # the 2^20-voxel instances start over the whole GPU; the plain call is timed beside it)
         paper_cpu = {(316, 316): 5.0, (1024, 1024): 9.5, (128, 128, 128): 3.0}
         for k, img in enumerate(cfg_inputs["noise"]):
             label = "noise_" + "x".join(map(str, img.shape))
             log("%s: plain call, forward" % label)
-            s1 = SingleCall(fc, torch, img, dev)
+            wide = fc.PH_H0 | fc.PH_HTOP | fc.PH_WIDE
+            s1 = SingleCall(fc, torch, img, dev, flags=wide)
             s1.forward()
             sync()
             r = s1.results()
-            s2 = SingleCall(fc, torch, img, dev, cap=max(len(r), 1))
+            s2 = SingleCall(fc, torch, img, dev, cap=max(len(r), 1), flags=wide)
             t_f = timed(lambda k: s2.forward(), steps=3)
             prof = profiled(lambda k: s2.forward(), 1)
-            forms[label] = {"value": round(img.size / t_f / 1e6, 3), "ms": round(t_f * 1e3, 4),
+            s3 = SingleCall(fc, torch, img, dev, cap=max(len(r), 1))
+            t_p = timed(lambda k: s3.forward(), steps=3)
+            forms[label] = {"value": round(img.size / t_f / 1e6, 3), "ms": round(t_f * 1e3, 4), "flags": "PH_WIDE",
+                            "ms_without_wide": round(t_p * 1e3, 4),
                             "shape": list(img.shape), "pairs": len(r), "kernels_ms": {n: round(v[1] / v[0], 4) for n, v in prof.items()},
                             "paper_cpu_context_mvox_s": paper_cpu.get(tuple(img.shape)),
                             "context": "the paper's single-threaded CPU rate for this workload (i7-12650H), not a target"}
-            del s1, s2
+            del s1, s2, s3
     if "c4" in cfg_inputs:
         imgs = cfg_inputs["c4"]
         log("config 4: %d images, autotuned tiles, one captured forward" % len(imgs))

@@ -103,7 +103,15 @@ enum {
  * tables), its boundary in critical cells beyond 64 edges, the columns' pool beyond 4 entries
  * per KEEP-square slot) are reported as PH_EINTERNAL.  Volumes
  * run the 3D classify pass on the default tiles under PH_H1. */
-enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16, PH_H1 = 32 };
+enum { PH_H0 = 1, PH_HTOP = 2, PH_IN_U8 = 4, PH_IN_U16 = 8, PH_TFILT = 16, PH_H1 = 32, PH_WIDE = 64 };
+
+/* PH_WIDE (not in the paper, a scheduling choice): the union-finds (H0 and the top dimension)
+ * of an instance of 2^20 or more voxels with more than 20,440 nodes (too many for one
+ * workgroup's LDS) start with 16 of their parallel rounds spread over the whole GPU (two
+ * launches a round), then finish in one workgroup as without the flag.  The pairs are the
+ * same.  It pays for inputs with many critical cells (noise: about a sixth of the pixels are
+ * H0 nodes); a smooth field rarely has that many nodes, and then the extra launches (a few
+ * microseconds each) are spent for nothing. */
 
 /* List fraction (flags bits 8-15; not in the paper, a sizing choice).  The workspace holds, per
  * instance, the lists of cells that survive pruning (KEEP edges, KEEP squares, H0 nodes, dual

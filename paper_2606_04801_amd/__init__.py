@@ -30,6 +30,7 @@ PH_H0, PH_HTOP = 1, 2
 PH_IN_U8, PH_IN_U16 = 4, 8          # input element type (float32 when neither is set)
 PH_TFILT = 16                       # T-filtration: pixels are the top cells (default: V)
 PH_H1 = 32                          # volumes: H1 as well (images: H1 is the top dimension)
+PH_WIDE = 64                        # union-finds of 2^20+ voxel instances with many nodes start over the whole GPU
 STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "NaN in input", -3: "capacity exceeded",
                 -4: "workspace too small", -5: "HIP error", -6: "internal bound exceeded",
                 -7: "lists outgrew the list fraction"}

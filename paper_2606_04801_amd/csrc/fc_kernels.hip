@@ -57,6 +57,10 @@ constexpr int kUfLdsNodesOnly = kUfLdsWords / 2;   // nodes whose par, moe alone
 constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
+constexpr int kWideRounds = 24;            // union-find rounds over many workgroups (PH_WIDE)
+constexpr int64_t kWideVoxels = 1 << 20;   // ... for instances of this many voxels
+constexpr int kWideBlocks = 2048, kWideThreads = 256;
+constexpr int32_t kFired = 1 << 30;        // wide rounds: an edge fired this round (above every node index)
 constexpr int32_t kInf = 0x7FFFFFFF;
 constexpr int kMaxInstances = 65535;       // instances of one call: the y extent of a grid
 // Halo key of a pixel outside the image.  Pixel keys are capped one below it (only the NaN bit
@@ -1127,6 +1131,11 @@ __device__ void bitonic_regs(uint64_t *s, uint64_t *s2, int P, uint64_t (&x)[4])
 // code: with the list chosen by a run-time argument, the gfx950 build of an earlier sort kernel
 // took the node-key branch without setting the scalar register pair that holds the count's
 // address, and loaded the count from near address 0.  The caller loads every count first.
+// a list the wide sort kernels take under PH_WIDE (k_sort_runs, k_sort_merge)
+__device__ __forceinline__ bool sort_is_wide(const Inst &I, int m) {
+    return I.N >= kWideVoxels && m > kSortCap && !I.h1;
+}
+
 template <int WHICH>
 __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &I, int32_t *cnt, int m,
                                           uint64_t *s, uint64_t *s2) {
@@ -1234,7 +1243,9 @@ __device__ __forceinline__ void sort_list(uint8_t *__restrict__ ws, const Inst &
 // the lists of all instances are sorted side by side.  A list longer than the LDS merges
 // through scratch of its own: the sort scratch (KEEP edges), the live-edge arrays (KEEP
 // squares) and the root arrays (node keys), which the union-find only uses afterwards.
-__global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict__ ws, int n) {
+// wide: the call sorts long lists with k_sort_runs and k_sort_merge (sort_is_wide), which this
+// launch leaves to them.
+__global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict__ ws, int n, int wide) {
     __shared__ uint64_t s[kSortCap];
     __shared__ uint64_t s2[kSortCap];
     const int i = blockIdx.x, w = blockIdx.y;
@@ -1242,6 +1253,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
     const int mE = cnt[CNT_E], mF = cnt[CNT_F], mN = cnt[CNT_M0];
+    if (wide) {                                  // (an oversized count stays sort_list's error)
+        const int m = w == 0 ? mE : (w == 1 ? mF : mN);
+        if (sort_is_wide(I, m) && m <= (w == 0 ? I.E : (w == 1 ? I.F : I.M0cap))) return;
+    }
     if (w == 0) {
         sort_list<0>(ws, I, cnt, mE, s, s2);
         if (I.h1 && I.ndim == 3) {
@@ -1258,6 +1273,130 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
         sort_list<1>(ws, I, cnt, mF, s, s2);
     } else {
         sort_list<2>(ws, I, cnt, mN, s, s2);
+    }
+}
+
+// ------------------------------------------------------------------ wide sort --
+// Under PH_WIDE a list longer than kSortCap keys of an instance of kWideVoxels or more voxels
+// (not under PH_H1) is sorted by the whole GPU: k_sort_runs sorts each of its kSortCap-key runs
+// in a workgroup of its own, then pass p of k_sort_merge merges the pairs of runs of
+// kSortCap << p keys, one workgroup an output tile of kSortCap keys (the merge-path tiles of
+// sort_list), from the list's output to its scratch on even passes and back on odd ones.
+// The first pass with nothing to merge copies a result left in the scratch back.  Grids
+// (blocks, n, 3): blockIdx.z = the list (KEEP edges, KEEP squares, H0 node keys).
+struct SortLists {
+    uint64_t *src, *dst, *scr;
+    int64_t cap;
+    int m;
+};
+__device__ __forceinline__ SortLists sort_lists_of(uint8_t *__restrict__ ws, const Inst &I, const int32_t *cnt, int w) {
+    SortLists L;
+    L.src = arr<uint64_t>(ws, w == 0 ? I.o_keyE : (w == 1 ? I.o_keyF : I.o_n0key));
+    L.dst = w == 2 ? arr<uint64_t>(ws, I.o_n0sorted) : L.src;
+    L.scr = arr<uint64_t>(ws, w == 0 ? I.o_scratch : (w == 1 ? I.o_live : I.o_ra));
+    L.cap = w == 0 ? I.E : (w == 1 ? I.F : I.M0cap);
+    L.m = cnt[w == 0 ? CNT_E : (w == 1 ? CNT_F : CNT_M0)];
+    return L;
+}
+
+// the list this block works on, or m = 0 (s_flag: the instance failed earlier)
+__device__ __forceinline__ SortLists sort_wide_list(uint8_t *__restrict__ ws, int n, int *s_flag) {
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (threadIdx.x == 0) *s_flag = failed(cnt);
+    __syncthreads();
+    SortLists L = sort_lists_of(ws, I, cnt, blockIdx.z);
+    if (*s_flag || !sort_is_wide(I, L.m) || L.m > L.cap) L.m = 0;   // (an oversized count: k_sort_lists reports it)
+    return L;
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_runs(uint8_t *__restrict__ ws, int n) {
+    __shared__ uint64_t s[kSortCap];
+    __shared__ uint64_t s2[kSortCap];
+    __shared__ int s_flag;
+    const SortLists L = sort_wide_list(ws, n, &s_flag);
+    const int m = L.m;
+    for (int64_t base = (int64_t)blockIdx.x * kSortCap; base < m; base += (int64_t)gridDim.x * kSortCap) {
+        const int len = (int)((m - base) < kSortCap ? (m - base) : kSortCap);
+        int P = 2;
+        while (P < len) P <<= 1;
+        for (int t = threadIdx.x; t < kSortCap; t += blockDim.x) s[t] = t < len ? L.src[base + t] : ~0ull;
+        __syncthreads();
+        uint64_t x[4];
+        bitonic_regs(s, s2, P, x);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            if (4 * (int)threadIdx.x + e < len) L.dst[base + 4 * threadIdx.x + e] = x[e];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(kSortThreads) void k_sort_merge(uint8_t *__restrict__ ws, int n, int pass) {
+    __shared__ uint64_t s[kSortCap];
+    __shared__ int64_t s_split[2];
+    __shared__ int s_flag;
+    const SortLists L = sort_wide_list(ws, n, &s_flag);
+    const int64_t m = L.m;
+    if (m == 0) return;
+    int np = 0;                                  // merge passes the list needs
+    while (((int64_t)kSortCap << np) < m) ++np;
+    if (pass >= np) {
+        if (pass == np && (np & 1))             // the last merge wrote the scratch
+            for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+                L.dst[t] = L.scr[t];
+        return;
+    }
+    const int64_t w = (int64_t)kSortCap << pass;
+    const uint64_t *a = pass & 1 ? L.scr : L.dst;
+    uint64_t *b = pass & 1 ? L.dst : L.scr;
+    const int64_t ntiles = (m + kSortCap - 1) / kSortCap;
+    for (int64_t k = blockIdx.x; k < ntiles; k += gridDim.x) {
+        // tile k: outputs [o0, o1) of its pair [ps, ps + la + lb); its first and last splits
+        // (left-run keys among the pair's first o - ps outputs, by merge path)
+        const int64_t o0 = k * kSortCap, ps = o0 / (2 * w) * (2 * w);
+        const int64_t la = (m - ps) < w ? (m - ps) : w;
+        const int64_t lb = (m - ps - la) < w ? (m - ps - la) : w;
+        const int64_t pend = ps + la + lb;
+        const int64_t o1 = o0 + kSortCap < pend ? o0 + kSortCap : pend;
+        if (threadIdx.x < 2) {
+            const int64_t o = threadIdx.x == 0 ? o0 : o1;
+            int64_t split = la;
+            if (o < pend) {
+                const int64_t d = o - ps;
+                int64_t lo = d > lb ? d - lb : 0, hi = d < la ? d : la;
+                while (lo < hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    if (a[ps + mid] < a[ps + w + d - 1 - mid]) lo = mid + 1;
+                    else hi = mid;
+                }
+                split = lo;
+            }
+            s_split[threadIdx.x] = split;
+        }
+        __syncthreads();
+        const int64_t i0 = s_split[0], j0 = o0 - ps - i0;
+        const int na = (int)(s_split[1] - i0), nt = (int)(o1 - o0), nb2 = nt - na;
+        for (int t = threadIdx.x; t < nt; t += blockDim.x)
+            s[t] = t < na ? a[ps + i0 + t] : a[ps + w + j0 + (t - na)];
+        __syncthreads();
+        // thread t writes outputs 4t .. 4t + 3 of the tile: its split in LDS, then a short
+        // sequential merge
+        const int d = 4 * (int)threadIdx.x;
+        if (d < nt) {
+            int lo = d > nb2 ? d - nb2 : 0, hi = d < na ? d : na;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (s[mid] < s[na + d - 1 - mid]) lo = mid + 1;
+                else hi = mid;
+            }
+            int ia = lo, ib = d - lo;
+            for (int e = 0; e < 4 && d + e < nt; ++e) {
+                const bool take_a = ib >= nb2 || (ia < na && s[ia] < s[na + ib]);
+                b[o0 + d + e] = take_a ? s[ia++] : s[na + ib++];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -1424,9 +1563,13 @@ __device__ __forceinline__ void st_node(int32_t *p, int32_t v) {
 // global memory, else in LDS; KG: the node keys are read from global memory, else copied to
 // LDS (s_key).  A fired edge is marked by complementing its q; compaction keeps the edges whose
 // ends still lie in different components and moves them down in place.
+// cont (global arrays only): the instance went through the wide rounds (k_uf_wide): par,
+// the deaths and the killers hold their state, and A[q], B[q] each edge's roots there (A[q] < 0:
+// done); the rounds go on from it.
 template <bool DUAL, bool GN, bool GL, bool KG = GN>
 __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t *par, int32_t *moe,
-                                        int32_t *live, int32_t *A, int32_t *B, uint64_t *s_key, int *s_wsum) {
+                                        int32_t *live, int32_t *A, int32_t *B, uint64_t *s_key, int *s_wsum,
+                                        bool cont = false) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1468,23 +1611,30 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     };
 
     for (int x = threadIdx.x; x < M; x += blockDim.x) {
-        st_node<GN>(&par[x], x);
+        if (!cont) st_node<GN>(&par[x], x);
         st_node<GN>(&moe[x], kInf);
         if (!KG) s_key[x] = gkey[x];
     }
-    if (DUAL) { for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1; }
-    else {
+    if (cont) {
+    } else if (DUAL) {
+        for (int r = threadIdx.x; r < m; r += blockDim.x) killer[r] = -1;
+    } else {
         for (int r = threadIdx.x; r < m; r += blockDim.x) neg0[r] = 0;
         for (int x = threadIdx.x; x < M; x += blockDim.x) death0[x] = -1;
     }
     __syncthreads();                                // the init stores land before any round's
 
-    // live list: walk positions q whose edge joins two different nodes
+    // live list: walk positions q whose edge joins two different nodes (after the wide
+    // rounds: whose edge is not done; compacted in place)
     int L = 0;
     for (int base = 0; base < m; base += blockDim.x) {
         const int q = base + threadIdx.x;
         int flag = 0, a = 0, b = 0;
-        if (q < m) {
+        if (q < m && cont) {
+            a = A[q];
+            b = B[q];
+            flag = a >= 0 && !(a & kFired);
+        } else if (q < m) {
             const int r = edge_of(q);
             a = ea[r];
             b = eb[r];
@@ -1544,7 +1694,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
         L = L2;
     }
     if (threadIdx.x == 0) {
-        cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] = round;
+        cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] = round + (cont ? cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] : 0);
         if (L > 0) cnt[CNT_SEQ] += L;
         for (int t = 0; t < L; ++t) {               // sequential finish, walk order
             const int q = live[t];
@@ -1556,6 +1706,170 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
     }
 }
 
+// ------------------------------------------------------------- wide union-find --
+// Under PH_WIDE an instance of kWideVoxels or more voxels with more nodes than one
+// workgroup's LDS holds (kUfLdsNodesOnly) first runs up to kWideRounds of the rounds above
+// spread over kWideBlocks workgroups, one phase a launch; k_unionfind then goes on from there
+// in one workgroup (uf_body with cont) if edges are left.  Phase 0 of round r counts the
+// edges it finds live (CNT_WLIVE0 / CNT_WLIVET + r % 2, one atomic a workgroup); a round that
+// finds none ends the work, and the later launches return at once.  An edge keeps its walk position q: A[q], B[q] hold its two
+// roots; A[q] = -1 once it is done (both ends in one component), A[q] | kFired in the round it
+// fires.  Round r lowers moe_r, one of two node arrays taken in turn (moe, and the live-edge
+// array the continuation fills later), to the edges' q.  Phase 0 of round r first restores to
+// kInf the entries of the other array that round r - 1 lowered (the two roots each edge still
+// names), then finds each live edge's roots and lowers theirs; phase 1 fires each root whose
+// minimum edge reaches an elder root.  These are the rounds of uf_body, taken by the whole grid.
+__device__ __forceinline__ bool uf_is_wide(const Inst &I, int M, int m) {
+    const int64_t L = I.E > I.F ? I.E : I.F;      // the second node array is a live-edge array
+    return I.N >= kWideVoxels && M > kUfLdsNodesOnly && M <= L;
+}
+
+// phase -1: initialise; 0, 1: the two phases of round `round`.  Grid (kWideBlocks, n, side)
+template <bool DUAL>
+__device__ __forceinline__ void uf_wide(uint8_t *__restrict__ ws, int n, int phase, int round, int *s_flag) {
+    const int i = blockIdx.y;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
+    const int m = DUAL ? (I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
+    if (threadIdx.x == 0) *s_flag = failed(cnt);
+    lds_barrier();
+    if (*s_flag || !uf_is_wide(I, M, m)) return;
+    if (M > (DUAL ? I.MTcap : I.M0cap) || m > (DUAL && I.ndim == 3 ? I.F : I.E)) {
+        if (threadIdx.x == 0 && blockIdx.x == 0 && phase < 0) set_err(cnt, PH_EINTERNAL);
+        return;
+    }
+    // wlive[r % 2]: nonzero when round r found a live edge.  Phase 1 of round r clears the
+    // other slot for round r + 1 (phase 0 of round r read it last); a round that found none
+    // leaves both at 0, so every later launch returns here.  One thread of a workgroup reads
+    // the flags (a word every workgroup reads at once is a hot spot).
+    int32_t *wlive = cnt + (DUAL ? CNT_WLIVET : CNT_WLIVE0);
+    const int t0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (phase >= 0) {
+        if (phase == 1 && t0 == 0) __hip_atomic_store(&wlive[(round + 1) & 1], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();                             // every thread has read s_flag[0]
+        if (threadIdx.x == 0) {
+            const int slot = phase == 0 ? (round - 1) & 1 : round & 1;
+            s_flag[0] = (phase == 0 && round == 0) ||
+                        __hip_atomic_load(&wlive[slot], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        }
+        __syncthreads();
+        if (!s_flag[0]) return;
+    }
+    int32_t *par = arr<int32_t>(ws, DUAL ? I.o_ufT : I.o_uf0);
+    int32_t *moe_even = arr<int32_t>(ws, DUAL ? I.o_moeT : I.o_moe0);
+    int32_t *moe_odd = arr<int32_t>(ws, DUAL ? I.o_live2 : I.o_live);
+    int32_t *cur = round & 1 ? moe_odd : moe_even, *prev = round & 1 ? moe_even : moe_odd;
+    const int64_t L = I.E > I.F ? I.E : I.F;
+    int32_t *A = DUAL ? arr<int32_t>(ws, I.o_scratch) : arr<int32_t>(ws, I.o_ra);
+    int32_t *B = DUAL ? arr<int32_t>(ws, I.o_scratch) + L : arr<int32_t>(ws, I.o_rb);
+    const uint64_t *nkey = arr<uint64_t>(ws, DUAL ? I.o_nTkey : I.o_n0key);
+    int32_t *neg0 = arr<int32_t>(ws, I.o_neg0);
+    int32_t *death0 = arr<int32_t>(ws, I.o_death0);
+    int32_t *killer = arr<int32_t>(ws, I.o_killer);
+    const int stride = gridDim.x * blockDim.x;
+    auto edge_of = [&](int q) { return DUAL ? m - 1 - q : q; };
+    if (phase < 0) {
+        const int32_t *ea = arr<int32_t>(ws, DUAL ? I.o_fa : I.o_ea);
+        const int32_t *eb = arr<int32_t>(ws, DUAL ? I.o_fb : I.o_eb);
+        if (t0 < 2) wlive[t0] = 0;
+        if (t0 == 0) cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0] = 0;
+        for (int x = t0; x < M; x += stride) {
+            par[x] = x;
+            moe_even[x] = kInf;
+            moe_odd[x] = kInf;
+            if (!DUAL) death0[x] = -1;
+        }
+        for (int q = t0; q < m; q += stride) {
+            const int r = edge_of(q), a = ea[r], b = eb[r];
+            const bool ok = a >= 0 && b >= 0 && a < M && b < M && a != b;
+            A[q] = ok ? a : -1;
+            B[q] = b;
+            if (DUAL) killer[r] = -1;
+            else neg0[r] = 0;
+        }
+        return;
+    }
+    auto elder = [&](int x, int y) -> bool {
+        if (DUAL) return x == 0 || (y != 0 && nkey[x] > nkey[y]);
+        return nkey[x] < nkey[y];
+    };
+    auto find = [&](int x) -> int {
+        for (int it = 0; it < kMaxChase; ++it) {
+            const int p = ld_node<true>(&par[x]);
+            if (p == x) return x;
+            const int g = ld_node<true>(&par[p]);
+            if (g != p) st_node<true>(&par[x], g);     // path halving (any ancestor is valid)
+            x = g;
+        }
+        set_err(cnt, PH_EINTERNAL);
+        return x;
+    };
+    int live = 0;
+    // The eldest node (the cell at infinity; for H0 the node of the least key, first of the
+    // sorted node keys) never dies, so its moe is never needed: its component, which grows
+    // to hold most edges' ends, would otherwise take one atomic per edge on one word.
+    int eldest = 0;
+    if (!DUAL) {
+        if (threadIdx.x == 0) {
+            const uint64_t k0 = arr<uint64_t>(ws, I.o_n0sorted)[0];
+            const uint32_t p0 = key_pix(k0);
+            const int id = p0 < (uint32_t)I.N ? -(arr<int32_t>(ws, I.o_par0)[p0] + 1) : -1;
+            s_flag[1] = id >= 0 && id < M ? id : -1;     // -1: every root takes its atomics
+        }
+        __syncthreads();
+        eldest = s_flag[1];
+    }
+    for (int q = t0; q < m; q += stride) {
+        const int a = A[q];
+        if (a < 0) continue;
+        if (phase == 0) {
+            const int b = B[q];
+            if (round > 0) {                        // the entries round - 1 lowered
+                prev[a & ~kFired] = kInf;
+                prev[b] = kInf;
+            }
+            if (a & kFired) { A[q] = -1; continue; }
+            const int x = find(a), y = find(b);
+            if (x == y) { A[q] = -1; continue; }
+            A[q] = x;
+            B[q] = y;
+            ++live;
+            // a root's moe is settled early by its first edges: read before the atomic
+            if (x != eldest && q < ld_node<true>(&cur[x])) atomicMin(&cur[x], q);
+            if (y != eldest && q < ld_node<true>(&cur[y])) atomicMin(&cur[y], q);
+        } else {
+            const int x = a, y = B[q];
+            int dead = -1, into = -1;
+            if (cur[x] == q && elder(y, x)) { dead = x; into = y; }
+            else if (cur[y] == q && elder(x, y)) { dead = y; into = x; }
+            if (dead >= 0) {
+                st_node<true>(&par[dead], into);
+                const int r = edge_of(q);
+                if (DUAL) killer[r] = dead;
+                else { death0[dead] = r; neg0[r] = 1; }
+                A[q] = a | kFired;
+            }
+        }
+    }
+    if (phase == 0 && __syncthreads_or(live > 0) && threadIdx.x == 0) {
+        // the flag and the rounds counter, written only while not yet set (read first)
+        if (__hip_atomic_load(&wlive[round & 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+            __hip_atomic_store(&wlive[round & 1], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int32_t *rc = &cnt[DUAL ? CNT_ROUNDST : CNT_ROUNDS0];
+        if (__hip_atomic_load(rc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < round + 1) atomicMax(rc, round + 1);
+    }
+}
+
+// blockIdx.y = instance; stage and blockIdx.z choose H0 or the dual as in k_unionfind
+__global__ __launch_bounds__(kWideThreads) void k_uf_wide(uint8_t *__restrict__ ws, int n, int stage, int htop,
+                                                          int phase, int round) {
+    __shared__ int s_flag[2];                    // the instance failed; the eldest H0 node
+    const bool vol = ((const Inst *)ws)[blockIdx.y].ndim == 3;
+    if (stage == 0 && blockIdx.z == 0) uf_wide<false>(ws, n, phase, round, s_flag);
+    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol)) uf_wide<true>(ws, n, phase, round, s_flag);
+}
+
 // Instances with at most kUfLdsNodes nodes keep par, moe and the node keys in LDS, and with
 // at most kUfLdsEdges edges their live-edge arrays too; up to kUfLdsNodesOnly nodes keep par
 // and moe in the whole LDS (keys and live edges in the workspace); larger ones use the
@@ -1563,7 +1877,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
 // dual keeps its live edges in the free second live array and its roots in the sort scratch
 // (8 max(L, N) bytes).  s_lds: kUfLdsWords int32 words, 8-byte aligned.
 template <bool DUAL>
-__device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_lds, int *s_wsum) {
+__device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_lds, int *s_wsum, bool wide) {
     const int i = blockIdx.x;
     const Inst &I = ((const Inst *)ws)[i];
     const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
@@ -1586,7 +1900,12 @@ __device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t 
     uint64_t *s_key = (uint64_t *)(s_b + kUfLdsEdges);
     static_assert((2 * kUfLdsNodes + 3 * kUfLdsEdges) % 2 == 0, "node keys 8-byte aligned");
     static_assert(2 * kUfLdsNodes + 3 * kUfLdsEdges + 2 * kUfLdsNodes <= kUfLdsWords, "LDS carve");
-    if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
+    if (wide && uf_is_wide(I, M, m)) {
+        // the wide rounds' last round found no live edge: nothing is left
+        if (cnt[(DUAL ? CNT_WLIVET : CNT_WLIVE0) + ((kWideRounds - 1) & 1)] == 0) return;
+        uf_body<DUAL, true, true>(ws, n, gpar, gmoe, glive, ga, gb, nullptr, s_wsum, true);
+    }
+    else if (M <= kUfLdsNodes && m <= kUfLdsEdges) uf_body<DUAL, false, false>(ws, n, s_par, s_moe, s_live, s_a, s_b, s_key, s_wsum);
     else if (M <= kUfLdsNodes) uf_body<DUAL, false, true>(ws, n, s_par, s_moe, glive, ga, gb, s_key, s_wsum);
     else if (M <= kUfLdsNodesOnly)
         uf_body<DUAL, false, true, true>(ws, n, s_lds, s_lds + kUfLdsNodesOnly, glive, ga, gb, nullptr, s_wsum);
@@ -1595,12 +1914,13 @@ __device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t 
 
 // Union-find passes, blockIdx.x = instance.  Stage 0: blockIdx.y = 0 H0 of every instance,
 // y = 1 (with the top dimension) the dual of the volumes; stage 1: the dual of the images.
-__global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ ws, int n, int stage, int htop) {
+// wide: the call ran the wide rounds (k_uf_wide) before this launch.
+__global__ __launch_bounds__(kUfThreads) void k_unionfind(uint8_t *__restrict__ ws, int n, int stage, int htop, int wide) {
     __shared__ __align__(8) int32_t s_lds[kUfLdsWords];
     __shared__ int s_wsum[kUfThreads / 64];
     const bool vol = ((const Inst *)ws)[blockIdx.x].ndim == 3;
-    if (stage == 0 && blockIdx.y == 0) uf_run<false>(ws, n, s_lds, s_wsum);
-    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol)) uf_run<true>(ws, n, s_lds, s_wsum);
+    if (stage == 0 && blockIdx.y == 0) uf_run<false>(ws, n, s_lds, s_wsum, wide != 0);
+    else if ((stage == 0 && htop && vol) || (stage == 1 && !vol)) uf_run<true>(ws, n, s_lds, s_wsum, wide != 0);
 }
 
 // ======================================================================= 3D H1 ====
@@ -2517,6 +2837,9 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_sort_lists", (const void *)k_sort_lists, kSortThreads},
         {"k_resolve", (const void *)k_resolve, 256},
         {"k_unionfind", (const void *)k_unionfind, kUfThreads},
+        {"k_uf_wide", (const void *)k_uf_wide, kWideThreads},
+        {"k_sort_runs", (const void *)k_sort_runs, kSortThreads},
+        {"k_sort_merge", (const void *)k_sort_merge, kSortThreads},
         {"k_output", (const void *)k_output, kUfThreads},
         {"k_zero", (const void *)k_zero, 256},
         {"k_scatter", (const void *)k_scatter, 256},
@@ -2699,11 +3022,12 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // stream is being captured into a graph).
 enum KernelId {
     K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1MORSE2, K_H1REDUCE,
-    K_OUTPUT, K_ZERO, K_SCATTER, K_COUNT
+    K_OUTPUT, K_ZERO, K_SCATTER, K_UFWIDE, K_UFWIDE_2D, K_SORTWIDE, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
-    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter"};
+    "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
+    "k_uf_wide", "k_uf_wide(2d top)", "k_sort_wide"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -2850,16 +3174,38 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     int64_t rb = (mv + 65535) / 65536;
     if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
-    FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n));
+    // PH_WIDE: the union-finds and the long lists of instances of kWideVoxels or more voxels
+    // are spread over the whole GPU (each instance's kernels decide for themselves, from its
+    // counts)
+    const int wide = (flags & PH_WIDE) && mv >= kWideVoxels ? 1 : 0;
+    FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n, wide));
+    if (wide) {
+        int64_t runs = (ml + kSortCap - 1) / kSortCap;
+        const unsigned sb = (unsigned)std::min<int64_t>(kWideBlocks, runs);
+        FC_LAUNCH(K_SORTWIDE, hipLaunchKernelGGL(k_sort_runs, dim3(sb, n, 3), dim3(kSortThreads), 0, st, ws, n));
+        int passes = 0;
+        while (((int64_t)kSortCap << passes) < ml) ++passes;
+        for (int p = 0; p <= passes; ++p)         // the last one only copies back
+            FC_LAUNCH(K_SORTWIDE, hipLaunchKernelGGL(k_sort_merge, dim3(sb, n, 3), dim3(kSortThreads), 0, st, ws, n, p));
+    }
     // volumes: the dual (resolve, union-find) beside H0; images: the dual after H0
     // T's H0 is the V top; 3D H1 needs the squares the dual union-find pairs
     const int htop = (tf || (flags & PH_HTOP) || (h1 && any3)) ? 1 : 0;
     const unsigned side = htop && any3 ? 2 : 1;
     FC_LAUNCH(K_RESOLVE, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n, side), dim3(256), 0, st, ws, n, 0, htop));
-    FC_LAUNCH(K_UF, hipLaunchKernelGGL(k_unionfind, dim3(n, side), dim3(kUfThreads), 0, st, ws, n, 0, htop));
+    auto wide_rounds = [&](int stage, unsigned sides, int kid) -> int {
+        for (int ph = -1, r = 0; r < kWideRounds; ph == 1 ? (ph = 0, ++r) : ++ph) {
+            FC_LAUNCH(kid, hipLaunchKernelGGL(k_uf_wide, dim3(kWideBlocks, n, sides), dim3(kWideThreads), 0, st, ws, n,
+                                              stage, htop, ph, r));
+        }
+        return PH_OK;
+    };
+    if (wide && wide_rounds(0, side, K_UFWIDE) != PH_OK) return PH_EHIP;
+    FC_LAUNCH(K_UF, hipLaunchKernelGGL(k_unionfind, dim3(n, side), dim3(kUfThreads), 0, st, ws, n, 0, htop, wide));
     if (htop && any2) {
         FC_LAUNCH(K_RESOLVE_2D, hipLaunchKernelGGL(k_resolve, dim3(rblocks, n), dim3(256), 0, st, ws, n, 1, htop));
-        FC_LAUNCH(K_UF_2D, hipLaunchKernelGGL(k_unionfind, dim3(n), dim3(kUfThreads), 0, st, ws, n, 1, htop));
+        if (wide && wide_rounds(1, 1, K_UFWIDE_2D) != PH_OK) return PH_EHIP;
+        FC_LAUNCH(K_UF_2D, hipLaunchKernelGGL(k_unionfind, dim3(n), dim3(kUfThreads), 0, st, ws, n, 1, htop, wide));
     }
     if (h1 && any3) {
         // one 64-thread workgroup per 512 voxels of the largest volume (at most 8192 per

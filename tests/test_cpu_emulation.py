@@ -380,3 +380,14 @@ def test_h1_touches_device_memory_only():
     out, _ = run(exe, imgs, mode=1, flags=3 | 32)
     for img, (got, st) in zip(imgs, out):
         assert st == 0 and diff_pairs(got, h1_ref(img)) is None, img.shape
+
+
+def test_wide_union_find_rounds():
+    """PH_WIDE on an image of 2^20 pixels of uniform noise (about 160k H0 nodes and as many
+    dual ones) beside a small image: both union-finds of the large one take the rounds spread
+    over many workgroups, then finish in one.  Built without the sanitizers (the instance is
+    large), against the oracle."""
+    exe = emu_build.build("poison")
+    imgs = [S.uniform((1024, 1024), 25), S.uniform((20, 21), 26)]
+    for img, (got, st) in zip(imgs, run(exe, imgs, mode=1, flags=3 | 64)[0]):
+        assert st == 0 and diff_pairs(got, oracle.diagram(img)) is None, img.shape

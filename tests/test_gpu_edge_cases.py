@@ -109,27 +109,54 @@ def test_specials_t_filtration_without_plus_inf():
 # Lists past one LDS sort (4096 keys) and forests past the union-find's LDS capacities, from
 # uniform noise (about a sixth of the edges kept): (KEEP edges, H0 nodes) of each, and which
 # layout the union-find takes (par, moe and keys in LDS up to 5120 nodes; par and moe alone up
-# to 20440; else the workspace).
+# to 20440; else the workspace, after six rounds over many workgroups when the instance has
+# 2^20 voxels or more).
 LARGE = {
     "noise_200x230": lambda: S.uniform((200, 230), 21),        # 14k edges, 9k nodes
     "noise_350x360": lambda: S.uniform((350, 360), 22),        # 39k edges, 25k nodes
     "noise_34x35x33": lambda: S.uniform((34, 35, 33), 23),     # 13k edges, 8k squares, 6k nodes
     "noise_1024x1024": lambda: S.uniform((1024, 1024), 25),    # 330k edges: 81 runs, 7 passes
     "noise_80x80x80": lambda: S.uniform((80, 80, 80), 26),     # long lists of all three kinds
+    "noise_128x128x128": lambda: S.uniform((128, 128, 128), 27),   # 2^21 voxels
 }
+WIDE = {"noise_1024x1024", "noise_128x128x128"}   # 2^20 voxels or more: PH_WIDE applies
 
 
 @pytest.mark.parametrize("name", sorted(LARGE))
 def test_long_lists_and_large_forests(name):
     img = LARGE[name]()
-    bt = fc.Batch([img.shape], device=DEV)
-    bt.set_images([torch.from_numpy(img)])
-    print("case", name, flush=True)
-    bt.ph_diagram_batch()
-    (got,) = bt.results()
-    assert diff_pairs(got, oracle.diagram(img)) is None, name
-    wc = bt.work_counters()
-    assert wc[0, 0] > 4096 and wc[0, 2] > 5120, wc[0]
+    ref = oracle.diagram(img)
+    for flags in ((fc.PH_H0 | fc.PH_HTOP, fc.PH_H0 | fc.PH_HTOP | fc.PH_WIDE) if name in WIDE else (fc.PH_H0 | fc.PH_HTOP,)):
+        bt = fc.Batch([img.shape], flags=flags, device=DEV)
+        bt.set_images([torch.from_numpy(img)])
+        print("case", name, "flags", flags, flush=True)
+        bt.ph_diagram_batch()
+        (got,) = bt.results()
+        assert diff_pairs(got, ref) is None, (name, flags)
+        wc = bt.work_counters()
+        assert wc[0, 0] > 4096 and wc[0, 2] > 5120, wc[0]
+        if flags & fc.PH_WIDE:                      # both forests past one workgroup's LDS
+            assert wc[0, 2] > 20440 and wc[0, 3] > 20440 and wc[0, 4] > 0 and wc[0, 5] > 0, wc[0]
+
+
+def test_wide_rounds_beside_small_instances():
+    """PH_WIDE on a batch whose largest instance takes the wide union-find rounds, with
+    instances that stay in one workgroup (each kernel decides per instance), twice in a row on
+    one batch, and the large image under the T-filtration."""
+    imgs = [LARGE["noise_200x230"](), LARGE["noise_1024x1024"](), S.grf((40, 30, 20), 2.0, 91),
+            LARGE["noise_34x35x33"]()]
+    refs = [oracle.diagram(a) for a in imgs]
+    bt = fc.Batch([a.shape for a in imgs], flags=fc.PH_H0 | fc.PH_HTOP | fc.PH_WIDE, device=DEV)
+    bt.set_images([torch.from_numpy(a) for a in imgs])
+    print("batch with a wide instance", flush=True)
+    for _ in range(2):
+        bt.ph_diagram_batch()
+        for a, got, ref in zip(imgs, bt.results(), refs):
+            assert diff_pairs(got, ref) is None, a.shape
+    img = LARGE["noise_1024x1024"]()
+    print("wide instance, T-filtration", flush=True)
+    got = fc.ph_diagram(torch.from_numpy(img).to(DEV), flags=fc.PH_H0 | fc.PH_HTOP | fc.PH_WIDE, filtration="T").numpy()
+    assert diff_pairs(got, oracle.diagram(img, filtration="T")) is None
 
 
 def test_long_lists_batched_and_t_filtration():
