@@ -159,6 +159,7 @@ enum {
     CNT_ERR = 128, CNT_ROUNDS0, CNT_ROUNDST, CNT_SEQ,
     CNT_H1COLS, CNT_H1UNSAFE, CNT_H1ROUNDS, CNT_H1RETRY, CNT_H1ADDS, CNT_HOPS0, CNT_HOPST,
     CNT_WLIVE0 = 144, CNT_WLIVET = 146,  // wide union-find rounds: live edges of a round, two slots by parity
+    CNT_OSEC0 = 148, CNT_OSECT,          // wide output: pairs of the H0 and the top-dimension lists
     CNT_H1POOL = 160, CNT_WORDS = 192
 };
 // pool entries per KEEP-square slot of an H1 volume: room for the Morse boundaries of the

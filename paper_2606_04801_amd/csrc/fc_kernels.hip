@@ -57,7 +57,7 @@ constexpr int kUfLdsNodesOnly = kUfLdsWords / 2;   // nodes whose par, moe alone
 constexpr int kSortThreads = 1024;
 constexpr int kSortCap = 4096;             // keys sorted entirely in LDS (32 KiB)
 constexpr int kMaxRounds = 48;             // parallel rounds before the sequential finish
-constexpr int kWideRounds = 24;            // union-find rounds over many workgroups (PH_WIDE)
+constexpr int kWideRounds = 32;            // union-find rounds over many workgroups (PH_WIDE)
 constexpr int64_t kWideVoxels = 1 << 20;   // ... for instances of this many voxels
 constexpr int kWideBlocks = 2048, kWideThreads = 256;
 constexpr int32_t kFired = 1 << 30;        // wide rounds: an edge fired this round (above every node index)
@@ -1794,11 +1794,14 @@ __device__ __forceinline__ void uf_wide(uint8_t *__restrict__ ws, int n, int pha
         if (DUAL) return x == 0 || (y != 0 && nkey[x] > nkey[y]);
         return nkey[x] < nkey[y];
     };
+    // Phase 0 changes par only by path halving, which keeps every link pointing to an
+    // ancestor, and lowers moe only: a stale read of either (through the workgroup's cache) is
+    // an older ancestor or a higher moe, so the roots found and the atomics taken stay right.
     auto find = [&](int x) -> int {
         for (int it = 0; it < kMaxChase; ++it) {
-            const int p = ld_node<true>(&par[x]);
+            const int p = ld_node<false>(&par[x]);
             if (p == x) return x;
-            const int g = ld_node<true>(&par[p]);
+            const int g = ld_node<false>(&par[p]);
             if (g != p) st_node<true>(&par[x], g);     // path halving (any ancestor is valid)
             x = g;
         }
@@ -1836,8 +1839,8 @@ __device__ __forceinline__ void uf_wide(uint8_t *__restrict__ ws, int n, int pha
             B[q] = y;
             ++live;
             // a root's moe is settled early by its first edges: read before the atomic
-            if (x != eldest && q < ld_node<true>(&cur[x])) atomicMin(&cur[x], q);
-            if (y != eldest && q < ld_node<true>(&cur[y])) atomicMin(&cur[y], q);
+            if (x != eldest && q < ld_node<false>(&cur[x])) atomicMin(&cur[x], q);
+            if (y != eldest && q < ld_node<false>(&cur[y])) atomicMin(&cur[y], q);
         } else {
             const int x = a, y = B[q];
             int dead = -1, into = -1;
@@ -2533,14 +2536,27 @@ __device__ __forceinline__ int64_t cell_index(const Inst &I, int64_t v, int code
     return (Z * (2 * (int64_t)I.H - 1) + Y) * (2 * (int64_t)I.W - 1) + X;
 }
 
+// An instance under PH_WIDE of kWideVoxels or more voxels (not under PH_H1) has its pairs
+// written by the whole GPU: mode 1 (grid (kWideBlocks, n)) counts the pairs of every chunk of
+// kUfThreads list entries of each section into the live-edge array (free once the union-finds
+// are done), k_output_scan turns the counts into each chunk's first position and the section
+// totals (CNT_OSEC0, CNT_OSECT), and mode 2 (the same grid) writes every chunk's pairs there.
+// Mode 0 (grid n) writes the other instances' pairs as one workgroup and, for the wide ones,
+// only their count and status.
+__device__ __forceinline__ bool out_is_wide(const Inst &I, uint32_t flags) {
+    return (flags & PH_WIDE) && I.N >= kWideVoxels && !I.h1;
+}
+
 __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ imgs,
                                                       uint8_t *__restrict__ ws, int n, uint32_t flags,
                                                       ph_pairs out, int64_t *__restrict__ d_counts,
-                                                      int32_t *__restrict__ d_status) {
+                                                      int32_t *__restrict__ d_status, int mode) {
     __shared__ int s_wsum[kUfThreads / 64];
-    const int i = blockIdx.x;
+    const int i = mode == 0 ? blockIdx.x : blockIdx.y;
     const Inst &I = ((const Inst *)ws)[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const bool wide = out_is_wide(I, flags);
+    if (mode != 0 && !wide) return;
     // pixel value as float32, from the caller's input of the element type the flags name
     auto img = [&](int64_t p) -> float {
         const int64_t q = I.src_off + p;
@@ -2561,9 +2577,14 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
     const int64_t cap = I.out_cap, o = I.out_off;
     int64_t P = 0;
     if (block_failed(cnt)) {
-        if (threadIdx.x == 0) { d_counts[i] = 0; d_status[i] = cnt[CNT_ERR]; }
+        if (threadIdx.x == 0 && mode == 0) { d_counts[i] = 0; d_status[i] = cnt[CNT_ERR]; }
         return;
     }
+    // chunks of kUfThreads entries: this block's first and step (mode 0: all, in order);
+    // wide: per-chunk counts, then first positions, H0 section first (ch0), then the top's (chT)
+    const int c_first = mode == 0 ? 0 : blockIdx.x, c_step = mode == 0 ? 1 : gridDim.x;
+    int32_t *ch0 = arr<int32_t>(ws, I.o_live);
+    int32_t *chT = ch0 + (M0 + kUfThreads - 1) / kUfThreads;
     // a pixel index and a cell code read back from a key must name a cell of this instance
     auto key_ok = [&](uint64_t k, int lo, int hi) {
         const int c = (int)key_code(k);
@@ -2610,7 +2631,7 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
     // H0 pairs of the V complex, by birth key (under the T-filtration: its top pairs)
     auto sec_h0 = [&](bool write, int64_t start, int64_t rev) -> int64_t {
         int64_t Q = 0;
-        for (int base = 0; base < M0; base += blockDim.x) {
+        for (int base = c_first * blockDim.x; base < M0; base += c_step * blockDim.x) {
             const int j = base + threadIdx.x;
             int flag = 0;
             uint64_t nk = 0, ek = 0;
@@ -2629,6 +2650,11 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
             }
             int tot;
             const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (mode == 1) {
+                if (threadIdx.x == 0) ch0[base / blockDim.x] = tot;
+                continue;
+            }
+            if (mode == 2) Q = ch0[base / blockDim.x];
             if (flag && write) {
                 const int32_t bp = (int32_t)key_pix(nk);
                 const int64_t at = place(start, rev, Q + pos);
@@ -2651,7 +2677,7 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
     // pairs; the one born on the frame is the essential class)
     auto sec_top = [&](bool write, int64_t start, int64_t rev) -> int64_t {
         int64_t Q = 0;
-        for (int base = 0; base < mf; base += blockDim.x) {
+        for (int base = c_first * blockDim.x; base < mf; base += c_step * blockDim.x) {
             const int r = base + threadIdx.x;
             int flag = 0;
             uint64_t fk = 0, tk = 0;
@@ -2668,6 +2694,11 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
             }
             int tot;
             const int pos = block_flag_scan(flag, s_wsum, &tot);
+            if (mode == 1) {
+                if (threadIdx.x == 0) chT[base / blockDim.x] = tot;
+                continue;
+            }
+            if (mode == 2) Q = chT[base / blockDim.x];
             if (flag && write) {
                 const int32_t bp = (int32_t)key_pix(fk), dp = (int32_t)key_pix(tk);
                 const int64_t at = place(start, rev, Q + pos);
@@ -2730,7 +2761,32 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
         return Q;
     };
 
-    if (!tf) {
+    if (wide) {
+        // section sizes from k_output_scan (mode 1 counts; mode 0 only reports)
+        const int64_t nh0 = cnt[CNT_OSEC0], ntop = cnt[CNT_OSECT];
+        if (mode == 1) {
+            if (flags & (tf ? PH_HTOP : PH_H0)) sec_h0(false, 0, -1);
+            if (flags & (tf ? PH_H0 : PH_HTOP)) sec_top(false, 0, -1);
+            return;
+        }
+        if (!tf) {
+            const int64_t a0 = (flags & PH_H0) ? nh0 : 0;
+            if (mode == 2) {
+                if (flags & PH_H0) sec_h0(true, 0, -1);
+                if (flags & PH_HTOP) sec_top(true, a0, -1);
+                return;
+            }
+            P = a0 + ((flags & PH_HTOP) ? ntop : 0);
+        } else {
+            const int64_t c0 = (flags & PH_H0) ? ntop : 0, ct = (flags & PH_HTOP) ? nh0 : 0;
+            if (mode == 2) {
+                if (flags & PH_H0) sec_top(true, 0, c0);
+                if (flags & PH_HTOP) sec_h0(true, c0, ct);
+                return;
+            }
+            P = c0 + ct;
+        }
+    } else if (!tf) {
         if (flags & PH_H0) P += sec_h0(true, P, -1);
         if (h1) P += sec_h1(true, P, -1);
         if (flags & PH_HTOP) P += sec_top(true, P, -1);
@@ -2750,6 +2806,47 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
         int st = __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (st == 0 && P > cap) st = PH_ECAPACITY;
         d_status[i] = st;
+    }
+}
+
+// Between modes 1 and 2 of k_output: each wide instance's chunk counts become the chunks'
+// first positions inside their section (exclusive sums), and the section totals go to
+// CNT_OSEC0 (H0 list) and CNT_OSECT (top list).  One workgroup an instance.
+__global__ __launch_bounds__(kUfThreads) void k_output_scan(uint8_t *__restrict__ ws, int n, uint32_t flags) {
+    __shared__ int32_t s_w[kUfThreads / 64];
+    __shared__ int64_t s_run;
+    const int i = blockIdx.x;
+    const Inst &I = ((const Inst *)ws)[i];
+    int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    if (!out_is_wide(I, flags) || block_failed(cnt)) return;
+    const int M0 = cnt[CNT_M0], mf = I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F];
+    const int n0 = (M0 + kUfThreads - 1) / kUfThreads, nt = (mf + kUfThreads - 1) / kUfThreads;
+    int32_t *ch = arr<int32_t>(ws, I.o_live);
+    const int lane = __lane_id(), wid = threadIdx.x >> 6;
+    for (int sec = 0; sec < 2; ++sec) {
+        int32_t *c = sec == 0 ? ch : ch + n0;
+        const int nc = sec == 0 ? n0 : nt;
+        if (threadIdx.x == 0) s_run = 0;
+        __syncthreads();
+        for (int base = 0; base < nc; base += blockDim.x) {
+            const int k = base + threadIdx.x;
+            const uint32_t v = k < nc ? (uint32_t)c[k] : 0u;
+            const uint32_t incl = wave_incl_sum(v);
+            if (lane == 63) s_w[wid] = (int32_t)incl;
+            __syncthreads();
+            int32_t before = 0, total = 0;
+            for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+                if (w < wid) before += s_w[w];
+                total += s_w[w];
+            }
+            const int64_t run = s_run;
+            if (k < nc) c[k] = (int32_t)(run + before + incl - v);
+            __syncthreads();                     // every thread has read s_w and s_run
+            if (threadIdx.x == 0) s_run = run + total;
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) cnt[sec == 0 ? CNT_OSEC0 : CNT_OSECT] = (int32_t)s_run;
+        __syncthreads();
     }
 }
 
@@ -2840,6 +2937,7 @@ int check_kernels(int dev, char *report, size_t len) {
         {"k_uf_wide", (const void *)k_uf_wide, kWideThreads},
         {"k_sort_runs", (const void *)k_sort_runs, kSortThreads},
         {"k_sort_merge", (const void *)k_sort_merge, kSortThreads},
+        {"k_output_scan", (const void *)k_output_scan, kUfThreads},
         {"k_output", (const void *)k_output, kUfThreads},
         {"k_zero", (const void *)k_zero, 256},
         {"k_scatter", (const void *)k_scatter, 256},
@@ -3022,12 +3120,12 @@ bool tuned_for(const ph_shape *h, int n, ph_tuning *t) {
 // stream is being captured into a graph).
 enum KernelId {
     K_PLAN, K_CLASSIFY2D, K_CLASSIFY3D, K_SORT, K_RESOLVE, K_UF, K_RESOLVE_2D, K_UF_2D, K_H1MORSE, K_H1MORSE2, K_H1REDUCE,
-    K_OUTPUT, K_ZERO, K_SCATTER, K_UFWIDE, K_UFWIDE_2D, K_SORTWIDE, K_COUNT
+    K_OUTPUT, K_ZERO, K_SCATTER, K_UFWIDE, K_UFWIDE_2D, K_SORTWIDE, K_OUTWIDE, K_COUNT
 };
 const char *const kKernelNames[K_COUNT] = {
     "k_plan", "k_classify2d", "k_classify3d", "k_sort", "k_resolve", "k_unionfind",
     "k_resolve(2d top)", "k_unionfind(2d top)", "k_h1_morse", "k_h1_morse(large)", "k_h1_reduce", "k_output", "k_zero", "k_scatter",
-    "k_uf_wide", "k_uf_wide(2d top)", "k_sort_wide"};
+    "k_uf_wide", "k_uf_wide(2d top)", "k_sort_wide", "k_output_wide"};
 
 struct ProfRec { int kid; hipEvent_t a, b; };
 std::mutex g_prof_mu;
@@ -3173,6 +3271,7 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     // so 256 threads per 64Ki voxels of the largest instance; the loops stride over the rest
     int64_t rb = (mv + 65535) / 65536;
     if (rb > (ml + 255) / 256) rb = (ml + 255) / 256;
+    if ((flags & PH_WIDE) && mv >= kWideVoxels) rb = (mv + 4095) / 4096;   // noise: lists of a sixth of the pixels
     const unsigned rblocks = (unsigned)(rb < 1 ? 1 : (rb > 1024 ? 1024 : rb));
     // PH_WIDE: the union-finds and the long lists of instances of kWideVoxels or more voxels
     // are spread over the whole GPU (each instance's kernels decide for themselves, from its
@@ -3225,8 +3324,15 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
         }
         FC_LAUNCH(K_H1REDUCE, hipLaunchKernelGGL(k_h1_reduce, dim3(n), dim3(kUfThreads), 0, st, ws, n));
     }
+    if (wide) {                                   // PH_WIDE: large instances' pairs by the whole GPU
+        FC_LAUNCH(K_OUTWIDE, hipLaunchKernelGGL(k_output, dim3(kWideBlocks / 4, n), dim3(kUfThreads), 0, st, d_imgs, ws, n,
+                                                flags, out, d_counts, d_status, 1));
+        FC_LAUNCH(K_OUTWIDE, hipLaunchKernelGGL(k_output_scan, dim3(n), dim3(kUfThreads), 0, st, ws, n, flags));
+        FC_LAUNCH(K_OUTWIDE, hipLaunchKernelGGL(k_output, dim3(kWideBlocks / 4, n), dim3(kUfThreads), 0, st, d_imgs, ws, n,
+                                                flags, out, d_counts, d_status, 2));
+    }
     FC_LAUNCH(K_OUTPUT, hipLaunchKernelGGL(k_output, dim3(n), dim3(kUfThreads), 0, st, d_imgs, ws, n, flags, out, d_counts,
-                                 d_status));
+                                 d_status, 0));
     return PH_OK;
 }
 
