@@ -3280,7 +3280,7 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     FC_LAUNCH(K_SORT, hipLaunchKernelGGL(k_sort_lists, dim3(n, 3), dim3(kSortThreads), 0, st, ws, n, wide));
     if (wide) {
         int64_t runs = (ml + kSortCap - 1) / kSortCap;
-        const unsigned sb = (unsigned)std::min<int64_t>(kWideBlocks, runs);
+        const unsigned sb = (unsigned)std::min<int64_t>(512, runs);   // workgroups per list: runs, then tiles
         FC_LAUNCH(K_SORTWIDE, hipLaunchKernelGGL(k_sort_runs, dim3(sb, n, 3), dim3(kSortThreads), 0, st, ws, n));
         int passes = 0;
         while (((int64_t)kSortCap << passes) < ml) ++passes;

@@ -159,6 +159,37 @@ def test_wide_rounds_beside_small_instances():
     assert diff_pairs(got, oracle.diagram(img, filtration="T")) is None
 
 
+def test_wide_with_uint8_backward_and_list_fraction():
+    """PH_WIDE beside the other flags on 1024^2 noise quantised to 256 levels (heavy ties): uint8
+    input, the backward scatter, and a list fraction, against the same calls without PH_WIDE
+    (pairs, gradient, counters bitwise); a fraction too small for the lists gives PH_ELISTS
+    with the true list sizes, as without the flag."""
+    img = S.quantize_u8(LARGE["noise_1024x1024"]())
+    base = fc.PH_H0 | fc.PH_HTOP | fc.PH_LIST_FRACTION(64)
+    got = {}
+    for flags in (base, base | fc.PH_WIDE):
+        bt = fc.Batch([img.shape], flags=flags, device=DEV, dtype=torch.uint8)
+        bt.set_images([torch.from_numpy(img)])
+        print("uint8 noise, flags", flags, flush=True)
+        bt.ph_diagram_batch()
+        (res,) = bt.results()
+        fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
+        diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
+        bt.ph_backward(-2.0 * diff, 2.0 * diff)
+        got[flags] = (res, bt.grad.cpu().numpy().copy(), bt.work_counters()[0, :4].copy())
+    (r0, g0, w0), (r1, g1, w1) = got[base], got[base | fc.PH_WIDE]
+    assert diff_pairs(r1, r0) is None and diff_pairs(r0, oracle.diagram(img.astype(np.float32))) is None
+    assert np.array_equal(g0, g1) and np.array_equal(w0, w1) and w0[2] > 20440, (w0, w1)
+    for flags in (fc.PH_H0 | fc.PH_HTOP | fc.PH_LIST_FRACTION(8), fc.PH_H0 | fc.PH_HTOP | fc.PH_LIST_FRACTION(8) | fc.PH_WIDE):
+        bt = fc.Batch([img.shape], flags=flags, device=DEV, dtype=torch.uint8)
+        bt.set_images([torch.from_numpy(img)])
+        print("uint8 noise, too small a fraction, flags", flags, flush=True)
+        bt.ph_diagram_batch()
+        torch.cuda.synchronize()
+        assert int(bt.status[0]) == fc.PH_ELISTS
+        assert np.array_equal(bt.work_counters()[0, :4], w0), bt.work_counters()[0, :4]
+
+
 def test_long_lists_batched_and_t_filtration():
     """The large cases side by side in one batch (each list with its own merge scratch), and
     two of them under the T-filtration."""
