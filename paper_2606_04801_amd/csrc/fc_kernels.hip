@@ -704,8 +704,8 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 
 // ================================================================ classify 3D ====
 // 256 threads, seven workgroups (28 waves) per compute unit at 72 registers, without spills.
-// Eight (the 64-register budget) measured up to 1.5 % faster, but its spilled registers added
-// about 45 % to the kernel's HBM traffic (FETCH_SIZE + WRITE_SIZE)
+// Eight (the 64-register budget) spill five registers and measured 0.8 % slower on the batched
+// step (an earlier version of the kernel: 1.5 % faster, with 45 % more HBM traffic from spills)
 template <int TW, int TH, int TD, typename T, bool H1 = false>
 __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut) {
