@@ -30,9 +30,10 @@ SPECIAL = {"vcc_lo": (106, 1), "vcc_hi": (107, 1), "vcc": (106, 2), "exec_lo": (
 FLOAT_INLINE = {"0.5": 0x3F000000, "-0.5": 0xBF000000, "1.0": 0x3F800000, "-1.0": 0xBF800000,
                 "2.0": 0x40000000, "-2.0": 0xC0000000, "4.0": 0x40800000, "-4.0": 0xC0800000,
                 "0.15915494": 0x3E22F983}
-# Flat addresses in [SHARED_APERTURE, SHARED_APERTURE + 2^32) are LDS.  Code that forms such
-# pointers parses; an access through one is refused (Memory has no allocation there), since
-# flat access to LDS is not emulated.
+# Flat addresses in [SHARED_APERTURE, SHARED_APERTURE + 2^32) are LDS: flat loads and stores
+# there go to the workgroup's LDS (bounds-checked against the kernel's LDS segment); other
+# instructions that reach the aperture (flat atomics) are refused, as Memory has no allocation
+# there.
 SHARED_APERTURE = 0x10000 << 32
 LANE = np.arange(LANES, dtype=np.int64)
 BIT = (np.uint64(1) << np.arange(LANES, dtype=np.uint64))
@@ -90,7 +91,7 @@ class Memory:
             base, size, _ = self.regions[k]
             near = " (nearest allocation below: 0x%x, %d bytes, access at +%d)" % (base, size, lo - base)
         if SHARED_APERTURE <= lo < SHARED_APERTURE + (1 << 32):
-            raise Fault("%s: flat access to LDS (0x%x) is not emulated" % (what, lo))
+            raise Fault("%s: this flat access to LDS (0x%x) is not emulated" % (what, lo))
         raise Fault("%s outside device memory: [0x%x, 0x%x)%s" % (what, lo, hi, near))
 
     def _idx(self, addrs, nbytes, what):
@@ -1189,6 +1190,18 @@ def _compile_scratch(op, O, mods, nxt):
     return f
 
 
+def _flat_lds(w, addrs, nbytes, what):
+    """(mask of the flat addresses that fall in the LDS aperture, their byte indices into the
+    workgroup's LDS); an LDS address outside the kernel's LDS segment stops the run"""
+    m = (addrs >= SHARED_APERTURE) & (addrs < SHARED_APERTURE + (1 << 32))
+    if not m.any():
+        return m, None
+    offs = addrs[m] - SHARED_APERTURE
+    if (offs + nbytes > w.wg.lds_size).any():
+        raise Fault("%s: flat LDS access past the %d-byte segment" % (what, w.wg.lds_size))
+    return m, offs[:, None] + np.arange(nbytes)
+
+
 def _compile_global(op, O, mods, nxt):
     off = _offset(mods)
     flat = op.startswith("flat_")
@@ -1213,7 +1226,16 @@ def _compile_global(op, O, mods, nxt):
             if not e.any():
                 return nxt
             addrs = ad(w)[e]
-            raw = w.wg.mem.gather(addrs, nbytes, "%s at pc 0x%x" % (op, w.pc))
+            what = "%s at pc 0x%x" % (op, w.pc)
+            m, li = _flat_lds(w, addrs, nbytes, what) if flat else (None, None)
+            if li is None:
+                raw = w.wg.mem.gather(addrs, nbytes, what)
+            else:                                   # flat: LDS lanes from the LDS, the rest from memory
+                raw = np.empty((len(addrs), nbytes), U8)
+                raw[m] = w.wg.lds[li]
+                if (~m).any():
+                    raw[~m] = w.wg.mem.gather(addrs[~m], nbytes, what).reshape(-1, nbytes)
+                raw = raw.reshape(-1)
             if nbytes >= 4:
                 vals = raw.view("<u4").reshape(len(addrs), nbytes // 4)
                 for k in range(nbytes // 4):
@@ -1240,7 +1262,15 @@ def _compile_global(op, O, mods, nxt):
                 data = np.stack([w.v[si + k][e] for k in range(nbytes // 4)], axis=1).astype("<u4").view(U8)
             else:
                 data = (w.v[si][e] & U32((1 << (8 * nbytes)) - 1)).astype("<u2" if nbytes == 2 else "<u1").view(U8)
-            w.wg.mem.scatter(addrs, data.reshape(len(addrs), nbytes), "%s at pc 0x%x" % (op, w.pc))
+            data = data.reshape(len(addrs), nbytes)
+            what = "%s at pc 0x%x" % (op, w.pc)
+            m, li = _flat_lds(w, addrs, nbytes, what) if flat else (None, None)
+            if li is None:
+                w.wg.mem.scatter(addrs, data, what)
+            else:
+                w.wg.lds[li] = data[m]
+                if (~m).any():
+                    w.wg.mem.scatter(addrs[~m], data[~m], what)
             return nxt
         return f
     if kind.startswith("atomic_"):
@@ -1254,8 +1284,8 @@ def _compile_global(op, O, mods, nxt):
         di = d.idx if d is not None else None
         dd = do.idx
         is64 = aop.endswith("_x2")
-        if is64:
-            raise Unsupported(op)
+        if is64 or aop not in ("add", "smin", "umin", "smax", "umax", "cmpswap", "add_f32", "or", "and"):
+            raise Unsupported(op)             # refused when the code object is read, not when run
 
         def f(w):
             e = w.exec()
@@ -1274,6 +1304,14 @@ def _compile_global(op, O, mods, nxt):
                     new = old if os_ <= xs else x
                 elif aop == "umin":
                     new = min(old, x)
+                elif aop == "smax":
+                    os_ = old - (1 << 32) if old >= 1 << 31 else old
+                    xs = x - (1 << 32) if x >= 1 << 31 else x
+                    new = old if os_ >= xs else x
+                elif aop == "umax":
+                    new = max(old, x)
+                elif aop == "and":
+                    new = old & x
                 elif aop == "cmpswap":
                     cmp = int(w.v[dd + 1][l])
                     new = x if old == cmp else old

@@ -89,6 +89,8 @@ class IsaRunner:
         vp, i32, i64, u32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
         H.ph_capacity_bound.argtypes = [ph_shape]
         H.ph_capacity_bound.restype = i64
+        H.ph_capacity_bound_flags.argtypes = [ph_shape, u32]
+        H.ph_capacity_bound_flags.restype = i64
         H.ph_workspace_bytes.argtypes = [ctypes.POINTER(ph_shape), i32, u32]
         H.ph_workspace_bytes.restype = ctypes.c_size_t
         H.ph_diagram.argtypes = [vp, ph_shape, u32, ph_pairs, i64, vp, vp, vp, ctypes.c_size_t, vp]
@@ -158,14 +160,19 @@ class IsaRunner:
         return out
 
     # -------------------------------------------------------------- entry points --
-    def diagram(self, img: np.ndarray, capacity: int | None = None, tfilt: bool = False):
+    def diagram(self, img: np.ndarray, capacity: int | None = None, tfilt: bool = False, h1: bool = False):
         """(pairs, status, count) of ph_diagram on one image or volume (T-filtration with
-        tfilt, flag 16)"""
+        tfilt, flag 16; a volume's H1 with h1, flag 32)"""
         img = self.dev(as_input(img))
-        flags = 3 | IN_FLAGS[img.dtype] | (16 if tfilt else 0)
+        flags = 3 | IN_FLAGS[img.dtype] | (16 if tfilt else 0) | (32 if h1 else 0)
         shp = make_shape(img.shape)
-        bound = make_shape(tuple(e + 2 for e in img.shape)) if tfilt else shp
-        cap = int(self.host.ph_capacity_bound(bound)) if capacity is None else capacity
+        if capacity is not None:
+            cap = capacity
+        elif h1:
+            cap = int(self.host.ph_capacity_bound_flags(shp, flags))
+        else:
+            bound = make_shape(tuple(e + 2 for e in img.shape)) if tfilt else shp
+            cap = int(self.host.ph_capacity_bound(bound))
         bufs, pr = self._pairs(cap)
         count = self.dev(np.full(1, -7, np.int64))
         status = self.dev(np.full(1, -77, np.int32))

@@ -168,3 +168,13 @@ def test_t_filtration(isa):
             got, st, _ = isa.diagram(img, tfilt=True)
             ref = oracle.diagram(np.asarray(img, np.float32), filtration="T")
             assert st == 0 and diff_pairs(got, ref) is None, (shape, img.dtype)
+
+
+def test_h1_volumes(isa):
+    """PH_H1 on the code object: the Morse expansion of each column (k_h1_morse) and the
+    reduction rounds over the unsafe columns (k_h1_reduce, which reads a column either from
+    the workspace or from LDS through one generic pointer), against the oracle's every
+    dimension, on noise (hundreds of H1 columns, several of them unsafe) and a field."""
+    for img in (S.uniform((10, 11, 12), 5), S.grf((20, 18, 16), 1.5, 5)):
+        got, st, _ = isa.diagram(img, h1=True)
+        assert st == 0 and diff_pairs(got, oracle.diagram(img, dims=(0, 1, 2))) is None, img.shape
