@@ -7,14 +7,17 @@ plain calls, on one MI355X; prints one JSON line.
 Headline workload (the differentiation configuration): 64 volumes 96^3 (random field, sigma 3,
 seeds 2000+i) and 64 images 512^2 (sigma 6, seeds 3000+i) in one batch; loss = sum over finite
 pairs of (death - birth)^2.  A step is one pass of the whole path over the batch: the forward
-(ph_diagram_batch) inside the batched autograd Function, the loss, and loss.backward(), whose
-backward is ph_backward.  The step is captured once in a HIP graph and replayed; timed steps
+(ph_diagram_batch_grad: the classify passes also clear the input gradient) inside the batched
+autograd Function, the loss, and loss.backward(), whose backward is ph_backward_scatter (the
+pairs' gradients scattered onto that cleared gradient).  The step is captured once in a HIP graph and replayed; timed steps
 alternate between two copies of inputs and buffers, so that a step does not find its inputs in
 the caches from the step before.  The same instances are also run as:
   per_image_fwd_bwd      plain per-image calls of the C ABI (ph_diagram, the loss gradient,
                          ph_backward) on buffers allocated beforehand, one stream, no graph;
   per_image_fwd_bwd_graph  the same calls captured in one HIP graph (no host launch overhead);
-  batched_fwd_bwd_manual the loss gradient computed by hand and ph_backward called directly;
+  batched_fwd_bwd_manual the loss gradient computed by hand and ph_backward_scatter called
+                         directly (parity: equal to ph_diagram_batch + ph_backward, the gradient
+                         first filled with NaNs);
   batched_fwd            the forward alone;
   batched_fwd_bwd_u8     the instances quantised to 256 levels (floor(256 x)) and read as uint8;
   batched_fwd_bwd_tfilt  the T-filtration (pixels as top cells);
@@ -163,12 +166,13 @@ def cpu_baseline(workers: int):
 
 
 # ------------------------------------------------------------------ byte models --
-def algorithmic_bytes(name, wc, npairs, shapes):
+def algorithmic_bytes(name, wc, npairs, shapes, grad=False):
     """Bytes one launch of `name` must move over the whole batch: the unavoidable reads and
     writes of its inputs and outputs (pixels, forest arrays, list keys, pairs), no re-reads; the
     resolve passes add 4 B per forest link they follow (counted by the kernels).
 
-    wc: per-instance work counters (KEEP edges, KEEP squares, H0 nodes, dual nodes, ...)."""
+    wc: per-instance work counters (KEEP edges, KEEP squares, H0 nodes, dual nodes, ...).
+    grad: the classify passes also clear the gradient (4 B per pixel; ph_diagram_batch_grad)."""
     is3 = np.array([len(s) == 3 for s in shapes])
     N = sum(int(np.prod(s)) for s in shapes)
     ke, kf, m0, mt = (int(wc[:, k].sum()) for k in range(4))
@@ -178,8 +182,8 @@ def algorithmic_bytes(name, wc, npairs, shapes):
         sel = is3 if name == "k_classify3d" else ~is3
         n = sum(int(np.prod(s)) for s, k in zip(shapes, sel) if k)
         t = sum(int(np.prod([e - 1 for e in s])) for s, k in zip(shapes, sel) if k)
-        return 4 * n + 4 * n + 4 * t + 8 * (int(wc[sel, 0].sum()) + int(wc[sel, 1].sum())
-                                            + int(wc[sel, 2].sum()) + int(wc[sel, 3].sum()))
+        return (4 * n + 4 * n + 4 * t + (4 * n if grad else 0)
+                + 8 * (int(wc[sel, 0].sum()) + int(wc[sel, 1].sum()) + int(wc[sel, 2].sum()) + int(wc[sel, 3].sum())))
     if name == "k_sort":
         return 16 * (ke + kf + m0)
     f3 = int(wc[is3, 1].sum())                          # facets of the volumes (walked beside H0)
@@ -200,12 +204,12 @@ def algorithmic_bytes(name, wc, npairs, shapes):
     return 0
 
 
-def kernel_table(prof, wc, npairs, shapes):
+def kernel_table(prof, wc, npairs, shapes, grad=False):
     """{kernel: mean ms, launches, algorithmic bytes and GB/s per launch, fraction of the peak}."""
     out = {}
     for k, (launches, total_ms) in prof.items():
         ms = total_ms / launches
-        b = algorithmic_bytes(k, wc, npairs, shapes)
+        b = algorithmic_bytes(k, wc, npairs, shapes, grad)
         gbs = b / (ms * 1e-3) / 1e9 if ms > 0 else 0.0
         out[k] = {"ms": round(ms, 4), "launches": launches, "bytes": int(b), "gbs": round(gbs, 1),
                   "frac": round(gbs / HBM_PEAK_GBS, 4) if b else None}
@@ -234,11 +238,12 @@ def profile_steps(steps, h1=False):
     bt = fc.Batch(shapes, device="cuda:0", flags=fc.PH_H0 | fc.PH_HTOP | (fc.PH_H1 if h1 else 0))
     bt.set_images([torch.from_numpy(a) for a in imgs])
     for k in range(steps):
-        bt.ph_diagram_batch()
+        # (the step as the headline takes it: the classify passes clear the gradient)
+        bt.ph_diagram_batch(grad=None if h1 else bt.grad)
         if not h1:
             fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
             diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
-            bt.ph_backward(-2.0 * diff, 2.0 * diff)
+            bt.ph_backward(-2.0 * diff, 2.0 * diff, zeroed=True)
         torch.cuda.synchronize()
         print("bench: profile step %d done" % k, file=sys.stderr, flush=True)
     a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda:0")
@@ -557,12 +562,15 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
         b, d = BatchFn.apply(bt.images, bt)
         loss_of(bt, b, d).backward()
 
-    def manual_step(bt, backward=True):
-        bt.ph_diagram_batch()
+    def manual_step(bt, backward=True, fused=True):
+        # fused: the classify passes clear bt.grad and the backward only scatters (as the
+        # autograd Function does); else ph_diagram_batch and ph_backward as they are
+        fused = fused and backward
+        bt.ph_diagram_batch(grad=bt.grad if fused else None)
         if backward:
             fin = bt.valid_mask() & (bt.pairs.death_cell >= 0)
             diff = torch.where(fin, bt.pairs.death - bt.pairs.birth, 0.0)
-            bt.ph_backward(-2.0 * diff, 2.0 * diff)
+            bt.ph_backward(-2.0 * diff, 2.0 * diff, zeroed=fused)
 
     # per-image plain calls on the same inputs, buffers allocated beforehand
     singles = [[SingleCall(fc, torch, a, dev, cap=max(int(caps[i]), 1)) for i, a in enumerate(imgs)]
@@ -576,11 +584,17 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
     log("parity")
     bt = bts[0]
     with torch.no_grad():
-        manual_step(bt)
+        manual_step(bt, fused=False)
     sync()
     bt.check()
     res = bt.results()
     g_manual = bt.grad.clone()
+    with torch.no_grad():                        # the fused clear, on a gradient full of NaNs
+        bt.grad.fill_(float("nan"))
+        manual_step(bt, fused=True)
+    sync()
+    if not torch.equal(bt.grad, g_manual):
+        raise SystemExit("bench: the gradient cleared inside the forward differs from ph_backward's")
     autograd_step(bt)
     sync()
     if not torch.allclose(bt.images.grad, g_manual, rtol=1e-6, atol=1e-7):
@@ -630,14 +644,14 @@ def run_gpu(fc, torch, shapes, args, ref, cfg_inputs, dev=None):
     wc = bt.work_counters()
     name, (launches, total_ms) = max(prof.items(), key=lambda kv: kv[1][1])
     mean_s = total_ms / launches / 1e3
-    algo = algorithmic_bytes(name, wc, npairs, shapes)
+    algo = algorithmic_bytes(name, wc, npairs, shapes, grad=True)   # the step clears the gradient in classify
     achieved = algo / mean_s / 1e9 if mean_s > 0 else 0.0
     traffic = None
     if args.traffic_json and os.path.exists(args.traffic_json):
         tj = json.load(open(args.traffic_json))
         if tj.get("_library_sha256") == library_sha256():
             traffic = tj.get(name)
-    kt = kernel_table(prof, wc, npairs, shapes)
+    kt = kernel_table(prof, wc, npairs, shapes, grad=True)
     sb = sum(v["bytes"] for v in kt.values())
     frac = lambda b, t: round(b / t / (HBM_PEAK_GBS * 1e9), 5)
     forms = {

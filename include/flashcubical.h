@@ -210,6 +210,20 @@ int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off,
                      int32_t *d_status, const ph_tuning *tuning, void *d_ws, size_t ws_bytes,
                      void *stream);
 
+/* ph_diagram_batch that also clears the gradient buffer a later ph_backward_scatter fills (not
+ * part of the paper: the zero fill of ph_backward, moved into the classify passes, which visit
+ * every pixel anyway).
+ *   d_grad_img : device float32, packed like d_imgs (instance i from element d_img_off[i]);
+ *                every pixel of every instance is set to 0.0f, in the caller's layout also
+ *                under PH_TFILT; elements outside the instances are left as they are.
+ * Otherwise (arguments, pairs, errors) as ph_diagram_batch; PH_EINVAL if d_grad_img is null.
+ * After an error return the buffer may be cleared in part or not at all. */
+int ph_diagram_batch_grad(int32_t n, const void *d_imgs, const int64_t *d_img_off,
+                          const ph_shape *d_shapes, const ph_shape *h_shapes, uint32_t flags,
+                          ph_pairs out, const int64_t *d_out_off, int64_t *d_counts,
+                          int32_t *d_status, const ph_tuning *tuning, void *d_ws, size_t ws_bytes,
+                          float *d_grad_img, void *stream);
+
 /* Autotuner (not part of the paper): runs the batch once per candidate tile choice (the 2D
  * choices if the batch holds images, the 3D ones if it holds volumes), one warm-up and `reps`
  * timed runs each, writes the fastest to *best and remembers it for the batch's size class
@@ -236,6 +250,14 @@ int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const p
 int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
                 const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
                 const int64_t *d_img_off, int64_t total_voxels, void *stream);
+
+/* ph_backward without its zero fill (not part of the paper): the pair gradients are added to
+ * d_grad_img as it stands, so it must hold zeros first, as ph_diagram_batch_grad leaves it;
+ * pixels no pair names keep their value.  Arguments and errors as ph_backward; the result on a
+ * buffer so cleared is bitwise that of ph_backward. */
+int ph_backward_scatter(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
+                        const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
+                        const int64_t *d_img_off, int64_t total_voxels, void *stream);
 
 /* Host-side view of the lookup table (Sec. 3.3), for inspection and tests.
  * ndim 2: raw_mask has 8 bits (neighbours up, left, right, down, up-left, up-right,

@@ -125,6 +125,11 @@ def lib():
         L.ph_autotune.restype = ctypes.c_int
         L.ph_backward.argtypes = [i32, ph_pairs, vp, vp, vp, vp, vp, vp, i64, vp]
         L.ph_backward.restype = ctypes.c_int
+        L.ph_diagram_batch_grad.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ph_shape), u32, ph_pairs, vp, vp, vp,
+                                            ctypes.POINTER(ph_tuning), vp, ctypes.c_size_t, vp, vp]
+        L.ph_diagram_batch_grad.restype = ctypes.c_int
+        L.ph_backward_scatter.argtypes = [i32, ph_pairs, vp, vp, vp, vp, vp, vp, i64, vp]
+        L.ph_backward_scatter.restype = ctypes.c_int
         L.ph_lut_entry.argtypes = [i32, u32, ctypes.POINTER(ctypes.c_uint64)]
         L.ph_lut_entry.restype = ctypes.c_int
         L.ph_lut_config_count.argtypes = [i32]
@@ -330,13 +335,17 @@ def _input_flags():
     return {torch.float32: 0, torch.uint8: PH_IN_U8, torch.uint16: PH_IN_U16}
 
 
-def ph_backward(bufs: PairBuffers, counts, out_off, img_off, grad_birth, grad_death, grad_img, stream=None):
-    """Scatter dL/dbirth, dL/ddeath into grad_img (overwritten) -- C ABI ph_backward."""
+def ph_backward(bufs: PairBuffers, counts, out_off, img_off, grad_birth, grad_death, grad_img, stream=None,
+                zeroed: bool = False):
+    """Scatter dL/dbirth, dL/ddeath into grad_img (overwritten) -- C ABI ph_backward; with
+    zeroed, grad_img already holds zeros (ph_diagram_batch_grad) and only the scatter runs --
+    C ABI ph_backward_scatter."""
     n = int(counts.numel())
-    rc = lib().ph_backward(n, bufs.c(), _ptr(out_off), _ptr(counts), _ptr(grad_birth), _ptr(grad_death),
-                           _ptr(grad_img), _ptr(img_off), int(grad_img.numel()), _stream_ptr(stream))
+    fn = lib().ph_backward_scatter if zeroed else lib().ph_backward
+    rc = fn(n, bufs.c(), _ptr(out_off), _ptr(counts), _ptr(grad_birth), _ptr(grad_death),
+            _ptr(grad_img), _ptr(img_off), int(grad_img.numel()), _stream_ptr(stream))
     if rc != PH_OK:
-        raise PHError(rc, "ph_backward")
+        raise PHError(rc, "ph_backward_scatter" if zeroed else "ph_backward")
 
 
 class Batch:
@@ -399,12 +408,23 @@ class Batch:
     def image(self, i):
         return self.images[self.img_off_h[i]:self.img_off_h[i + 1]].view(self.shapes[i])
 
-    def ph_diagram_batch(self, stream=None):
+    def ph_diagram_batch(self, stream=None, grad=None):
+        """The batch's diagrams (C ABI ph_diagram_batch); with grad (a float32 tensor of
+        total_voxels elements, e.g. self.grad), also set it to zero inside the classify passes
+        for ph_backward(..., zeroed=True) (C ABI ph_diagram_batch_grad)."""
         tp = ctypes.byref(self.tuning) if self.tuning is not None else None
-        rc = lib().ph_diagram_batch(self.n, _ptr(self.images), _ptr(self.img_off), _ptr(self.d_shapes),
-                                    self.h_shapes, self.flags, self.pairs.c(), _ptr(self.out_off),
-                                    _ptr(self.counts), _ptr(self.status), tp, _ptr(self.ws), self.ws_bytes,
-                                    _stream_ptr(stream))
+        if grad is None:
+            rc = lib().ph_diagram_batch(self.n, _ptr(self.images), _ptr(self.img_off), _ptr(self.d_shapes),
+                                        self.h_shapes, self.flags, self.pairs.c(), _ptr(self.out_off),
+                                        _ptr(self.counts), _ptr(self.status), tp, _ptr(self.ws), self.ws_bytes,
+                                        _stream_ptr(stream))
+        else:
+            if grad.dtype != _torch().float32 or grad.numel() != self.total_voxels or not grad.is_contiguous():
+                raise PHError(PH_EINVAL, "ph_diagram_batch: grad must be a contiguous float32 tensor of total_voxels")
+            rc = lib().ph_diagram_batch_grad(self.n, _ptr(self.images), _ptr(self.img_off), _ptr(self.d_shapes),
+                                             self.h_shapes, self.flags, self.pairs.c(), _ptr(self.out_off),
+                                             _ptr(self.counts), _ptr(self.status), tp, _ptr(self.ws), self.ws_bytes,
+                                             _ptr(grad), _stream_ptr(stream))
         if rc != PH_OK:
             raise PHError(rc, "ph_diagram_batch")
 
@@ -420,9 +440,10 @@ class Batch:
             raise PHError(rc, "ph_autotune")
         return (int(best.tile2d), int(best.tile3d))
 
-    def ph_backward(self, grad_birth, grad_death, stream=None):
+    def ph_backward(self, grad_birth, grad_death, stream=None, zeroed: bool = False):
+        """Gradient into self.grad; zeroed: the last forward cleared it (grad=self.grad)."""
         ph_backward(self.pairs, self.counts, self.out_off, self.img_off, grad_birth, grad_death, self.grad,
-                    stream)
+                    stream, zeroed)
 
     def work_counters(self):
         """Per-instance counters of the last call (C ABI ph_work_counters), as an (n, 16) array:
@@ -509,11 +530,13 @@ def _autograd():
         (batch.pairs.cap entries, instance i from batch.out_off_h[i]); slots past an
         instance's count hold no pair: batch.valid_mask() marks the stored ones, and
         batch.pairs.death_cell >= 0 the finite ones.  `images` is the batch's packed float32
-        input; when it is not batch.images itself it is copied there first.  backward
-        scatters dL/dbirth and dL/ddeath to the critical pixels (ph_backward) into a new
-        gradient tensor, from the pair vertices and counts this forward saved, so a later
-        forward on the same batch does not change it.  Captured in a HIP graph together
-        with the loss and its backward, a replay recomputes everything in place."""
+        input; when it is not batch.images itself it is copied there first.  When a gradient
+        is wanted, the forward also allocates the gradient tensor and has the classify passes
+        clear it (ph_diagram_batch_grad); backward then scatters dL/dbirth and dL/ddeath to the
+        critical pixels (ph_backward_scatter) from the pair vertices and counts this forward
+        saved, so a later forward on the same batch does not change it.  Captured in a HIP
+        graph together with the loss and its backward, a replay recomputes everything in
+        place."""
 
         @staticmethod
         def forward(ctx, images, batch):
@@ -521,8 +544,12 @@ def _autograd():
                 raise PHError(PH_EINVAL, "BatchDiagramFn: float32 images of the batch's total size")
             if images.data_ptr() != batch.images.data_ptr():
                 batch.images.copy_(images.detach().reshape(-1))
-            batch.ph_diagram_batch()
+            gimg = None
+            if ctx.needs_input_grad[0]:
+                gimg = torch.empty(batch.total_voxels, dtype=torch.float32, device=batch.images.device)
+            batch.ph_diagram_batch(grad=gimg)
             ctx.batch = batch
+            ctx.gimg = gimg
             ctx.save_for_backward(batch.pairs.birth_vertex.clone(), batch.pairs.death_vertex.clone(),
                                   batch.counts.clone())
             ctx.img_shape = images.shape
@@ -537,11 +564,14 @@ def _autograd():
             gb = g_birth.contiguous() if g_birth is not None else torch.zeros(cap, device=dev)
             gd = g_death.contiguous() if g_death is not None else torch.zeros(cap, device=dev)
             pairs = ph_pairs(None, None, None, None, None, bv.data_ptr(), dv.data_ptr())
-            gimg = torch.empty(b.total_voxels, dtype=torch.float32, device=dev)
-            rc = lib().ph_backward(b.n, pairs, _ptr(b.out_off), _ptr(counts), _ptr(gb), _ptr(gd), _ptr(gimg),
-                                   _ptr(b.img_off), b.total_voxels, _stream_ptr(None))
+            gimg = ctx.gimg                          # cleared by the forward's classify passes
+            ctx.gimg = None
+            if gimg is None:
+                raise PHError(PH_EINVAL, "BatchDiagramFn: backward without a gradient buffer")
+            rc = lib().ph_backward_scatter(b.n, pairs, _ptr(b.out_off), _ptr(counts), _ptr(gb), _ptr(gd),
+                                           _ptr(gimg), _ptr(b.img_off), b.total_voxels, _stream_ptr(None))
             if rc != PH_OK:
-                raise PHError(rc, "ph_backward")
+                raise PHError(rc, "ph_backward_scatter")
             return gimg.view(ctx.img_shape), None
 
     return PHDiagramFn, BatchDiagramFn

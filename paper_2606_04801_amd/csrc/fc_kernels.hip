@@ -456,10 +456,63 @@ __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[
     return s_scan[wid] + x - packed;
 }
 
+// ph_diagram_batch_grad: the caller's gradient of one classify tile's pixels (TD layers of TH
+// rows of TW, 1024 in all) set to zero for ph_backward_scatter; under the T-filtration only the
+// inner pixels of the framed grid are the caller's, at the reflected index.  Where the rows
+// start on 16-byte boundaries (the gradient base of the instance and W a multiple of 4) each
+// thread clears four neighbours of a row with one store; else four pixels 256 apart.  The
+// tile's pixels per thread go with the index computed once: 256 is a whole number of layers
+// (3D tiles) or rows (2D tiles), so only z (or y) moves between them.
+template <int TW, int TH, int TD>
+__device__ __forceinline__ void clear_grad_tile(float *__restrict__ g, int tfilt, int D, int H, int W, int z0,
+                                                int y0, int x0) {
+    static_assert(TW * TH * TD == 1024 && TW % 4 == 0, "a tile is 1024 pixels in rows of whole quads");
+    constexpr int LAY = TD > 1 ? TW * TH : TW;     // pixels per step of the moving coordinate
+    static_assert(256 % LAY == 0, "a block covers whole layers (3D) or rows (2D)");
+    constexpr int DM = 256 / LAY;                  // steps of the moving coordinate per pass
+    const int HW = H * W, t = threadIdx.x;
+    if (!tfilt && (((uintptr_t)g & 15) | (uintptr_t)(W & 3)) == 0) {
+        constexpr int Q = TW / 4;
+        const int lx = (t % Q) * 4, r = t / Q, ly = r % TH, lz = r / TH;
+        const int gz = z0 + lz, gy = y0 + ly, gx = x0 + lx;
+        if (gz < D && gy < H && gx < W)            // W % 4 == 0: the quad lies in the row
+            *(float4 *)(g + (uint32_t)(gz * HW + gy * W + gx)) = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const int lx = t % TW, ly = (t / TW) % TH, lz = t / (TW * TH);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    // the moving coordinate m (z in 3D, y in 2D), its range, the fixed ones' test, the index
+    // at the first pass and its step between passes
+    int m, mlo, mhi, idx, step;
+    bool fixed_in;
+    if (!tfilt) {
+        m = TD > 1 ? gz : gy;
+        mlo = 0;
+        mhi = (TD > 1 ? D : H) - 1;
+        fixed_in = gx < W && (TD > 1 ? gy < H : true);
+        idx = gz * HW + gy * W + gx;
+        step = DM * (TD > 1 ? HW : W);
+    } else {
+        const int sH = H - 2, sW = W - 2;
+        m = TD > 1 ? gz : gy;
+        mlo = 1;
+        mhi = (TD > 1 ? D : H) - 2;
+        fixed_in = gx >= 1 && gx <= sW && (TD > 1 ? gy >= 1 && gy <= sH : true);
+        idx = TD > 1 ? ((D - 2 - gz) * sH + (sH - gy)) * sW + (sW - gx) : (sH - gy) * sW + (sW - gx);
+        step = -DM * (TD > 1 ? sH * sW : sW);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int mk = m + k * DM;
+        if (fixed_in && mk >= mlo && mk <= mhi) g[(uint32_t)(idx + k * step)] = 0.0f;
+    }
+}
+
 // ================================================================ classify 2D ====
 template <int TW, int TH, typename T>
 __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
-                                                    uint8_t *__restrict__ ws, int n, Luts lut) {
+                                                    uint8_t *__restrict__ ws, int n, Luts lut,
+                                                    float *__restrict__ grad) {
     static_assert((TW * TH) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, PW = TW + 1, NP = (TH + 1) * (TW + 1);
     constexpr int NIT = TH * TW / 256, NKT = (NP + 255) / 256;
@@ -480,11 +533,13 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed_classify(cnt, &s_fail)) return;
     const int H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
     const int y0 = ty * TH, x0 = tx * TW;
+    // before the error check: an instance that fails still has its gradient cleared
+    if (grad) clear_grad_tile<TW, TH, 1>(grad + I.src_off, I.tfilt, 1, H, W, 0, y0, x0);
+    if (block_failed_classify(cnt, &s_fail)) return;
     const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
@@ -708,7 +763,8 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 // step (an earlier version of the kernel: 1.5 % faster, with 45 % more HBM traffic from spills)
 template <int TW, int TH, int TD, typename T, bool H1 = false>
 __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
-                                                    uint8_t *__restrict__ ws, int n, Luts lut) {
+                                                    uint8_t *__restrict__ ws, int n, Luts lut,
+                                                    float *__restrict__ grad) {
     static_assert((TW * TH * TD) % 256 == 0, "tile must be a multiple of the block");
     constexpr int KW = TW + 2, KH = TH + 2, KD = TD + 2;
     constexpr int PW = TW + 1, PH = TH + 1, PD = TD + 1, NP = PW * PH * PD;
@@ -735,12 +791,14 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, tile);
     const Inst &I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
-    if (block_failed_classify(cnt, &s_fail)) return;
     const int D = I.D, H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
     const int ty = rem / I.tx, tx = rem - ty * I.tx;
     const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
+    // before the error check: an instance that fails still has its gradient cleared
+    if (grad) clear_grad_tile<TW, TH, TD>(grad + I.src_off, I.tfilt, D, H, W, z0, y0, x0);
+    if (block_failed_classify(cnt, &s_fail)) return;
     const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
@@ -3069,12 +3127,14 @@ int64_t max_list(const ph_shape *h, int n) {
 }
 
 template <int A, int B, typename T = float>
-void launch2d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify2d<A, B, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
+void launch2d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st, float *grad) {
+    hipLaunchKernelGGL((k_classify2d<A, B, T>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut,
+                       grad);
 }
 template <int A, int B, int C, typename T = float, bool H1 = false>
-void launch3d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st) {
-    hipLaunchKernelGGL((k_classify3d<A, B, C, T, H1>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n, lut);
+void launch3d(int64_t tiles, const void *imgs, uint8_t *ws, int n, Luts lut, hipStream_t st, float *grad) {
+    hipLaunchKernelGGL((k_classify3d<A, B, C, T, H1>), dim3((unsigned)tiles), dim3(256), 0, st, (const T *)imgs, ws, n,
+                       lut, grad);
 }
 
 Luts current_luts() {
@@ -3177,10 +3237,12 @@ int trace_after(int kid, hipStream_t st) {
     return e == hipSuccess ? PH_OK : PH_EHIP;
 }
 
+// d_grad: with ph_diagram_batch_grad, the caller's gradient buffer the classify passes set to
+// zero (packed like the inputs); else null
 int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
         const ph_shape *h_shapes, ph_shape single, uint32_t flags, ph_pairs out,
         const int64_t *d_out_off, int64_t single_cap, int64_t *d_counts, int32_t *d_status,
-        const ph_tuning *tuning, void *d_ws, size_t ws_bytes, hipStream_t st) {
+        const ph_tuning *tuning, void *d_ws, size_t ws_bytes, hipStream_t st, float *d_grad = nullptr) {
     if (n < 1 || n > kMaxInstances || !d_imgs || !h_shapes || !d_counts || !d_status || !d_ws) return PH_EINVAL;
     if (!out.dim || !out.birth || !out.death || !out.birth_cell || !out.death_cell ||
         !out.birth_vertex || !out.death_vertex)
@@ -3250,22 +3312,22 @@ int run(int n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_s
     const void *cimgs = d_imgs;                    // what the classify passes read
     const Luts lut = current_luts();
     if (t2 > 0) {
-        if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, cimgs, ws, n, lut, st)));
-        else if (elem == 2) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint16_t>(t2, cimgs, ws, n, lut, st)));
-        else if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, cimgs, ws, n, lut, st));
-        else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, cimgs, ws, n, lut, st));
-        else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, cimgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint8_t>(t2, cimgs, ws, n, lut, st, d_grad)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY2D, (launch2d<64, 16, uint16_t>(t2, cimgs, ws, n, lut, st, d_grad)));
+        else if (tile2 == 1) FC_LAUNCH(K_CLASSIFY2D, launch2d<32, 32>(t2, cimgs, ws, n, lut, st, d_grad));
+        else if (tile2 == 2) FC_LAUNCH(K_CLASSIFY2D, launch2d<128, 8>(t2, cimgs, ws, n, lut, st, d_grad));
+        else FC_LAUNCH(K_CLASSIFY2D, launch2d<64, 16>(t2, cimgs, ws, n, lut, st, d_grad));
     }
     if (t3 > 0 && h1) {                            // 3D H1 keeps every configuration: default tiles
-        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t, true>(t3, cimgs, ws, n, lut, st)));
-        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t, true>(t3, cimgs, ws, n, lut, st)));
-        else FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, float, true>(t3, cimgs, ws, n, lut, st)));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t, true>(t3, cimgs, ws, n, lut, st, d_grad)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t, true>(t3, cimgs, ws, n, lut, st, d_grad)));
+        else FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, float, true>(t3, cimgs, ws, n, lut, st, d_grad)));
     } else if (t3 > 0) {
-        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, cimgs, ws, n, lut, st)));
-        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, cimgs, ws, n, lut, st)));
-        else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, cimgs, ws, n, lut, st));
-        else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, cimgs, ws, n, lut, st));
-        else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, cimgs, ws, n, lut, st));
+        if (elem == 1) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint8_t>(t3, cimgs, ws, n, lut, st, d_grad)));
+        else if (elem == 2) FC_LAUNCH(K_CLASSIFY3D, (launch3d<16, 8, 8, uint16_t>(t3, cimgs, ws, n, lut, st, d_grad)));
+        else if (tile3 == 1) FC_LAUNCH(K_CLASSIFY3D, launch3d<32, 8, 4>(t3, cimgs, ws, n, lut, st, d_grad));
+        else if (tile3 == 2) FC_LAUNCH(K_CLASSIFY3D, launch3d<8, 8, 16>(t3, cimgs, ws, n, lut, st, d_grad));
+        else FC_LAUNCH(K_CLASSIFY3D, launch3d<16, 8, 8>(t3, cimgs, ws, n, lut, st, d_grad));
     }
     // resolve grid: the lists are a small share of the voxels for any field that is not noise,
     // so 256 threads per 64Ki voxels of the largest instance; the loops stride over the rest
@@ -3352,6 +3414,50 @@ static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 // ====================================================================== C ABI ====
 
+namespace fc {
+namespace {
+// ph_backward and ph_backward_scatter: the zero fill (zero) then the scatter
+int backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
+             const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
+             const int64_t *d_img_off, int64_t total_voxels, void *stream, bool zero) {
+    if (n < 1 || n > fc::kMaxInstances || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
+        !pairs.birth_vertex || !pairs.death_vertex)
+        return PH_EINVAL;
+    if (!d_out_off || !d_img_off) return PH_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    int rc = fc::device_luts();
+    if (rc != PH_OK) return rc;
+    const bool prof = fc::prof_enabled(), trace = fc::trace_enabled();
+    if (zero) {
+        const int64_t zb = (total_voxels + 255) / 256;
+        if (trace) fc::trace_before(fc::K_ZERO);
+        hipEvent_t z0 = prof ? fc::prof_mark(st) : nullptr;
+        (void)hipGetLastError();
+        hipLaunchKernelGGL(fc::k_zero, dim3((unsigned)(zb < 8192 ? zb : 8192)), dim3(256), 0, st, d_grad_img,
+                           total_voxels);
+        if (hipGetLastError() != hipSuccess) {
+            if (z0) (void)hipEventDestroy(z0);
+            return PH_EHIP;
+        }
+        if (prof) fc::prof_push(fc::K_ZERO, z0, fc::prof_mark(st));
+        if (trace && fc::trace_after(fc::K_ZERO, st) != PH_OK) return PH_EHIP;
+    }
+    if (trace) fc::trace_before(fc::K_SCATTER);
+    hipEvent_t s0 = prof ? fc::prof_mark(st) : nullptr;
+    // pairs are a small share of the voxels for any field that is not noise: one 256-thread
+    // block per 64Ki voxels of the mean instance (1..64 per instance); the loop strides over the rest
+    int64_t sb = (total_voxels / n + 65535) / 65536;
+    sb = sb < 1 ? 1 : (sb > 64 ? 64 : sb);
+    hipLaunchKernelGGL(fc::k_scatter, dim3((unsigned)sb, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
+                       d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
+    const bool ok = hipGetLastError() == hipSuccess;
+    if (prof) fc::prof_push(fc::K_SCATTER, s0, ok ? fc::prof_mark(st) : nullptr);
+    if (ok && trace && fc::trace_after(fc::K_SCATTER, st) != PH_OK) return PH_EHIP;
+    return ok ? PH_OK : PH_EHIP;
+}
+}  // namespace
+}  // namespace fc
+
 extern "C" {
 
 int64_t ph_capacity_bound(ph_shape s) {
@@ -3426,6 +3532,18 @@ int ph_diagram_batch(int32_t n, const void *d_imgs, const int64_t *d_img_off, co
                    d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream);
 }
 
+int ph_diagram_batch_grad(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
+                          const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
+                          int64_t *d_counts, int32_t *d_status, const ph_tuning *tuning, void *d_ws,
+                          size_t ws_bytes, float *d_grad_img, void *stream) {
+    if (!d_img_off || !d_shapes || !d_out_off || !h_shapes || n < 1 || !d_grad_img) return PH_EINVAL;
+    ph_shape dummy{2, {1, 1, 1}};
+    ph_tuning tuned;
+    if (!tuning && !(flags & PH_TFILT) && fc::tuned_for(h_shapes, n, &tuned)) tuning = &tuned;
+    return fc::run(n, d_imgs, d_img_off, d_shapes, h_shapes, dummy, flags, out, d_out_off, 0, d_counts,
+                   d_status, tuning, d_ws, ws_bytes, (hipStream_t)stream, d_grad_img);
+}
+
 int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const ph_shape *d_shapes,
                 const ph_shape *h_shapes, uint32_t flags, ph_pairs out, const int64_t *d_out_off,
                 int64_t *d_counts, int32_t *d_status, void *d_ws, size_t ws_bytes, int32_t reps,
@@ -3475,38 +3593,15 @@ int ph_autotune(int32_t n, const void *d_imgs, const int64_t *d_img_off, const p
 int ph_backward(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
                 const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
                 const int64_t *d_img_off, int64_t total_voxels, void *stream) {
-    if (n < 1 || n > fc::kMaxInstances || !d_counts || !d_grad_birth || !d_grad_death || !d_grad_img || total_voxels < 1 ||
-        !pairs.birth_vertex || !pairs.death_vertex)
-        return PH_EINVAL;
-    if (!d_out_off || !d_img_off) return PH_EINVAL;
-    hipStream_t st = (hipStream_t)stream;
-    int rc = fc::device_luts();
-    if (rc != PH_OK) return rc;
-    const int64_t zb = (total_voxels + 255) / 256;
-    const bool prof = fc::prof_enabled(), trace = fc::trace_enabled();
-    if (trace) fc::trace_before(fc::K_ZERO);
-    hipEvent_t z0 = prof ? fc::prof_mark(st) : nullptr;
-    (void)hipGetLastError();
-    hipLaunchKernelGGL(fc::k_zero, dim3((unsigned)(zb < 8192 ? zb : 8192)), dim3(256), 0, st, d_grad_img,
-                       total_voxels);
-    if (hipGetLastError() != hipSuccess) {
-        if (z0) (void)hipEventDestroy(z0);
-        return PH_EHIP;
-    }
-    if (prof) fc::prof_push(fc::K_ZERO, z0, fc::prof_mark(st));
-    if (trace && fc::trace_after(fc::K_ZERO, st) != PH_OK) return PH_EHIP;
-    if (trace) fc::trace_before(fc::K_SCATTER);
-    hipEvent_t s0 = prof ? fc::prof_mark(st) : nullptr;
-    // pairs are a small share of the voxels for any field that is not noise: one 256-thread
-    // block per 64Ki voxels of the mean instance (1..64 per instance); the loop strides over the rest
-    int64_t sb = (total_voxels / n + 65535) / 65536;
-    sb = sb < 1 ? 1 : (sb > 64 ? 64 : sb);
-    hipLaunchKernelGGL(fc::k_scatter, dim3((unsigned)sb, n), dim3(256), 0, st, pairs, d_out_off, d_counts,
-                       d_grad_birth, d_grad_death, d_grad_img, d_img_off, (int)n, total_voxels);
-    const bool ok = hipGetLastError() == hipSuccess;
-    if (prof) fc::prof_push(fc::K_SCATTER, s0, ok ? fc::prof_mark(st) : nullptr);
-    if (ok && trace && fc::trace_after(fc::K_SCATTER, st) != PH_OK) return PH_EHIP;
-    return ok ? PH_OK : PH_EHIP;
+    return fc::backward(n, pairs, d_out_off, d_counts, d_grad_birth, d_grad_death, d_grad_img, d_img_off,
+                        total_voxels, stream, true);
+}
+
+int ph_backward_scatter(int32_t n, ph_pairs pairs, const int64_t *d_out_off, const int64_t *d_counts,
+                        const float *d_grad_birth, const float *d_grad_death, float *d_grad_img,
+                        const int64_t *d_img_off, int64_t total_voxels, void *stream) {
+    return fc::backward(n, pairs, d_out_off, d_counts, d_grad_birth, d_grad_death, d_grad_img, d_img_off,
+                        total_voxels, stream, false);
 }
 
 int ph_lut_entry(int32_t ndim, uint32_t raw_mask, uint64_t *entry) {

@@ -5,7 +5,9 @@
 // in.bin (little-endian): int32 n, uint32 flags, int32 mode (0: ph_diagram, n must be 1;
 // 1: ph_diagram_batch; 2: ph_autotune then ph_diagram_batch), int32 tile2d, int32 tile3d
 // (-1: no tuning argument), int32 backward (1: also run ph_backward for the loss
-// sum over finite pairs of (death - birth)^2), int32 capacity per instance (-1: the bound);
+// sum over finite pairs of (death - birth)^2; 2: the same gradient from ph_diagram_batch_grad,
+// on a gradient buffer full of NaNs, then ph_backward_scatter; mode 1 or 2 only), int32
+// capacity per instance (-1: the bound);
 // then n x (int32 ndim, int32 ext[3]); then the pixels of all instances, float32,
 // concatenated.
 // out.bin: per instance int64 count, int32 status, then the stored pairs as int32 dim,
@@ -181,6 +183,15 @@ int main(int argc, char **argv) {
     ph_pairs out{dim, birth, death, bcell, dcell, bvert, dvert};
     ph_tuning tune{hdr[3], hdr[4]};
     const ph_tuning *tp = hdr[3] >= 0 ? &tune : nullptr;
+    float *grad = nullptr;
+    if (backward) {
+        grad = dev_alloc<float>(img.size());
+        uninit(grad, img.size());
+    }
+    if (backward == 2) {
+        if (mode == 0) return 2;
+        for (size_t k = 0; k < img.size(); ++k) grad[k] = __builtin_nanf("");
+    }
     emu_after_launch = guard_workspace;
     int rc;
     if (mode == 0) {
@@ -194,8 +205,12 @@ int main(int argc, char **argv) {
             unguard();
             if (rc != PH_OK) { fprintf(stderr, "driver: autotune rc %d\n", rc); return 3; }
         }
-        rc = ph_diagram_batch(n, d_img, d_img_off, d_shapes, shapes.data(), flags, out, d_out_off, counts, status,
-                              tp, ws, g_wsb, nullptr);
+        if (backward == 2)
+            rc = ph_diagram_batch_grad(n, d_img, d_img_off, d_shapes, shapes.data(), flags, out, d_out_off, counts,
+                                       status, tp, ws, g_wsb, grad, nullptr);
+        else
+            rc = ph_diagram_batch(n, d_img, d_img_off, d_shapes, shapes.data(), flags, out, d_out_off, counts,
+                                  status, tp, ws, g_wsb, nullptr);
     }
     unguard();
     emu_after_launch = nullptr;
@@ -211,7 +226,6 @@ int main(int argc, char **argv) {
         }
     }
 
-    float *grad = nullptr;
     if (backward) {
         std::vector<float> gb(cap, 0.f), gd(cap, 0.f);
         for (int i = 0; i < n; ++i)
@@ -223,9 +237,8 @@ int main(int argc, char **argv) {
                 gd[k] = 2.f * d;
             }
         float *d_gb = dev_copy(gb), *d_gd = dev_copy(gd);
-        grad = dev_alloc<float>(img.size());
-        uninit(grad, img.size());
-        rc = ph_backward(n, out, d_out_off, counts, d_gb, d_gd, grad, d_img_off, (int64_t)img.size(), nullptr);
+        rc = (backward == 2 ? ph_backward_scatter : ph_backward)(n, out, d_out_off, counts, d_gb, d_gd, grad,
+                                                                 d_img_off, (int64_t)img.size(), nullptr);
         if (rc != PH_OK) { fprintf(stderr, "driver: backward rc %d\n", rc); return 3; }
     }
 

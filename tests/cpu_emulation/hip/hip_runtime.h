@@ -82,6 +82,8 @@ inline void emu_check_access(const void *, size_t, int) {}
 
 struct int2 { int x, y; };
 inline int2 make_int2(int x, int y) { return int2{x, y}; }
+struct alignas(16) float4 { float x, y, z, w; };
+inline float4 make_float4(float x, float y, float z, float w) { return float4{x, y, z, w}; }
 
 struct dim3 {
     unsigned x, y, z;

@@ -100,13 +100,35 @@ def mixed_batch():
             S.grf((9, 12, 10), 1.5, 7103), S.levels((1, 7), 5, 7104), S.uniform((20, 21), 7105)]
 
 
-@pytest.mark.parametrize("tuning", [None, (1, 2), (2, 1)])
-def test_batch_with_backward(driver, tuning):
+@pytest.mark.parametrize("tuning, fused", [(None, 0), ((1, 2), 0), ((2, 1), 0), (None, 1), ((2, 1), 1)])
+def test_batch_with_backward(driver, tuning, fused):
+    """ph_backward after ph_diagram_batch, or (fused) ph_backward_scatter after
+    ph_diagram_batch_grad cleared a gradient full of NaNs: the oracle's gradient."""
     imgs = mixed_batch()
-    out, grad = run(driver, imgs, mode=1, tuning=tuning, backward=True)
+    out, grad = run(driver, imgs, mode=1, tuning=tuning, backward=2 if fused else True)
     off = 0
     for img, (got, st) in zip(imgs, out):
         ref = oracle.diagram(img)
+        assert st == 0 and diff_pairs(got, ref) is None, img.shape
+        f = ref["death_cell"] >= 0
+        d = np.where(f, ref["death"] - ref["birth"], 0).astype(np.float32)
+        g = oracle.gradient(ref, -2 * d, 2 * d, img.shape).reshape(-1)
+        np.testing.assert_allclose(grad[off:off + img.size], g, rtol=1e-6, atol=1e-7)
+        off += img.size
+
+
+@pytest.mark.parametrize("variant", ["asan", "poison"])
+def test_t_filtration_fused_gradient(variant):
+    """Under the T-filtration (PH_TFILT) the classify passes clear the caller's pixels through
+    the reflection of the framed grid: ph_diagram_batch_grad then ph_backward_scatter, on a
+    gradient full of NaNs, under AddressSanitizer and on a garbage workspace, give the oracle's
+    T pairs and gradient."""
+    exe = emu_build.build(variant)
+    imgs = mixed_batch()
+    out, grad = run(exe, imgs, mode=1, flags=3 | 16, backward=2)
+    off = 0
+    for img, (got, st) in zip(imgs, out):
+        ref = oracle.diagram(img, filtration="T")
         assert st == 0 and diff_pairs(got, ref) is None, img.shape
         f = ref["death_cell"] >= 0
         d = np.where(f, ref["death"] - ref["birth"], 0).astype(np.float32)

@@ -94,6 +94,12 @@ def test_host_validation_before_any_device_call():
                               one, one, one, None, one, 1 << 30, None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EINVAL
     assert L.ph_backward(1, fc.ph_pairs(), None, None, None, None, None, None, 0, None) == fc.PH_EINVAL
+    assert L.ph_backward_scatter(1, fc.ph_pairs(), None, None, None, None, None, None, 16, None) == fc.PH_EINVAL
+    pr = fc.ph_pairs(one, one, one, one, one, one, one)
+    assert L.ph_diagram_batch_grad(1, one, one, one, sh, 3, pr, one, one, one, None, one, 1 << 30, None,
+                                   None) == fc.PH_EINVAL       # no gradient buffer
+    assert L.ph_diagram_batch_grad(0, one, one, one, sh, 3, pr, one, one, one, None, one, 1 << 30, one,
+                                   None) == fc.PH_EINVAL
     best = fc.ph_tuning(0, 0)
     assert L.ph_autotune(1, None, None, None, sh, 3, fc.ph_pairs(), None, None, None, None, 0, 1,
                          ctypes.byref(best), None) == fc.PH_EINVAL
