@@ -152,6 +152,13 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
             if (I.ndim == 2) v[1] = (int64_t)I.tx * I.ty;
             else v[2] = (int64_t)I.tx * I.ty * I.tz;
         }
+        // the counter words of this chunk's instances set to zero by the whole block, a word a
+        // thread, in coalesced stores (the barriers of the scan order them before each
+        // instance's own non-zero words below)
+        {
+            const int c1 = n - c0 < kPlanThreads ? n : c0 + kPlanThreads;
+            for (int64_t w = (int64_t)c0 * CNT_WORDS + t; w < (int64_t)c1 * CNT_WORDS; w += kPlanThreads) cnt[w] = 0;
+        }
         // inclusive Hillis-Steele scan of the three sizes over the block
         int b = 0;
         for (int k = 0; k < 3; ++k) s_scan[0][k][t] = v[k];
@@ -172,7 +179,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(int n, const ph_shape *__
             I.tile_base = I.ndim == 2 ? tb2[i] : tb3[i];
             layout(I, at);
             tab[i] = I;
-            for (int k = 0; k < CNT_WORDS; ++k) cnt[i * CNT_WORDS + k] = 0;
             cnt[i * CNT_WORDS + CNT_MT] = 1;           // dual node 0 is the cell at infinity
             if (!ok || I.out_cap < 0) cnt[i * CNT_WORDS + CNT_ERR] = PH_EINVAL;
             d_counts[i] = 0;
