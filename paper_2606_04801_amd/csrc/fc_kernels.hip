@@ -257,6 +257,16 @@ __device__ __forceinline__ bool block_failed_classify(const int32_t *cnt, int *s
     lds_barrier();
     return *s_flag != 0;
 }
+// The same in two steps, so that the word's load is in flight while the block does other work:
+// err_word (thread 0 reads the word, the others 0), then block_failed_from with its value.
+__device__ __forceinline__ int err_word(const int32_t *cnt) {
+    return threadIdx.x == 0 ? __hip_atomic_load(&cnt[CNT_ERR], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0;
+}
+__device__ __forceinline__ bool block_failed_from(int e, int *s_flag) {
+    if (threadIdx.x == 0) *s_flag = e != 0 && e != PH_ELISTS;
+    lds_barrier();
+    return *s_flag != 0;
+}
 
 template <typename T>
 __device__ __forceinline__ T *arr(uint8_t *ws, int64_t off) { return (T *)(ws + off); }
@@ -419,10 +429,11 @@ __device__ __forceinline__ void jump_links(int32_t *sp0, int32_t *spT, int32_t (
 // Block-wide reservation of slots in up to four per-instance lists at once.  Each thread
 // passes its counts packed 16 bits per list (every block total stays below 2^16: a tile has
 // 1024 vertices and at most 12 kept cells each of one kind); the block scans them once and
-// one thread reserves each list's block total with a single atomic, so a tile costs one
-// atomic per non-empty list instead of one per wave and pass.  Returns the thread's
-// exclusive prefix (packed the same way); the lists' first slots are left in s_base.  All
-// threads call it.
+// lane k of wave 0 reserves list k's block total with a single atomic, all lists' atomics in
+// flight together, so a tile costs one atomic per non-empty list instead of one per wave and
+// pass, and one round trip to L2.  lists8 holds the lists' counter words, a byte each (list k
+// in bits 8k..8k+7).  Returns the thread's exclusive prefix (packed the same way); the lists'
+// first slots are left in s_base.  All threads call it.
 // Inclusive sum of x over the lanes of a wave up to each lane, with data-parallel-primitive
 // moves: sums inside each row of 16 lanes (row shifts by 1, 2, 4 and 8 lanes, a lane shifted in
 // from outside the row reading 0), then the totals carried up (lane 15 of row 0 and 2 added
@@ -438,7 +449,7 @@ __device__ __forceinline__ uint32_t wave_incl_sum(uint32_t x) {
 }
 
 template <int NLIST>
-__device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[NLIST], uint64_t packed,
+__device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, uint32_t lists8, uint64_t packed,
                                                 uint64_t *s_scan, int32_t *s_base) {
     const int lane = __lane_id(), wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
     // the 16-bit fields never carry: each block total stays below 2^16, so the two 32-bit
@@ -446,20 +457,18 @@ __device__ __forceinline__ uint64_t block_alloc(int32_t *cnt, const int (&list)[
     const uint64_t x = (uint64_t)wave_incl_sum((uint32_t)(packed >> 32)) << 32 | wave_incl_sum((uint32_t)packed);
     if (lane == 63) s_scan[wid] = x;
     lds_barrier();
-    if (threadIdx.x == 0) {
+    uint64_t pre = 0;                                // the block's entries before this wave's
+    for (int w = 0; w < wid; ++w) pre += s_scan[w];
+    if (wid == 0 && lane < NLIST) {
+        // lane k of wave 0 takes list k's block of entries: the atomics are in flight together
         uint64_t tot = 0;
-        for (int w = 0; w < nw; ++w) {
-            const uint64_t v = s_scan[w];
-            s_scan[w] = tot;
-            tot += v;
-        }
-        for (int k = 0; k < NLIST; ++k) {
-            const int t = (int)((tot >> (16 * k)) & 0xFFFFu);
-            s_base[k] = t ? atomicAdd(&cnt[list[k]], t) : 0;
-        }
+        for (int w = 0; w < nw; ++w) tot += s_scan[w];
+        const int li = (int)((lists8 >> (8 * lane)) & 0xFFu);   // counter word of list `lane`
+        const int t = (int)((tot >> (16 * lane)) & 0xFFFFu);
+        s_base[lane] = t ? atomicAdd(&cnt[li], t) : 0;
     }
     lds_barrier();
-    return s_scan[wid] + x - packed;
+    return pre + x - packed;
 }
 
 // ph_diagram_batch_grad: the caller's gradient of one classify tile's pixels (TD layers of TH
@@ -537,15 +546,18 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = find_inst((const int64_t *)(ws + off_tb2(n)), n, tile);
-    const Inst &I = tab[i];
+    // the instance's record copied before the kernel's first store or atomic: its fields load as
+    // scalar loads in one batch (after a store they would be vector loads where first used)
+    const Inst I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const int err = err_word(cnt);
     const int H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int ty = lt / I.tx, tx = lt - ty * I.tx;
     const int y0 = ty * TH, x0 = tx * TW;
     // before the error check: an instance that fails still has its gradient cleared
     if (grad) clear_grad_tile<TW, TH, 1>(grad + I.src_off, I.tfilt, 1, H, W, 0, y0, x0);
-    if (block_failed_classify(cnt, &s_fail)) return;
+    if (block_failed_from(err, &s_fail)) return;
     const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
@@ -657,9 +669,9 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
         c_root += __popc((e >> kL2Root) & 15u);
         ev[it] = e;
     }
-    const int lists[3] = {CNT_M0, CNT_E, CNT_MT};
+    constexpr uint32_t lists8 = CNT_M0 | CNT_E << 8 | CNT_MT << 16;
     const uint64_t packed = c_min | c_edge << 16 | (uint64_t)c_root << 32;
-    const uint64_t pre = block_alloc<3>(cnt, lists, packed, s_scan, s_base);
+    const uint64_t pre = block_alloc<3>(cnt, lists8, packed, s_scan, s_base);
     int id0 = s_base[0] + (int)(pre & 0xFFFFu);
     int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
     int rb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
@@ -764,9 +776,12 @@ __global__ __launch_bounds__(256) void k_classify2d(const T *__restrict__ imgs,
 }
 
 // ================================================================ classify 3D ====
-// 256 threads, seven workgroups (28 waves) per compute unit at 72 registers, without spills.
-// Eight (the 64-register budget) spill five registers and measured 0.8 % slower on the batched
-// step (an earlier version of the kernel: 1.5 % faster, with 45 % more HBM traffic from spills)
+// 256 threads; at least seven workgroups per compute unit are asked for, and at 52 registers
+// without spills the kernel runs eight (32 waves).  The instance's record is copied before the
+// first store, so its fields sit in scalar registers: read after a store, they were vector
+// loads into vector registers, and the kernel needed 72 registers and ran seven workgroups,
+// 9 % slower on the batched step.  Asking for eight makes the 32 x 8 x 4 tile spill scalar
+// registers.
 template <int TW, int TH, int TD, typename T, bool H1 = false>
 __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ imgs,
                                                     uint8_t *__restrict__ ws, int n, Luts lut,
@@ -795,8 +810,11 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     const Inst *tab = (const Inst *)ws;
     const int64_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const int i = find_inst((const int64_t *)(ws + off_tb3(n)), n, tile);
-    const Inst &I = tab[i];
+    // the instance's record copied before the kernel's first store or atomic: its fields load as
+    // scalar loads in one batch (after a store they would be vector loads where first used)
+    const Inst I = tab[i];
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
+    const int err = err_word(cnt);
     const int D = I.D, H = I.H, W = I.W;
     const int lt = (int)(tile - I.tile_base);
     const int tz = lt / (I.tx * I.ty), rem = lt - tz * I.tx * I.ty;
@@ -804,7 +822,7 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
     const int z0 = tz * TD, y0 = ty * TH, x0 = tx * TW;
     // before the error check: an instance that fails still has its gradient cleared
     if (grad) clear_grad_tile<TW, TH, TD>(grad + I.src_off, I.tfilt, D, H, W, z0, y0, x0);
-    if (block_failed_classify(cnt, &s_fail)) return;
+    if (block_failed_from(err, &s_fail)) return;
     const T *img = imgs + I.src_off;
     int32_t *par0 = arr<int32_t>(ws, I.o_par0);
     int32_t *parT = arr<int32_t>(ws, I.o_parT);
@@ -978,9 +996,9 @@ __global__ __launch_bounds__(256, 7) void k_classify3d(const T *__restrict__ img
         ev[it] = e;
     }
     if (bad) set_err(cnt, PH_EINTERNAL);
-    const int lists[4] = {CNT_M0, CNT_E, CNT_F, CNT_MT};
+    constexpr uint32_t lists8 = CNT_M0 | CNT_E << 8 | CNT_F << 16 | (uint32_t)CNT_MT << 24;
     const uint64_t packed = c_min | c_edge << 16 | (uint64_t)(c_sq | c_root << 16) << 32;
-    const uint64_t pre = block_alloc<4>(cnt, lists, packed, s_scan, s_base);
+    const uint64_t pre = block_alloc<4>(cnt, lists8, packed, s_scan, s_base);
     int id0 = s_base[0] + (int)(pre & 0xFFFFu);
     int kb = s_base[1] + (int)((pre >> 16) & 0xFFFFu);
     int fb = s_base[2] + (int)((pre >> 32) & 0xFFFFu);
