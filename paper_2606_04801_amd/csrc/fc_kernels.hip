@@ -1331,7 +1331,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_lists(uint8_t *__restrict
     __shared__ uint64_t s[kSortCap];
     __shared__ uint64_t s2[kSortCap];
     const int i = blockIdx.x, w = blockIdx.y;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (block_failed(cnt)) return;
     const int mE = cnt[CNT_E], mF = cnt[CNT_F], mN = cnt[CNT_M0];
@@ -1526,7 +1526,7 @@ __device__ __forceinline__ void wave_count(int32_t *counter, int v) {
 // H0: the two endpoints of every sorted KEEP edge of instance i, as H0 nodes (local minima).
 // The blocks of one instance are blockIdx.x of gridDim.x; the links followed are counted.
 __device__ __forceinline__ void resolve_edges(uint8_t *__restrict__ ws, int n, int i) {
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (failed(cnt)) return;
     const int m = cnt[CNT_E], M0 = cnt[CNT_M0];
@@ -1555,7 +1555,7 @@ __device__ __forceinline__ void resolve_edges(uint8_t *__restrict__ ws, int n, i
 // Top dimension: the two cofacets of every facet of instance i walked by the dual union-find,
 // as dual nodes (0 = the cell at infinity).  2D walks the KEEP edges that H0 did not use.
 __device__ __forceinline__ void resolve_facets(uint8_t *__restrict__ ws, int n, int i) {
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (failed(cnt)) return;
     const bool is2d = I.ndim == 2;
@@ -1653,7 +1653,7 @@ __device__ __forceinline__ void uf_body(uint8_t *__restrict__ ws, int n, int32_t
                                         int32_t *live, int32_t *A, int32_t *B, uint64_t *s_key, int *s_wsum,
                                         bool cont = false) {
     const int i = blockIdx.x;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     const bool is2d = I.ndim == 2;
     const int m = DUAL ? (is2d ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
@@ -1810,7 +1810,7 @@ __device__ __forceinline__ bool uf_is_wide(const Inst &I, int M, int m) {
 template <bool DUAL>
 __device__ __forceinline__ void uf_wide(uint8_t *__restrict__ ws, int n, int phase, int round, int *s_flag) {
     const int i = blockIdx.y;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
     const int m = DUAL ? (I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
@@ -1964,7 +1964,7 @@ __global__ __launch_bounds__(kWideThreads) void k_uf_wide(uint8_t *__restrict__ 
 template <bool DUAL>
 __device__ __forceinline__ void uf_run(uint8_t *__restrict__ ws, int n, int32_t *s_lds, int *s_wsum, bool wide) {
     const int i = blockIdx.x;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     const int32_t *cnt = (const int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     const int M = DUAL ? cnt[CNT_MT] : cnt[CNT_M0];
     const int m = DUAL ? (I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F]) : cnt[CNT_E];
@@ -2233,7 +2233,7 @@ __global__ __launch_bounds__(64) void k_h1_morse(const T *__restrict__ imgs, uin
     __shared__ int s_used, s_tail, s_over, s_nb;
     __shared__ int32_t s_bnd[kH1MaxBoundary];
     const int i = blockIdx.y;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (I.ndim != 3 || !I.h1) return;
     if (block_failed(cnt)) return;
@@ -2434,7 +2434,7 @@ __global__ __launch_bounds__(kUfThreads) void k_h1_reduce(uint8_t *__restrict__ 
     __shared__ int32_t s_ul[kRedList], s_off[kRedList], s_len[kRedList];
     __shared__ int s_top, s_any, s_fail;
     const int i = blockIdx.x;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (I.ndim != 3 || !I.h1) return;
     if (block_failed(cnt)) return;
@@ -2635,7 +2635,7 @@ __global__ __launch_bounds__(kUfThreads) void k_output(const void *__restrict__ 
                                                       int32_t *__restrict__ d_status, int mode) {
     __shared__ int s_wsum[kUfThreads / 64];
     const int i = mode == 0 ? blockIdx.x : blockIdx.y;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     const bool wide = out_is_wide(I, flags);
     if (mode != 0 && !wide) return;
@@ -2898,7 +2898,7 @@ __global__ __launch_bounds__(kUfThreads) void k_output_scan(uint8_t *__restrict_
     __shared__ int32_t s_w[kUfThreads / 64];
     __shared__ int64_t s_run;
     const int i = blockIdx.x;
-    const Inst &I = ((const Inst *)ws)[i];
+    const Inst I = ((const Inst *)ws)[i];           // one batch of loads, before any atomic
     int32_t *cnt = (int32_t *)(ws + off_cnt(n)) + i * CNT_WORDS;
     if (!out_is_wide(I, flags) || block_failed(cnt)) return;
     const int M0 = cnt[CNT_M0], mf = I.ndim == 2 ? cnt[CNT_E] : cnt[CNT_F];
